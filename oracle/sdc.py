@@ -1,0 +1,367 @@
+"""SI-SDC and SI-MLSDC in the weak (dual) form, following the paper's steps.
+
+Notation (Sec. 3 and 4): level l = 1 (coarsest) .. L (finest); on a level the
+collocation nodes are t_m = t + tau_m dt, m = 1..M, with substeps
+dt_m = (tau_m - tau_{m-1}) dt and u_0 the step's initial value.  A level is
+any object with
+
+    mass(x), conv(u), frhs(u), coef(u_b, dt_m, params), K(coef, x),
+    solve(coef, dt_m, b, x0), tt (a temporal.TimeTable)
+
+so the same code runs the DG discretisation and the scalar test equation.
+
+Low-order term (eq. H_SI(1)), weak form:
+    H(a, b, c) = dt_m [ C(a) - K_{D_m(b)} c ],
+with D_m(b) the implicit coefficient (physics.py).  Semi-implicit systems are
+solved as (M + dt_m K_{D_m(b)}) x = rhs.
+
+Predictor SI(2) (eq. sdc:incremental_predictor_si2):
+    M y   = M u_{m-1} + H(u_{m-1}, u_{m-1}, y)
+    M u_m = M u_{m-1} + H(y,       u_{m-1}, u_m)
+SI(1) (eq. sdc:incremental_predictor_si1) is the first line with y -> u_m.
+
+Corrector SI(2), sweep k (eqs. sdc:incremental_corrector, DeltaH_SI2 and the
+stage u^(1); with the FAS term g_m of eq. ml-sdc:incremental):
+    q_m   = sum_i S_{m,i} f(u^{k-1}_i),   S = dt w^nn
+    M y   = M u^k_{m-1} + q_m + g_m + H(u^k_{m-1}, u^k_{m-1}, y)
+                                    - H(u^{k-1}_{m-1}, u^{k-1}_{m-1}, u^{k-1}_m)
+    M u^k_m = M u^k_{m-1} + q_m + g_m + H(y, u^k_{m-1}, u^k_m)
+                                    - H(u^{k-1}_m, u^{k-1}_{m-1}, u^{k-1}_m)
+g_m enters both stages (reading: the paper writes the FAS term once; only
+then is the collocation solution a fixed point of the two-stage sweep).
+SI(1) is the first line with y -> u^k_m (eq. DeltaH_SI1).
+
+Residual and FAS (eqs. cm:incremental:op, ml-cm:incremental:fas-mg:rhs,
+MLSDC:incremental:residual):
+    F_m(u) = M (u_m - u_{m-1}) - q_m(u),   r_l = g_l - F_l(u_l),
+    g_{l-1} = F_{l-1}(P u_l) + R r_l,  g_L = 0.
+Transfers (Sec. 4 "MLSDC transfer operators", Sec. 6 "MLSDC transfer
+operators"): space-time products of 1-D Lagrange interpolation matrices,
+I = I_t (x) I_x, P = P_t (x) P_x (embedded interpolation), R = I^T.
+V-cycle: Alg. 2; cascade start: Alg. 3; FMG start: Alg. 4.
+"""
+import numpy as np
+
+from .element import RefElement, lagrange_matrix
+from .temporal import TimeTable, time_transfer
+from .mesh import Mesh
+from .dg import DG
+from . import solve as _solve
+
+
+# --------------------------------------------------------------------------
+# levels
+# --------------------------------------------------------------------------
+class DGLevel:
+    """One space-time level: DG-SEM of degree P on a mesh, M Radau nodes."""
+
+    def __init__(self, phys, n_elem, lo, hi, P, M, c_tau=2.0, rtol=1e-14,
+                 maxit=20000, solver="cg"):
+        self.phys = phys
+        self.ref = RefElement(P)
+        self.mesh = Mesh(n_elem, lo, hi, P)
+        self.dg = DG(self.ref, self.mesh, phys, c_tau)
+        self.tt = TimeTable(M)
+        self.rtol = rtol
+        self.maxit = maxit
+        self.solver = solver
+        self.nv = phys.nv
+        self.solve_log = []
+
+    def shape(self):
+        return self.mesh.shape(self.nv)
+
+    def mass(self, x):
+        return self.dg.mass(x)
+
+    def conv(self, u):
+        return self.dg.conv(u)
+
+    def frhs(self, u):
+        return self.dg.frhs(u)
+
+    def coef(self, ub, dtm, params):
+        return self.phys.coef(ub, dtm, params)
+
+    def K(self, Dc, x):
+        return self.dg.sipg(Dc, x)
+
+    def solve(self, Dc, dtm, b, x0):
+        apply = lambda x: self.dg.helmholtz(Dc, dtm, x)
+        if self.solver == "dense":
+            x = _solve.dense_solve(apply, b)
+            self.solve_log.append((0, 0.0))
+            return x
+        pre = self.dg.Wm * np.ones_like(b)
+        x, it, rel = _solve.cg(apply, b, x0, pre, rtol=self.rtol, maxit=self.maxit)
+        self.solve_log.append((it, rel))
+        return x
+
+    def coords(self):
+        return self.mesh.node_coords(self.ref.x)
+
+
+class SpaceTransfer:
+    """p-coarsening transfer between two DG levels on the same mesh:
+    I_x (coarse -> fine), P_x (fine -> coarse, embedded interpolation) and
+    R_x = I_x^T, each the 1-D Lagrange matrix applied along every axis."""
+
+    def __init__(self, fine, coarse):
+        self.fine, self.coarse = fine, coarse
+        self.I1 = lagrange_matrix(coarse.ref.x, fine.ref.x)     # (Pf+1, Pc+1)
+        self.P1 = lagrange_matrix(fine.ref.x, coarse.ref.x)     # (Pc+1, Pf+1)
+
+    def _apply(self, X, A):
+        mesh = self.fine.mesh
+        for d in range(mesh.dim):
+            ax = mesh.node_axis(d)
+            X = np.moveaxis(np.tensordot(A, X, axes=([1], [ax])), 0, ax)
+        return X
+
+    def I(self, xc):
+        return self._apply(xc, self.I1)
+
+    def P(self, xf):
+        return self._apply(xf, self.P1)
+
+    def R(self, rf):
+        return self._apply(rf, self.I1.T)
+
+
+# --------------------------------------------------------------------------
+# single-level building blocks
+# --------------------------------------------------------------------------
+def substeps(lv, dt):
+    return dt * lv.tt.dtau
+
+
+def quadrature(lv, F, dt):
+    """q_m = sum_i S_{m,i} f_i, S = dt w^nn (eq. cm:incremental).  F holds
+    f at nodes 1..M; returns q for nodes 1..M (index 0 unused: None)."""
+    S = lv.tt.S(dt)
+    M = lv.tt.M
+    q = [None]
+    for m in range(M):
+        acc = np.zeros_like(F[1])
+        for i in range(M):
+            acc = acc + S[m, i] * F[i + 1]
+        q.append(acc)
+    return q
+
+
+def H(lv, a, b, c, dtm, params):
+    """Weak H^SI(a, b, c) = dt_m [C(a) - K_{D_m(b)} c]."""
+    return dtm * (lv.conv(a) - lv.K(lv.coef(b, dtm, params), c))
+
+
+def predictor(lv, u0, dt, params, scheme="si2"):
+    """SI(1) / SI(2) predictor sweep: returns [u_0, u_1, ..., u_M]."""
+    U = [u0]
+    dts = substeps(lv, dt)
+    for m in range(1, lv.tt.M + 1):
+        dtm = dts[m - 1]
+        ua = U[m - 1]
+        Dc = lv.coef(ua, dtm, params)
+        y = lv.solve(Dc, dtm, lv.mass(ua) + dtm * lv.conv(ua), ua)
+        if scheme == "si1":
+            U.append(y)
+            continue
+        U.append(lv.solve(Dc, dtm, lv.mass(ua) + dtm * lv.conv(y), y))
+    return U
+
+
+def sweep(lv, U, dt, params, g=None, scheme="si2"):
+    """One incremental SI(1)/SI(2) corrector sweep (Alg. 1 with N = 1)."""
+    M = lv.tt.M
+    dts = substeps(lv, dt)
+    F = [None] + [lv.frhs(U[i]) for i in range(1, M + 1)]
+    q = quadrature(lv, F, dt)
+    Unew = [U[0]]
+    for m in range(1, M + 1):
+        dtm = dts[m - 1]
+        h1_old = H(lv, U[m - 1], U[m - 1], U[m], dtm, params)
+        ua = Unew[m - 1]
+        Dc = lv.coef(ua, dtm, params)
+        base = lv.mass(ua) + q[m]
+        if g is not None:
+            base = base + g[m]
+        y = lv.solve(Dc, dtm, base + dtm * lv.conv(ua) - h1_old, U[m])
+        if scheme == "si1":
+            Unew.append(y)
+            continue
+        h2_old = H(lv, U[m], U[m - 1], U[m], dtm, params)
+        Unew.append(lv.solve(Dc, dtm, base + dtm * lv.conv(y) - h2_old, y))
+    return Unew
+
+
+def collocation_residual(lv, U, dt):
+    """F_m(u) = M (u_m - u_{m-1}) - q_m(u), m = 1..M (index 0: None)."""
+    M = lv.tt.M
+    F = [None] + [lv.frhs(U[i]) for i in range(1, M + 1)]
+    q = quadrature(lv, F, dt)
+    return [None] + [lv.mass(U[m] - U[m - 1]) - q[m] for m in range(1, M + 1)]
+
+
+# --------------------------------------------------------------------------
+# space-time transfers
+# --------------------------------------------------------------------------
+class Transfer:
+    """Space-time transfer between level l (fine) and l-1 (coarse)."""
+
+    def __init__(self, fine, coarse, space=None):
+        self.fine, self.coarse = fine, coarse
+        self.It, self.Pt, self.Rt = time_transfer(fine.tt, coarse.tt)
+        self.space = space if space is not None else SpaceTransfer(fine, coarse)
+
+    def interp(self, Uc):
+        """(I_t (x) I_x) on nodes 1..M_c -> nodes 1..M_f (index 0: None)."""
+        Mf, Mc = self.fine.tt.M, self.coarse.tt.M
+        xs = [None] + [self.space.I(Uc[j]) for j in range(1, Mc + 1)]
+        out = [None]
+        for i in range(Mf):
+            acc = 0.0
+            for j in range(Mc):
+                acc = acc + self.It[i, j] * xs[j + 1]
+            out.append(acc)
+        return out
+
+    def project(self, Uf):
+        Mf, Mc = self.fine.tt.M, self.coarse.tt.M
+        xs = [None] + [self.space.P(Uf[j]) for j in range(1, Mf + 1)]
+        out = [None]
+        for i in range(Mc):
+            acc = 0.0
+            for j in range(Mf):
+                acc = acc + self.Pt[i, j] * xs[j + 1]
+            out.append(acc)
+        return out
+
+    def restrict(self, rf):
+        Mf, Mc = self.fine.tt.M, self.coarse.tt.M
+        xs = [None] + [self.space.R(rf[i]) for i in range(1, Mf + 1)]
+        out = [None]
+        for j in range(Mc):
+            acc = 0.0
+            for i in range(Mf):
+                acc = acc + self.It[i, j] * xs[i + 1]
+            out.append(acc)
+        return out
+
+
+# --------------------------------------------------------------------------
+# multilevel driver
+# --------------------------------------------------------------------------
+class MLSDC:
+    """SI-MLSDC on levels[0] (l = 1, coarsest) .. levels[L-1] (l = L)."""
+
+    def __init__(self, levels, transfers=None, scheme="si2", n_coarse=2,
+                 start="cascade", cycles=3, post_sweep=True, c_fmg=1):
+        self.levels = levels
+        self.L = len(levels)
+        if transfers is None:
+            transfers = [None] + [Transfer(levels[i], levels[i - 1]) for i in range(1, self.L)]
+        self.tr = transfers            # tr[i]: between levels[i] and levels[i-1]
+        self.scheme = scheme
+        self.n_coarse = n_coarse
+        self.start = start
+        self.cycles = cycles
+        self.post_sweep = post_sweep
+        self.c_fmg = c_fmg
+        self.U = [None] * self.L
+        self.g = [None] * self.L
+        self.v = [None] * self.L
+        self.u0 = [None] * self.L
+        self.params = None
+
+    # ---- pieces --------------------------------------------------------
+    def set_initial(self, u0_fine, params):
+        """u_{l,0}: the fine initial value, projected level by level
+        (reading: the coarse initial values are P_x of the fine one)."""
+        self.params = params
+        self.u0[self.L - 1] = u0_fine
+        for i in range(self.L - 1, 0, -1):
+            self.u0[i - 1] = self.tr[i].space.P(self.u0[i])
+
+    def sdc_sweep(self, i, dt, g):
+        self.U[i] = sweep(self.levels[i], self.U[i], dt, self.params, g, self.scheme)
+
+    def vcycle(self, top, dt):
+        """Alg. 2 on levels[0..top]; the top level has g = 0."""
+        self.g[top] = None
+        for i in range(top, 0, -1):
+            lv, lc, tr = self.levels[i], self.levels[i - 1], self.tr[i]
+            self.sdc_sweep(i, dt, self.g[i])                          # pre-sweep
+            Fl = collocation_residual(lv, self.U[i], dt)
+            r = [None] + [(self.g[i][m] if self.g[i] is not None else 0.0) - Fl[m]
+                          for m in range(1, lv.tt.M + 1)]             # residual
+            v = tr.project(self.U[i])                                 # restriction
+            v[0] = self.u0[i - 1]
+            self.v[i - 1] = v
+            Fc = collocation_residual(lc, v, dt)
+            Rr = tr.restrict(r)
+            self.g[i - 1] = [None] + [Fc[m] + Rr[m] for m in range(1, lc.tt.M + 1)]
+            self.U[i - 1] = list(v)
+        for _ in range(self.n_coarse):                                # coarse solve
+            self.sdc_sweep(0, dt, self.g[0])
+        for i in range(1, top + 1):
+            tr = self.tr[i]
+            diff = [None] + [self.U[i - 1][m] - self.v[i - 1][m]
+                             for m in range(1, self.levels[i - 1].tt.M + 1)]
+            corr = tr.interp(diff)                                    # prolongation
+            self.U[i] = [self.U[i][0]] + [self.U[i][m] + corr[m]
+                                          for m in range(1, self.levels[i].tt.M + 1)]
+            if i < top:
+                self.sdc_sweep(i, dt, self.g[i])                      # post-sweep
+
+    def interpolate_up(self, i):
+        """u_{l+1} <- I u_l on nodes 1..M (the initial value stays)."""
+        up = self.tr[i + 1].interp(self.U[i])
+        self.U[i + 1] = [self.u0[i + 1]] + up[1:]
+
+    def start_levels(self, dt):
+        L = self.L
+        if self.start == "predictor":
+            for i in range(L):
+                self.U[i] = predictor(self.levels[i], self.u0[i], dt, self.params, self.scheme)
+            return
+        self.U[0] = predictor(self.levels[0], self.u0[0], dt, self.params, self.scheme)
+        if L == 1:
+            return
+        if self.start == "cascade":                                   # Alg. 3
+            for i in range(0, L - 1):
+                self.sdc_sweep(i, dt, None)
+                self.interpolate_up(i)
+        elif self.start == "fmg":                                     # Alg. 4
+            self.sdc_sweep(0, dt, None)
+            self.interpolate_up(0)
+            for i in range(1, L - 1):
+                for _ in range(self.c_fmg):
+                    self.vcycle(i, dt)
+                self.interpolate_up(i)
+        else:
+            raise ValueError(self.start)
+
+    def step(self, u0_fine, dt):
+        """One time step; returns u at t + dt (u_{L,M}, Radau right)."""
+        params = self.levels[-1].phys.step_params(u0_fine) \
+            if hasattr(self.levels[-1], "phys") else None
+        self.set_initial(u0_fine, params)
+        self.start_levels(dt)
+        if self.L == 1:
+            for _ in range(self.cycles):
+                self.sdc_sweep(0, dt, None)
+        else:
+            for _ in range(self.cycles):
+                self.vcycle(self.L - 1, dt)
+            if self.post_sweep:
+                self.sdc_sweep(self.L - 1, dt, None)
+        return self.U[self.L - 1][-1]
+
+
+def sdc_step(lv, u0, dt, sweeps, scheme="si2"):
+    """Single-level SI-SDC step: predictor and `sweeps` corrector sweeps."""
+    params = lv.phys.step_params(u0) if hasattr(lv, "phys") else None
+    U = predictor(lv, u0, dt, params, scheme)
+    for _ in range(sweeps):
+        U = sweep(lv, U, dt, params, None, scheme)
+    return U[-1]
