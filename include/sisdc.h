@@ -1,0 +1,208 @@
+/*
+ * sisdc.h -- C ABI of libsisdc: semi-implicit (multilevel) spectral deferred
+ * correction, SI-SDC / SI-MLSDC, with a nodal DG-SEM discretisation on
+ * periodic Cartesian meshes, running on AMD MI355X (gfx950).
+ *
+ * Method: Pfister & Stiller, "Semi-implicit multilevel spectral deferred
+ * correction" (arXiv 2504.18526).
+ *   - problem:  u_t + div f_c(u) = div f_d(u, grad u)              (Sec. 2)
+ *   - SDC:      incremental collocation on M Radau-right nodes, SI(1)/SI(2)
+ *               predictor and corrector                            (Sec. 3)
+ *   - MLSDC:    FAS right-hand side, transfers I, P, R = I^T, V-cycle,
+ *               cascade and FMG starts                 (Sec. 4, Alg. 1-4)
+ *   - space:    DG on piecewise polynomials of degree P per element (Sec. 6)
+ *
+ * Conventions shared by every call
+ *   Errors     every call returns int: SISDC_OK (0) or a negative code below;
+ *              sisdc_last_error() returns a message for the calling thread.
+ *              No C++ exception or abort crosses the ABI.  SISDC_ENOTCONV
+ *              still leaves the best iterate in the output.
+ *   Memory     `mem` says whether the caller's pointers are host memory
+ *              (SISDC_MEM_HOST) or device memory of the handle's GPU
+ *              (SISDC_MEM_DEVICE).  Caller buffers are only read/written
+ *              during the call; the library keeps no caller pointer.  The
+ *              handle owns every level and work buffer.
+ *   Streams    the handle is bound to one hipStream_t at creation (NULL: the
+ *              null stream); every call is stream-ordered and returns after
+ *              its work has completed (calls synchronise the stream).
+ *   Threads    one handle is used by one thread at a time.
+ *   Levels     level index 0 is the FINEST level, n_levels-1 the coarsest
+ *              (the paper numbers levels the other way, l = 1 coarsest).
+ *   Layout     a nodal vector is double u[var][elem][node]: elem =
+ *              e_x + n_x (e_y + n_y e_z) (x fastest), node = i_x + (P+1)
+ *              (i_y + (P+1) i_z) on the Gauss-Lobatto-Legendre points, x
+ *              fastest.  Collocation arrays are [m][var][elem][node] with
+ *              m = 0..M, m = 0 being the step's initial value u_0.
+ *   Weak form  right-hand sides, residuals and FAS terms g live in the dual
+ *              space: the value at a node is the functional tested with that
+ *              node's basis function (the discrete collocation equation of
+ *              Sec. 6 is written this way).  Mass matrix: GLL-lumped.
+ */
+#ifndef SISDC_H
+#define SISDC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SISDC_OK = 0,
+  SISDC_EINVAL = -1,     /* invalid argument (message says which)          */
+  SISDC_ENOMEM = -2,     /* device or host allocation failed               */
+  SISDC_EDEVICE = -3,    /* a HIP runtime call failed                      */
+  SISDC_ENOTCONV = -4,   /* an implicit solve missed its tolerance         */
+  SISDC_ENONFINITE = -5, /* a non-finite value appeared in the state       */
+  SISDC_ESTATE = -6      /* call order violated (e.g. step before state)   */
+};
+
+enum { SISDC_MEM_HOST = 0, SISDC_MEM_DEVICE = 1 };
+
+typedef enum {
+  SISDC_EQ_CONVDIFF = 0, /* u_t + div(a u) = nu lap u           (Sec. 2)   */
+  SISDC_EQ_BURGERS = 1,  /* u_t + div(u^2/2 (1,..,1)) = nu lap u (Sec. 2)  */
+  SISDC_EQ_EULER = 2     /* compressible Euler, perfect gas      (Sec. 2)  */
+} sisdc_eq;
+
+enum { SISDC_SI2 = 0, SISDC_SI1 = 1 };                 /* Sec. 3            */
+enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
+       SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
+enum { SISDC_FP64 = 0 };
+
+typedef struct {
+  int dim;             /* 2 or 3                                            */
+  int n_elem[3];       /* elements per axis (periodic uniform mesh)         */
+  double lo[3], hi[3]; /* box                                               */
+  int eq;              /* sisdc_eq                                          */
+  double a[3];         /* convection velocity (CONVDIFF)                    */
+  double nu;           /* diffusivity (CONVDIFF, BURGERS)                   */
+  double gamma;        /* ratio of specific heats (EULER)                   */
+} sisdc_problem;
+
+typedef struct {
+  int n_levels;        /* 1..3                                              */
+  int P[3];            /* polynomial degree per level (index 0 finest), 1..8 */
+  int M[3];            /* Radau-right nodes per level, 1..8                 */
+  int integrator;      /* SISDC_SI2 (default) or SISDC_SI1                  */
+  int start;           /* SISDC_START_*  (multilevel only)                  */
+  int n_coarse_sweeps; /* N_c, sweeps on the coarsest level per V-cycle     */
+  int post_sweep;      /* final fine sweep after the last V-cycle (0/1)     */
+  int n_iter;          /* sweeps K (one level) or V-cycles C (multilevel)   */
+  double cg_rtol;      /* relative residual ||b-Ax||_2 <= rtol ||b||_2      */
+  int cg_maxit;        /* iteration cap per solve                           */
+  double c_tau;        /* SIPG penalty factor C_tau (tau = C_tau (P+1)^2 kappa / h) */
+  int precision;       /* SISDC_FP64                                        */
+} sisdc_method;
+
+typedef struct {
+  int fine_sweeps;        /* predictor + corrector sweeps on level 0        */
+  int solves;             /* Helmholtz solves on all levels                 */
+  long long cg_iters;     /* CG iterations summed over all solves           */
+  int cg_iters_max;       /* largest iteration count of one solve           */
+  int not_converged;      /* solves that hit cg_maxit                       */
+  double max_rel_residual;/* largest final relative residual                */
+} sisdc_stats;
+
+typedef struct {
+  int iters;
+  int converged;
+  double rel_residual;
+} sisdc_solve_stats;
+
+typedef struct sisdc_handle sisdc_handle;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* sisdc_last_error(void);
+
+/* Create a handle for `prob` discretised with `meth` on the current HIP
+ * device, bound to `hip_stream` (a hipStream_t, NULL = null stream).
+ * Validates every field (EINVAL), allocates all level buffers (ENOMEM). */
+int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth,
+                 void* hip_stream, sisdc_handle** out);
+int sisdc_destroy(sisdc_handle* h);
+
+/* Sizes of a level: elements, nodes per element, variables, M. */
+int sisdc_level_info(const sisdc_handle* h, int level, int* n_elem_total,
+                     int* nodes_per_elem, int* n_var, int* M);
+
+/* Physical node coordinates of a level, x[d][elem][node] (d < dim). */
+int sisdc_node_coords(sisdc_handle* h, int level, double* x, int mem);
+
+/* Fine-level initial value u_0 (one nodal vector, [var][elem][node]). */
+int sisdc_set_state(sisdc_handle* h, const double* u0, int mem);
+
+/* Read / write the collocation iterate of a level, all nodes m = 0..M
+ * ([m][var][elem][node]).  Writing it also marks the stored f, C and
+ * K-terms of that level stale (they are recomputed on the next sweep). */
+int sisdc_get_level(sisdc_handle* h, int level, double* u, int mem);
+int sisdc_set_level(sisdc_handle* h, int level, const double* u, int mem);
+
+/* Read / write the FAS right-hand side g of a level ([m-1][var][elem][node],
+ * m = 1..M, weak form).  Level 0 normally has g = 0 (eq. ml-cm fas-mg rhs). */
+int sisdc_get_fas(sisdc_handle* h, int level, double* g, int mem);
+int sisdc_set_fas(sisdc_handle* h, int level, const double* g, int mem);
+
+/* The fine solution at t+dt (u_{M}) after the last sisdc_step. */
+int sisdc_get_state(sisdc_handle* h, double* u, int mem);
+
+/* Per-step parameter of the systems' implicit term: lam* = max over the
+ * nodes of max_d(|v_d| + c) of the current fine u_0 (EULER; 0 otherwise).
+ * Computed on the device at the start of every step; this call computes it
+ * from the current fine u_0 and stores it for the next sweeps. */
+int sisdc_update_step_params(sisdc_handle* h, double* lam_out);
+
+/* One time step of length dt from the stored fine u_0 (Sec. 3 and 4):
+ * one level: SI predictor and n_iter corrector sweeps; several levels:
+ * start strategy (Alg. 3 / Alg. 4), n_iter V-cycles (Alg. 2) and an
+ * optional fine post-sweep.  Afterwards u_0 <- u_{fine, M}. */
+int sisdc_step(sisdc_handle* h, double t, double dt, sisdc_stats* st);
+
+/* SI predictor on a level from that level's u_0 (eqs. sdc incremental
+ * predictor si1/si2): fills u_1..u_M. */
+int sisdc_predict(sisdc_handle* h, int level, double dt, sisdc_stats* st);
+
+/* One incremental SI corrector sweep on a level (Alg. 1, N = 1, eqs.
+ * sdc incremental corrector / DeltaH_SI1 / DeltaH_SI2 / ml-sdc incremental).
+ * g: FAS right-hand side ([m-1][var][elem][node]); NULL uses the level's
+ * stored g (zero unless set by a V-cycle or sisdc_set_fas). */
+int sisdc_sweep(sisdc_handle* h, int level, double dt, const double* g, int mem,
+                sisdc_stats* st);
+
+/* One MLSDC V-cycle (Alg. 2) on levels top_level (finest of the cycle)
+ * down to the coarsest, g = 0 on top_level. */
+int mlsdc_vcycle(sisdc_handle* h, int top_level, double dt, sisdc_stats* st);
+
+/* Solve (M + dt_m K_D) x = b on a level (the implicit part of H^SI, eq.
+ * H_SI(1)) by Jacobi-preconditioned CG: on entry x holds the initial guess,
+ * on exit the solution.  coef_state: u_b, the state the coefficient D is
+ * evaluated at (BURGERS needs it; may be NULL otherwise).  b, x, coef_state
+ * are nodal vectors ([var][elem][node]).  rtol <= 0 / maxit <= 0 select the
+ * handle's cg_rtol / cg_maxit. */
+int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_state,
+                    const double* b, double* x, int mem, double rtol, int maxit,
+                    sisdc_solve_stats* st);
+
+/* Stage-level entry points (one operator application each, for parity
+ * checks and for callers that compose their own schemes):
+ *   SISDC_OP_MASS    out = M in
+ *   SISDC_OP_CONV    out = C(in)                 weak convective operator
+ *   SISDC_OP_FRHS    out = F(in) = C(in) - K_nu in (scalars), C(in) (Euler)
+ *   SISDC_OP_SIPG    out = K_D in, D = D_m(aux) at step dt_m (aux may be NULL)
+ *   SISDC_OP_HELM    out = M in + dt_m K_D in
+ *   SISDC_OP_PROJECT out(level+1) = P_x in(level)       (space, fine->coarse)
+ *   SISDC_OP_INTERP  out(level)   = I_x in(level+1)     (space, coarse->fine)
+ *   SISDC_OP_RESTRICT out(level+1) = I_x^T in(level)    (space, fine->coarse)
+ * All vectors are single nodal vectors of the named level. */
+enum { SISDC_OP_MASS = 0, SISDC_OP_CONV = 1, SISDC_OP_FRHS = 2, SISDC_OP_SIPG = 3,
+       SISDC_OP_HELM = 4, SISDC_OP_PROJECT = 5, SISDC_OP_INTERP = 6,
+       SISDC_OP_RESTRICT = 7 };
+int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* in,
+                const double* aux, double* out, int mem);
+
+/* Collocation residual F_l(u) of a level's stored iterate, eq. cm
+ * incremental op in weak form: out[m-1] = M (u_m - u_{m-1}) - q_m(u). */
+int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* out, int mem);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SISDC_H */

@@ -1,0 +1,690 @@
+// HIP kernels of the SI-MLSDC / DG-SEM hot path for gfx950 (MI355X).
+//
+// Element kernels: one workgroup holds EPB elements, one thread per node;
+// the (P+1)^d nodal tile of each element and the 1-D GLL tables are staged in
+// LDS, derivatives are sum-factorised (one 1-D contraction per axis).  Face
+// terms read the neighbour's face trace straight from global memory (the
+// neighbour index follows from the periodic Cartesian numbering).
+//
+// Reductions: wave shuffles (64 lanes), LDS across waves, one partial per
+// workgroup, and the last workgroup to finish (atomic ticket) sums the
+// partials in a fixed order, so every dot product is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace sisdc {
+
+template <int DIM, int P>
+struct EL {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+  static constexpr int NF = DIM == 2 ? N1 : N1 * N1;
+  static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
+  static constexpr int NT = ((EPB * NP + 63) / 64) * 64;
+  static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
+};
+
+template <int DIM, int N1>
+__device__ __forceinline__ void decomp(int n, int (&i)[3]) {
+  i[0] = n % N1;
+  i[1] = (n / N1) % N1;
+  i[2] = DIM == 3 ? n / (N1 * N1) : 0;
+}
+
+template <int DIM, int N1>
+__device__ __forceinline__ int face_index(int d, const int (&i)[3]) {
+  if (DIM == 2) return i[1 - d];
+  return d == 0 ? i[1] + N1 * i[2] : (d == 1 ? i[0] + N1 * i[2] : i[0] + N1 * i[1]);
+}
+
+// Element across the face of element e normal to d on side s (-1 / +1).
+__device__ __forceinline__ int neighbour(const Geo& g, int e, int d, int s) {
+  int c[3];
+  c[0] = e % g.ne[0];
+  c[1] = (e / g.ne[0]) % g.ne[1];
+  c[2] = g.dim == 3 ? e / (g.ne[0] * g.ne[1]) : 0;
+  c[d] += s;
+  if (c[d] < 0) c[d] += g.ne[d];
+  if (c[d] >= g.ne[d]) c[d] -= g.ne[d];
+  return c[0] + g.ne[0] * (c[1] + g.ne[1] * c[2]);
+}
+
+// ---------------------------------------------------------------- reduction
+template <int K>
+__device__ bool block_reduce_last(double (&v)[K], double* partials, unsigned* counter,
+                                  double (&tot)[K]) {
+  __shared__ double sred[K][16];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sred[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sred[k][w];
+      partials[(size_t)blockIdx.x * K + k] = s;
+    }
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double acc[K];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+    for (int k = 0; k < K; ++k) acc[k] += __builtin_nontemporal_load(&partials[(size_t)b * K + k]);
+  for (int k = 0; k < K; ++k) {
+    double x = acc[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sred[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sred[k][w];
+      tot[k] = s;
+    }
+    *counter = 0u;
+  }
+  return threadIdx.x == 0;
+}
+
+// ---------------------------------------------------------------- fluxes
+template <int NV>
+__device__ __forceinline__ void flux(const EqP& q, int d, const double (&u)[NV], double (&f)[NV]) {
+  if constexpr (NV == 1) {
+    f[0] = q.eq == EQ_CONVDIFF ? q.a[d] * u[0] : 0.5 * u[0] * u[0];
+  } else {
+    constexpr int D = NV - 2;
+    const double ir = 1.0 / u[0];
+    double ke = 0.0;
+    for (int k = 0; k < D; ++k) ke += u[1 + k] * u[1 + k];
+    const double p = (q.gamma - 1.0) * (u[D + 1] - 0.5 * ke * ir);
+    const double vd = u[1 + d] * ir;
+    f[0] = u[1 + d];
+    for (int k = 0; k < D; ++k) f[1 + k] = u[1 + k] * vd + (k == d ? p : 0.0);
+    f[D + 1] = (u[D + 1] + p) * vd;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double wave_speed(const EqP& q, int d, const double (&u)[NV]) {
+  if constexpr (NV == 1) {
+    return q.eq == EQ_CONVDIFF ? fabs(q.a[d]) : fabs(u[0]);
+  } else {
+    constexpr int D = NV - 2;
+    const double ir = 1.0 / u[0];
+    double ke = 0.0;
+    for (int k = 0; k < D; ++k) ke += u[1 + k] * u[1 + k];
+    const double p = (q.gamma - 1.0) * (u[D + 1] - 0.5 * ke * ir);
+    return fabs(u[1 + d] * ir) + sqrt(q.gamma * p * ir);
+  }
+}
+
+// ---------------------------------------------------------------- C(u)
+// out = C(u): -J w (sum_d 2/h_d D_d f_d(u)) - sum_faces J_f w_f (f* - f(u^-)).n
+template <int DIM, int P, int NV>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
+       const double* __restrict__ tab, long vs) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sf[EPB * NV * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  double uu[NV], acc[NV];
+  for (int v = 0; v < NV; ++v) {
+    uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
+    acc[v] = 0.0;
+  }
+  __syncthreads();
+  for (int d = 0; d < DIM; ++d) {
+    if (act) {
+      double f[NV];
+      flux<NV>(q, d, uu, f);
+      for (int v = 0; v < NV; ++v) sf[(le * NV + v) * NP + n] = f[v];
+    }
+    __syncthreads();
+    if (act) {
+      const int st = L::stride(d);
+      const int base = n - ii[d] * st;
+      for (int v = 0; v < NV; ++v) {
+        const double* row = &sf[(le * NV + v) * NP + base];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+        acc[v] -= g.rh2[d] * s;
+      }
+    }
+    __syncthreads();
+  }
+  if (!act) return;
+  double wn = 1.0;
+  for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  for (int v = 0; v < NV; ++v) acc[v] *= g.J * wn;
+  for (int d = 0; d < DIM; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      if (ii[d] != (side ? P : 0)) continue;
+      const double sgn = side ? 1.0 : -1.0;
+      const int nb = neighbour(g, e, d, side ? 1 : -1);
+      const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+      double uo[NV], fi[NV], fo[NV];
+      for (int v = 0; v < NV; ++v) uo[v] = u[v * vs + (long)nb * NP + nn];
+      flux<NV>(q, d, uu, fi);
+      flux<NV>(q, d, uo, fo);
+      const double lam = fmax(wave_speed<NV>(q, d, uu), wave_speed<NV>(q, d, uo));
+      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+      for (int v = 0; v < NV; ++v) {
+        const double fin = sgn * fi[v], fout = sgn * fo[v];
+        const double fstar = 0.5 * (fin + fout) - 0.5 * lam * (uo[v] - uu[v]);
+        acc[v] -= jfwf * (fstar - fin);
+      }
+    }
+  }
+  for (int v = 0; v < NV; ++v) out[v * vs + (long)e * NP + n] = acc[v];
+}
+
+// ---------------------------------------------------------------- SIPG
+__device__ __forceinline__ double coef_w2(const CoefP& cf, long idx) {
+  if (cf.ub == nullptr) return cf.c;
+  const double w = cf.ub[idx];
+  return cf.c * w * w;
+}
+
+// Pass 1: (D grad x)_d on every face node, trace[c][e][d][side][f].
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_sipg_trace(const double* __restrict__ x, int nv, long vs, CoefP cf,
+             double* __restrict__ trace, Geo g, const double* __restrict__ tab,
+             const int* __restrict__ done) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
+  if (done != nullptr && *done) return;
+  __shared__ double sD[N1 * N1];
+  __shared__ double sx[EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const double cw = act ? coef_w2(cf, (long)e * NP + n) : 0.0;
+  for (int c = 0; c < nv; ++c) {
+    __syncthreads();
+    if (act) sx[le * NP + n] = x[c * vs + (long)e * NP + n];
+    __syncthreads();
+    if (!act) continue;
+    double gr[DIM];
+    for (int d = 0; d < DIM; ++d) {
+      const int st = L::stride(d);
+      const double* row = &sx[le * NP + n - ii[d] * st];
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+      gr[d] = g.rh2[d] * s;
+    }
+    double vg = 0.0;
+    for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+    for (int d = 0; d < DIM; ++d) {
+      const bool lo = ii[d] == 0, hi = ii[d] == P;
+      if (!lo && !hi) continue;
+      const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
+      const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
+      if (lo) trace[base] = qd;
+      if (hi) trace[base + NF] = qd;
+    }
+  }
+}
+
+// Pass 2: out = alpha M x + beta K_D x (weak SIPG), optional dot(out, dotv).
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_sipg_apply(const double* __restrict__ x, double* __restrict__ out, int nv, long vs, CoefP cf,
+             const double* __restrict__ trace, double alpha, double beta, double ctau, Geo g,
+             const double* __restrict__ tab, const double* __restrict__ dotv, double* partials,
+             unsigned* counter, CGScal* scal, const int* __restrict__ done) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
+  if (done != nullptr && *done) return;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sx[EPB * NP];
+  __shared__ double sQ[EPB * DIM * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const long own = (long)e * NP + n;
+  const double cw = act ? coef_w2(cf, own) : 0.0;
+  double dacc = 0.0;
+  __syncthreads();
+  double wn = 1.0;
+  for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  const double jw = g.J * wn;
+  const double pen = ctau * (double)(N1 * N1);
+  for (int c = 0; c < nv; ++c) {
+    __syncthreads();
+    if (act) sx[le * NP + n] = x[c * vs + own];
+    __syncthreads();
+    double r = 0.0, xo = 0.0;
+    if (act) {
+      xo = sx[le * NP + n];
+      double gr[DIM];
+      for (int d = 0; d < DIM; ++d) {
+        const int st = L::stride(d);
+        const double* row = &sx[le * NP + n - ii[d] * st];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+        gr[d] = g.rh2[d] * s;
+      }
+      double vg = 0.0;
+      for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+      double qv[DIM];
+      for (int d = 0; d < DIM; ++d) qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
+      double Qd[DIM];
+      for (int d = 0; d < DIM; ++d) Qd[d] = jw * qv[d];
+      for (int d = 0; d < DIM; ++d) {
+        for (int side = 0; side < 2; ++side) {
+          if (ii[d] != (side ? P : 0)) continue;
+          const double sgn = side ? 1.0 : -1.0;
+          const int nb = neighbour(g, e, d, side ? 1 : -1);
+          const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+          const long nbi = (long)nb * NP + nn;
+          const double xnb = x[c * vs + nbi];
+          const double qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
+                                   face_index<DIM, N1>(d, ii)];
+          const double dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
+          const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+          const double qn = 0.5 * sgn * (qv[d] + qnb);
+          const double tau = pen * fmax(dow, dnb) * 0.5 * g.rh2[d];
+          const double jump = xo - xnb;
+          const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+          r += jfwf * (-qn + tau * jump);
+          for (int d2 = 0; d2 < DIM; ++d2)
+            Qd[d2] -= 0.5 * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : 0.0));
+        }
+      }
+      for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
+    }
+    __syncthreads();
+    if (act) {
+      for (int d = 0; d < DIM; ++d) {
+        const int st = L::stride(d);
+        const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
+        r += g.rh2[d] * s;
+      }
+      const double val = alpha * jw * xo + beta * r;
+      out[c * vs + own] = val;
+      if (dotv != nullptr) dacc += val * dotv[c * vs + own];
+    }
+  }
+  if (partials != nullptr) {
+    double v1[1] = {dacc}, tot[1];
+    if (block_reduce_last<1>(v1, partials, counter, tot)) scal->pAp = tot[0];
+  }
+}
+
+// Jacobi diagonal of M + dt_m K_D (volume terms with d = d' and the face
+// terms of the node itself); any positive diagonal gives the same solution.
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_helm_diag(double* __restrict__ diag, int nv, long vs, CoefP cf, double dtm, double ctau, Geo g,
+            const double* __restrict__ tab) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sc[EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const long own = (long)e * NP + n;
+  if (act) sc[le * NP + n] = coef_w2(cf, own);
+  __syncthreads();
+  if (!act) return;
+  double wn = 1.0;
+  for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  double kd = 0.0;
+  for (int d = 0; d < DIM; ++d) {
+    const int st = L::stride(d);
+    double s = 0.0;
+    for (int k = 0; k < N1; ++k) {
+      const int nk = n + (k - ii[d]) * st;
+      const double dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + cf.nu;
+      const double wk = wn / sw[ii[d]] * sw[k];
+      s += sD[k * N1 + ii[d]] * sD[k * N1 + ii[d]] * wk * dd;
+    }
+    kd += g.rh2[d] * g.rh2[d] * g.J * s;
+  }
+  const double dow_c = sc[le * NP + n];
+  for (int d = 0; d < DIM; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      if (ii[d] != (side ? P : 0)) continue;
+      const double sgn = side ? 1.0 : -1.0;
+      const int nb = neighbour(g, e, d, side ? 1 : -1);
+      const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+      const double dnb = coef_w2(cf, (long)nb * NP + nn) * cf.v[d] * cf.v[d] + cf.nu;
+      const double dow = dow_c * cf.v[d] * cf.v[d] + cf.nu;
+      const double tau = ctau * (double)(N1 * N1) * fmax(dow, dnb) * 0.5 * g.rh2[d];
+      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+      kd += jfwf * (tau - sgn * g.rh2[d] * dow * sD[ii[d] * N1 + ii[d]]);
+    }
+  }
+  const double val = g.J * wn + dtm * kd;
+  for (int c = 0; c < nv; ++c) diag[c * vs + own] = val;
+}
+
+// ---------------------------------------------------------------- vectors
+__global__ void k_lincomb(double* __restrict__ out, LinComb lc, long n, const double* __restrict__ mw,
+                          int np) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double m = mw[i % np];
+    double s = 0.0;
+    for (int j = 0; j < lc.n; ++j) s += lc.c[j] * (lc.m[j] ? m : 1.0) * lc.x[j][i];
+    out[i] = s;
+  }
+}
+
+// r = b - Ax, z = r / diag, p = z; scal <- (r.z, r.r, b.b)
+__global__ void k_cg_init(const double* __restrict__ b, const double* __restrict__ Ax,
+                          const double* __restrict__ diag, double* __restrict__ r, double* __restrict__ z,
+                          double* __restrict__ p, long n, double* partials, unsigned* counter,
+                          CGScal* scal) {
+  double a[3] = {0.0, 0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double bi = b[i];
+    const double ri = bi - Ax[i];
+    const double zi = ri / diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    a[0] += ri * zi;
+    a[1] += ri * ri;
+    a[2] += bi * bi;
+  }
+  double tot[3];
+  if (block_reduce_last<3>(a, partials, counter, tot)) {
+    scal->rz = tot[0];
+    scal->rr = tot[1];
+    scal->bb = tot[2];
+    scal->it = 0;
+    scal->done = (tot[1] <= scal->tol2 * tot[2]) || tot[2] == 0.0 || scal->maxit <= 0;
+  }
+}
+
+// x += alpha p, r -= alpha Ap, z = r / diag; scal <- (r.z, r.r), beta, done
+__global__ void k_cg_update(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                            const double* __restrict__ p, const double* __restrict__ Ap,
+                            const double* __restrict__ diag, long n, double* partials,
+                            unsigned* counter, CGScal* scal) {
+  if (scal->done) return;
+  const double alpha = scal->rz / scal->pAp;
+  double a[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Ap[i];
+    const double zi = ri / diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    a[0] += ri * zi;
+    a[1] += ri * ri;
+  }
+  double tot[2];
+  if (block_reduce_last<2>(a, partials, counter, tot)) {
+    scal->beta = tot[0] / scal->rz;
+    scal->rz = tot[0];
+    scal->rr = tot[1];
+    scal->it += 1;
+    scal->done = (tot[1] <= scal->tol2 * scal->bb) || (scal->it >= scal->maxit) || !(tot[1] == tot[1]);
+  }
+}
+
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, long n,
+                         const CGScal* scal) {
+  if (scal->done) return;
+  const double beta = scal->beta;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
+__global__ void k_space_transfer(const double* __restrict__ in, double* __restrict__ out, int dim,
+                                 int n1i, int n1o, int E, const double* __restrict__ A) {
+  __shared__ double sA[(kMaxP + 1) * (kMaxP + 1)];
+  __shared__ double sin_[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
+  const int npi = dim == 2 ? n1i * n1i : n1i * n1i * n1i;
+  const int npo = dim == 2 ? n1o * n1o : n1o * n1o * n1o;
+  const long blk = blockIdx.x;  // (var, e)
+  for (int k = threadIdx.x; k < n1i * n1o; k += blockDim.x) sA[k] = A[k];
+  for (int k = threadIdx.x; k < npi; k += blockDim.x) sin_[k] = in[blk * npi + k];
+  __syncthreads();
+  for (int o = threadIdx.x; o < npo; o += blockDim.x) {
+    const int ox = o % n1o, oy = (o / n1o) % n1o, oz = dim == 3 ? o / (n1o * n1o) : 0;
+    double s = 0.0;
+    if (dim == 2) {
+      for (int b = 0; b < n1i; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[b * n1i + a];
+        s += sA[oy * n1i + b] * t;
+      }
+    } else {
+      for (int c = 0; c < n1i; ++c) {
+        double tc = 0.0;
+        for (int b = 0; b < n1i; ++b) {
+          double t = 0.0;
+          for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[(c * n1i + b) * n1i + a];
+          tc += sA[oy * n1i + b] * t;
+        }
+        s += sA[oz * n1i + c] * tc;
+      }
+    }
+    out[blk * npo + o] = s;
+  }
+}
+
+// lam* = max over nodes of max_d (|v_d| + c) (Euler), reduced by the last block.
+template <int DIM>
+__global__ void k_euler_lam(const double* __restrict__ u, long vs, EqP q, double* partials,
+                            unsigned* counter, double* result) {
+  constexpr int NV = DIM + 2;
+  double m = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vs; i += (long)gridDim.x * blockDim.x) {
+    double uu[NV];
+    for (int v = 0; v < NV; ++v) uu[v] = u[v * vs + i];
+    for (int d = 0; d < DIM; ++d) m = fmax(m, wave_speed<NV>(q, d, uu));
+  }
+  // max reduction: reuse the sum machinery on exp-free max via shuffles
+  __shared__ double sm[16];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if (lane == 0) sm[wid] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s = fmax(s, sm[w]);
+    partials[blockIdx.x] = s;
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) s = fmax(s, __builtin_nontemporal_load(&partials[b]));
+    *result = s;
+    *counter = 0u;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int blocks_for(long n, int bs, int cap) {
+  long b = (n + bs - 1) / bs;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <int DIM, int P>
+static int elem_blocks(const Geo& g) {
+  return (g.E + EL<DIM, P>::EPB - 1) / EL<DIM, P>::EPB;
+}
+
+#define SISDC_DISPATCH_P(P_, BODY)        \
+  switch (P_) {                           \
+    case 1: { constexpr int PP = 1; BODY; } break; \
+    case 2: { constexpr int PP = 2; BODY; } break; \
+    case 3: { constexpr int PP = 3; BODY; } break; \
+    case 4: { constexpr int PP = 4; BODY; } break; \
+    case 5: { constexpr int PP = 5; BODY; } break; \
+    case 6: { constexpr int PP = 6; BODY; } break; \
+    case 7: { constexpr int PP = 7; BODY; } break; \
+    case 8: { constexpr int PP = 8; BODY; } break; \
+    default: return hipErrorInvalidValue;   \
+  }
+
+template <int DIM, int P>
+static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const EqP& q,
+                             const double* tab, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  if (q.nv == 1)
+    hipLaunchKernelGGL((k_conv<DIM, P, 1>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+  else if (q.nv == DIM + 2)
+    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
+                       hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (conv_dim_p<2, PP>(u, out, g, q, tab, s))); }
+  else if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (conv_dim_p<3, PP>(u, out, g, q, tab, s))); }
+  return hipErrorInvalidValue;
+}
+
+template <int DIM, int P>
+static hipError_t sipg_dim_p(const double* x, double* out, int nv, const CoefP& cf, double* trace,
+                             double alpha, double beta, double ctau, const Geo& g, const double* tab,
+                             const double* dotv, double* partials, unsigned* counter, CGScal* scal,
+                             const int* done, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  const int nb = elem_blocks<DIM, P>(g);
+  hipLaunchKernelGGL((k_sipg_trace<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, nv, vs, cf, trace, g, tab, done);
+  hipLaunchKernelGGL((k_sipg_apply<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha,
+                     beta, ctau, g, tab, dotv, partials, counter, scal, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_sipg(const double* x, double* out, int nv, const CoefP& cf, double* trace, double alpha,
+                       double beta, double ctau, const Geo& g, const double* tab, const double* dotv,
+                       double* partials, unsigned* counter, CGScal* scal, const int* done,
+                       hipStream_t s) {
+  if (g.dim == 2) {
+    SISDC_DISPATCH_P(g.P, return (sipg_dim_p<2, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
+                                                     partials, counter, scal, done, s)));
+  } else if (g.dim == 3) {
+    SISDC_DISPATCH_P(g.P, return (sipg_dim_p<3, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
+                                                     partials, counter, scal, done, s)));
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DIM, int P>
+static hipError_t diag_dim_p(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
+                             const double* tab, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  hipLaunchKernelGGL((k_helm_diag<DIM, P>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf,
+                     dtm, ctau, g, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_helm_diag(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
+                            const double* tab, hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<2, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
+  else if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<3, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
+  return hipErrorInvalidValue;
+}
+
+int elem_block_count(const Geo& g) {
+  int r = 0;
+  auto f = [&](int npb) { r = (g.E + npb - 1) / npb; };
+  const int np = g.np;
+  f(np >= 256 ? 1 : 256 / np);
+  return r;
+}
+
+hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const double* b, const double* Ax, const double* diag, double* r, double* z,
+                          double* p, long n, double* partials, unsigned* counter, CGScal* scal,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, b, Ax, diag, r, z, p, n,
+                     partials, counter, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap,
+                            const double* diag, long n, double* partials, unsigned* counter, CGScal* scal,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, x, r, z, p, Ap, diag,
+                     n, partials, counter, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dir(double* p, const double* z, long n, const CGScal* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, p, z, n, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
+                                 const double* A, hipStream_t s) {
+  hipLaunchKernelGGL(k_space_transfer, dim3((unsigned)((long)nv * E)), dim3(256), 0, s, in, out, dim, n1i, n1o,
+                     E, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* partials,
+                            unsigned* counter, double* result, hipStream_t s) {
+  const int nb = blocks_for(vs, 256, kVecBlocks);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_euler_lam<2>, dim3(nb), dim3(256), 0, s, u, vs, q, partials, counter, result);
+  else
+    hipLaunchKernelGGL(k_euler_lam<3>, dim3(nb), dim3(256), 0, s, u, vs, q, partials, counter, result);
+  return hipGetLastError();
+}
+
+}  // namespace sisdc

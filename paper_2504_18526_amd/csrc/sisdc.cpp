@@ -1,0 +1,1003 @@
+// libsisdc host side: level storage, the SI-SDC sweep, the FAS V-cycle and the
+// start strategies, the Jacobi-PCG driver, and the C ABI of include/sisdc.h.
+//
+// Method (arXiv 2504.18526): incremental SI(1)/SI(2) predictor and corrector
+// (Sec. 3), FAS multilevel SDC with transfers I, P, R = I^T, V-cycle and the
+// cascade / FMG starts (Sec. 4, Alg. 1-4), DG-SEM in space (Sec. 6).  Every
+// vector lives in device memory; the host only sequences kernel launches and
+// reads back the CG convergence flag once per batch of iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sisdc.h"
+#include "common.hpp"
+#include "launch.hpp"
+#include "tables.hpp"
+
+using namespace sisdc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Err {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHECK(x)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) throw Err{SISDC_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void fail(int code, const std::string& m) { throw Err{code, m}; }
+
+double* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+  return (double*)p;
+}
+
+struct Level {
+  int P = 0, M = 0, n1 = 0, np = 0, E = 0, nv = 0;
+  long vs = 0, vlen = 0;
+  Geo g{};
+  std::vector<double> xg, wg, D, tau, dtau, wnn;
+  double* tab = nullptr;  // D (n1*n1) then w (n1)
+  double* mw = nullptr;   // J w per node (np)
+  double* u = nullptr;    // (M+1) x vlen
+  double* unew = nullptr; // (M+1) x vlen
+  double* f = nullptr;    // M x vlen, f(u_m), m = 1..M
+  double* C = nullptr;    // (M+1) x vlen, C(u_m), m = 0..M
+  double* Cnew = nullptr; // (M+1) x vlen
+  double* X = nullptr;    // M x vlen, K_{D(u_{m-1})} u_m
+  double* gf = nullptr;   // M x vlen, FAS right-hand side
+  double* v = nullptr;    // (M+1) x vlen, projected fine iterate
+  double* r = nullptr;    // M x vlen, residual
+  double* q = nullptr;    // M x vlen, quadrature
+  double *b = nullptr, *y = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cAp = nullptr;
+  double* trace = nullptr;
+  bool stale = true;
+  double stored_dt = -1.0;
+  bool has_g = false;
+  int last_iters = 8;
+  double* um(int m) const { return u + (long)m * vlen; }
+  double* unm(int m) const { return unew + (long)m * vlen; }
+};
+
+struct Transfer {  // between level i (fine) and i+1 (coarse)
+  double* Ix = nullptr;  // (n1f x n1c) coarse -> fine
+  double* Px = nullptr;  // (n1c x n1f) fine -> coarse
+  double* Rx = nullptr;  // (n1c x n1f) = Ix^T
+  std::vector<double> It, Pt;  // It: (Mf x Mc), Pt: (Mc x Mf)
+};
+
+}  // namespace
+
+struct sisdc_handle {
+  sisdc_problem prob{};
+  sisdc_method meth{};
+  hipStream_t stream = nullptr;
+  EqP eq{};
+  std::vector<Level> lv;
+  std::vector<Transfer> tr;
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+  CGScal* scal = nullptr;
+  CGScal* hscal = nullptr;  // pinned host mirror
+  double* lam_dev = nullptr;
+  double* state = nullptr;
+  double* io = nullptr;      // staging for host pointers, (Mmax+1) x vlen_max
+  size_t io_len = 0;
+  double lam = 0.0;
+  bool have_state = false;
+  double ctau = 2.0;
+  sisdc_stats st{};
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+void lincomb(sisdc_handle* h, const Level& L, double* out, std::initializer_list<std::pair<double, const double*>> terms,
+             std::initializer_list<int> mflags = {}) {
+  LinComb lc{};
+  int k = 0;
+  auto mit = mflags.begin();
+  for (auto& t : terms) {
+    if (k >= 8) fail(SISDC_EINVAL, "lincomb: too many terms");
+    lc.x[k] = t.second;
+    lc.c[k] = t.first;
+    lc.m[k] = (mit != mflags.end()) ? *mit++ : 0;
+    ++k;
+  }
+  lc.n = k;
+  HIPCHECK(launch_lincomb(out, lc, L.vlen, L.mw, L.np, h->stream));
+}
+
+void lincomb_v(sisdc_handle* h, const Level& L, double* out, const std::vector<double>& c,
+               const std::vector<const double*>& x, const std::vector<int>& m) {
+  // chunks of 8 terms: out = sum; later chunks accumulate onto out
+  size_t i = 0;
+  bool first = true;
+  while (i < c.size() || first) {
+    LinComb lc{};
+    int k = 0;
+    if (!first) {
+      lc.x[0] = out;
+      lc.c[0] = 1.0;
+      lc.m[0] = 0;
+      k = 1;
+    }
+    while (k < 8 && i < c.size()) {
+      lc.x[k] = x[i];
+      lc.c[k] = c[i];
+      lc.m[k] = m.empty() ? 0 : m[i];
+      ++k;
+      ++i;
+    }
+    lc.n = k;
+    HIPCHECK(launch_lincomb(out, lc, L.vlen, L.mw, L.np, h->stream));
+    first = false;
+  }
+}
+
+void copy_d2d(sisdc_handle* h, double* dst, const double* src, long n) {
+  HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+}
+
+CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
+  CoefP c{};
+  switch (h->eq.eq) {
+    case EQ_CONVDIFF:
+      c.c = 0.5 * dtm;
+      for (int d = 0; d < 3; ++d) c.v[d] = h->eq.a[d];
+      c.nu = h->eq.nu;
+      c.ub = nullptr;
+      break;
+    case EQ_BURGERS:
+      c.c = 0.5 * dtm;
+      for (int d = 0; d < 3; ++d) c.v[d] = 1.0;
+      c.nu = h->eq.nu;
+      c.ub = ub;
+      break;
+    default:  // systems: kappa_m I, kappa_m = (dt_m / 2) lam*^2
+      c.c = 0.0;
+      c.nu = 0.5 * dtm * h->lam * h->lam;
+      c.ub = nullptr;
+  }
+  (void)L;
+  return c;
+}
+
+CoefP coef_nu(sisdc_handle* h) {
+  CoefP c{};
+  c.nu = h->eq.nu;
+  return c;
+}
+
+void conv(sisdc_handle* h, const Level& L, const double* in, double* out) {
+  HIPCHECK(launch_conv(in, out, L.g, h->eq, L.tab, h->stream));
+}
+
+void sipg(sisdc_handle* h, const Level& L, const CoefP& cf, const double* x, double* out, double alpha,
+          double beta) {
+  HIPCHECK(launch_sipg(x, out, L.nv, cf, L.trace, alpha, beta, h->ctau, L.g, L.tab, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, h->stream));
+}
+
+bool has_physical_diffusion(sisdc_handle* h) { return h->eq.eq != EQ_EULER && h->eq.nu != 0.0; }
+
+// f = F(u) = C(u) - K_nu u  (scalars), C(u) (Euler); Cu = C(u) precomputed
+void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double* Cu, double* f) {
+  if (has_physical_diffusion(h)) {
+    sipg(h, L, coef_nu(h), u, L.t3, 0.0, 1.0);
+    lincomb(h, L, f, {{1.0, Cu}, {-1.0, L.t3}});
+  } else if (f != Cu) {
+    copy_d2d(h, f, Cu, L.vlen);
+  }
+}
+
+// ------------------------------------------------------------------ PCG
+sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                           double rtol, int maxit) {
+  hipStream_t s = h->stream;
+  HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dtm, h->ctau, L.g, L.tab, s));
+  HIPCHECK(launch_sipg(x, L.cAp, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, s));
+  h->hscal->tol2 = rtol * rtol;
+  h->hscal->maxit = maxit;
+  h->hscal->done = 0;
+  h->hscal->it = 0;
+  HIPCHECK(hipMemcpyAsync(h->scal, h->hscal, sizeof(CGScal), hipMemcpyHostToDevice, s));
+  HIPCHECK(launch_cg_init(b, L.cAp, L.diag, L.cr, L.cz, L.cp, L.vlen, h->partials, h->counter, h->scal, s));
+  int chunk = std::max(2, L.last_iters + 1);
+  int issued = 0;
+  while (true) {
+    for (int k = 0; k < chunk; ++k) {
+      HIPCHECK(launch_sipg(L.cp, L.cAp, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cp, h->partials,
+                           h->counter, h->scal, &h->scal->done, s));
+      HIPCHECK(launch_cg_update(x, L.cr, L.cz, L.cp, L.cAp, L.diag, L.vlen, h->partials, h->counter, h->scal, s));
+      HIPCHECK(launch_cg_dir(L.cp, L.cz, L.vlen, h->scal, s));
+    }
+    issued += chunk;
+    HIPCHECK(hipMemcpyAsync(h->hscal, h->scal, sizeof(CGScal), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (h->hscal->done || issued >= maxit) break;
+    chunk = std::min(8, maxit - issued);
+  }
+  sisdc_solve_stats r{};
+  r.iters = h->hscal->it;
+  const double rel = h->hscal->bb > 0.0 ? std::sqrt(h->hscal->rr / h->hscal->bb) : 0.0;
+  r.rel_residual = rel;
+  r.converged = (h->hscal->bb == 0.0) || (h->hscal->rr <= h->hscal->tol2 * h->hscal->bb);
+  if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
+  L.last_iters = std::max(1, r.iters);
+  h->st.solves += 1;
+  h->st.cg_iters += r.iters;
+  h->st.cg_iters_max = std::max(h->st.cg_iters_max, r.iters);
+  h->st.max_rel_residual = std::max(h->st.max_rel_residual, rel);
+  if (!r.converged) h->st.not_converged += 1;
+  return r;
+}
+
+sisdc_solve_stats solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x) {
+  return cg_solve(h, L, cf, dtm, b, x, h->meth.cg_rtol, h->meth.cg_maxit);
+}
+
+// ------------------------------------------------------------------ sweeps
+// Stored terms of the current iterate: C(u_m), m = 0..M; f(u_m) and
+// X_m = K_{D_m(u_{m-1})} u_m, m = 1..M (implementation note of Sec. 3:
+// the f of sweep k-1 are kept).
+void ensure_stored(sisdc_handle* h, Level& L, double dt) {
+  if (!L.stale && L.stored_dt == dt) return;
+  for (int m = 0; m <= L.M; ++m) conv(h, L, L.um(m), L.C + (long)m * L.vlen);
+  for (int m = 1; m <= L.M; ++m) {
+    const double dtm = dt * L.dtau[m - 1];
+    frhs_from_c(h, L, L.um(m), L.C + (long)m * L.vlen, L.f + (long)(m - 1) * L.vlen);
+    sipg(h, L, coef_for(h, L, dtm, L.um(m - 1)), L.um(m), L.X + (long)(m - 1) * L.vlen, 0.0, 1.0);
+  }
+  L.stale = false;
+  L.stored_dt = dt;
+}
+
+// q_m = sum_i S_{m,i} f_i, S = dt w^nn, for m = 1..M
+void quadrature(sisdc_handle* h, Level& L, double dt) {
+  for (int m = 0; m < L.M; ++m) {
+    std::vector<double> c;
+    std::vector<const double*> x;
+    for (int i = 0; i < L.M; ++i) {
+      c.push_back(dt * L.wnn[m * L.M + i]);
+      x.push_back(L.f + (long)i * L.vlen);
+    }
+    lincomb_v(h, L, L.q + (long)m * L.vlen, c, x, {});
+  }
+}
+
+void predictor(sisdc_handle* h, Level& L, double dt) {
+  const bool si1 = h->meth.integrator == SISDC_SI1;
+  for (int m = 1; m <= L.M; ++m) {
+    const double dtm = dt * L.dtau[m - 1];
+    const double* ua = L.um(m - 1);
+    CoefP cf = coef_for(h, L, dtm, ua);
+    conv(h, L, ua, L.t1);
+    lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
+    double* y = si1 ? L.um(m) : L.y;
+    copy_d2d(h, y, ua, L.vlen);
+    solve(h, L, cf, dtm, L.b, y);
+    if (!si1) {
+      conv(h, L, y, L.t1);
+      lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
+      copy_d2d(h, L.um(m), y, L.vlen);
+      solve(h, L, cf, dtm, L.b, L.um(m));
+    }
+  }
+  L.stale = true;
+}
+
+// One incremental SI(1)/SI(2) corrector sweep (Alg. 1 with N = 1).
+void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
+  const bool si1 = h->meth.integrator == SISDC_SI1;
+  ensure_stored(h, L, dt);
+  quadrature(h, L, dt);
+  const long n = L.vlen;
+  copy_d2d(h, L.unm(0), L.um(0), n);
+  copy_d2d(h, L.Cnew, L.C, n);
+  for (int m = 1; m <= L.M; ++m) {
+    const double dtm = dt * L.dtau[m - 1];
+    const double* ua = L.unm(m - 1);
+    const double* Ca = L.Cnew + (long)(m - 1) * n;
+    const double* qm = L.q + (long)(m - 1) * n;
+    const double* Xm = L.X + (long)(m - 1) * n;
+    const double* Cold_prev = L.C + (long)(m - 1) * n;
+    const double* Cold_m = L.C + (long)m * n;
+    const double* gm = g ? g + (long)(m - 1) * n : nullptr;
+    CoefP cf = coef_for(h, L, dtm, ua);
+    // stage 1: M y = M u^k_{m-1} + q_m + g_m + H(u^k_{m-1},u^k_{m-1},y) - H(u^{k-1}_{m-1},u^{k-1}_{m-1},u^{k-1}_m)
+    if (gm)
+      lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0});
+    else
+      lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0});
+    double* y = si1 ? L.unm(m) : L.y;
+    copy_d2d(h, y, L.um(m), n);
+    solve(h, L, cf, dtm, L.b, y);
+    if (!si1) {
+      // stage 2: M u^k_m = M u^k_{m-1} + q_m + g_m + H(y,u^k_{m-1},u^k_m) - H(u^{k-1}_m,u^{k-1}_{m-1},u^{k-1}_m)
+      conv(h, L, y, L.t1);
+      if (gm)
+        lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0});
+      else
+        lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0});
+      copy_d2d(h, L.unm(m), y, n);
+      solve(h, L, cf, dtm, L.b, L.unm(m));
+    }
+    // stored terms of the new iterate at node m
+    double* Cm = L.Cnew + (long)m * n;
+    conv(h, L, L.unm(m), Cm);
+    sipg(h, L, cf, L.unm(m), L.X + (long)(m - 1) * n, 0.0, 1.0);
+    frhs_from_c(h, L, L.unm(m), Cm, L.f + (long)(m - 1) * n);
+  }
+  std::swap(L.u, L.unew);
+  std::swap(L.C, L.Cnew);
+  L.stale = false;
+  L.stored_dt = dt;
+}
+
+// F_m(u) = M (u_m - u_{m-1}) - q_m(u) into out[m-1]
+void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const double* g_minus) {
+  ensure_stored(h, L, dt);
+  quadrature(h, L, dt);
+  for (int m = 1; m <= L.M; ++m) {
+    double* o = out + (long)(m - 1) * L.vlen;
+    const double* qm = L.q + (long)(m - 1) * L.vlen;
+    if (g_minus)  // r = g - F
+      lincomb(h, L, o, {{1.0, g_minus + (long)(m - 1) * L.vlen}, {-1.0, L.um(m)}, {1.0, L.um(m - 1)}, {1.0, qm}},
+              {0, 1, 1, 0});
+    else
+      lincomb(h, L, o, {{1.0, L.um(m)}, {-1.0, L.um(m - 1)}, {-1.0, qm}}, {1, 1, 0});
+  }
+}
+
+void space_transfer(sisdc_handle* h, const Level& from, const Level& to, const double* in, double* out,
+                    const double* A) {
+  HIPCHECK(launch_space_transfer(in, out, from.nv, from.g.dim, from.n1, to.n1, from.E, A, h->stream));
+}
+
+// FAS restriction from fine level i to coarse level i+1 (Alg. 2, residual
+// evaluation, solution restriction and RHS composition).
+void restrict_fas(sisdc_handle* h, int i, double dt) {
+  Level& F = h->lv[i];
+  Level& Cc = h->lv[i + 1];
+  Transfer& T = h->tr[i];
+  colloc_residual(h, F, dt, F.r, F.has_g ? F.gf : nullptr);
+  if (!F.has_g) {  // r = 0 - F(u)
+    for (int m = 0; m < F.M; ++m) lincomb(h, F, F.r + (long)m * F.vlen, {{-1.0, F.r + (long)m * F.vlen}});
+  }
+  // v_c = (P_t x P_x) u_f, v_c[0] = coarse u_0
+  copy_d2d(h, Cc.v, Cc.um(0), Cc.vlen);
+  for (int mc = 0; mc < Cc.M; ++mc) {
+    std::vector<double> c;
+    std::vector<const double*> x;
+    for (int j = 0; j < F.M; ++j) {
+      c.push_back(T.Pt[mc * F.M + j]);
+      x.push_back(F.um(j + 1));
+    }
+    lincomb_v(h, F, F.t1, c, x, {});
+    space_transfer(h, F, Cc, F.t1, Cc.v + (long)(mc + 1) * Cc.vlen, T.Px);
+  }
+  // u_c <- v_c, then g_c = F_c(v_c) + R r_f
+  copy_d2d(h, Cc.u, Cc.v, (long)(Cc.M + 1) * Cc.vlen);
+  Cc.stale = true;
+  Cc.has_g = false;
+  colloc_residual(h, Cc, dt, Cc.gf, nullptr);
+  for (int mc = 0; mc < Cc.M; ++mc) {
+    std::vector<double> c;
+    std::vector<const double*> x;
+    for (int i2 = 0; i2 < F.M; ++i2) {
+      c.push_back(T.It[i2 * Cc.M + mc]);
+      x.push_back(F.r + (long)i2 * F.vlen);
+    }
+    lincomb_v(h, F, F.t1, c, x, {});
+    space_transfer(h, F, Cc, F.t1, Cc.t1, T.Rx);
+    double* gm = Cc.gf + (long)mc * Cc.vlen;
+    lincomb(h, Cc, gm, {{1.0, gm}, {1.0, Cc.t1}});
+  }
+  Cc.has_g = true;
+}
+
+// u_f[m] += (I_t x I_x)(u_c - v_c)[m], m = 1..M_f (correction prolongation)
+void prolong_correction(sisdc_handle* h, int i) {
+  Level& F = h->lv[i];
+  Level& Cc = h->lv[i + 1];
+  Transfer& T = h->tr[i];
+  for (int mf = 0; mf < F.M; ++mf) {
+    std::vector<double> c;
+    std::vector<const double*> x;
+    for (int j = 0; j < Cc.M; ++j) {
+      c.push_back(T.It[mf * Cc.M + j]);
+      x.push_back(Cc.um(j + 1));
+      c.push_back(-T.It[mf * Cc.M + j]);
+      x.push_back(Cc.v + (long)(j + 1) * Cc.vlen);
+    }
+    lincomb_v(h, Cc, Cc.t1, c, x, {});
+    space_transfer(h, Cc, F, Cc.t1, F.t1, T.Ix);
+    lincomb(h, F, F.um(mf + 1), {{1.0, F.um(mf + 1)}, {1.0, F.t1}});
+  }
+  F.stale = true;
+}
+
+// u_f[m] = (I_t x I_x) u_c [m], m = 1..M_f  (cascade / FMG interpolation)
+void interpolate_up(sisdc_handle* h, int i) {
+  Level& F = h->lv[i];
+  Level& Cc = h->lv[i + 1];
+  Transfer& T = h->tr[i];
+  for (int mf = 0; mf < F.M; ++mf) {
+    std::vector<double> c;
+    std::vector<const double*> x;
+    for (int j = 0; j < Cc.M; ++j) {
+      c.push_back(T.It[mf * Cc.M + j]);
+      x.push_back(Cc.um(j + 1));
+    }
+    lincomb_v(h, Cc, Cc.t1, c, x, {});
+    space_transfer(h, Cc, F, Cc.t1, F.um(mf + 1), T.Ix);
+  }
+  F.stale = true;
+}
+
+void level_sweep(sisdc_handle* h, int i, double dt) {
+  Level& L = h->lv[i];
+  sweep(h, L, dt, L.has_g ? L.gf : nullptr);
+  if (i == 0) h->st.fine_sweeps += 1;
+}
+
+// Alg. 2 on levels top (finest of the cycle) .. coarsest; g = 0 on top.
+void vcycle(sisdc_handle* h, int top, double dt) {
+  const int Lc = (int)h->lv.size() - 1;
+  h->lv[top].has_g = false;
+  for (int i = top; i < Lc; ++i) {
+    level_sweep(h, i, dt);
+    restrict_fas(h, i, dt);
+  }
+  for (int k = 0; k < h->meth.n_coarse_sweeps; ++k) level_sweep(h, Lc, dt);
+  for (int i = Lc - 1; i >= top; --i) {
+    prolong_correction(h, i);
+    if (i > top) level_sweep(h, i, dt);
+  }
+}
+
+void set_level_initial(sisdc_handle* h) {
+  copy_d2d(h, h->lv[0].um(0), h->state, h->lv[0].vlen);
+  for (size_t i = 1; i < h->lv.size(); ++i)
+    space_transfer(h, h->lv[i - 1], h->lv[i], h->lv[i - 1].um(0), h->lv[i].um(0), h->tr[i - 1].Px);
+  for (auto& L : h->lv) {
+    L.stale = true;
+    L.has_g = false;
+  }
+}
+
+void update_lam(sisdc_handle* h) {
+  if (h->eq.eq != EQ_EULER) { h->lam = 0.0; return; }
+  Level& L = h->lv[0];
+  HIPCHECK(launch_euler_lam(L.um(0), L.vs, h->eq, L.g.dim, h->partials, h->counter, h->lam_dev, h->stream));
+  HIPCHECK(hipMemcpyAsync(&h->hscal->rz, h->lam_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->lam = h->hscal->rz;
+}
+
+void do_step(sisdc_handle* h, double dt) {
+  set_level_initial(h);
+  update_lam(h);
+  const int nl = (int)h->lv.size();
+  const int Lc = nl - 1;
+  if (nl == 1) {
+    predictor(h, h->lv[0], dt);
+    h->st.fine_sweeps += 1;
+    for (int k = 0; k < h->meth.n_iter; ++k) level_sweep(h, 0, dt);
+  } else {
+    const int start = h->meth.start;
+    if (start == SISDC_START_PREDICTOR) {
+      for (int i = 0; i < nl; ++i) predictor(h, h->lv[i], dt);
+      h->st.fine_sweeps += 1;
+    } else {
+      predictor(h, h->lv[Lc], dt);
+      if (start == SISDC_START_CASCADE) {  // Alg. 3
+        for (int i = Lc; i >= 1; --i) {
+          level_sweep(h, i, dt);
+          interpolate_up(h, i - 1);
+        }
+      } else {  // Alg. 4, C_fmg = 1
+        level_sweep(h, Lc, dt);
+        interpolate_up(h, Lc - 1);
+        for (int i = Lc - 1; i >= 1; --i) {
+          vcycle(h, i, dt);
+          interpolate_up(h, i - 1);
+        }
+      }
+    }
+    for (int c = 0; c < h->meth.n_iter; ++c) vcycle(h, 0, dt);
+    if (h->meth.post_sweep) {
+      h->lv[0].has_g = false;
+      level_sweep(h, 0, dt);
+    }
+  }
+  Level& F = h->lv[0];
+  copy_d2d(h, h->state, F.um(F.M), F.vlen);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+// ------------------------------------------------------------------ setup
+void build_level(sisdc_handle* h, Level& L, int P, int M) {
+  const sisdc_problem& pr = h->prob;
+  L.P = P;
+  L.M = M;
+  L.n1 = P + 1;
+  L.np = pr.dim == 2 ? L.n1 * L.n1 : L.n1 * L.n1 * L.n1;
+  L.E = 1;
+  for (int d = 0; d < pr.dim; ++d) L.E *= pr.n_elem[d];
+  L.nv = h->eq.nv;
+  L.vs = (long)L.E * L.np;
+  L.vlen = L.vs * L.nv;
+  Geo& g = L.g;
+  g.dim = pr.dim;
+  g.P = P;
+  g.n1 = L.n1;
+  g.np = L.np;
+  g.nf = pr.dim == 2 ? L.n1 : L.n1 * L.n1;
+  g.E = L.E;
+  g.J = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    g.ne[d] = d < pr.dim ? pr.n_elem[d] : 1;
+    g.h[d] = d < pr.dim ? (pr.hi[d] - pr.lo[d]) / pr.n_elem[d] : 1.0;
+    g.rh2[d] = 2.0 / g.h[d];
+    if (d < pr.dim) g.J *= 0.5 * g.h[d];
+  }
+  gll(P, L.xg, L.wg);
+  if ((int)L.xg.size() != L.n1) fail(SISDC_EDEVICE, "GLL node construction failed");
+  L.D = derivative_matrix(L.xg);
+  L.tau = radau_right(M);
+  if ((int)L.tau.size() != M) fail(SISDC_EDEVICE, "Radau node construction failed");
+  L.dtau.resize(M);
+  for (int m = 0; m < M; ++m) L.dtau[m] = L.tau[m] - (m ? L.tau[m - 1] : 0.0);
+  L.wnn = nn_weights(L.tau);
+  std::vector<double> tab(L.D);
+  tab.insert(tab.end(), L.wg.begin(), L.wg.end());
+  L.tab = dalloc(tab.size());
+  HIPCHECK(hipMemcpy(L.tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<double> mw(L.np);
+  for (int n = 0; n < L.np; ++n) {
+    int i0 = n % L.n1, i1 = (n / L.n1) % L.n1, i2 = n / (L.n1 * L.n1);
+    double w = L.wg[i0] * L.wg[i1];
+    if (pr.dim == 3) w *= L.wg[i2];
+    mw[n] = g.J * w;
+  }
+  L.mw = dalloc(L.np);
+  HIPCHECK(hipMemcpy(L.mw, mw.data(), L.np * sizeof(double), hipMemcpyHostToDevice));
+  const long n = L.vlen;
+  L.u = dalloc((M + 1) * n);
+  L.unew = dalloc((M + 1) * n);
+  L.f = dalloc(M * n);
+  L.C = dalloc((M + 1) * n);
+  L.Cnew = dalloc((M + 1) * n);
+  L.X = dalloc(M * n);
+  L.gf = dalloc(M * n);
+  L.v = dalloc((M + 1) * n);
+  L.r = dalloc(M * n);
+  L.q = dalloc(M * n);
+  L.b = dalloc(n);
+  L.y = dalloc(n);
+  L.t1 = dalloc(n);
+  L.t2 = dalloc(n);
+  L.t3 = dalloc(n);
+  L.diag = dalloc(n);
+  L.cr = dalloc(n);
+  L.cz = dalloc(n);
+  L.cp = dalloc(n);
+  L.cAp = dalloc(n);
+  L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
+  HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
+  HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
+}
+
+void free_level(Level& L) {
+  double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cAp, L.trace};
+  for (double* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+void build_transfer(Transfer& T, const Level& F, const Level& Cc) {
+  std::vector<double> I = lagrange(Cc.xg, F.xg);   // (n1f x n1c)
+  std::vector<double> P = lagrange(F.xg, Cc.xg);   // (n1c x n1f)
+  std::vector<double> R(Cc.n1 * F.n1);
+  for (int i = 0; i < F.n1; ++i)
+    for (int j = 0; j < Cc.n1; ++j) R[j * F.n1 + i] = I[i * Cc.n1 + j];
+  T.Ix = dalloc(I.size());
+  T.Px = dalloc(P.size());
+  T.Rx = dalloc(R.size());
+  HIPCHECK(hipMemcpy(T.Ix, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(T.Px, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(T.Rx, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice));
+  T.It = lagrange(Cc.tau, F.tau);  // (Mf x Mc)
+  T.Pt = lagrange(F.tau, Cc.tau);  // (Mc x Mf)
+}
+
+void validate(const sisdc_problem* p, const sisdc_method* m) {
+  if (!p || !m) fail(SISDC_EINVAL, "null problem or method");
+  if (p->dim != 2 && p->dim != 3) fail(SISDC_EINVAL, "dim must be 2 or 3");
+  for (int d = 0; d < p->dim; ++d) {
+    if (p->n_elem[d] < 1) fail(SISDC_EINVAL, "n_elem must be >= 1");
+    if (!(p->hi[d] > p->lo[d])) fail(SISDC_EINVAL, "hi must exceed lo");
+  }
+  if (p->eq < SISDC_EQ_CONVDIFF || p->eq > SISDC_EQ_EULER) fail(SISDC_EINVAL, "unknown equation");
+  if (p->eq == SISDC_EQ_EULER && !(p->gamma > 1.0)) fail(SISDC_EINVAL, "gamma must exceed 1");
+  if (p->eq != SISDC_EQ_EULER && !(p->nu >= 0.0)) fail(SISDC_EINVAL, "nu must be >= 0");
+  if (m->n_levels < 1 || m->n_levels > 3) fail(SISDC_EINVAL, "n_levels must be 1..3");
+  for (int l = 0; l < m->n_levels; ++l) {
+    if (m->P[l] < 1 || m->P[l] > kMaxP) fail(SISDC_EINVAL, "P must be 1..8");
+    if (m->M[l] < 1 || m->M[l] > 8) fail(SISDC_EINVAL, "M must be 1..8");
+    if (l > 0 && m->P[l] > m->P[l - 1]) fail(SISDC_EINVAL, "coarser levels need P <= finer P");
+  }
+  if (m->integrator != SISDC_SI2 && m->integrator != SISDC_SI1) fail(SISDC_EINVAL, "integrator");
+  if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
+  if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
+  if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
+  if (m->precision != SISDC_FP64) fail(SISDC_EINVAL, "precision");
+}
+
+// Caller pointer -> device pointer (host data staged through h->io).
+const double* dev_in(sisdc_handle* h, const double* p, long n, int mem, double* stage) {
+  if (mem == SISDC_MEM_DEVICE) return p;
+  if (mem != SISDC_MEM_HOST) fail(SISDC_EINVAL, "mem must be SISDC_MEM_HOST or SISDC_MEM_DEVICE");
+  HIPCHECK(hipMemcpyAsync(stage, p, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return stage;
+}
+
+void dev_out(sisdc_handle* h, double* user, const double* src, long n, int mem) {
+  if (mem == SISDC_MEM_DEVICE) {
+    if (user != src) copy_d2d(h, user, src, n);
+  } else {
+    HIPCHECK(hipMemcpyAsync(user, src, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+Level& level_at(sisdc_handle* h, int level) {
+  if (!h) fail(SISDC_EINVAL, "null handle");
+  if (level < 0 || level >= (int)h->lv.size()) fail(SISDC_EINVAL, "level out of range");
+  return h->lv[level];
+}
+
+template <class F>
+int guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return SISDC_OK;
+  } catch (const Err& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SISDC_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return SISDC_EDEVICE;
+  }
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+const char* sisdc_last_error(void) { return g_last_error.c_str(); }
+
+int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_stream, sisdc_handle** out) {
+  if (!out) {
+    g_last_error = "null output pointer";
+    return SISDC_EINVAL;
+  }
+  *out = nullptr;
+  sisdc_handle* h = nullptr;
+  int rc = guard([&] {
+    validate(prob, meth);
+    h = new sisdc_handle();
+    h->prob = *prob;
+    h->meth = *meth;
+    h->stream = (hipStream_t)hip_stream;
+    h->ctau = meth->c_tau > 0.0 ? meth->c_tau : 2.0;
+    h->eq.eq = prob->eq;
+    h->eq.nv = prob->eq == SISDC_EQ_EULER ? prob->dim + 2 : 1;
+    for (int d = 0; d < 3; ++d) h->eq.a[d] = d < prob->dim ? prob->a[d] : 0.0;
+    h->eq.nu = prob->eq == SISDC_EQ_EULER ? 0.0 : prob->nu;
+    h->eq.gamma = prob->gamma;
+    h->lv.resize(meth->n_levels);
+    for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
+    h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
+    for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1]);
+    int maxblocks = kVecBlocks;
+    for (auto& L : h->lv) maxblocks = std::max(maxblocks, elem_block_count(L.g));
+    h->partials = dalloc((size_t)3 * maxblocks);
+    void* pc = nullptr;
+    if (hipMalloc(&pc, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->counter = (unsigned*)pc;
+    HIPCHECK(hipMemset(h->counter, 0, 64));
+    void* ps = nullptr;
+    if (hipMalloc(&ps, sizeof(CGScal)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->scal = (CGScal*)ps;
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, sizeof(CGScal)) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
+    h->hscal = (CGScal*)hp;
+    h->lam_dev = dalloc(1);
+    h->state = dalloc(h->lv[0].vlen);
+    size_t io = 0;
+    for (auto& L : h->lv) io = std::max(io, (size_t)(L.M + 1) * L.vlen);
+    h->io_len = io;
+    h->io = dalloc(io);
+  });
+  if (rc != SISDC_OK) {
+    if (h) sisdc_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SISDC_OK;
+}
+
+int sisdc_destroy(sisdc_handle* h) {
+  if (!h) return SISDC_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& L : h->lv) free_level(L);
+  for (auto& T : h->tr) {
+    if (T.Ix) (void)hipFree(T.Ix);
+    if (T.Px) (void)hipFree(T.Px);
+    if (T.Rx) (void)hipFree(T.Rx);
+  }
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->counter) (void)hipFree(h->counter);
+  if (h->scal) (void)hipFree(h->scal);
+  if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->lam_dev) (void)hipFree(h->lam_dev);
+  if (h->state) (void)hipFree(h->state);
+  if (h->io) (void)hipFree(h->io);
+  delete h;
+  return SISDC_OK;
+}
+
+int sisdc_level_info(const sisdc_handle* hc, int level, int* n_elem_total, int* nodes_per_elem, int* n_var,
+                     int* M) {
+  return guard([&] {
+    sisdc_handle* h = const_cast<sisdc_handle*>(hc);
+    Level& L = level_at(h, level);
+    if (n_elem_total) *n_elem_total = L.E;
+    if (nodes_per_elem) *nodes_per_elem = L.np;
+    if (n_var) *n_var = L.nv;
+    if (M) *M = L.M;
+  });
+}
+
+int sisdc_node_coords(sisdc_handle* h, int level, double* x, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!x) fail(SISDC_EINVAL, "null output");
+    const int dim = h->prob.dim;
+    std::vector<double> c((size_t)dim * L.E * L.np);
+    for (int e = 0; e < L.E; ++e) {
+      int ec[3] = {e % L.g.ne[0], (e / L.g.ne[0]) % L.g.ne[1], dim == 3 ? e / (L.g.ne[0] * L.g.ne[1]) : 0};
+      for (int n = 0; n < L.np; ++n) {
+        int ic[3] = {n % L.n1, (n / L.n1) % L.n1, n / (L.n1 * L.n1)};
+        for (int d = 0; d < dim; ++d)
+          c[((size_t)d * L.E + e) * L.np + n] = h->prob.lo[d] + L.g.h[d] * (ec[d] + 0.5 * (L.xg[ic[d]] + 1.0));
+      }
+    }
+    if (mem == SISDC_MEM_HOST) {
+      std::memcpy(x, c.data(), c.size() * sizeof(double));
+    } else {
+      HIPCHECK(hipMemcpy(x, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  });
+}
+
+int sisdc_set_state(sisdc_handle* h, const double* u0, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, 0);
+    if (!u0) fail(SISDC_EINVAL, "null state");
+    const double* d = dev_in(h, u0, L.vlen, mem, h->io);
+    copy_d2d(h, h->state, d, L.vlen);
+    copy_d2d(h, L.um(0), d, L.vlen);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    h->have_state = true;
+  });
+}
+
+int sisdc_get_state(sisdc_handle* h, double* u, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, 0);
+    if (!u) fail(SISDC_EINVAL, "null output");
+    dev_out(h, u, h->state, L.vlen, mem);
+  });
+}
+
+int sisdc_get_level(sisdc_handle* h, int level, double* u, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!u) fail(SISDC_EINVAL, "null output");
+    dev_out(h, u, L.u, (long)(L.M + 1) * L.vlen, mem);
+  });
+}
+
+int sisdc_set_level(sisdc_handle* h, int level, const double* u, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!u) fail(SISDC_EINVAL, "null input");
+    const long n = (long)(L.M + 1) * L.vlen;
+    const double* d = dev_in(h, u, n, mem, h->io);
+    copy_d2d(h, L.u, d, n);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    L.stale = true;
+  });
+}
+
+int sisdc_get_fas(sisdc_handle* h, int level, double* g, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!g) fail(SISDC_EINVAL, "null output");
+    if (!L.has_g) {
+      HIPCHECK(hipMemsetAsync(L.gf, 0, (size_t)L.M * L.vlen * sizeof(double), h->stream));
+    }
+    dev_out(h, g, L.gf, (long)L.M * L.vlen, mem);
+  });
+}
+
+int sisdc_set_fas(sisdc_handle* h, int level, const double* g, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!g) {
+      L.has_g = false;
+      return;
+    }
+    const long n = (long)L.M * L.vlen;
+    const double* d = dev_in(h, g, n, mem, h->io);
+    copy_d2d(h, L.gf, d, n);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    L.has_g = true;
+  });
+}
+
+int sisdc_update_step_params(sisdc_handle* h, double* lam_out) {
+  return guard([&] {
+    level_at(h, 0);
+    update_lam(h);
+    if (lam_out) *lam_out = h->lam;
+  });
+}
+
+int sisdc_step(sisdc_handle* h, double t, double dt, sisdc_stats* st) {
+  (void)t;
+  return guard([&] {
+    level_at(h, 0);
+    if (!h->have_state) fail(SISDC_ESTATE, "sisdc_set_state must precede sisdc_step");
+    if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
+    h->st = sisdc_stats{};
+    do_step(h, dt);
+    if (st) *st = h->st;
+    if (h->st.not_converged) fail(SISDC_ENOTCONV, "a Helmholtz solve reached cg_maxit");
+  });
+}
+
+int sisdc_predict(sisdc_handle* h, int level, double dt, sisdc_stats* st) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
+    h->st = sisdc_stats{};
+    predictor(h, L, dt);
+    if (level == 0) h->st.fine_sweeps += 1;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (st) *st = h->st;
+  });
+}
+
+int sisdc_sweep(sisdc_handle* h, int level, double dt, const double* g, int mem, sisdc_stats* st) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
+    h->st = sisdc_stats{};
+    if (g) {
+      const long n = (long)L.M * L.vlen;
+      const double* d = dev_in(h, g, n, mem, h->io);
+      if (d != L.gf) copy_d2d(h, L.gf, d, n);
+      L.has_g = true;
+    }
+    sweep(h, L, dt, L.has_g ? L.gf : nullptr);
+    if (level == 0) h->st.fine_sweeps += 1;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (st) *st = h->st;
+  });
+}
+
+int mlsdc_vcycle(sisdc_handle* h, int top_level, double dt, sisdc_stats* st) {
+  return guard([&] {
+    level_at(h, top_level);
+    if (top_level >= (int)h->lv.size() - 1) fail(SISDC_EINVAL, "top_level must have a coarser level");
+    if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
+    h->st = sisdc_stats{};
+    vcycle(h, top_level, dt);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (st) *st = h->st;
+  });
+}
+
+int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_state, const double* b, double* x,
+                    int mem, double rtol, int maxit, sisdc_solve_stats* st) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!b || !x) fail(SISDC_EINVAL, "null b or x");
+    if (!(dt_m >= 0.0)) fail(SISDC_EINVAL, "dt_m must be >= 0");
+    if (h->eq.eq == EQ_BURGERS && !coef_state) fail(SISDC_EINVAL, "Burgers needs coef_state");
+    const long n = L.vlen;
+    const double* db = dev_in(h, b, n, mem, L.t1);
+    const double* dub = coef_state ? dev_in(h, coef_state, n, mem, L.t2) : nullptr;
+    double* dx = x;
+    if (mem == SISDC_MEM_HOST) {
+      HIPCHECK(hipMemcpyAsync(L.y, x, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      dx = L.y;
+    }
+    copy_d2d(h, L.b, db, n);
+    CoefP cf = coef_for(h, L, dt_m, dub);
+    sisdc_solve_stats r = cg_solve(h, L, cf, dt_m, L.b, dx, rtol > 0 ? rtol : h->meth.cg_rtol,
+                                   maxit > 0 ? maxit : h->meth.cg_maxit);
+    if (mem == SISDC_MEM_HOST) dev_out(h, x, dx, n, mem);
+    if (st) *st = r;
+    if (!r.converged) fail(SISDC_ENOTCONV, "CG reached maxit before the tolerance");
+  });
+}
+
+int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* in, const double* aux, double* out,
+                int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!in || !out) fail(SISDC_EINVAL, "null in or out");
+    const bool down = op == SISDC_OP_PROJECT || op == SISDC_OP_RESTRICT;
+    const bool up = op == SISDC_OP_INTERP;
+    if ((down || up) && level + 1 >= (int)h->lv.size()) fail(SISDC_EINVAL, "transfer needs level+1");
+    const Level& Lin = up ? h->lv[level + 1] : L;
+    const Level& Lout = down ? h->lv[level + 1] : L;
+    const double* din = dev_in(h, in, Lin.vlen, mem, Lin.t2);
+    const double* daux = aux ? dev_in(h, aux, L.vlen, mem, L.t3) : nullptr;
+    double* dout = mem == SISDC_MEM_DEVICE ? out : Lout.b;
+    switch (op) {
+      case SISDC_OP_MASS: lincomb(h, L, dout, {{1.0, din}}, {1}); break;
+      case SISDC_OP_CONV: conv(h, L, din, dout); break;
+      case SISDC_OP_FRHS:
+        conv(h, L, din, L.t1);
+        frhs_from_c(h, L, din, L.t1, dout);
+        break;
+      case SISDC_OP_SIPG: sipg(h, L, coef_for(h, L, dt_m, daux), din, dout, 0.0, 1.0); break;
+      case SISDC_OP_HELM: sipg(h, L, coef_for(h, L, dt_m, daux), din, dout, 1.0, dt_m); break;
+      case SISDC_OP_PROJECT: space_transfer(h, L, Lout, din, dout, h->tr[level].Px); break;
+      case SISDC_OP_RESTRICT: space_transfer(h, L, Lout, din, dout, h->tr[level].Rx); break;
+      case SISDC_OP_INTERP: space_transfer(h, Lin, L, din, dout, h->tr[level].Ix); break;
+      default: fail(SISDC_EINVAL, "unknown op");
+    }
+    dev_out(h, out, dout, Lout.vlen, mem);
+  });
+}
+
+int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* out, int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!out) fail(SISDC_EINVAL, "null output");
+    colloc_residual(h, L, dt, L.r, nullptr);
+    dev_out(h, out, L.r, (long)L.M * L.vlen, mem);
+  });
+}
+
+}  // extern "C"

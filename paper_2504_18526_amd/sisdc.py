@@ -1,0 +1,286 @@
+"""ctypes binding of libsisdc (include/sisdc.h): argument marshalling only.
+
+Every numerical step runs in the HIP library.  Arrays may be torch tensors
+on the GPU (passed as device pointers) or numpy arrays (host pointers); the
+binding picks SISDC_MEM_DEVICE / SISDC_MEM_HOST accordingly.  If the shared
+library has not been built the import of this module raises: there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsisdc.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+EQ_CONVDIFF, EQ_BURGERS, EQ_EULER = 0, 1, 2
+SI2, SI1 = 0, 1
+START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
+FP64 = 0
+OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT = range(8)
+
+EXPORTS = [
+    "sisdc_last_error", "sisdc_create", "sisdc_destroy", "sisdc_level_info",
+    "sisdc_node_coords", "sisdc_set_state", "sisdc_get_level", "sisdc_set_level",
+    "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
+    "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
+    "sisdc_apply", "sisdc_collocation_residual",
+]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("eq", ctypes.c_int), ("a", ctypes.c_double * 3),
+                ("nu", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class Method(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("P", ctypes.c_int * 3), ("M", ctypes.c_int * 3),
+                ("integrator", ctypes.c_int), ("start", ctypes.c_int),
+                ("n_coarse_sweeps", ctypes.c_int), ("post_sweep", ctypes.c_int),
+                ("n_iter", ctypes.c_int), ("cg_rtol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
+                ("precision", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("fine_sweeps", ctypes.c_int), ("solves", ctypes.c_int),
+                ("cg_iters", ctypes.c_longlong), ("cg_iters_max", ctypes.c_int),
+                ("not_converged", ctypes.c_int), ("max_rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double)]
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsisdc.so is not built: run __graft_entry__.build() or "
+                          "python -m paper_2504_18526_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "sisdc_last_error": ([], ctypes.c_char_p),
+        "sisdc_create": ([ctypes.POINTER(Problem), ctypes.POINTER(Method), P, ctypes.POINTER(P)], I),
+        "sisdc_destroy": ([P], I),
+        "sisdc_level_info": ([P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "sisdc_node_coords": ([P, I, P, I], I),
+        "sisdc_set_state": ([P, P, I], I),
+        "sisdc_get_state": ([P, P, I], I),
+        "sisdc_get_level": ([P, I, P, I], I),
+        "sisdc_set_level": ([P, I, P, I], I),
+        "sisdc_get_fas": ([P, I, P, I], I),
+        "sisdc_set_fas": ([P, I, P, I], I),
+        "sisdc_update_step_params": ([P, ctypes.POINTER(D)], I),
+        "sisdc_step": ([P, D, D, ctypes.POINTER(Stats)], I),
+        "sisdc_predict": ([P, I, D, ctypes.POINTER(Stats)], I),
+        "sisdc_sweep": ([P, I, D, P, I, ctypes.POINTER(Stats)], I),
+        "mlsdc_vcycle": ([P, I, D, ctypes.POINTER(Stats)], I),
+        "helmholtz_solve": ([P, I, D, P, P, P, I, D, I, ctypes.POINTER(SolveStats)], I),
+        "sisdc_apply": ([P, I, I, D, P, P, P, I], I),
+        "sisdc_collocation_residual": ([P, I, D, P, I], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+class SisdcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsisdc error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise SisdcError(rc, lib().sisdc_last_error().decode())
+
+
+def _ptr(a, writable=False):
+    """(pointer, mem) of a torch tensor or numpy array (contiguous, float64)."""
+    if a is None:
+        return None, MEM_DEVICE
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if str(a.dtype) != "torch.float64":
+            raise ValueError("tensor must be float64")
+        return ctypes.c_void_p(a.data_ptr()), (MEM_DEVICE if a.is_cuda else MEM_HOST)
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError("numpy array must be C-contiguous float64")
+    if writable and not a.flags.writeable:
+        raise ValueError("output array is read-only")
+    return ctypes.c_void_p(a.ctypes.data), MEM_HOST
+
+
+def _mem_of(*arrays):
+    mems = {(_ptr(a)[1]) for a in arrays if a is not None}
+    if len(mems) > 1:
+        raise ValueError("mixing host and device arrays in one call")
+    return mems.pop() if mems else MEM_HOST
+
+
+def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4):
+    p = Problem()
+    p.dim = dim
+    for d in range(3):
+        p.n_elem[d] = n_elem[d] if d < dim else 1
+        p.lo[d] = lo[d] if d < dim else 0.0
+        p.hi[d] = hi[d] if d < dim else 1.0
+        p.a[d] = a[d] if d < len(a) else 0.0
+    p.eq = eq
+    p.nu = nu
+    p.gamma = gamma
+    return p
+
+
+def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
+                n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64):
+    m = Method()
+    m.n_levels = len(P)
+    for i in range(3):
+        m.P[i] = P[i] if i < len(P) else 0
+        m.M[i] = M[i] if i < len(M) else 0
+    m.integrator = integrator
+    m.start = start
+    m.n_coarse_sweeps = n_coarse_sweeps
+    m.post_sweep = post_sweep
+    m.n_iter = n_iter
+    m.cg_rtol = cg_rtol
+    m.cg_maxit = cg_maxit
+    m.c_tau = c_tau
+    m.precision = precision
+    return m
+
+
+class Solver:
+    """One libsisdc handle.  Level 0 is the finest level."""
+
+    def __init__(self, problem, method, stream=None):
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream) if stream is not None else None
+        _check(self._lib.sisdc_create(ctypes.byref(problem), ctypes.byref(method), s, ctypes.byref(h)))
+        self.h = h
+        self.problem = problem
+        self.method = method
+        self.dim = problem.dim
+
+    def close(self):
+        if self.h:
+            self._lib.sisdc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level=0):
+        E, Np, nv, M = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.sisdc_level_info(self.h, level, ctypes.byref(E), ctypes.byref(Np),
+                                          ctypes.byref(nv), ctypes.byref(M)))
+        return E.value, Np.value, nv.value, M.value
+
+    def coords(self, level=0):
+        E, Np, nv, M = self.level_info(level)
+        x = np.empty((self.dim, E, Np))
+        _check(self._lib.sisdc_node_coords(self.h, level, x.ctypes.data_as(ctypes.c_void_p), MEM_HOST))
+        return x
+
+    def set_state(self, u0):
+        p, mem = _ptr(u0)
+        _check(self._lib.sisdc_set_state(self.h, p, mem))
+
+    def get_state(self, out):
+        p, mem = _ptr(out, True)
+        _check(self._lib.sisdc_get_state(self.h, p, mem))
+        return out
+
+    def get_level(self, level, out):
+        p, mem = _ptr(out, True)
+        _check(self._lib.sisdc_get_level(self.h, level, p, mem))
+        return out
+
+    def set_level(self, level, u):
+        p, mem = _ptr(u)
+        _check(self._lib.sisdc_set_level(self.h, level, p, mem))
+
+    def get_fas(self, level, out):
+        p, mem = _ptr(out, True)
+        _check(self._lib.sisdc_get_fas(self.h, level, p, mem))
+        return out
+
+    def set_fas(self, level, g):
+        p, mem = _ptr(g)
+        _check(self._lib.sisdc_set_fas(self.h, level, p, mem))
+
+    def update_step_params(self):
+        lam = ctypes.c_double()
+        _check(self._lib.sisdc_update_step_params(self.h, ctypes.byref(lam)))
+        return lam.value
+
+    def step(self, dt, t=0.0):
+        st = Stats()
+        _check(self._lib.sisdc_step(self.h, t, dt, ctypes.byref(st)))
+        return st.as_dict()
+
+    def predict(self, level, dt):
+        st = Stats()
+        _check(self._lib.sisdc_predict(self.h, level, dt, ctypes.byref(st)))
+        return st.as_dict()
+
+    def sweep(self, level, dt, g=None):
+        st = Stats()
+        p, mem = _ptr(g) if g is not None else (None, MEM_DEVICE)
+        _check(self._lib.sisdc_sweep(self.h, level, dt, p, mem, ctypes.byref(st)))
+        return st.as_dict()
+
+    def vcycle(self, top_level, dt):
+        st = Stats()
+        _check(self._lib.mlsdc_vcycle(self.h, top_level, dt, ctypes.byref(st)))
+        return st.as_dict()
+
+    def helmholtz_solve(self, level, dt_m, b, x, coef_state=None, rtol=0.0, maxit=0):
+        mem = _mem_of(b, x, coef_state)
+        st = SolveStats()
+        pb, _ = _ptr(b)
+        px, _ = _ptr(x, True)
+        pc, _ = _ptr(coef_state)
+        rc = self._lib.helmholtz_solve(self.h, level, dt_m, pc, pb, px, mem, rtol, maxit, ctypes.byref(st))
+        _check(rc)
+        return {"iters": st.iters, "converged": st.converged, "rel_residual": st.rel_residual}
+
+    def apply(self, op, level, x, out, dt_m=0.0, aux=None):
+        mem = _mem_of(x, out, aux)
+        px, _ = _ptr(x)
+        po, _ = _ptr(out, True)
+        pa, _ = _ptr(aux)
+        _check(self._lib.sisdc_apply(self.h, op, level, dt_m, px, pa, po, mem))
+        return out
+
+    def collocation_residual(self, level, dt, out):
+        p, mem = _ptr(out, True)
+        _check(self._lib.sisdc_collocation_residual(self.h, level, dt, p, mem))
+        return out

@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every stage is fed the same seeded input on both sides and compared by the
+relative L2 norm of the difference; the bar for the FP64 path is 1e-12 per
+stage.  Meshes are small enough for the oracle, with element counts that
+leave a ragged last workgroup (EPB elements per workgroup: 10 at P = 4,
+3 at P = 8, 5 at P = 6 in 2-D; 4 at P = 3 in 3-D).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import sdc as osdc
+from oracle.sdc import DGLevel, SpaceTransfer, MLSDC
+from oracle import solve as osolve
+from helpers import rel_l2, oracle_phys, lib_problem, random_state, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_18526_amd import sisdc
+    return sisdc
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def make_pair(S, eq, dim, n, Ps, Ms, lo=None, hi=None, nu=0.01, rtol=1e-14, **meth):
+    lo = lo if lo is not None else [0.0] * dim
+    hi = hi if hi is not None else [1.0 + 0.25 * d for d in range(dim)]
+    phys = oracle_phys(eq, dim, nu=nu)
+    levels = [DGLevel(phys, n, lo, hi, P, M, rtol=1e-14) for P, M in zip(Ps, Ms)]
+    prob = lib_problem(S, eq, dim, n, lo, hi, nu=nu)
+    m = S.make_method(list(Ps), list(Ms), cg_rtol=rtol, cg_maxit=5000, **meth)
+    return phys, levels, S.Solver(prob, m)
+
+
+# shapes: (eq, dim, n_elem, P)
+OPS = [
+    ("convdiff", 2, (7, 3), 4),
+    ("burgers", 2, (5, 4), 8),
+    ("euler", 2, (4, 3), 6),
+    ("convdiff", 3, (3, 2, 3), 3),
+    ("burgers", 3, (2, 3, 2), 2),
+    ("euler", 3, (2, 2, 3), 3),
+    ("burgers", 2, (1, 3), 5),
+]
+
+
+@pytest.mark.parametrize("eq,dim,n,P", OPS)
+def test_coords_and_conv(S, eq, dim, n, P):
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3])
+    xo = np.stack([c.reshape(-1) for c in lv.coords()])
+    xl = sv.coords(0).reshape(dim, -1)
+    assert np.max(np.abs(xo - xl)) < 1e-14
+    rng = np.random.default_rng(10 + P)
+    U = random_state(phys, lv.mesh, rng)
+    out = torch.empty(U.size, dtype=torch.float64, device="cuda")
+    sv.apply(S.OP_CONV, 0, dev(U.ravel()), out)
+    assert rel_l2(host(out), lv.conv(U)) < TOL
+    sv.apply(S.OP_FRHS, 0, dev(U.ravel()), out)
+    assert rel_l2(host(out), lv.frhs(U)) < TOL
+    sv.apply(S.OP_MASS, 0, dev(U.ravel()), out)
+    assert rel_l2(host(out), lv.mass(U)) < TOL
+
+
+@pytest.mark.parametrize("eq,dim,n,P", OPS)
+def test_sipg_and_helmholtz_apply(S, eq, dim, n, P):
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3])
+    rng = np.random.default_rng(20 + P)
+    Ub = random_state(phys, lv.mesh, rng)
+    X = rng.standard_normal(lv.shape())
+    dtm = 0.037
+    params = phys.step_params(Ub)
+    if params is not None:
+        lam = sv.set_state(dev(Ub.ravel())) or sv.update_step_params()
+        assert abs(lam - params["lam"]) < 1e-14 * params["lam"]
+    Dc = lv.coef(Ub, dtm, params)
+    out = torch.empty(X.size, dtype=torch.float64, device="cuda")
+    aux = dev(Ub[:1].ravel()) if eq == "burgers" else None
+    sv.apply(S.OP_SIPG, 0, dev(X.ravel()), out, dt_m=dtm, aux=aux)
+    assert rel_l2(host(out), lv.K(Dc, X)) < TOL
+    sv.apply(S.OP_HELM, 0, dev(X.ravel()), out, dt_m=dtm, aux=aux)
+    assert rel_l2(host(out), lv.dg.helmholtz(Dc, dtm, X)) < TOL
+
+
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[4]])
+def test_helmholtz_solve(S, eq, dim, n, P):
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3])
+    rng = np.random.default_rng(30 + P)
+    Ub = random_state(phys, lv.mesh, rng)
+    params = phys.step_params(Ub)
+    if params is not None:
+        sv.set_state(dev(Ub.ravel()))
+        sv.update_step_params()
+    dtm = 0.05
+    Dc = lv.coef(Ub, dtm, params)
+    b = rng.standard_normal(lv.shape())
+    xo = lv.solve(Dc, dtm, b, np.zeros_like(b))
+    x = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    st = sv.helmholtz_solve(0, dtm, dev(b.ravel()), x,
+                            coef_state=dev(Ub[:1].ravel()) if eq == "burgers" else None,
+                            rtol=1e-14, maxit=5000)
+    assert st["converged"]
+    assert rel_l2(host(x), xo) < TOL
+    # a second solve from the solution converges at once
+    st2 = sv.helmholtz_solve(0, dtm, dev(b.ravel()), x,
+                             coef_state=dev(Ub[:1].ravel()) if eq == "burgers" else None,
+                             rtol=1e-10, maxit=5000)
+    assert st2["iters"] <= 1
+
+
+@pytest.mark.parametrize("dim,n,Pf,Pc", [(2, (3, 2), 8, 4), (2, (2, 3), 6, 4), (3, (2, 1, 2), 7, 3)])
+def test_space_transfers(S, dim, n, Pf, Pc):
+    phys, (lf, lc), sv = make_pair(S, "convdiff", dim, n, [Pf, Pc], [3, 2])
+    tr = SpaceTransfer(lf, lc)
+    rng = np.random.default_rng(40)
+    Xf = rng.standard_normal(lf.shape())
+    Xc = rng.standard_normal(lc.shape())
+    oc = torch.empty(Xc.size, dtype=torch.float64, device="cuda")
+    of = torch.empty(Xf.size, dtype=torch.float64, device="cuda")
+    sv.apply(S.OP_PROJECT, 0, dev(Xf.ravel()), oc)
+    assert rel_l2(host(oc), tr.P(Xf)) < TOL
+    sv.apply(S.OP_RESTRICT, 0, dev(Xf.ravel()), oc)
+    assert rel_l2(host(oc), tr.R(Xf)) < TOL
+    sv.apply(S.OP_INTERP, 0, dev(Xc.ravel()), of)
+    assert rel_l2(host(of), tr.I(Xc)) < TOL
+    # embedded interpolation: P I = identity (Sec. 4 transfer operators)
+    sv.apply(S.OP_PROJECT, 0, of, oc)
+    assert rel_l2(host(oc), Xc) < 1e-13
+
+
+def level_array(lv, U):
+    return np.concatenate([u.ravel() for u in U])
+
+
+@pytest.mark.parametrize("eq,dim,n,P,M,scheme", [
+    ("convdiff", 2, (7, 3), 4, 3, "si2"),
+    ("burgers", 2, (5, 4), 6, 4, "si2"),
+    ("burgers", 2, (3, 3), 4, 3, "si1"),
+    ("euler", 2, (4, 3), 4, 3, "si2"),
+    ("convdiff", 3, (2, 3, 2), 3, 2, "si2"),
+])
+def test_predictor_and_sweep(S, eq, dim, n, P, M, scheme):
+    integ = S.SI2 if scheme == "si2" else S.SI1
+    hi = [10.0, 10.0, 10.0][:dim] if eq == "euler" else None
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [M], hi=hi, integrator=integ)
+    rng = np.random.default_rng(50 + P)
+    u0 = smooth_state(phys, lv, rng)
+    dt = 0.3 if eq == "euler" else 0.02
+    params = phys.step_params(u0)
+    sv.set_state(dev(u0.ravel()))
+    sv.update_step_params()
+    # predictor from u0
+    full = np.zeros((M + 1,) + u0.shape)
+    full[0] = u0
+    sv.set_level(0, dev(full.ravel()))
+    sv.predict(0, dt)
+    got = torch.empty(full.size, dtype=torch.float64, device="cuda")
+    sv.get_level(0, got)
+    Uo = osdc.predictor(lv, u0, dt, params, scheme)
+    assert rel_l2(host(got), level_array(lv, Uo)) < TOL
+    # one sweep with a FAS term g from a perturbed iterate
+    Up = [Uo[0]] + [Uo[m] + 1e-3 * rng.standard_normal(u0.shape) * (1 if phys.nv == 1 else u0)
+                    for m in range(1, M + 1)]
+    g = [None] + [1e-3 * rng.standard_normal(u0.shape) * lv.mass(np.ones_like(u0)) for _ in range(M)]
+    sv.set_level(0, dev(level_array(lv, Up)))
+    sv.sweep(0, dt, dev(np.concatenate([gm.ravel() for gm in g[1:]])))
+    sv.get_level(0, got)
+    Uo2 = osdc.sweep(lv, Up, dt, params, g, scheme)
+    assert rel_l2(host(got), level_array(lv, Uo2)) < TOL
+    # a second sweep reuses the stored f, C and K-terms of the first
+    sv.sweep(0, dt)
+    sv.get_level(0, got)
+    Uo3 = osdc.sweep(lv, Uo2, dt, params, g, scheme)
+    assert rel_l2(host(got), level_array(lv, Uo3)) < TOL
+    # collocation residual of the result
+    res = torch.empty(M * u0.size, dtype=torch.float64, device="cuda")
+    sv.collocation_residual(0, dt, res)
+    Fo = osdc.collocation_residual(lv, Uo3, dt)
+    # the residual is a difference of O(1) terms that cancel to ~1e-6, so
+    # its rounding error is measured against the size of the terms (M u_m)
+    Fo_flat = np.concatenate([f.ravel() for f in Fo[1:]])
+    scale = np.linalg.norm(np.concatenate([lv.mass(Uo3[m]).ravel() for m in range(1, M + 1)]))
+    assert np.linalg.norm(host(res) - Fo_flat) / scale < TOL
+
+
+def test_vcycle_two_levels(S):
+    phys, (lf, lc), sv = make_pair(S, "burgers", 2, (4, 3), [6, 3], [4, 2], nu=0.02)
+    ml = MLSDC([lc, lf], n_coarse=2)
+    rng = np.random.default_rng(60)
+    u0 = smooth_state(phys, lf, rng)
+    dt = 0.01
+    ml.set_initial(u0, None)
+    Uf = osdc.predictor(lf, u0, dt, None)
+    Uc = osdc.predictor(lc, ml.u0[0], dt, None)
+    ml.U[1], ml.U[0] = list(Uf), list(Uc)
+    sv.set_state(dev(u0.ravel()))
+    sv.set_level(0, dev(level_array(lf, Uf)))
+    sv.set_level(1, dev(level_array(lc, Uc)))
+    sv.vcycle(0, dt)
+    ml.vcycle(1, dt)
+    gf = torch.empty(5 * u0.size, dtype=torch.float64, device="cuda")
+    gc = torch.empty(3 * ml.U[0][0].size, dtype=torch.float64, device="cuda")
+    sv.get_level(0, gf)
+    sv.get_level(1, gc)
+    assert rel_l2(host(gf), level_array(lf, ml.U[1])) < TOL
+    assert rel_l2(host(gc), level_array(lc, ml.U[0])) < TOL
+    g = torch.empty(2 * ml.U[0][0].size, dtype=torch.float64, device="cuda")
+    sv.get_fas(1, g)
+    assert rel_l2(host(g), np.concatenate([x.ravel() for x in ml.g[0][1:]])) < TOL
+
+
+@pytest.mark.parametrize("case", ["convdiff_sl", "burgers_2l_cascade", "euler_3l_fmg", "convdiff_3d_2l"])
+def test_steps(S, case):
+    if case == "convdiff_sl":
+        args = dict(eq="convdiff", dim=2, n=(3, 4), Ps=[4], Ms=[3], n_iter=4)
+        dt, nsteps = 1.686e-2, 3
+    elif case == "burgers_2l_cascade":
+        args = dict(eq="burgers", dim=2, n=(4, 3), Ps=[8, 4], Ms=[5, 3], n_iter=3, nu=5e-3,
+                    start=S.START_CASCADE)
+        dt, nsteps = 5e-3, 2
+    elif case == "euler_3l_fmg":
+        args = dict(eq="euler", dim=2, n=(4, 4), Ps=[6, 4, 2], Ms=[5, 3, 2], n_iter=2,
+                    start=S.START_FMG, lo=[0, 0], hi=[10, 10])
+        dt, nsteps = 0.1, 2
+    else:
+        args = dict(eq="convdiff", dim=3, n=(2, 2, 3), Ps=[3, 2], Ms=[3, 2], n_iter=2,
+                    start=S.START_CASCADE)
+        dt, nsteps = 0.01, 2
+    eq, dim = args["eq"], args["dim"]
+    phys, levels, sv = make_pair(S, eq, dim, args["n"], args["Ps"], args["Ms"], lo=args.get("lo"),
+                                 hi=args.get("hi"), nu=args.get("nu", 0.01), n_iter=args["n_iter"],
+                                 start=args.get("start", S.START_CASCADE))
+    fine = levels[0]
+    rng = np.random.default_rng(70)
+    if eq == "euler":
+        from paper_2504_18526_amd.inputs import isentropic_vortex
+        u = isentropic_vortex(fine.coords())
+    else:
+        u = smooth_state(phys, fine, rng)
+    if len(levels) == 1:
+        stepper = lambda v: osdc.sdc_step(fine, v, dt, args["n_iter"])
+    else:
+        start = {S.START_CASCADE: "cascade", S.START_FMG: "fmg"}[args.get("start", S.START_CASCADE)]
+        ml = MLSDC(list(reversed(levels)), n_coarse=2, start=start, cycles=args["n_iter"], post_sweep=True)
+        stepper = lambda v: ml.step(v, dt)
+    sv.set_state(dev(u.ravel()))
+    out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    mass0 = fine.dg.integral(u)
+    for k in range(nsteps):
+        st = sv.step(dt)
+        u = stepper(u)
+        sv.get_state(out)
+        assert rel_l2(host(out), u) < TOL, (case, k)
+        assert st["not_converged"] == 0
+    # conservation of every conserved variable
+    got = host(out).reshape(u.shape)
+    assert np.max(np.abs(fine.dg.integral(got) - mass0)) < 1e-12 * max(1.0, np.max(np.abs(mass0)))
