@@ -1,0 +1,174 @@
+"""Throughput of the SI-MLSDC / DG-SEM hot path on one MI355X.
+
+Workload: two-level SI-MLSDC for 2-D viscous Burgers, 32 x 32 elements,
+fine P = 8 / M = 5, coarse P = 4 / M = 3 (see paper_2504_18526_amd/workloads.py).
+One step = one time step of the method: cascade start, 3 V-cycles, fine
+post-sweep, every implicit system solved by PCG to a relative residual of
+1e-10.  Metric: fine-level DOF-updates/s =
+nodes_fine * n_var * M_fine * fine_sweeps_per_step / (s / step).
+
+Prints one JSON line with the contract fields plus `roofline` (the CG
+matvec kernel, timed with HIP events on the solver's stream) and
+`cpu_baseline` (the CPU oracle on a bounded sample, rank 0, N = 1).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reps", type=int, default=400, help="launches timed for the roofline kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, u0_path, gpu_step1_path, nsteps):
+    """Time the CPU oracle on `nsteps` steps in a child process with one
+    BLAS/OpenMP thread (the paper's runs were single-threaded)."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    code = f"""
+import sys, time, json, numpy as np
+sys.path.insert(0, {ROOT!r})
+from oracle.sdc import DGLevel, MLSDC
+from oracle.physics import Burgers
+w = {json.dumps({k: v for k, v in w.items()})}
+ph = Burgers(w['dim'], w['nu'])
+lv = [DGLevel(ph, w['n_elem'], w['lo'], w['hi'], P, M, rtol=w['cg_rtol']) for P, M in zip(w['P'], w['M'])]
+ml = MLSDC(list(reversed(lv)), n_coarse=w['n_coarse'], start=w['start'], cycles=w['cycles'],
+           post_sweep=bool(w['post_sweep']))
+u = np.load({u0_path!r}).reshape(lv[0].mesh.shape(1))
+g1 = np.load({gpu_step1_path!r}).reshape(u.shape)
+t = time.perf_counter()
+for k in range({nsteps}):
+    u = ml.step(u, w['dt'])
+    if k == 0:
+        u1 = u.copy()
+el = time.perf_counter() - t
+err = float(np.linalg.norm(g1 - u1) / np.linalg.norm(u1))
+print(json.dumps({{"seconds": el, "steps": {nsteps}, "rel_l2_step1": err}}))
+"""
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2504_18526_amd import sisdc as S
+    from paper_2504_18526_amd.inputs import burgers_field
+    from paper_2504_18526_amd.workloads import burgers_2level, fine_sweeps_per_step
+
+    w = burgers_2level()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    prob = S.make_problem(w["dim"], w["n_elem"], w["lo"], w["hi"], S.EQ_BURGERS, nu=w["nu"])
+    meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+                         post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
+                         cg_maxit=1000)
+    sv = S.Solver(prob, meth, stream=stream.cuda_stream)
+    E, Np, nv, M = sv.level_info(0)
+    x = sv.coords(0)
+    u0 = burgers_field([x[d] for d in range(w["dim"])], seed=w["seed"], kmax=w["kmax"]).reshape(1, E, Np)
+    u0 = np.ascontiguousarray(u0)
+    ud = torch.from_numpy(u0).to(dev)
+    sv.set_state(ud)
+    dt = w["dt"]
+
+    # warm-up (the first warm-up step is kept for the parity check against the oracle)
+    step1 = None
+    for k in range(max(1, a.warmup)):
+        sv.step(dt)
+        if k == 0:
+            out = torch.empty_like(ud)
+            sv.get_state(out)
+            step1 = out.cpu().numpy()
+
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+    t0 = time.perf_counter()
+    tot = {"cg_iters": 0, "solves": 0, "fine_sweeps": 0, "not_converged": 0, "max_rel_residual": 0.0}
+    for _ in range(a.steps):
+        st = sv.step(dt)
+        for k in ("cg_iters", "solves", "fine_sweeps", "not_converged"):
+            tot[k] += st[k]
+        tot["max_rel_residual"] = max(tot["max_rel_residual"], st["max_rel_residual"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / a.steps
+
+    sweeps = fine_sweeps_per_step(w)
+    dof_updates = E * Np * nv * M * sweeps
+    value = dof_updates / (ms_step / 1000.0)
+
+    # roofline of the dominant kernel: the CG matvec pass (M + dt_m K_D) p
+    # with its fused dot product, fine level, at the first substep
+    dtm = dt / M  # a representative substep length
+    us = sv.profile_kernel(S.K_SIPG_APPLY, 0, dtm, reps=a.reps)
+    nf = 9  # (P+1)^(d-1) face nodes at P = 8, d = 2
+    bytes_per_dof = 8.0 * (3.0 + 2 * w["dim"] * nf / Np)  # read p, read u_b, write Ap, read neighbour traces
+    algo_bytes = bytes_per_dof * E * Np * nv
+    achieved = algo_bytes / (us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sipg_apply<2,8> (CG matvec)", "avg_launch_us": round(us, 3),
+                "algo_bytes_per_launch": int(algo_bytes)}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        with tempfile.TemporaryDirectory() as td:
+            p0 = os.path.join(td, "u0.npy")
+            p1 = os.path.join(td, "g1.npy")
+            np.save(p0, u0)
+            np.save(p1, step1)
+            r = cpu_baseline(w, p0, p1, a.cpu_steps)
+        cpu_rate = dof_updates * r["steps"] / r["seconds"]
+        cpu = {"value": cpu_rate, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{r['steps']} time steps of the same workload from the same u0 "
+                         f"(oracle CG to the same 1e-10 tolerance), {r['seconds']:.1f} s",
+               "gpu_vs_oracle_rel_l2_step1": r["rel_l2_step1"]}
+
+    rec = {
+        "metric": "fine-level DOF-updates/s (s/step at fixed PCG tolerance 1e-10)",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded Fourier initial data)",
+        "config": {"workload": w["name"], "global_batch": 1, "seq_len": None, "parallelism": "none",
+                   "dt": dt, "fine_dof": E * Np * nv, "fine_sweeps_per_step": sweeps,
+                   "cg_iters_per_step": tot["cg_iters"] / a.steps, "solves_per_step": tot["solves"] / a.steps,
+                   "not_converged": tot["not_converged"], "max_rel_residual": tot["max_rel_residual"],
+                   "wall_s": wall},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    sv.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -202,6 +202,19 @@ int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* i
  * incremental op in weak form: out[m-1] = M (u_m - u_{m-1}) - q_m(u). */
 int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* out, int mem);
 
+/* Measurement hook: average device time (microseconds) of one launch of a
+ * hot-path kernel on a level, from HIP events recorded on the handle's stream
+ * around `reps` back-to-back launches.  Inputs are the level's current
+ * iterate (u_1, with the coefficient state u_0) at step dt_m; only scratch
+ * vectors of the handle are written.  kernel:
+ *   SISDC_K_SIPG_APPLY  the CG matvec pass M x + dt_m K_D x with its fused
+ *                       dot product (face traces from SISDC_K_SIPG_TRACE)
+ *   SISDC_K_SIPG_TRACE  the face-flux trace pass of the SIPG operator
+ *   SISDC_K_CONV        the convective operator C(u)
+ *   SISDC_K_CG_UPDATE   the CG vector update with its two dot products */
+enum { SISDC_K_SIPG_APPLY = 0, SISDC_K_SIPG_TRACE = 1, SISDC_K_CONV = 2, SISDC_K_CG_UPDATE = 3 };
+int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, int reps, double* avg_us);
+
 #ifdef __cplusplus
 }
 #endif

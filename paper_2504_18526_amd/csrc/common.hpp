@@ -33,10 +33,32 @@ struct CoefP {
   const double* ub;  // state the coefficient is evaluated at (nullable)
 };
 
-// Device-resident CG scalars.
-struct CGScal {
-  double rz, pAp, rr, bb, beta, tol2;
-  int done, it, maxit, pad;
+// Result record of one CG solve, written by the single block that detects
+// convergence (or by block 0 of every iteration kernel for the last state).
+struct CGRes {
+  double rr;      // squared residual norm at the last checked iterate
+  double bb;      // squared norm of the right-hand side
+  double thresh;  // rtol^2 * bb
+  int it;         // iterations taken when converged
+  int it_last;    // last iteration index that ran
+};
+
+// Device work buffers of the Chronopoulos-Gear PCG (one matvec and one
+// fused reduction phase per iteration).
+struct CGState {
+  double *x, *r, *z, *p, *s, *w;
+  double* trace;   // face traces of (D grad z)
+  const double* b;
+  const double* diag;
+  double* gam;     // 3 x cap partial sums of (r, z), by iteration mod 3
+  double* rr;      // 2 x cap partial sums of (r, r), by iteration mod 2
+  double* del;     // cap partial sums of (w, z)
+  double* bbp;     // cap partial sums of (b, b)
+  double* alpha;   // 2 step lengths, by iteration mod 2
+  int* done_gen;   // id of the last solve that converged
+  CGRes* res;
+  double tol2;
+  int cap;         // partial slots per array (>= grid of the element kernels)
 };
 
 // Up to 8 vectors combined node-wise: out = sum_j c_j (m_j ? Jw : 1) x_j.

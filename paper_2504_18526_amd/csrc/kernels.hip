@@ -1,14 +1,18 @@
 // HIP kernels of the SI-MLSDC / DG-SEM hot path for gfx950 (MI355X).
 //
-// Element kernels: one workgroup holds EPB elements, one thread per node;
-// the (P+1)^d nodal tile of each element and the 1-D GLL tables are staged in
-// LDS, derivatives are sum-factorised (one 1-D contraction per axis).  Face
-// terms read the neighbour's face trace straight from global memory (the
-// neighbour index follows from the periodic Cartesian numbering).
+// Element kernels: one workgroup holds EPB elements ("a tile"), one thread
+// per node; the (P+1)^d nodal tile of each element and the 1-D GLL tables
+// are staged in LDS, derivatives are sum-factorised (one 1-D contraction per
+// axis).  Face terms read the neighbour's face trace straight from global
+// memory (the neighbour index follows from the periodic Cartesian
+// numbering).  Kernels that reduce are launched on at most kElemCap blocks
+// and loop over tiles, so the number of partial sums stays small.
 //
-// Reductions: wave shuffles (64 lanes), LDS across waves, one partial per
-// workgroup, and the last workgroup to finish (atomic ticket) sums the
-// partials in a fixed order, so every dot product is deterministic.
+// Reductions never synchronise workgroups inside a kernel (a device-scope
+// fence costs an L2 write-back on this multi-XCD part): every block writes
+// one partial per quantity, and the consumer -- always a later kernel --
+// sums all partials in a fixed order in every block.  Dot products are
+// therefore deterministic, and no atomics are used.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -51,17 +55,22 @@ __device__ __forceinline__ int neighbour(const Geo& g, int e, int d, int s) {
   return c[0] + g.ne[0] * (c[1] + g.ne[1] * c[2]);
 }
 
-// ---------------------------------------------------------------- reduction
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Block-wide sums of K per-thread values; thread 0 stores them in
+// part[k][blockIdx.x].  Every thread of the block must call it.
 template <int K>
-__device__ bool block_reduce_last(double (&v)[K], double* partials, unsigned* counter,
-                                  double (&tot)[K]) {
+__device__ void block_partials(const double (&v)[K], double* const (&part)[K]) {
   __shared__ double sred[K][16];
-  __shared__ int s_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
   for (int k = 0; k < K; ++k) {
-    double x = v[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    const double x = wave_sum(v[k]);
     if (lane == 0) sred[k][wid] = x;
   }
   __syncthreads();
@@ -69,34 +78,33 @@ __device__ bool block_reduce_last(double (&v)[K], double* partials, unsigned* co
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += sred[k][w];
-      partials[(size_t)blockIdx.x * K + k] = s;
+      part[k][blockIdx.x] = s;
     }
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
   }
+}
+
+// Fixed-order sums of the first n partials of each of K arrays, returned to
+// every thread of the block (the same bits in every block).  Every thread of
+// the block must call it.
+template <int K>
+__device__ void sum_partials(const double* const (&part)[K], int n, double (&tot)[K]) {
+  __shared__ double sred[K][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double acc[K];
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-    for (int k = 0; k < K; ++k) acc[k] += __builtin_nontemporal_load(&partials[(size_t)b * K + k]);
   for (int k = 0; k < K; ++k) {
-    double x = acc[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) sred[k][wid] = x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) a += part[k][b];
+    a = wave_sum(a);
+    if (lane == 0) sred[k][wid] = a;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < K; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += sred[k][w];
-      tot[k] = s;
-    }
-    *counter = 0u;
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sred[k][w];
+    tot[k] = s;
   }
-  return threadIdx.x == 0;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- fluxes
@@ -207,15 +215,45 @@ __device__ __forceinline__ double coef_w2(const CoefP& cf, long idx) {
   return cf.c * w * w;
 }
 
-// Pass 1: (D grad x)_d on every face node, trace[c][e][d][side][f].
+// (D grad x)_d at the face nodes of one element from its LDS tile sx,
+// stored in trace[c][e][d][side][f].
+template <int DIM, int P>
+__device__ __forceinline__ void store_trace(const double* sx, const double* sD, int n, const int (&ii)[3],
+                                            double cw, const CoefP& cf, const Geo& g, double* trace, int c,
+                                            int e) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NF = L::NF;
+  bool face = false;
+  for (int d = 0; d < DIM; ++d) face = face || ii[d] == 0 || ii[d] == P;
+  if (!face) return;
+  double gr[DIM];
+  for (int d = 0; d < DIM; ++d) {
+    const int st = L::stride(d);
+    const double* row = &sx[n - ii[d] * st];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+    gr[d] = g.rh2[d] * s;
+  }
+  double vg = 0.0;
+  for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+  for (int d = 0; d < DIM; ++d) {
+    const bool lo = ii[d] == 0, hi = ii[d] == P;
+    if (!lo && !hi) continue;
+    const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
+    const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
+    if (lo) trace[base] = qd;
+    if (hi) trace[base + NF] = qd;
+  }
+}
+
+// Pass 1 of K_D x: the face traces of (D grad x).
 template <int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_sipg_trace(const double* __restrict__ x, int nv, long vs, CoefP cf,
-             double* __restrict__ trace, Geo g, const double* __restrict__ tab,
-             const int* __restrict__ done) {
+k_sipg_trace(const double* __restrict__ x, int nv, long vs, CoefP cf, double* __restrict__ trace, Geo g,
+             const double* __restrict__ tab) {
   using L = EL<DIM, P>;
-  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
-  if (done != nullptr && *done) return;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
   __shared__ double sD[N1 * N1];
   __shared__ double sx[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
@@ -229,120 +267,108 @@ k_sipg_trace(const double* __restrict__ x, int nv, long vs, CoefP cf,
     __syncthreads();
     if (act) sx[le * NP + n] = x[c * vs + (long)e * NP + n];
     __syncthreads();
-    if (!act) continue;
-    double gr[DIM];
-    for (int d = 0; d < DIM; ++d) {
-      const int st = L::stride(d);
-      const double* row = &sx[le * NP + n - ii[d] * st];
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
-      gr[d] = g.rh2[d] * s;
-    }
-    double vg = 0.0;
-    for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
-    for (int d = 0; d < DIM; ++d) {
-      const bool lo = ii[d] == 0, hi = ii[d] == P;
-      if (!lo && !hi) continue;
-      const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
-      const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
-      if (lo) trace[base] = qd;
-      if (hi) trace[base + NF] = qd;
-    }
+    if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, trace, c, e);
   }
 }
 
-// Pass 2: out = alpha M x + beta K_D x (weak SIPG), optional dot(out, dotv).
+// Pass 2: out = alpha M x + beta K_D x (weak SIPG).  With part != NULL the
+// block partial of (out, dotv) is stored in part[blockIdx.x].  Blocks loop
+// over tiles.  done_gen (nullable): skip when *done_gen == id.
 template <int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
 k_sipg_apply(const double* __restrict__ x, double* __restrict__ out, int nv, long vs, CoefP cf,
              const double* __restrict__ trace, double alpha, double beta, double ctau, Geo g,
-             const double* __restrict__ tab, const double* __restrict__ dotv, double* partials,
-             unsigned* counter, CGScal* scal, const int* __restrict__ done) {
+             const double* __restrict__ tab, const double* __restrict__ dotv, double* part,
+             const int* __restrict__ done_gen, int id) {
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
-  if (done != nullptr && *done) return;
+  if (done_gen != nullptr && *done_gen == id) return;
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sx[EPB * NP];
   __shared__ double sQ[EPB * DIM * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
-  const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
   int ii[3];
   decomp<DIM, N1>(n, ii);
-  const long own = (long)e * NP + n;
-  const double cw = act ? coef_w2(cf, own) : 0.0;
-  double dacc = 0.0;
   __syncthreads();
   double wn = 1.0;
   for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
   const double jw = g.J * wn;
   const double pen = ctau * (double)(N1 * N1);
-  for (int c = 0; c < nv; ++c) {
-    __syncthreads();
-    if (act) sx[le * NP + n] = x[c * vs + own];
-    __syncthreads();
-    double r = 0.0, xo = 0.0;
-    if (act) {
-      xo = sx[le * NP + n];
-      double gr[DIM];
-      for (int d = 0; d < DIM; ++d) {
-        const int st = L::stride(d);
-        const double* row = &sx[le * NP + n - ii[d] * st];
-        double s = 0.0;
+  const int ntiles = (g.E + EPB - 1) / EPB;
+  double dacc = 0.0;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e = tile * EPB + le;
+    const bool act = (le < EPB) && (e < g.E);
+    const long own = (long)e * NP + n;
+    const double cw = act ? coef_w2(cf, own) : 0.0;
+    for (int c = 0; c < nv; ++c) {
+      __syncthreads();
+      if (act) sx[le * NP + n] = x[c * vs + own];
+      __syncthreads();
+      double r = 0.0, xo = 0.0;
+      if (act) {
+        xo = sx[le * NP + n];
+        double gr[DIM];
+        for (int d = 0; d < DIM; ++d) {
+          const int st = L::stride(d);
+          const double* row = &sx[le * NP + n - ii[d] * st];
+          double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
-        gr[d] = g.rh2[d] * s;
-      }
-      double vg = 0.0;
-      for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
-      double qv[DIM];
-      for (int d = 0; d < DIM; ++d) qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
-      double Qd[DIM];
-      for (int d = 0; d < DIM; ++d) Qd[d] = jw * qv[d];
-      for (int d = 0; d < DIM; ++d) {
-        for (int side = 0; side < 2; ++side) {
-          if (ii[d] != (side ? P : 0)) continue;
-          const double sgn = side ? 1.0 : -1.0;
-          const int nb = neighbour(g, e, d, side ? 1 : -1);
-          const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
-          const long nbi = (long)nb * NP + nn;
-          const double xnb = x[c * vs + nbi];
-          const double qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
-                                   face_index<DIM, N1>(d, ii)];
-          const double dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
-          const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
-          const double qn = 0.5 * sgn * (qv[d] + qnb);
-          const double tau = pen * fmax(dow, dnb) * 0.5 * g.rh2[d];
-          const double jump = xo - xnb;
-          const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
-          r += jfwf * (-qn + tau * jump);
-          for (int d2 = 0; d2 < DIM; ++d2)
-            Qd[d2] -= 0.5 * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : 0.0));
+          for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+          gr[d] = g.rh2[d] * s;
         }
+        double vg = 0.0;
+        for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+        double qv[DIM], Qd[DIM];
+        for (int d = 0; d < DIM; ++d) {
+          qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
+          Qd[d] = jw * qv[d];
+        }
+        for (int d = 0; d < DIM; ++d) {
+          for (int side = 0; side < 2; ++side) {
+            if (ii[d] != (side ? P : 0)) continue;
+            const double sgn = side ? 1.0 : -1.0;
+            const int nb = neighbour(g, e, d, side ? 1 : -1);
+            const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+            const long nbi = (long)nb * NP + nn;
+            const double xnb = x[c * vs + nbi];
+            const double qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
+                                     face_index<DIM, N1>(d, ii)];
+            const double dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
+            const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+            const double qn = 0.5 * sgn * (qv[d] + qnb);
+            const double tau = pen * fmax(dow, dnb) * 0.5 * g.rh2[d];
+            const double jump = xo - xnb;
+            const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+            r += jfwf * (-qn + tau * jump);
+            for (int d2 = 0; d2 < DIM; ++d2)
+              Qd[d2] -= 0.5 * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : 0.0));
+          }
+        }
+        for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
       }
-      for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
-    }
-    __syncthreads();
-    if (act) {
-      for (int d = 0; d < DIM; ++d) {
-        const int st = L::stride(d);
-        const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
-        double s = 0.0;
+      __syncthreads();
+      if (act) {
+        for (int d = 0; d < DIM; ++d) {
+          const int st = L::stride(d);
+          const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
+          double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
-        r += g.rh2[d] * s;
+          for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
+          r += g.rh2[d] * s;
+        }
+        const double val = alpha * jw * xo + beta * r;
+        out[c * vs + own] = val;
+        if (dotv != nullptr) dacc += val * dotv[c * vs + own];
       }
-      const double val = alpha * jw * xo + beta * r;
-      out[c * vs + own] = val;
-      if (dotv != nullptr) dacc += val * dotv[c * vs + own];
     }
   }
-  if (partials != nullptr) {
-    double v1[1] = {dacc}, tot[1];
-    if (block_reduce_last<1>(v1, partials, counter, tot)) scal->pAp = tot[0];
+  if (part != nullptr) {
+    const double v1[1] = {dacc};
+    double* const pp[1] = {part};
+    block_partials<1>(v1, pp);
   }
 }
 
@@ -399,6 +425,136 @@ k_helm_diag(double* __restrict__ diag, int nv, long vs, CoefP cf, double dtm, do
   for (int c = 0; c < nv; ++c) diag[c * vs + own] = val;
 }
 
+// ---------------------------------------------------------------- PCG
+// Chronopoulos-Gear form of Jacobi-PCG: per iteration one element kernel
+// (vector updates, z = diag^-1 r, face traces of z, partials of (r,z) and
+// (r,r)) and one matvec kernel (w = A z with the partial of (w,z)):
+//   beta_i = g_i / g_{i-1},  alpha_i = g_i / (d_i - beta_i g_i / alpha_{i-1})
+//   p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   z = r / diag,  w = A z,  g = (r, z),  d = (w, z).
+//
+// Start: r = b - A x0 (A x0 given in w), z = r / diag, traces of z; partials
+// (r,z) -> gam[0], (r,r) -> rr[0], (b,b) -> bbp.
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_cg_start(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict__ tab) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  __shared__ double sD[N1 * N1];
+  __shared__ double sx[EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const int ntiles = (g.E + EPB - 1) / EPB;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e = tile * EPB + le;
+    const bool act = (le < EPB) && (e < g.E);
+    const long own = (long)e * NP + n;
+    const double cw = act ? coef_w2(cf, own) : 0.0;
+    for (int c = 0; c < nv; ++c) {
+      const long i = c * vs + own;
+      __syncthreads();
+      if (act) {
+        const double bi = cg.b[i];
+        const double ri = bi - cg.w[i];
+        const double zi = ri / cg.diag[i];
+        cg.r[i] = ri;
+        cg.z[i] = zi;
+        sx[le * NP + n] = zi;
+        a[0] += ri * zi;
+        a[1] += ri * ri;
+        a[2] += bi * bi;
+      }
+      __syncthreads();
+      if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
+    }
+  }
+  double* const pp[3] = {cg.gam, cg.rr, cg.bbp};
+  block_partials<3>(a, pp);
+}
+
+// Iteration `it` of the element part.  Reads the partials of g_it (gam[it%3]),
+// g_{it-1}, d_it (del), (r,r)_it (rr[it%2]); stops the solve if
+// (r,r)_it <= rtol^2 (b,b); otherwise updates p, s, x, r, z, writes the face
+// traces of the new z and the partials of g_{it+1} and (r,r)_{it+1}.
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_cg_iter(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict__ tab, int it, int id,
+          int nparts) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  if (*cg.done_gen == id) return;
+  __shared__ double sD[N1 * N1];
+  __shared__ double sx[EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const int cap = cg.cap;
+  double tot[5];
+  {
+    const double* const pr[5] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.del,
+                                 cg.rr + (it % 2) * cap, cg.bbp};
+    sum_partials<5>(pr, nparts, tot);
+  }
+  const double gi = tot[0], gprev = tot[1], di = tot[2], rri = tot[3], bb = tot[4];
+  const double thresh = cg.tol2 * bb;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cg.res->rr = rri;
+    cg.res->bb = bb;
+    cg.res->thresh = thresh;
+    cg.res->it_last = it;
+  }
+  if (rri <= thresh || !(rri == rri)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cg.res->it = it;
+      *cg.done_gen = id;
+    }
+    return;
+  }
+  double beta = 0.0, alpha;
+  if (it == 0) {
+    alpha = gi / di;
+  } else {
+    beta = gi / gprev;
+    alpha = gi / (di - beta * gi / cg.alpha[(it + 1) % 2]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg.alpha[it % 2] = alpha;
+  const int ntiles = (g.E + EPB - 1) / EPB;
+  double a[2] = {0.0, 0.0};
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e = tile * EPB + le;
+    const bool act = (le < EPB) && (e < g.E);
+    const long own = (long)e * NP + n;
+    const double cw = act ? coef_w2(cf, own) : 0.0;
+    for (int c = 0; c < nv; ++c) {
+      const long i = c * vs + own;
+      __syncthreads();
+      if (act) {
+        const double zi0 = cg.z[i], wi = cg.w[i];
+        const double pi = it == 0 ? zi0 : zi0 + beta * cg.p[i];
+        const double si = it == 0 ? wi : wi + beta * cg.s[i];
+        cg.p[i] = pi;
+        cg.s[i] = si;
+        cg.x[i] += alpha * pi;
+        const double ri = cg.r[i] - alpha * si;
+        const double zi = ri / cg.diag[i];
+        cg.r[i] = ri;
+        cg.z[i] = zi;
+        sx[le * NP + n] = zi;
+        a[0] += ri * zi;
+        a[1] += ri * ri;
+      }
+      __syncthreads();
+      if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
+    }
+  }
+  double* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
+  block_partials<2>(a, pp);
+}
+
 // ---------------------------------------------------------------- vectors
 __global__ void k_lincomb(double* __restrict__ out, LinComb lc, long n, const double* __restrict__ mw,
                           int np) {
@@ -408,68 +564,6 @@ __global__ void k_lincomb(double* __restrict__ out, LinComb lc, long n, const do
     for (int j = 0; j < lc.n; ++j) s += lc.c[j] * (lc.m[j] ? m : 1.0) * lc.x[j][i];
     out[i] = s;
   }
-}
-
-// r = b - Ax, z = r / diag, p = z; scal <- (r.z, r.r, b.b)
-__global__ void k_cg_init(const double* __restrict__ b, const double* __restrict__ Ax,
-                          const double* __restrict__ diag, double* __restrict__ r, double* __restrict__ z,
-                          double* __restrict__ p, long n, double* partials, unsigned* counter,
-                          CGScal* scal) {
-  double a[3] = {0.0, 0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double bi = b[i];
-    const double ri = bi - Ax[i];
-    const double zi = ri / diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    p[i] = zi;
-    a[0] += ri * zi;
-    a[1] += ri * ri;
-    a[2] += bi * bi;
-  }
-  double tot[3];
-  if (block_reduce_last<3>(a, partials, counter, tot)) {
-    scal->rz = tot[0];
-    scal->rr = tot[1];
-    scal->bb = tot[2];
-    scal->it = 0;
-    scal->done = (tot[1] <= scal->tol2 * tot[2]) || tot[2] == 0.0 || scal->maxit <= 0;
-  }
-}
-
-// x += alpha p, r -= alpha Ap, z = r / diag; scal <- (r.z, r.r), beta, done
-__global__ void k_cg_update(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                            const double* __restrict__ p, const double* __restrict__ Ap,
-                            const double* __restrict__ diag, long n, double* partials,
-                            unsigned* counter, CGScal* scal) {
-  if (scal->done) return;
-  const double alpha = scal->rz / scal->pAp;
-  double a[2] = {0.0, 0.0};
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    const double zi = ri / diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    a[0] += ri * zi;
-    a[1] += ri * ri;
-  }
-  double tot[2];
-  if (block_reduce_last<2>(a, partials, counter, tot)) {
-    scal->beta = tot[0] / scal->rz;
-    scal->rz = tot[0];
-    scal->rr = tot[1];
-    scal->it += 1;
-    scal->done = (tot[1] <= scal->tol2 * scal->bb) || (scal->it >= scal->maxit) || !(tot[1] == tot[1]);
-  }
-}
-
-__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, long n,
-                         const CGScal* scal) {
-  if (scal->done) return;
-  const double beta = scal->beta;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
 }
 
 // out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
@@ -507,20 +601,17 @@ __global__ void k_space_transfer(const double* __restrict__ in, double* __restri
   }
 }
 
-// lam* = max over nodes of max_d (|v_d| + c) (Euler), reduced by the last block.
+// Per-block maxima of max_d (|v_d| + c) (Euler); reduced by k_max_partials.
 template <int DIM>
-__global__ void k_euler_lam(const double* __restrict__ u, long vs, EqP q, double* partials,
-                            unsigned* counter, double* result) {
+__global__ void k_euler_lam(const double* __restrict__ u, long vs, EqP q, double* part) {
   constexpr int NV = DIM + 2;
+  __shared__ double sm[16];
   double m = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vs; i += (long)gridDim.x * blockDim.x) {
     double uu[NV];
     for (int v = 0; v < NV; ++v) uu[v] = u[v * vs + i];
     for (int d = 0; d < DIM; ++d) m = fmax(m, wave_speed<NV>(q, d, uu));
   }
-  // max reduction: reuse the sum machinery on exp-free max via shuffles
-  __shared__ double sm[16];
-  __shared__ int s_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
   if (lane == 0) sm[wid] = m;
@@ -528,19 +619,22 @@ __global__ void k_euler_lam(const double* __restrict__ u, long vs, EqP q, double
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s = fmax(s, sm[w]);
-    partials[blockIdx.x] = s;
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
+    part[blockIdx.x] = s;
   }
+}
+
+__global__ void k_max_partials(const double* __restrict__ part, int n, double* result) {
+  __shared__ double sm[16];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) m = fmax(m, part[b]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if (lane == 0) sm[wid] = m;
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) s = fmax(s, __builtin_nontemporal_load(&partials[b]));
+    for (int w = 0; w < nw; ++w) s = fmax(s, sm[w]);
     *result = s;
-    *counter = 0u;
   }
 }
 
@@ -553,32 +647,47 @@ static inline int blocks_for(long n, int bs, int cap) {
 }
 
 template <int DIM, int P>
-static int elem_blocks(const Geo& g) {
+static int elem_tiles(const Geo& g) {
   return (g.E + EL<DIM, P>::EPB - 1) / EL<DIM, P>::EPB;
 }
 
-#define SISDC_DISPATCH_P(P_, BODY)        \
-  switch (P_) {                           \
-    case 1: { constexpr int PP = 1; BODY; } break; \
-    case 2: { constexpr int PP = 2; BODY; } break; \
-    case 3: { constexpr int PP = 3; BODY; } break; \
-    case 4: { constexpr int PP = 4; BODY; } break; \
-    case 5: { constexpr int PP = 5; BODY; } break; \
-    case 6: { constexpr int PP = 6; BODY; } break; \
-    case 7: { constexpr int PP = 7; BODY; } break; \
-    case 8: { constexpr int PP = 8; BODY; } break; \
-    default: return hipErrorInvalidValue;   \
+int elem_tile_count(const Geo& g) {
+  const int epb = g.np >= 256 ? 1 : 256 / g.np;
+  return (g.E + epb - 1) / epb;
+}
+
+int reduce_grid(const Geo& g) { return std::min(elem_tile_count(g), kElemCap); }
+
+#define SISDC_DISPATCH_P(P_, BODY)                   \
+  switch (P_) {                                      \
+    case 1: { constexpr int PP = 1; BODY; } break;  \
+    case 2: { constexpr int PP = 2; BODY; } break;  \
+    case 3: { constexpr int PP = 3; BODY; } break;  \
+    case 4: { constexpr int PP = 4; BODY; } break;  \
+    case 5: { constexpr int PP = 5; BODY; } break;  \
+    case 6: { constexpr int PP = 6; BODY; } break;  \
+    case 7: { constexpr int PP = 7; BODY; } break;  \
+    case 8: { constexpr int PP = 8; BODY; } break;  \
+    default: return hipErrorInvalidValue;            \
   }
 
+#define SISDC_DISPATCH(G_, FN, ...)                                                            \
+  do {                                                                                         \
+    if ((G_).dim == 2) { SISDC_DISPATCH_P((G_).P, return (FN<2, PP>(__VA_ARGS__))); }         \
+    else if ((G_).dim == 3) { SISDC_DISPATCH_P((G_).P, return (FN<3, PP>(__VA_ARGS__))); }    \
+    return hipErrorInvalidValue;                                                               \
+  } while (0)
+
 template <int DIM, int P>
-static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const EqP& q,
-                             const double* tab, hipStream_t s) {
+static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
+                             hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
   if (q.nv == 1)
-    hipLaunchKernelGGL((k_conv<DIM, P, 1>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+    hipLaunchKernelGGL((k_conv<DIM, P, 1>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
   else if (q.nv == DIM + 2)
-    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q,
+                       tab, vs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -586,37 +695,47 @@ static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const E
 
 hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
                        hipStream_t s) {
-  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (conv_dim_p<2, PP>(u, out, g, q, tab, s))); }
-  else if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (conv_dim_p<3, PP>(u, out, g, q, tab, s))); }
-  return hipErrorInvalidValue;
+  SISDC_DISPATCH(g, conv_dim_p, u, out, g, q, tab, s);
 }
 
 template <int DIM, int P>
-static hipError_t sipg_dim_p(const double* x, double* out, int nv, const CoefP& cf, double* trace,
-                             double alpha, double beta, double ctau, const Geo& g, const double* tab,
-                             const double* dotv, double* partials, unsigned* counter, CGScal* scal,
-                             const int* done, hipStream_t s) {
+static hipError_t trace_dim_p(const double* x, int nv, const CoefP& cf, double* trace, const Geo& g,
+                              const double* tab, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  const int nb = elem_blocks<DIM, P>(g);
-  hipLaunchKernelGGL((k_sipg_trace<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, nv, vs, cf, trace, g, tab, done);
-  hipLaunchKernelGGL((k_sipg_apply<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha,
-                     beta, ctau, g, tab, dotv, partials, counter, scal, done);
+  hipLaunchKernelGGL((k_sipg_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, x, nv, vs, cf, trace,
+                     g, tab);
   return hipGetLastError();
 }
 
+hipError_t launch_sipg_trace(const double* x, int nv, const CoefP& cf, double* trace, const Geo& g,
+                             const double* tab, hipStream_t s) {
+  SISDC_DISPATCH(g, trace_dim_p, x, nv, cf, trace, g, tab, s);
+}
+
+template <int DIM, int P>
+static hipError_t apply_dim_p(const double* x, double* out, int nv, const CoefP& cf, const double* trace,
+                              double alpha, double beta, double ctau, const Geo& g, const double* tab,
+                              const double* dotv, double* part, const int* done_gen, int id, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
+  hipLaunchKernelGGL((k_sipg_apply<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha, beta,
+                     ctau, g, tab, dotv, part, done_gen, id);
+  return hipGetLastError();
+}
+
+hipError_t launch_sipg_apply(const double* x, double* out, int nv, const CoefP& cf, const double* trace,
+                             double alpha, double beta, double ctau, const Geo& g, const double* tab,
+                             const double* dotv, double* part, const int* done_gen, int id, hipStream_t s) {
+  SISDC_DISPATCH(g, apply_dim_p, x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv, part, done_gen, id, s);
+}
+
 hipError_t launch_sipg(const double* x, double* out, int nv, const CoefP& cf, double* trace, double alpha,
-                       double beta, double ctau, const Geo& g, const double* tab, const double* dotv,
-                       double* partials, unsigned* counter, CGScal* scal, const int* done,
-                       hipStream_t s) {
-  if (g.dim == 2) {
-    SISDC_DISPATCH_P(g.P, return (sipg_dim_p<2, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
-                                                     partials, counter, scal, done, s)));
-  } else if (g.dim == 3) {
-    SISDC_DISPATCH_P(g.P, return (sipg_dim_p<3, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
-                                                     partials, counter, scal, done, s)));
-  }
-  return hipErrorInvalidValue;
+                       double beta, double ctau, const Geo& g, const double* tab, hipStream_t s) {
+  hipError_t e = launch_sipg_trace(x, nv, cf, trace, g, tab, s);
+  if (e != hipSuccess) return e;
+  return launch_sipg_apply(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, nullptr, nullptr, nullptr, 0, s);
 }
 
 template <int DIM, int P>
@@ -624,49 +743,48 @@ static hipError_t diag_dim_p(double* diag, int nv, const CoefP& cf, double dtm, 
                              const double* tab, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_helm_diag<DIM, P>), dim3(elem_blocks<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf,
-                     dtm, ctau, g, tab);
+  hipLaunchKernelGGL((k_helm_diag<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf, dtm,
+                     ctau, g, tab);
   return hipGetLastError();
 }
 
 hipError_t launch_helm_diag(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
                             const double* tab, hipStream_t s) {
-  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<2, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
-  else if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<3, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
-  return hipErrorInvalidValue;
+  SISDC_DISPATCH(g, diag_dim_p, diag, nv, cf, dtm, ctau, g, tab, s);
 }
 
-int elem_block_count(const Geo& g) {
-  int r = 0;
-  auto f = [&](int npb) { r = (g.E + npb - 1) / npb; };
-  const int np = g.np;
-  f(np >= 256 ? 1 : 256 / np);
-  return r;
+template <int DIM, int P>
+static hipError_t cg_start_dim_p(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab,
+                                 hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  hipLaunchKernelGGL((k_cg_start<DIM, P>), dim3(std::min(elem_tiles<DIM, P>(g), kElemCap)), dim3(L::NT), 0, s, cg,
+                     nv, vs, cf, g, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab,
+                           hipStream_t s) {
+  SISDC_DISPATCH(g, cg_start_dim_p, cg, nv, cf, g, tab, s);
+}
+
+template <int DIM, int P>
+static hipError_t cg_iter_dim_p(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab, int it,
+                                int id, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  const int nb = std::min(elem_tiles<DIM, P>(g), kElemCap);
+  hipLaunchKernelGGL((k_cg_iter<DIM, P>), dim3(nb), dim3(L::NT), 0, s, cg, nv, vs, cf, g, tab, it, id, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iter(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab, int it,
+                          int id, hipStream_t s) {
+  SISDC_DISPATCH(g, cg_iter_dim_p, cg, nv, cf, g, tab, it, id, s);
 }
 
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_init(const double* b, const double* Ax, const double* diag, double* r, double* z,
-                          double* p, long n, double* partials, unsigned* counter, CGScal* scal,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, b, Ax, diag, r, z, p, n,
-                     partials, counter, scal);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap,
-                            const double* diag, long n, double* partials, unsigned* counter, CGScal* scal,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, x, r, z, p, Ap, diag,
-                     n, partials, counter, scal);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_dir(double* p, const double* z, long n, const CGScal* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(blocks_for(n, 256, kVecBlocks)), dim3(256), 0, s, p, z, n, scal);
   return hipGetLastError();
 }
 
@@ -677,13 +795,14 @@ hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim,
   return hipGetLastError();
 }
 
-hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* partials,
-                            unsigned* counter, double* result, hipStream_t s) {
-  const int nb = blocks_for(vs, 256, kVecBlocks);
+hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
+                            hipStream_t s) {
+  const int nb = blocks_for(vs, 256, kElemCap);
   if (dim == 2)
-    hipLaunchKernelGGL(k_euler_lam<2>, dim3(nb), dim3(256), 0, s, u, vs, q, partials, counter, result);
+    hipLaunchKernelGGL(k_euler_lam<2>, dim3(nb), dim3(256), 0, s, u, vs, q, part);
   else
-    hipLaunchKernelGGL(k_euler_lam<3>, dim3(nb), dim3(256), 0, s, u, vs, q, partials, counter, result);
+    hipLaunchKernelGGL(k_euler_lam<3>, dim3(nb), dim3(256), 0, s, u, vs, q, part);
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, part, nb, result);
   return hipGetLastError();
 }
 

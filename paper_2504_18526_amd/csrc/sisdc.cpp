@@ -65,7 +65,7 @@ struct Level {
   double* r = nullptr;    // M x vlen, residual
   double* q = nullptr;    // M x vlen, quadrature
   double *b = nullptr, *y = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
-  double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cAp = nullptr;
+  double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cs = nullptr, *cw = nullptr;
   double* trace = nullptr;
   bool stale = true;
   double stored_dt = -1.0;
@@ -91,11 +91,15 @@ struct sisdc_handle {
   EqP eq{};
   std::vector<Level> lv;
   std::vector<Transfer> tr;
-  double* partials = nullptr;
-  unsigned* counter = nullptr;
-  CGScal* scal = nullptr;
-  CGScal* hscal = nullptr;  // pinned host mirror
+  double* partials = nullptr;  // CG partial sums: gam (3 cap), rr (2 cap), del, bbp (cap each)
+  double* alpha = nullptr;     // 2 CG step lengths
+  int* done_gen = nullptr;     // id of the last converged solve
+  CGRes* res = nullptr;        // device result record
+  CGRes* hres = nullptr;       // pinned host mirror of res ...
+  int* hdone = nullptr;        // ... and of done_gen
+  int solve_id = 0;
   double* lam_dev = nullptr;
+  double* hlam = nullptr;      // pinned
   double* state = nullptr;
   double* io = nullptr;      // staging for host pointers, (Mmax+1) x vlen_max
   size_t io_len = 0;
@@ -191,8 +195,7 @@ void conv(sisdc_handle* h, const Level& L, const double* in, double* out) {
 
 void sipg(sisdc_handle* h, const Level& L, const CoefP& cf, const double* x, double* out, double alpha,
           double beta) {
-  HIPCHECK(launch_sipg(x, out, L.nv, cf, L.trace, alpha, beta, h->ctau, L.g, L.tab, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, h->stream));
+  HIPCHECK(launch_sipg(x, out, L.nv, cf, L.trace, alpha, beta, h->ctau, L.g, L.tab, h->stream));
 }
 
 bool has_physical_diffusion(sisdc_handle* h) { return h->eq.eq != EQ_EULER && h->eq.nu != 0.0; }
@@ -208,38 +211,68 @@ void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double*
 }
 
 // ------------------------------------------------------------------ PCG
+CGState cg_state(sisdc_handle* h, Level& L, const double* b, double* x, double rtol) {
+  CGState cg{};
+  cg.x = x;
+  cg.r = L.cr;
+  cg.z = L.cz;
+  cg.p = L.cp;
+  cg.s = L.cs;
+  cg.w = L.cw;
+  cg.trace = L.trace;
+  cg.b = b;
+  cg.diag = L.diag;
+  cg.cap = kElemCap;
+  cg.gam = h->partials;
+  cg.rr = h->partials + 3 * kElemCap;
+  cg.del = h->partials + 5 * kElemCap;
+  cg.bbp = h->partials + 6 * kElemCap;
+  cg.alpha = h->alpha;
+  cg.done_gen = h->done_gen;
+  cg.res = h->res;
+  cg.tol2 = rtol * rtol;
+  return cg;
+}
+
+// Jacobi-PCG (Chronopoulos-Gear form) on M + dt_m K_D; x holds the initial
+// guess on entry.  Iterations are enqueued in batches; the host reads the
+// convergence record once per batch.
 sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                            double rtol, int maxit) {
   hipStream_t s = h->stream;
+  const int id = ++h->solve_id;
+  CGState cg = cg_state(h, L, b, x, rtol);
   HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dtm, h->ctau, L.g, L.tab, s));
-  HIPCHECK(launch_sipg(x, L.cAp, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, s));
-  h->hscal->tol2 = rtol * rtol;
-  h->hscal->maxit = maxit;
-  h->hscal->done = 0;
-  h->hscal->it = 0;
-  HIPCHECK(hipMemcpyAsync(h->scal, h->hscal, sizeof(CGScal), hipMemcpyHostToDevice, s));
-  HIPCHECK(launch_cg_init(b, L.cAp, L.diag, L.cr, L.cz, L.cp, L.vlen, h->partials, h->counter, h->scal, s));
+  HIPCHECK(launch_sipg(x, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, s));  // A x0
+  HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
+  HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cz, cg.del, nullptr, 0,
+                             s));
   int chunk = std::max(2, L.last_iters + 1);
-  int issued = 0;
+  int it = 0;
+  bool converged = false;
   while (true) {
-    for (int k = 0; k < chunk; ++k) {
-      HIPCHECK(launch_sipg(L.cp, L.cAp, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cp, h->partials,
-                           h->counter, h->scal, &h->scal->done, s));
-      HIPCHECK(launch_cg_update(x, L.cr, L.cz, L.cp, L.cAp, L.diag, L.vlen, h->partials, h->counter, h->scal, s));
-      HIPCHECK(launch_cg_dir(L.cp, L.cz, L.vlen, h->scal, s));
+    const int stop = std::min(maxit + 1, it + chunk);  // iteration kernel `it` checks the residual after it updates
+    for (; it < stop; ++it) {
+      HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, L.tab, it, id, s));
+      if (it < maxit)
+        HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cz, cg.del,
+                                   h->done_gen, id, s));
     }
-    issued += chunk;
-    HIPCHECK(hipMemcpyAsync(h->hscal, h->scal, sizeof(CGScal), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(h->hres, h->res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(h->hdone, h->done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    if (h->hscal->done || issued >= maxit) break;
-    chunk = std::min(8, maxit - issued);
+    if (*h->hdone == id) {
+      converged = true;
+      break;
+    }
+    if (it > maxit) break;
+    chunk = 8;
   }
   sisdc_solve_stats r{};
-  r.iters = h->hscal->it;
-  const double rel = h->hscal->bb > 0.0 ? std::sqrt(h->hscal->rr / h->hscal->bb) : 0.0;
+  r.iters = converged ? h->hres->it : maxit;
+  const double rel = h->hres->bb > 0.0 ? std::sqrt(h->hres->rr / h->hres->bb) : 0.0;
   r.rel_residual = rel;
-  r.converged = (h->hscal->bb == 0.0) || (h->hscal->rr <= h->hscal->tol2 * h->hscal->bb);
+  r.converged = converged;
   if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
   L.last_iters = std::max(1, r.iters);
   h->st.solves += 1;
@@ -487,10 +520,10 @@ void set_level_initial(sisdc_handle* h) {
 void update_lam(sisdc_handle* h) {
   if (h->eq.eq != EQ_EULER) { h->lam = 0.0; return; }
   Level& L = h->lv[0];
-  HIPCHECK(launch_euler_lam(L.um(0), L.vs, h->eq, L.g.dim, h->partials, h->counter, h->lam_dev, h->stream));
-  HIPCHECK(hipMemcpyAsync(&h->hscal->rz, h->lam_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(launch_euler_lam(L.um(0), L.vs, h->eq, L.g.dim, h->partials, h->lam_dev, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->hlam, h->lam_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  h->lam = h->hscal->rz;
+  h->lam = *h->hlam;
 }
 
 void do_step(sisdc_handle* h, double dt) {
@@ -601,7 +634,8 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cr = dalloc(n);
   L.cz = dalloc(n);
   L.cp = dalloc(n);
-  L.cAp = dalloc(n);
+  L.cs = dalloc(n);
+  L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
   HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
@@ -609,7 +643,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
 
 void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
-                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cAp, L.trace};
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -724,19 +758,21 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
     for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1]);
-    int maxblocks = kVecBlocks;
-    for (auto& L : h->lv) maxblocks = std::max(maxblocks, elem_block_count(L.g));
-    h->partials = dalloc((size_t)3 * maxblocks);
-    void* pc = nullptr;
-    if (hipMalloc(&pc, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
-    h->counter = (unsigned*)pc;
-    HIPCHECK(hipMemset(h->counter, 0, 64));
-    void* ps = nullptr;
-    if (hipMalloc(&ps, sizeof(CGScal)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
-    h->scal = (CGScal*)ps;
+    h->partials = dalloc((size_t)7 * kElemCap);
+    h->alpha = dalloc(2);
+    void* pi = nullptr;
+    if (hipMalloc(&pi, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->done_gen = (int*)pi;
+    HIPCHECK(hipMemset(h->done_gen, 0, 64));
+    void* pr = nullptr;
+    if (hipMalloc(&pr, sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->res = (CGRes*)pr;
+    HIPCHECK(hipMemset(h->res, 0, sizeof(CGRes)));
     void* hp = nullptr;
-    if (hipHostMalloc(&hp, sizeof(CGScal)) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
-    h->hscal = (CGScal*)hp;
+    if (hipHostMalloc(&hp, 256) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
+    h->hres = (CGRes*)hp;
+    h->hdone = (int*)((char*)hp + 128);
+    h->hlam = (double*)((char*)hp + 192);
     h->lam_dev = dalloc(1);
     h->state = dalloc(h->lv[0].vlen);
     size_t io = 0;
@@ -762,9 +798,10 @@ int sisdc_destroy(sisdc_handle* h) {
     if (T.Rx) (void)hipFree(T.Rx);
   }
   if (h->partials) (void)hipFree(h->partials);
-  if (h->counter) (void)hipFree(h->counter);
-  if (h->scal) (void)hipFree(h->scal);
-  if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->alpha) (void)hipFree(h->alpha);
+  if (h->done_gen) (void)hipFree(h->done_gen);
+  if (h->res) (void)hipFree(h->res);
+  if (h->hres) (void)hipHostFree(h->hres);
   if (h->lam_dev) (void)hipFree(h->lam_dev);
   if (h->state) (void)hipFree(h->state);
   if (h->io) (void)hipFree(h->io);
@@ -997,6 +1034,51 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
     if (!out) fail(SISDC_EINVAL, "null output");
     colloc_residual(h, L, dt, L.r, nullptr);
     dev_out(h, out, L.r, (long)L.M * L.vlen, mem);
+  });
+}
+
+int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, int reps, double* avg_us) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (reps < 1 || !avg_us) fail(SISDC_EINVAL, "reps >= 1 and an output pointer required");
+    if (kernel < SISDC_K_SIPG_APPLY || kernel > SISDC_K_CG_UPDATE) fail(SISDC_EINVAL, "unknown kernel");
+    hipStream_t s = h->stream;
+    CoefP cf = coef_for(h, L, dt_m, L.um(0));
+    const double* x = L.M >= 1 ? L.um(1) : L.um(0);
+    // a CG state on the level's data: b = M u_1, x0 = 0, never converging (rtol = 0)
+    lincomb(h, L, L.b, {{1.0, x}}, {1});
+    HIPCHECK(hipMemsetAsync(L.t2, 0, L.vlen * sizeof(double), s));
+    const int id = ++h->solve_id;
+    CGState cg = cg_state(h, L, L.b, L.t2, 0.0);
+    HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
+    HIPCHECK(launch_sipg(L.t2, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, s));
+    HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
+    HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del, nullptr,
+                               0, s));
+    auto once = [&]() {
+      switch (kernel) {
+        case SISDC_K_SIPG_APPLY:
+          HIPCHECK(launch_sipg_apply(L.cz, L.t1, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
+                                     h->done_gen, id, s));
+          break;
+        case SISDC_K_SIPG_TRACE: HIPCHECK(launch_sipg_trace(L.cz, L.nv, cf, L.t3, L.g, L.tab, s)); break;
+        case SISDC_K_CONV: conv(h, L, x, L.t1); break;
+        default: HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, L.tab, 0, id, s));
+      }
+    };
+    once();
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) once();
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_us = 1000.0 * ms / reps;
   });
 }
 

@@ -27,8 +27,9 @@ EXPORTS = [
     "sisdc_node_coords", "sisdc_set_state", "sisdc_get_level", "sisdc_set_level",
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
-    "sisdc_apply", "sisdc_collocation_residual",
+    "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
 ]
+K_SIPG_APPLY, K_SIPG_TRACE, K_CONV, K_CG_UPDATE = 0, 1, 2, 3
 
 
 class Problem(ctypes.Structure):
@@ -87,6 +88,7 @@ def load():
         "helmholtz_solve": ([P, I, D, P, P, P, I, D, I, ctypes.POINTER(SolveStats)], I),
         "sisdc_apply": ([P, I, I, D, P, P, P, I], I),
         "sisdc_collocation_residual": ([P, I, D, P, I], I),
+        "sisdc_profile_kernel": ([P, I, I, D, I, ctypes.POINTER(D)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -279,6 +281,11 @@ class Solver:
         pa, _ = _ptr(aux)
         _check(self._lib.sisdc_apply(self.h, op, level, dt_m, px, pa, po, mem))
         return out
+
+    def profile_kernel(self, kernel, level, dt_m, reps=200):
+        us = ctypes.c_double()
+        _check(self._lib.sisdc_profile_kernel(self.h, kernel, level, dt_m, reps, ctypes.byref(us)))
+        return us.value
 
     def collocation_residual(self, level, dt, out):
         p, mem = _ptr(out, True)
