@@ -67,6 +67,7 @@ enum { SISDC_SI2 = 0, SISDC_SI1 = 1 };                 /* Sec. 3            */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
 enum { SISDC_FP64 = 0 };
+enum { SISDC_CG_AUTO = 0, SISDC_CG_MULTI_KERNEL = 1 };
 
 typedef struct {
   int dim;             /* 2 or 3                                            */
@@ -91,6 +92,11 @@ typedef struct {
   int cg_maxit;        /* iteration cap per solve                           */
   double c_tau;        /* SIPG penalty factor C_tau (tau = C_tau (P+1)^2 kappa / h) */
   int precision;       /* SISDC_FP64                                        */
+  int cg_variant;      /* SISDC_CG_AUTO: one cooperative launch per solve
+                          (pipelined PCG) when the level's elements fit on the
+                          GPU at once and rtol >= 1e-11, else the multi-kernel
+                          form; SISDC_CG_MULTI_KERNEL: always the multi-kernel
+                          form                                              */
 } sisdc_method;
 
 typedef struct {

@@ -61,6 +61,26 @@ struct CGState {
   int cap;         // partial slots per array (>= grid of the element kernels)
 };
 
+// Arguments of the persistent (one launch per solve) PCG kernel.  Face data
+// exchanged between workgroups and the barrier records go through
+// device-scope (L2 write-through) stores and loads; bar[64] is the abort word.
+struct PCGArgs {
+  const double* b;
+  double* x;       // in: initial guess, out: solution
+  double* fz;      // face values of the exchanged vector, 2 x [c][e][dim][side][f]
+  double* ft;      // face traces of (D grad .),      2 x [c][e][dim][side][f]
+  double* part;    // barrier records: cap records of 8 doubles, then the broadcast record
+  unsigned* bar;
+  CGRes* res;      // result record of this solve
+  double tol2;
+  double dtm;
+  double ctau;
+  int maxit;
+  int cap;
+  long spin_limit; // polls before a barrier gives up (abort, no hang)
+  double epoch0;   // first barrier epoch of this launch (never reused)
+};
+
 // Up to 8 vectors combined node-wise: out = sum_j c_j (m_j ? Jw : 1) x_j.
 struct LinComb {
   const double* x[8];

@@ -37,6 +37,12 @@ hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim,
                                  const double* A, hipStream_t s);
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
                             hipStream_t s);
+// Persistent PCG: one cooperative launch per solve (pcg_persistent.hip).
+// Fails with hipErrorCooperativeLaunchTooLarge when the level's tiles exceed
+// max_blocks (co-resident workgroups) or the partial-sum capacity.
+hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
+                                 int max_blocks, hipStream_t s);
+int pcg_persistent_blocks_per_cu(const Geo& g, int nv);
 int elem_tile_count(const Geo& g);
 int reduce_grid(const Geo& g);
 

@@ -1,0 +1,494 @@
+// Persistent Jacobi-PCG for levels whose elements fit on the GPU at once:
+// one cooperative launch per Helmholtz solve (M + dt_m K_D) x = b.
+//
+// Every workgroup owns one tile of EPB elements for the whole solve; a
+// thread owns one node and keeps the CG vectors and the Jacobi diagonal in
+// registers.  The iteration is the pipelined form of preconditioned CG
+// (Ghysels & Vanroose): the global reduction of (r,u), (w,u), (r,r) travels
+// with the face data of m = diag^-1 w, so each iteration needs ONE grid
+// barrier.  The only data that leave a workgroup are the face values and
+// face traces (D grad m) of its elements and three partial sums; they are
+// written with device-scope stores and read with device-scope loads (both go
+// through to the point of coherence; no L2 write-back is needed).  When the
+// recurred residual meets the tolerance the true residual b - A x is
+// computed; if it misses the tolerance (the recurrences drifted), r, u and w
+// are replaced by their true values and the iteration continues.  The
+// recurrences of the pipelined form lose accuracy near 1e-12, so the host
+// uses this solver for tolerances >= 1e-11 only.
+//
+// The grid barrier is an all-gather of per-workgroup records (no atomics,
+// one writer per word) with bounded spins: a barrier that does
+// not complete within spin_limit polls sets the abort word and every
+// workgroup leaves, so the kernel always ends.
+//
+// Convergence decisions are made by every workgroup from the same partial
+// sums summed in the same order, so all workgroups take the same branch.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace sisdc {
+
+namespace {
+
+template <int DIM, int P>
+struct PT {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+  static constexpr int NF = DIM == 2 ? N1 : N1 * N1;
+  static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
+  static constexpr int NT = ((EPB * NP + 63) / 64) * 64;
+  static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
+};
+
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wsum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// All-gather grid barrier with reduction (epoch = a number never used before
+// on these records).  Each workgroup stores its K block sums and then the
+// epoch in its own 64-byte record; then every workgroup waits for all records
+// to carry the epoch and sums them in workgroup order (thread t takes records
+// t, t + blockDim, ...; the same shuffle and LDS order everywhere), so all
+// workgroups obtain the same bits.  No atomics: every word has one writer.
+// The stores a workgroup issued before the barrier (face data) complete
+// before its record is written, so after the barrier every workgroup sees
+// them.  Bounded spins: returns false (and sets the abort word) when a wait
+// exceeds spin_limit polls.
+template <int K>
+__device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], double* rec, unsigned* abort_w, double epoch,
+                            long spin_limit, int* s_ok) {
+  static_assert(K >= 1 && K <= 6, "a record holds up to 6 values");
+  __shared__ double sred[K][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int k = 0; k < K; ++k) {
+    const double x = wsum(v[k]);
+    if (lane == 0) sred[k][wid] = x;
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* my = rec + 8 * (long)blockIdx.x;
+    for (int k = 0; k < K; ++k) {
+      double sb = 0.0;
+      for (int w = 0; w < nw; ++w) sb += sred[k][w];
+      st_dev(&my[k], sb);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    st_dev(&my[7], epoch);
+    *s_ok = 1;
+  }
+  __syncthreads();
+  double acc[K];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  int ok = 1;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+    const double* rb = rec + 8 * (long)b;
+    long spins = 0;
+    while (ld_dev(&rb[7]) != epoch) {
+      if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > spin_limit) {
+        __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) break;
+    for (int k = 0; k < K; ++k) acc[k] += ld_dev(&rb[k]);
+  }
+  if (!ok) *s_ok = 0;  // benign race: every writer stores 0
+  for (int k = 0; k < K; ++k) {
+    const double x = wsum(acc[k]);
+    if (lane == 0) sred[k][wid] = x;
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    double sb = 0.0;
+    for (int w = 0; w < nw; ++w) sb += sred[k][w];
+    tot[k] = sb;
+  }
+  const bool res = *s_ok != 0;
+  __syncthreads();
+  return res;
+}
+
+__device__ __forceinline__ int nbr(const Geo& g, int e, int d, int s) {
+  int c[3];
+  c[0] = e % g.ne[0];
+  c[1] = (e / g.ne[0]) % g.ne[1];
+  c[2] = g.dim == 3 ? e / (g.ne[0] * g.ne[1]) : 0;
+  c[d] += s;
+  if (c[d] < 0) c[d] += g.ne[d];
+  if (c[d] >= g.ne[d]) c[d] -= g.ne[d];
+  return c[0] + g.ne[0] * (c[1] + g.ne[1] * c[2]);
+}
+
+template <int DIM, int N1>
+__device__ __forceinline__ int fidx(int d, const int (&i)[3]) {
+  if (DIM == 2) return i[1 - d];
+  return d == 0 ? i[1] + N1 * i[2] : (d == 1 ? i[0] + N1 * i[2] : i[0] + N1 * i[1]);
+}
+
+}  // namespace
+
+template <int DIM, int P, int NV>
+__global__ void __launch_bounds__((PT<DIM, P>::NT))
+k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
+  using L = PT<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sx[NV * EPB * NP];
+  __shared__ double sQ[EPB * DIM * NP];
+  __shared__ double sc[EPB * NP];
+  __shared__ int s_ok;
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  const long vs = (long)g.E * NP;
+  const long own = (long)e * NP + n;
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  ii[0] = n % N1;
+  ii[1] = (n / N1) % N1;
+  ii[2] = DIM == 3 ? n / (N1 * N1) : 0;
+  const double cw = act ? (cf.ub ? cf.c * cf.ub[own] * cf.ub[own] : cf.c) : 0.0;
+  if (act) sc[le * NP + n] = cw;
+  __syncthreads();
+  unsigned gen = 0u;  // barriers passed in this launch
+  double wn = 1.0;
+  for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  const double jw = g.J * wn;
+  const double pen = a.ctau * (double)(N1 * N1);
+
+  // neighbour coefficient D_dd at the face nodes (read-only during the solve)
+  double dnb[DIM][2];
+  for (int d = 0; d < DIM; ++d)
+    for (int side = 0; side < 2; ++side) {
+      dnb[d][side] = 0.0;
+      if (act && ii[d] == (side ? P : 0)) {
+        const int nb = nbr(g, e, d, side ? 1 : -1);
+        const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+        const long nbi = (long)nb * NP + nn;
+        const double cwn = cf.ub ? cf.c * cf.ub[nbi] * cf.ub[nbi] : cf.c;
+        dnb[d][side] = cwn * cf.v[d] * cf.v[d] + cf.nu;
+      }
+    }
+
+  // Jacobi diagonal (same formula as the multi-kernel path)
+  double dg = 1.0;
+  if (act) {
+    double kd = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const int st = L::stride(d);
+      double s = 0.0;
+      for (int k = 0; k < N1; ++k) {
+        const int nk = n + (k - ii[d]) * st;
+        const double dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + cf.nu;
+        const double wk = wn / sw[ii[d]] * sw[k];
+        s += sD[k * N1 + ii[d]] * sD[k * N1 + ii[d]] * wk * dd;
+      }
+      kd += g.rh2[d] * g.rh2[d] * g.J * s;
+    }
+    for (int d = 0; d < DIM; ++d)
+      for (int side = 0; side < 2; ++side) {
+        if (ii[d] != (side ? P : 0)) continue;
+        const double sgn = side ? 1.0 : -1.0;
+        const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+        const double tau = pen * fmax(dow, dnb[d][side]) * 0.5 * g.rh2[d];
+        const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+        kd += jfwf * (tau - sgn * g.rh2[d] * dow * sD[ii[d] * N1 + ii[d]]);
+      }
+    dg = jw + a.dtm * kd;
+  }
+
+  // Face data are double-buffered by barrier parity: a workgroup may publish
+  // the next vector while a slower neighbour still reads the previous one.
+  const long fsize = (long)NV * g.E * DIM * 2 * NF;
+  long fofs = 0;  // buffer of the last publish
+  // publish: stage v in LDS, store its face values and face traces
+  auto publish = [&](const double (&v)[NV]) {
+    fofs = (long)(gen & 1u) * fsize;
+    for (int c = 0; c < NV; ++c)
+      if (act) sx[(c * EPB + le) * NP + n] = v[c];
+    __syncthreads();
+    if (!act) return;
+    bool face = false;
+    for (int d = 0; d < DIM; ++d) face = face || ii[d] == 0 || ii[d] == P;
+    if (!face) return;
+    for (int c = 0; c < NV; ++c) {
+      const double* tile = &sx[(c * EPB + le) * NP];
+      double gr[DIM];
+      for (int d = 0; d < DIM; ++d) {
+        const int st = L::stride(d);
+        const double* row = &tile[n - ii[d] * st];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+        gr[d] = g.rh2[d] * s;
+      }
+      double vg = 0.0;
+      for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+      for (int d = 0; d < DIM; ++d) {
+        const bool lo = ii[d] == 0, hi = ii[d] == P;
+        if (!lo && !hi) continue;
+        const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
+        const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + fidx<DIM, N1>(d, ii);
+        if (lo) { st_dev(&a.ft[fofs + base], qd); st_dev(&a.fz[fofs + base], v[c]); }
+        if (hi) { st_dev(&a.ft[fofs + base + NF], qd); st_dev(&a.fz[fofs + base + NF], v[c]); }
+      }
+    }
+  };
+
+  // out = M v + dt_m K_D v, v staged in LDS by publish(), neighbours' face data published
+  auto apply = [&](double (&out)[NV]) {
+    for (int c = 0; c < NV; ++c) {
+      const double* tile = &sx[(c * EPB + le) * NP];
+      double r = 0.0, xo = 0.0;
+      if (act) {
+        xo = tile[n];
+        double gr[DIM];
+        for (int d = 0; d < DIM; ++d) {
+          const int st = L::stride(d);
+          const double* row = &tile[n - ii[d] * st];
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+          gr[d] = g.rh2[d] * s;
+        }
+        double vg = 0.0;
+        for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
+        double qv[DIM], Qd[DIM];
+        for (int d = 0; d < DIM; ++d) {
+          qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
+          Qd[d] = jw * qv[d];
+        }
+        for (int d = 0; d < DIM; ++d)
+          for (int side = 0; side < 2; ++side) {
+            if (ii[d] != (side ? P : 0)) continue;
+            const double sgn = side ? 1.0 : -1.0;
+            const int nb = nbr(g, e, d, side ? 1 : -1);
+            const long fb = (((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + fidx<DIM, N1>(d, ii);
+            const double xnb = ld_dev(&a.fz[fofs + fb]);
+            const double qnb = ld_dev(&a.ft[fofs + fb]);
+            const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+            const double qn = 0.5 * sgn * (qv[d] + qnb);
+            const double tau = pen * fmax(dow, dnb[d][side]) * 0.5 * g.rh2[d];
+            const double jump = xo - xnb;
+            const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+            r += jfwf * (-qn + tau * jump);
+            for (int d2 = 0; d2 < DIM; ++d2)
+              Qd[d2] -= 0.5 * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : 0.0));
+          }
+        for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
+      }
+      __syncthreads();
+      if (act) {
+        for (int d = 0; d < DIM; ++d) {
+          const int st = L::stride(d);
+          const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
+          r += g.rh2[d] * s;
+        }
+      }
+      out[c] = act ? jw * xo + a.dtm * r : 0.0;
+      __syncthreads();
+    }
+  };
+
+  // vectors of the pipelined iteration (Ghysels-Vanroose, preconditioned)
+  double x[NV], r[NV], u[NV], w[NV], m[NV], nn[NV], zv[NV], q[NV], s[NV], p[NV];
+  for (int c = 0; c < NV; ++c) {
+    x[c] = act ? a.x[c * vs + own] : 0.0;
+    zv[c] = q[c] = s[c] = p[c] = 0.0;
+  }
+  const double idg = act ? 1.0 / dg : 0.0;
+  double bb_l = 0.0;
+  for (int c = 0; c < NV; ++c) {
+    const double bi = act ? a.b[c * vs + own] : 0.0;
+    bb_l += bi * bi;
+  }
+  double* rec = a.part;
+  unsigned* abort_w = &a.bar[64];
+  double epoch = a.epoch0;
+  // barrier with K reduced values; advances the epoch and the face-buffer parity
+  auto barrier1 = [&](const double (&v)[1], double (&tt)[1]) -> bool {
+    const bool r = sync_reduce<1>(v, tt, rec, abort_w, epoch, a.spin_limit, &s_ok);
+    epoch += 1.0;
+    gen += 1u;
+    return r;
+  };
+  // r = b - A x, u = diag^-1 r, w = A u (also used to replace the residual)
+  auto true_residual = [&]() -> bool {
+    const double z1[1] = {0.0};
+    double t1[1];
+    publish(x);
+    if (!barrier1(z1, t1)) return false;
+    apply(w);
+    for (int c = 0; c < NV; ++c) {
+      const double bi = act ? a.b[c * vs + own] : 0.0;
+      r[c] = act ? bi - w[c] : 0.0;
+      u[c] = r[c] * idg;
+    }
+    publish(u);
+    if (!barrier1(z1, t1)) return false;
+    apply(w);
+    return true;
+  };
+  bool ok = true_residual();
+  double bb = -1.0, thresh = 0.0, gprev = 0.0, aprev = 0.0, rr = 0.0;
+  int it = 0, replaced = 0;
+  bool converged = false;
+  while (ok) {
+    // local (r,u), (w,u), (r,r), (b,b); m = diag^-1 w; one barrier carries
+    // the face data of m and the four sums
+    double g_l = 0.0, d_l = 0.0, r_l = 0.0;
+    for (int c = 0; c < NV; ++c) {
+      g_l += r[c] * u[c];
+      d_l += w[c] * u[c];
+      r_l += r[c] * r[c];
+      m[c] = w[c] * idg;
+    }
+    publish(m);
+    const double v4[4] = {g_l, d_l, r_l, bb < 0.0 ? bb_l : 0.0};
+    double tt[4];
+    ok = sync_reduce<4>(v4, tt, rec, abort_w, epoch, a.spin_limit, &s_ok);
+    epoch += 1.0;
+    gen += 1u;
+    if (!ok) break;
+    if (bb < 0.0) {
+      bb = tt[3];
+      thresh = a.tol2 * bb;
+    }
+    const double gi = tt[0], di = tt[1];
+    rr = tt[2];
+    if (!(rr == rr)) break;
+    if (rr <= thresh) {
+      // confirm with the true residual; replace the recurred one if it misses
+      ok = true_residual();
+      if (!ok) break;
+      double t_l = 0.0;
+      for (int c = 0; c < NV; ++c) t_l += r[c] * r[c];
+      const double v1[1] = {t_l};
+      double tr[1];
+      ok = barrier1(v1, tr);
+      if (!ok) break;
+      rr = tr[0];
+      if (rr <= thresh) { converged = true; break; }
+      // restart the recurrences from the true residual (at most 3 times)
+      if (++replaced > 3 || it >= a.maxit) break;
+      for (int c = 0; c < NV; ++c) zv[c] = q[c] = s[c] = p[c] = 0.0;
+      gprev = 0.0;
+      aprev = 0.0;
+      continue;
+    }
+    if (it >= a.maxit) break;
+    apply(nn);  // n = A m (neighbour face data published before the barrier)
+    double beta = 0.0, alpha;
+    if (gprev == 0.0) {
+      alpha = gi / di;
+    } else {
+      beta = gi / gprev;
+      alpha = gi / (di - beta * gi / aprev);
+    }
+    gprev = gi;
+    aprev = alpha;
+    for (int c = 0; c < NV; ++c) {
+      zv[c] = nn[c] + beta * zv[c];
+      q[c] = m[c] + beta * q[c];
+      s[c] = w[c] + beta * s[c];
+      p[c] = u[c] + beta * p[c];
+      x[c] += alpha * p[c];
+      r[c] -= alpha * s[c];
+      u[c] -= alpha * q[c];
+      w[c] -= alpha * zv[c];
+    }
+    ++it;
+  }
+  if (act)
+    for (int c = 0; c < NV; ++c) a.x[c * vs + own] = x[c];
+  if (blockIdx.x == 0 && t == 0) {
+    a.res->rr = rr;
+    a.res->bb = bb;
+    a.res->thresh = thresh;
+    a.res->it = it;
+    a.res->it_last = ok ? (converged ? 2 : 0) : -1;  // 2: converged, 0: not converged, -1: aborted
+  }
+}
+
+template <int DIM, int P, int NV>
+static hipError_t pcg_dim_p_nv(const PCGArgs& a, const CoefP& cf, const Geo& g, const double* tab, int max_blocks,
+                               hipStream_t s) {
+  using L = PT<DIM, P>;
+  const int nb = (g.E + L::EPB - 1) / L::EPB;
+  if (nb > max_blocks || nb > a.cap) return hipErrorCooperativeLaunchTooLarge;
+  PCGArgs aa = a;
+  CoefP cc = cf;
+  Geo gg = g;
+  const double* tt = tab;
+  void* args[] = {&aa, &cc, &gg, &tt};
+  return hipLaunchCooperativeKernel((const void*)k_pcg_persistent<DIM, P, NV>, dim3(nb), dim3(L::NT), args, 0, s);
+}
+
+template <int DIM, int P>
+static hipError_t pcg_dim_p(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
+                            int max_blocks, hipStream_t s) {
+  if (nv == 1) return pcg_dim_p_nv<DIM, P, 1>(a, cf, g, tab, max_blocks, s);
+  if (nv == DIM + 2) return pcg_dim_p_nv<DIM, P, DIM + 2>(a, cf, g, tab, max_blocks, s);
+  return hipErrorInvalidValue;
+}
+
+template <int DIM, int P, int NV>
+static int occ_dim_p_nv() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_pcg_persistent<DIM, P, NV>,
+                                                   PT<DIM, P>::NT, 0) != hipSuccess)
+    return 0;
+  return per_cu;
+}
+
+template <int DIM, int P>
+static int occ_dim_p(int nv) {
+  if (nv == 1) return occ_dim_p_nv<DIM, P, 1>();
+  if (nv == DIM + 2) return occ_dim_p_nv<DIM, P, DIM + 2>();
+  return 0;
+}
+
+#define SISDC_PDISPATCH(P_, BODY)                    \
+  switch (P_) {                                      \
+    case 1: { constexpr int PP = 1; BODY; } break;  \
+    case 2: { constexpr int PP = 2; BODY; } break;  \
+    case 3: { constexpr int PP = 3; BODY; } break;  \
+    case 4: { constexpr int PP = 4; BODY; } break;  \
+    case 5: { constexpr int PP = 5; BODY; } break;  \
+    case 6: { constexpr int PP = 6; BODY; } break;  \
+    case 7: { constexpr int PP = 7; BODY; } break;  \
+    case 8: { constexpr int PP = 8; BODY; } break;  \
+    default: break;                                  \
+  }
+
+hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
+                                 int max_blocks, hipStream_t s) {
+  if (g.dim == 2) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<2, PP>(a, nv, cf, g, tab, max_blocks, s))); }
+  if (g.dim == 3) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<3, PP>(a, nv, cf, g, tab, max_blocks, s))); }
+  return hipErrorInvalidValue;
+}
+
+int pcg_persistent_blocks_per_cu(const Geo& g, int nv) {
+  if (g.dim == 2) { SISDC_PDISPATCH(g.P, return (occ_dim_p<2, PP>(nv))); }
+  if (g.dim == 3) { SISDC_PDISPATCH(g.P, return (occ_dim_p<3, PP>(nv))); }
+  return 0;
+}
+
+}  // namespace sisdc

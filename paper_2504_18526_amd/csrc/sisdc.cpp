@@ -67,6 +67,9 @@ struct Level {
   double *b = nullptr, *y = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cs = nullptr, *cw = nullptr;
   double* trace = nullptr;
+  double* fz = nullptr;        // face values exchanged by the persistent PCG (2 buffers)
+  double* ft = nullptr;        // face traces exchanged by the persistent PCG (2 buffers)
+  bool persistent = false;     // solves run as one cooperative launch
   bool stale = true;
   double stored_dt = -1.0;
   bool has_g = false;
@@ -98,6 +101,15 @@ struct sisdc_handle {
   CGRes* hres = nullptr;       // pinned host mirror of res ...
   int* hdone = nullptr;        // ... and of done_gen
   int solve_id = 0;
+  // persistent PCG
+  double* ppart = nullptr;     // barrier records of the persistent PCG (8 x pcap + 8)
+  double epoch = 0.0;          // last barrier epoch handed out
+  int pcap = 0;
+  unsigned* bar = nullptr;     // grid barrier words
+  CGRes* ring = nullptr;       // result records of solves not yet collected
+  CGRes* hring = nullptr;      // pinned host mirror
+  int ring_n = 0;              // records in flight
+  std::vector<std::pair<int, int>> ring_meta;  // (level, maxit) per record
   double* lam_dev = nullptr;
   double* hlam = nullptr;      // pinned
   double* state = nullptr;
@@ -237,9 +249,90 @@ CGState cg_state(sisdc_handle* h, Level& L, const double* b, double* x, double r
 // Jacobi-PCG (Chronopoulos-Gear form) on M + dt_m K_D; x holds the initial
 // guess on entry.  Iterations are enqueued in batches; the host reads the
 // convergence record once per batch.
+constexpr int kRing = 2048;
+constexpr double kPersistentMinRtol = 1e-11;
+constexpr long kSpinLimit = 1L << 21;
+
+void account(sisdc_handle* h, int iters, bool converged, double rel) {
+  h->st.solves += 1;
+  h->st.cg_iters += iters;
+  h->st.cg_iters_max = std::max(h->st.cg_iters_max, iters);
+  h->st.max_rel_residual = std::max(h->st.max_rel_residual, rel);
+  if (!converged) h->st.not_converged += 1;
+}
+
+// Collect the result records of persistent solves enqueued since the last
+// collection (one stream synchronisation).
+void drain(sisdc_handle* h) {
+  if (h->ring_n == 0) return;
+  HIPCHECK(hipMemcpyAsync(h->hring, h->ring, h->ring_n * sizeof(CGRes), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  bool aborted = false, nonfinite = false;
+  for (int i = 0; i < h->ring_n; ++i) {
+    const CGRes& r = h->hring[i];
+    if (r.it_last < 0) aborted = true;
+    const bool conv = (r.it_last & 2) != 0;
+    const double rel = r.bb > 0.0 ? std::sqrt(r.rr / r.bb) : 0.0;
+    if (!std::isfinite(rel)) nonfinite = true;
+    account(h, r.it, conv, rel);
+    Level& L = h->lv[h->ring_meta[i].first];
+    L.last_iters = std::max(1, r.it);
+  }
+  h->ring_n = 0;
+  h->ring_meta.clear();
+  if (aborted) {
+    HIPCHECK(hipMemsetAsync(h->bar, 0, 512, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    for (auto& L : h->lv) L.persistent = false;
+    fail(SISDC_EDEVICE, "persistent PCG barrier timed out; persistent solves disabled for this handle");
+  }
+  if (nonfinite) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
+}
+
+bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                      double rtol, int maxit) {
+  if (h->ring_n >= kRing) drain(h);
+  PCGArgs a{};
+  a.b = b;
+  a.x = x;
+  a.fz = L.fz;
+  a.ft = L.ft;
+  a.part = h->ppart;
+  a.bar = h->bar;
+  a.res = h->ring + h->ring_n;
+  a.tol2 = rtol * rtol;
+  a.dtm = dtm;
+  a.ctau = h->ctau;
+  a.maxit = maxit;
+  a.cap = h->pcap;
+  a.spin_limit = kSpinLimit;
+  a.epoch0 = h->epoch + 1.0;
+  h->epoch += (double)(4 * maxit + 64);  // more epochs than a launch can use
+  int dev = 0, ncu = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int max_blocks = pcg_persistent_blocks_per_cu(L.g, L.nv) * ncu;
+  hipError_t e = launch_pcg_persistent(a, L.nv, cf, L.g, L.tab, max_blocks, h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    L.persistent = false;
+    return false;
+  }
+  h->ring_meta.emplace_back((int)(&L - h->lv.data()), maxit);
+  h->ring_n += 1;
+  return true;
+}
+
 sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                            double rtol, int maxit) {
   hipStream_t s = h->stream;
+  // the pipelined persistent form is used for production tolerances only
+  if (L.persistent && rtol >= kPersistentMinRtol && persistent_solve(h, L, cf, dtm, b, x, rtol, maxit)) {
+    sisdc_solve_stats r{};
+    r.iters = -1;  // collected later by drain()
+    r.converged = 1;
+    return r;
+  }
   const int id = ++h->solve_id;
   CGState cg = cg_state(h, L, b, x, rtol);
   HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dtm, h->ctau, L.g, L.tab, s));
@@ -275,11 +368,7 @@ sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dt
   r.converged = converged;
   if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
   L.last_iters = std::max(1, r.iters);
-  h->st.solves += 1;
-  h->st.cg_iters += r.iters;
-  h->st.cg_iters_max = std::max(h->st.cg_iters_max, r.iters);
-  h->st.max_rel_residual = std::max(h->st.max_rel_residual, rel);
-  if (!r.converged) h->st.not_converged += 1;
+  account(h, r.iters, r.converged, rel);
   return r;
 }
 
@@ -564,6 +653,7 @@ void do_step(sisdc_handle* h, double dt) {
   }
   Level& F = h->lv[0];
   copy_d2d(h, h->state, F.um(F.M), F.vlen);
+  drain(h);
   HIPCHECK(hipStreamSynchronize(h->stream));
 }
 
@@ -637,13 +727,15 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cs = dalloc(n);
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
+  L.fz = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
+  L.ft = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
   HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
 }
 
 void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
-                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace};
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -685,6 +777,7 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64) fail(SISDC_EINVAL, "precision");
+  if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL) fail(SISDC_EINVAL, "cg_variant");
 }
 
 // Caller pointer -> device pointer (host data staged through h->io).
@@ -774,6 +867,21 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hdone = (int*)((char*)hp + 128);
     h->hlam = (double*)((char*)hp + 192);
     h->lam_dev = dalloc(1);
+    h->pcap = 1024;
+    h->ppart = dalloc((size_t)8 * h->pcap + 8);
+    HIPCHECK(hipMemset(h->ppart, 0, ((size_t)8 * h->pcap + 8) * sizeof(double)));
+    void* pb = nullptr;
+    if (hipMalloc(&pb, 512) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->bar = (unsigned*)pb;
+    HIPCHECK(hipMemset(h->bar, 0, 512));
+    void* prr = nullptr;
+    if (hipMalloc(&prr, kRing * sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->ring = (CGRes*)prr;
+    void* hrr = nullptr;
+    if (hipHostMalloc(&hrr, kRing * sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
+    h->hring = (CGRes*)hrr;
+    for (auto& L : h->lv)
+      L.persistent = meth->cg_variant == SISDC_CG_AUTO && elem_tile_count(L.g) <= h->pcap;
     h->state = dalloc(h->lv[0].vlen);
     size_t io = 0;
     for (auto& L : h->lv) io = std::max(io, (size_t)(L.M + 1) * L.vlen);
@@ -803,6 +911,10 @@ int sisdc_destroy(sisdc_handle* h) {
   if (h->res) (void)hipFree(h->res);
   if (h->hres) (void)hipHostFree(h->hres);
   if (h->lam_dev) (void)hipFree(h->lam_dev);
+  if (h->ppart) (void)hipFree(h->ppart);
+  if (h->bar) (void)hipFree(h->bar);
+  if (h->ring) (void)hipFree(h->ring);
+  if (h->hring) (void)hipHostFree(h->hring);
   if (h->state) (void)hipFree(h->state);
   if (h->io) (void)hipFree(h->io);
   delete h;
@@ -937,6 +1049,7 @@ int sisdc_predict(sisdc_handle* h, int level, double dt, sisdc_stats* st) {
     h->st = sisdc_stats{};
     predictor(h, L, dt);
     if (level == 0) h->st.fine_sweeps += 1;
+    drain(h);
     HIPCHECK(hipStreamSynchronize(h->stream));
     if (st) *st = h->st;
   });
@@ -955,6 +1068,7 @@ int sisdc_sweep(sisdc_handle* h, int level, double dt, const double* g, int mem,
     }
     sweep(h, L, dt, L.has_g ? L.gf : nullptr);
     if (level == 0) h->st.fine_sweeps += 1;
+    drain(h);
     HIPCHECK(hipStreamSynchronize(h->stream));
     if (st) *st = h->st;
   });
@@ -967,6 +1081,7 @@ int mlsdc_vcycle(sisdc_handle* h, int top_level, double dt, sisdc_stats* st) {
     if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
     h->st = sisdc_stats{};
     vcycle(h, top_level, dt);
+    drain(h);
     HIPCHECK(hipStreamSynchronize(h->stream));
     if (st) *st = h->st;
   });
@@ -989,8 +1104,15 @@ int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_
     }
     copy_d2d(h, L.b, db, n);
     CoefP cf = coef_for(h, L, dt_m, dub);
+    h->st = sisdc_stats{};
     sisdc_solve_stats r = cg_solve(h, L, cf, dt_m, L.b, dx, rtol > 0 ? rtol : h->meth.cg_rtol,
                                    maxit > 0 ? maxit : h->meth.cg_maxit);
+    drain(h);
+    if (r.iters < 0) {
+      r.iters = (int)h->st.cg_iters;
+      r.converged = h->st.not_converged == 0;
+      r.rel_residual = h->st.max_rel_residual;
+    }
     if (mem == SISDC_MEM_HOST) dev_out(h, x, dx, n, mem);
     if (st) *st = r;
     if (!r.converged) fail(SISDC_ENOTCONV, "CG reached maxit before the tolerance");

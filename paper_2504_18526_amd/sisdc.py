@@ -20,6 +20,7 @@ EQ_CONVDIFF, EQ_BURGERS, EQ_EULER = 0, 1, 2
 SI2, SI1 = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64 = 0
+CG_AUTO, CG_MULTI_KERNEL = 0, 1
 OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT = range(8)
 
 EXPORTS = [
@@ -45,7 +46,7 @@ class Method(ctypes.Structure):
                 ("n_coarse_sweeps", ctypes.c_int), ("post_sweep", ctypes.c_int),
                 ("n_iter", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -157,7 +158,7 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4):
 
 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
-                n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64):
+                n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -172,6 +173,7 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.cg_maxit = cg_maxit
     m.c_tau = c_tau
     m.precision = precision
+    m.cg_variant = cg_variant
     return m
 
 
