@@ -66,7 +66,12 @@ typedef enum {
 enum { SISDC_SI2 = 0, SISDC_SI1 = 1 };                 /* Sec. 3            */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
-enum { SISDC_FP64 = 0 };
+enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
+       SISDC_MIXED = 1 }; /* FP32 Jacobi-PCG inside FP64 iterative refinement:
+                             the outer residual b - A x, the solution update,
+                             the node quadrature and the node updates stay
+                             FP64; operators and CG vectors of the inner
+                             solves are FP32 with FP32 accumulation        */
 enum { SISDC_CG_AUTO = 0, SISDC_CG_MULTI_KERNEL = 1 };
 
 typedef struct {
@@ -91,12 +96,14 @@ typedef struct {
   double cg_rtol;      /* relative residual ||b-Ax||_2 <= rtol ||b||_2      */
   int cg_maxit;        /* iteration cap per solve                           */
   double c_tau;        /* SIPG penalty factor C_tau (tau = C_tau (P+1)^2 kappa / h) */
-  int precision;       /* SISDC_FP64                                        */
+  int precision;       /* SISDC_FP64 or SISDC_MIXED                         */
   int cg_variant;      /* SISDC_CG_AUTO: one cooperative launch per solve
                           (pipelined PCG) when the level's elements fit on the
                           GPU at once and rtol >= 1e-11, else the multi-kernel
                           form; SISDC_CG_MULTI_KERNEL: always the multi-kernel
                           form                                              */
+  double inner_rtol;   /* SISDC_MIXED: relative tolerance of each FP32 inner
+                          solve (<= 0: 1e-5)                                */
 } sisdc_method;
 
 typedef struct {
@@ -106,6 +113,7 @@ typedef struct {
   int cg_iters_max;       /* largest iteration count of one solve           */
   int not_converged;      /* solves that hit cg_maxit                       */
   double max_rel_residual;/* largest final relative residual                */
+  int ir_rounds;          /* SISDC_MIXED: FP32 inner solves (refinement rounds) */
 } sisdc_stats;
 
 typedef struct {

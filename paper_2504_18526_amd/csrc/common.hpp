@@ -25,13 +25,16 @@ struct EqP {
   double gamma;
 };
 
-// Implicit coefficient D_ij = c w^2 v_i v_j + nu delta_ij, w = ub[node] or 1.
-struct CoefP {
-  double c;
-  double v[3];
-  double nu;
-  const double* ub;  // state the coefficient is evaluated at (nullable)
+// Implicit coefficient D_ij = c w^2 v_i v_j + nu delta_ij, w = ub[node] or 1,
+// in the arithmetic type T of the operator.
+template <typename T>
+struct CoefT {
+  T c;
+  T v[3];
+  T nu;
+  const T* ub;  // state the coefficient is evaluated at (nullable)
 };
+using CoefP = CoefT<double>;
 
 // Result record of one CG solve, written by the single block that detects
 // convergence (or by block 0 of every iteration kernel for the last state).
@@ -44,22 +47,24 @@ struct CGRes {
 };
 
 // Device work buffers of the Chronopoulos-Gear PCG (one matvec and one
-// fused reduction phase per iteration).
-struct CGState {
-  double *x, *r, *z, *p, *s, *w;
-  double* trace;   // face traces of (D grad z)
-  const double* b;
-  const double* diag;
-  double* gam;     // 3 x cap partial sums of (r, z), by iteration mod 3
-  double* rr;      // 2 x cap partial sums of (r, r), by iteration mod 2
-  double* del;     // cap partial sums of (w, z)
-  double* bbp;     // cap partial sums of (b, b)
-  double* alpha;   // 2 step lengths, by iteration mod 2
+// fused reduction phase per iteration), in the arithmetic type T.
+template <typename T>
+struct CGStateT {
+  T *x, *r, *z, *p, *s, *w;
+  T* trace;        // face traces of (D grad z)
+  const T* b;
+  const T* diag;
+  T* gam;          // 3 x cap partial sums of (r, z), by iteration mod 3
+  T* rr;           // 2 x cap partial sums of (r, r), by iteration mod 2
+  T* del;          // cap partial sums of (w, z)
+  T* bbp;          // cap partial sums of (b, b)
+  T* alpha;        // 2 step lengths, by iteration mod 2
   int* done_gen;   // id of the last solve that converged
   CGRes* res;
-  double tol2;
+  T tol2;
   int cap;         // partial slots per array (>= grid of the element kernels)
 };
+using CGState = CGStateT<double>;
 
 // Arguments of the persistent (one launch per solve) PCG kernel.  Face data
 // exchanged between workgroups and the barrier records go through

@@ -56,27 +56,28 @@ __device__ __forceinline__ int neighbour(const Geo& g, int e, int d, int s) {
 }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_sum(double x) {
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
   return x;
 }
 
 // Block-wide sums of K per-thread values; thread 0 stores them in
 // part[k][blockIdx.x].  Every thread of the block must call it.
-template <int K>
-__device__ void block_partials(const double (&v)[K], double* const (&part)[K]) {
-  __shared__ double sred[K][16];
+template <typename T, int K>
+__device__ void block_partials(const T (&v)[K], T* const (&part)[K]) {
+  __shared__ T sred[K][16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   for (int k = 0; k < K; ++k) {
-    const double x = wave_sum(v[k]);
+    const T x = wave_sum(v[k]);
     if (lane == 0) sred[k][wid] = x;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 0; k < K; ++k) {
-      double s = 0.0;
+      T s = T(0);
       for (int w = 0; w < nw; ++w) s += sred[k][w];
       part[k][blockIdx.x] = s;
     }
@@ -86,21 +87,21 @@ __device__ void block_partials(const double (&v)[K], double* const (&part)[K]) {
 // Fixed-order sums of the first n partials of each of K arrays, returned to
 // every thread of the block (the same bits in every block).  Every thread of
 // the block must call it.
-template <int K>
-__device__ void sum_partials(const double* const (&part)[K], int n, double (&tot)[K]) {
-  __shared__ double sred[K][16];
+template <typename T, int K>
+__device__ void sum_partials(const T* const (&part)[K], int n, T (&tot)[K]) {
+  __shared__ T sred[K][16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   for (int k = 0; k < K; ++k) {
-    double a = 0.0;
+    T a = T(0);
     for (int b = threadIdx.x; b < n; b += blockDim.x) a += part[k][b];
     a = wave_sum(a);
     if (lane == 0) sred[k][wid] = a;
   }
   __syncthreads();
   for (int k = 0; k < K; ++k) {
-    double s = 0.0;
+    T s = T(0);
     for (int w = 0; w < nw; ++w) s += sred[k][w];
     tot[k] = s;
   }
@@ -209,38 +210,40 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
 }
 
 // ---------------------------------------------------------------- SIPG
-__device__ __forceinline__ double coef_w2(const CoefP& cf, long idx) {
+template <typename T>
+__device__ __forceinline__ T coef_w2(const CoefT<T>& cf, long idx) {
   if (cf.ub == nullptr) return cf.c;
-  const double w = cf.ub[idx];
+  const T w = cf.ub[idx];
   return cf.c * w * w;
 }
 
 // (D grad x)_d at the face nodes of one element from its LDS tile sx,
 // stored in trace[c][e][d][side][f].
-template <int DIM, int P>
-__device__ __forceinline__ void store_trace(const double* sx, const double* sD, int n, const int (&ii)[3],
-                                            double cw, const CoefP& cf, const Geo& g, double* trace, int c,
+template <typename T, int DIM, int P>
+__device__ __forceinline__ void store_trace(const T* sx, const T* sD, int n, const int (&ii)[3],
+                                            T cw, const CoefT<T>& cf, const Geo& g, T* trace, int c,
                                             int e) {
   using L = EL<DIM, P>;
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
   constexpr int N1 = L::N1, NF = L::NF;
   bool face = false;
   for (int d = 0; d < DIM; ++d) face = face || ii[d] == 0 || ii[d] == P;
   if (!face) return;
-  double gr[DIM];
+  T gr[DIM];
   for (int d = 0; d < DIM; ++d) {
     const int st = L::stride(d);
-    const double* row = &sx[n - ii[d] * st];
-    double s = 0.0;
+    const T* row = &sx[n - ii[d] * st];
+    T s = T(0.0);
 #pragma unroll
     for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
-    gr[d] = g.rh2[d] * s;
+    gr[d] = rh2[d] * s;
   }
-  double vg = 0.0;
+  T vg = T(0.0);
   for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
   for (int d = 0; d < DIM; ++d) {
     const bool lo = ii[d] == 0, hi = ii[d] == P;
     if (!lo && !hi) continue;
-    const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
+    const T qd = cw * cf.v[d] * vg + cf.nu * gr[d];
     const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
     if (lo) trace[base] = qd;
     if (hi) trace[base + NF] = qd;
@@ -248,80 +251,84 @@ __device__ __forceinline__ void store_trace(const double* sx, const double* sD, 
 }
 
 // Pass 1 of K_D x: the face traces of (D grad x).
-template <int DIM, int P>
+template <typename T, int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_sipg_trace(const double* __restrict__ x, int nv, long vs, CoefP cf, double* __restrict__ trace, Geo g,
-             const double* __restrict__ tab) {
+k_sipg_trace(const T* __restrict__ x, int nv, long vs, CoefT<T> cf, T* __restrict__ trace, Geo g,
+             const T* __restrict__ tab) {
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
+  const T gJ = (T)g.J;
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
-  __shared__ double sD[N1 * N1];
-  __shared__ double sx[EPB * NP];
+  __shared__ T sD[N1 * N1];
+  __shared__ T sx[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   const int e = blockIdx.x * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   int ii[3];
   decomp<DIM, N1>(n, ii);
-  const double cw = act ? coef_w2(cf, (long)e * NP + n) : 0.0;
+  const T cw = act ? coef_w2(cf, (long)e * NP + n) : T(0.0);
   for (int c = 0; c < nv; ++c) {
     __syncthreads();
     if (act) sx[le * NP + n] = x[c * vs + (long)e * NP + n];
     __syncthreads();
-    if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, trace, c, e);
+    if (act) store_trace<T, DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, trace, c, e);
   }
 }
 
 // Pass 2: out = alpha M x + beta K_D x (weak SIPG).  With part != NULL the
 // block partial of (out, dotv) is stored in part[blockIdx.x].  Blocks loop
 // over tiles.  done_gen (nullable): skip when *done_gen == id.
-template <int DIM, int P>
+template <typename T, int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_sipg_apply(const double* __restrict__ x, double* __restrict__ out, int nv, long vs, CoefP cf,
-             const double* __restrict__ trace, double alpha, double beta, double ctau, Geo g,
-             const double* __restrict__ tab, const double* __restrict__ dotv, double* part,
+k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, CoefT<T> cf,
+             const T* __restrict__ trace, T alpha, T beta, T ctau, Geo g,
+             const T* __restrict__ tab, const T* __restrict__ dotv, T* part,
              const int* __restrict__ done_gen, int id) {
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
+  const T gJ = (T)g.J;
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB;
   if (done_gen != nullptr && *done_gen == id) return;
-  __shared__ double sD[N1 * N1], sw[N1];
-  __shared__ double sx[EPB * NP];
-  __shared__ double sQ[EPB * DIM * NP];
+  __shared__ T sD[N1 * N1], sw[N1];
+  __shared__ T sx[EPB * NP];
+  __shared__ T sQ[EPB * DIM * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
   int ii[3];
   decomp<DIM, N1>(n, ii);
   __syncthreads();
-  double wn = 1.0;
+  T wn = T(1.0);
   for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
-  const double jw = g.J * wn;
-  const double pen = ctau * (double)(N1 * N1);
+  const T jw = gJ * wn;
+  const T pen = ctau * (T)(N1 * N1);
   const int ntiles = (g.E + EPB - 1) / EPB;
-  double dacc = 0.0;
+  T dacc = T(0.0);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
-    const double cw = act ? coef_w2(cf, own) : 0.0;
+    const T cw = act ? coef_w2(cf, own) : T(0.0);
     for (int c = 0; c < nv; ++c) {
       __syncthreads();
       if (act) sx[le * NP + n] = x[c * vs + own];
       __syncthreads();
-      double r = 0.0, xo = 0.0;
+      T r = T(0.0), xo = T(0.0);
       if (act) {
         xo = sx[le * NP + n];
-        double gr[DIM];
+        T gr[DIM];
         for (int d = 0; d < DIM; ++d) {
           const int st = L::stride(d);
-          const double* row = &sx[le * NP + n - ii[d] * st];
-          double s = 0.0;
+          const T* row = &sx[le * NP + n - ii[d] * st];
+          T s = T(0.0);
 #pragma unroll
           for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
-          gr[d] = g.rh2[d] * s;
+          gr[d] = rh2[d] * s;
         }
-        double vg = 0.0;
+        T vg = T(0.0);
         for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
-        double qv[DIM], Qd[DIM];
+        T qv[DIM], Qd[DIM];
         for (int d = 0; d < DIM; ++d) {
           qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
           Qd[d] = jw * qv[d];
@@ -329,22 +336,22 @@ k_sipg_apply(const double* __restrict__ x, double* __restrict__ out, int nv, lon
         for (int d = 0; d < DIM; ++d) {
           for (int side = 0; side < 2; ++side) {
             if (ii[d] != (side ? P : 0)) continue;
-            const double sgn = side ? 1.0 : -1.0;
+            const T sgn = side ? T(1.0) : -T(1.0);
             const int nb = neighbour(g, e, d, side ? 1 : -1);
             const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
             const long nbi = (long)nb * NP + nn;
-            const double xnb = x[c * vs + nbi];
-            const double qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
+            const T xnb = x[c * vs + nbi];
+            const T qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
                                      face_index<DIM, N1>(d, ii)];
-            const double dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
-            const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
-            const double qn = 0.5 * sgn * (qv[d] + qnb);
-            const double tau = pen * fmax(dow, dnb) * 0.5 * g.rh2[d];
-            const double jump = xo - xnb;
-            const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+            const T dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
+            const T dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+            const T qn = T(0.5) * sgn * (qv[d] + qnb);
+            const T tau = pen * fmax(dow, dnb) * T(0.5) * rh2[d];
+            const T jump = xo - xnb;
+            const T jfwf = gJ * rh2[d] * wn / sw[ii[d]];
             r += jfwf * (-qn + tau * jump);
             for (int d2 = 0; d2 < DIM; ++d2)
-              Qd[d2] -= 0.5 * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : 0.0));
+              Qd[d2] -= T(0.5) * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : T(0.0)));
           }
         }
         for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
@@ -353,35 +360,37 @@ k_sipg_apply(const double* __restrict__ x, double* __restrict__ out, int nv, lon
       if (act) {
         for (int d = 0; d < DIM; ++d) {
           const int st = L::stride(d);
-          const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
-          double s = 0.0;
+          const T* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
+          T s = T(0.0);
 #pragma unroll
           for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
-          r += g.rh2[d] * s;
+          r += rh2[d] * s;
         }
-        const double val = alpha * jw * xo + beta * r;
+        const T val = alpha * jw * xo + beta * r;
         out[c * vs + own] = val;
         if (dotv != nullptr) dacc += val * dotv[c * vs + own];
       }
     }
   }
   if (part != nullptr) {
-    const double v1[1] = {dacc};
-    double* const pp[1] = {part};
-    block_partials<1>(v1, pp);
+    const T v1[1] = {dacc};
+    T* const pp[1] = {part};
+    block_partials<T, 1>(v1, pp);
   }
 }
 
 // Jacobi diagonal of M + dt_m K_D (volume terms with d = d' and the face
 // terms of the node itself); any positive diagonal gives the same solution.
-template <int DIM, int P>
+template <typename T, int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_helm_diag(double* __restrict__ diag, int nv, long vs, CoefP cf, double dtm, double ctau, Geo g,
-            const double* __restrict__ tab) {
+k_helm_diag(T* __restrict__ diag, int nv, long vs, CoefT<T> cf, T dtm, T ctau, Geo g,
+            const T* __restrict__ tab) {
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
+  const T gJ = (T)g.J;
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
-  __shared__ double sD[N1 * N1], sw[N1];
-  __shared__ double sc[EPB * NP];
+  __shared__ T sD[N1 * N1], sw[N1];
+  __shared__ T sc[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   const int e = blockIdx.x * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
@@ -393,35 +402,35 @@ k_helm_diag(double* __restrict__ diag, int nv, long vs, CoefP cf, double dtm, do
   if (act) sc[le * NP + n] = coef_w2(cf, own);
   __syncthreads();
   if (!act) return;
-  double wn = 1.0;
+  T wn = T(1.0);
   for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
-  double kd = 0.0;
+  T kd = T(0.0);
   for (int d = 0; d < DIM; ++d) {
     const int st = L::stride(d);
-    double s = 0.0;
+    T s = T(0.0);
     for (int k = 0; k < N1; ++k) {
       const int nk = n + (k - ii[d]) * st;
-      const double dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + cf.nu;
-      const double wk = wn / sw[ii[d]] * sw[k];
+      const T dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + cf.nu;
+      const T wk = wn / sw[ii[d]] * sw[k];
       s += sD[k * N1 + ii[d]] * sD[k * N1 + ii[d]] * wk * dd;
     }
-    kd += g.rh2[d] * g.rh2[d] * g.J * s;
+    kd += rh2[d] * rh2[d] * gJ * s;
   }
-  const double dow_c = sc[le * NP + n];
+  const T dow_c = sc[le * NP + n];
   for (int d = 0; d < DIM; ++d) {
     for (int side = 0; side < 2; ++side) {
       if (ii[d] != (side ? P : 0)) continue;
-      const double sgn = side ? 1.0 : -1.0;
+      const T sgn = side ? T(1.0) : -T(1.0);
       const int nb = neighbour(g, e, d, side ? 1 : -1);
       const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
-      const double dnb = coef_w2(cf, (long)nb * NP + nn) * cf.v[d] * cf.v[d] + cf.nu;
-      const double dow = dow_c * cf.v[d] * cf.v[d] + cf.nu;
-      const double tau = ctau * (double)(N1 * N1) * fmax(dow, dnb) * 0.5 * g.rh2[d];
-      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
-      kd += jfwf * (tau - sgn * g.rh2[d] * dow * sD[ii[d] * N1 + ii[d]]);
+      const T dnb = coef_w2(cf, (long)nb * NP + nn) * cf.v[d] * cf.v[d] + cf.nu;
+      const T dow = dow_c * cf.v[d] * cf.v[d] + cf.nu;
+      const T tau = ctau * (T)(N1 * N1) * fmax(dow, dnb) * T(0.5) * rh2[d];
+      const T jfwf = gJ * rh2[d] * wn / sw[ii[d]];
+      kd += jfwf * (tau - sgn * rh2[d] * dow * sD[ii[d] * N1 + ii[d]]);
     }
   }
-  const double val = g.J * wn + dtm * kd;
+  const T val = gJ * wn + dtm * kd;
   for (int c = 0; c < nv; ++c) diag[c * vs + own] = val;
 }
 
@@ -435,31 +444,33 @@ k_helm_diag(double* __restrict__ diag, int nv, long vs, CoefP cf, double dtm, do
 //
 // Start: r = b - A x0 (A x0 given in w), z = r / diag, traces of z; partials
 // (r,z) -> gam[0], (r,r) -> rr[0], (b,b) -> bbp.
-template <int DIM, int P>
+template <typename T, int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_cg_start(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict__ tab) {
+k_cg_start(CGStateT<T> cg, int nv, long vs, CoefT<T> cf, Geo g, const T* __restrict__ tab) {
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
+  const T gJ = (T)g.J;
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
-  __shared__ double sD[N1 * N1];
-  __shared__ double sx[EPB * NP];
+  __shared__ T sD[N1 * N1];
+  __shared__ T sx[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   int ii[3];
   decomp<DIM, N1>(n, ii);
   const int ntiles = (g.E + EPB - 1) / EPB;
-  double a[3] = {0.0, 0.0, 0.0};
+  T a[3] = {T(0.0), T(0.0), T(0.0)};
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
-    const double cw = act ? coef_w2(cf, own) : 0.0;
+    const T cw = act ? coef_w2(cf, own) : T(0.0);
     for (int c = 0; c < nv; ++c) {
       const long i = c * vs + own;
       __syncthreads();
       if (act) {
-        const double bi = cg.b[i];
-        const double ri = bi - cg.w[i];
-        const double zi = ri / cg.diag[i];
+        const T bi = cg.b[i];
+        const T ri = bi - cg.w[i];
+        const T zi = ri / cg.diag[i];
         cg.r[i] = ri;
         cg.z[i] = zi;
         sx[le * NP + n] = zi;
@@ -468,39 +479,41 @@ k_cg_start(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restric
         a[2] += bi * bi;
       }
       __syncthreads();
-      if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
+      if (act) store_trace<T, DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
     }
   }
-  double* const pp[3] = {cg.gam, cg.rr, cg.bbp};
-  block_partials<3>(a, pp);
+  T* const pp[3] = {cg.gam, cg.rr, cg.bbp};
+  block_partials<T, 3>(a, pp);
 }
 
 // Iteration `it` of the element part.  Reads the partials of g_it (gam[it%3]),
 // g_{it-1}, d_it (del), (r,r)_it (rr[it%2]); stops the solve if
 // (r,r)_it <= rtol^2 (b,b); otherwise updates p, s, x, r, z, writes the face
 // traces of the new z and the partials of g_{it+1} and (r,r)_{it+1}.
-template <int DIM, int P>
+template <typename T, int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
-k_cg_iter(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict__ tab, int it, int id,
+k_cg_iter(CGStateT<T> cg, int nv, long vs, CoefT<T> cf, Geo g, const T* __restrict__ tab, int it, int id,
           int nparts) {
+  const T rh2[3] = {(T)g.rh2[0], (T)g.rh2[1], (T)g.rh2[2]};
+  const T gJ = (T)g.J;
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
   if (*cg.done_gen == id) return;
-  __shared__ double sD[N1 * N1];
-  __shared__ double sx[EPB * NP];
+  __shared__ T sD[N1 * N1];
+  __shared__ T sx[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   int ii[3];
   decomp<DIM, N1>(n, ii);
   const int cap = cg.cap;
-  double tot[5];
+  T tot[5];
   {
-    const double* const pr[5] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.del,
+    const T* const pr[5] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.del,
                                  cg.rr + (it % 2) * cap, cg.bbp};
-    sum_partials<5>(pr, nparts, tot);
+    sum_partials<T, 5>(pr, nparts, tot);
   }
-  const double gi = tot[0], gprev = tot[1], di = tot[2], rri = tot[3], bb = tot[4];
-  const double thresh = cg.tol2 * bb;
+  const T gi = tot[0], gprev = tot[1], di = tot[2], rri = tot[3], bb = tot[4];
+  const T thresh = cg.tol2 * bb;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cg.res->rr = rri;
     cg.res->bb = bb;
@@ -514,7 +527,7 @@ k_cg_iter(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict
     }
     return;
   }
-  double beta = 0.0, alpha;
+  T beta = T(0.0), alpha;
   if (it == 0) {
     alpha = gi / di;
   } else {
@@ -523,24 +536,24 @@ k_cg_iter(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cg.alpha[it % 2] = alpha;
   const int ntiles = (g.E + EPB - 1) / EPB;
-  double a[2] = {0.0, 0.0};
+  T a[2] = {T(0.0), T(0.0)};
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
-    const double cw = act ? coef_w2(cf, own) : 0.0;
+    const T cw = act ? coef_w2(cf, own) : T(0.0);
     for (int c = 0; c < nv; ++c) {
       const long i = c * vs + own;
       __syncthreads();
       if (act) {
-        const double zi0 = cg.z[i], wi = cg.w[i];
-        const double pi = it == 0 ? zi0 : zi0 + beta * cg.p[i];
-        const double si = it == 0 ? wi : wi + beta * cg.s[i];
+        const T zi0 = cg.z[i], wi = cg.w[i];
+        const T pi = it == 0 ? zi0 : zi0 + beta * cg.p[i];
+        const T si = it == 0 ? wi : wi + beta * cg.s[i];
         cg.p[i] = pi;
         cg.s[i] = si;
         cg.x[i] += alpha * pi;
-        const double ri = cg.r[i] - alpha * si;
-        const double zi = ri / cg.diag[i];
+        const T ri = cg.r[i] - alpha * si;
+        const T zi = ri / cg.diag[i];
         cg.r[i] = ri;
         cg.z[i] = zi;
         sx[le * NP + n] = zi;
@@ -548,11 +561,11 @@ k_cg_iter(CGState cg, int nv, long vs, CoefP cf, Geo g, const double* __restrict
         a[1] += ri * ri;
       }
       __syncthreads();
-      if (act) store_trace<DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
+      if (act) store_trace<T, DIM, P>(&sx[le * NP], sD, n, ii, cw, cf, g, cg.trace, c, e);
     }
   }
-  double* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
-  block_partials<2>(a, pp);
+  T* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
+  block_partials<T, 2>(a, pp);
 }
 
 // ---------------------------------------------------------------- vectors
@@ -599,6 +612,44 @@ __global__ void k_space_transfer(const double* __restrict__ in, double* __restri
     }
     out[blk * npo + o] = s;
   }
+}
+
+// ---------------------------------------------------------------- mixed precision
+__global__ void k_cast_f(const double* __restrict__ in, float* __restrict__ out, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+// r32 = (float)(b - Ax) with FP64 partial sums of (r,r) and (b,b) per block.
+__global__ void k_resid_cast(const double* __restrict__ b, const double* __restrict__ Ax, float* __restrict__ r32,
+                             long n, double* part) {
+  double a[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double bi = b[i];
+    const double ri = bi - Ax[i];
+    r32[i] = (float)ri;
+    a[0] += ri * ri;
+    a[1] += bi * bi;
+  }
+  double* const pp[2] = {part, part + kElemCap};
+  block_partials<double, 2>(a, pp);
+}
+
+// tot[0..1] = fixed-order sums of the n partials in part and part + kElemCap.
+__global__ void k_sum2(const double* __restrict__ part, int n, double* tot) {
+  const double* const pp[2] = {part, part + kElemCap};
+  double t[2];
+  sum_partials<double, 2>(pp, n, t);
+  if (threadIdx.x == 0) {
+    tot[0] = t[0];
+    tot[1] = t[1];
+  }
+}
+
+// x += (double) e
+__global__ void k_add_f2d(double* __restrict__ x, const float* __restrict__ e, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] += (double)e[i];
 }
 
 // Per-block maxima of max_d (|v_d| + c) (Euler); reduced by k_max_partials.
@@ -698,90 +749,136 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
   SISDC_DISPATCH(g, conv_dim_p, u, out, g, q, tab, s);
 }
 
-template <int DIM, int P>
-static hipError_t trace_dim_p(const double* x, int nv, const CoefP& cf, double* trace, const Geo& g,
-                              const double* tab, hipStream_t s) {
+template <typename T, int DIM, int P>
+static hipError_t trace_dim_p(const T* x, int nv, const CoefT<T>& cf, T* trace, const Geo& g, const T* tab,
+                              hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_sipg_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, x, nv, vs, cf, trace,
-                     g, tab);
+  hipLaunchKernelGGL((k_sipg_trace<T, DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, x, nv, vs, cf,
+                     trace, g, tab);
   return hipGetLastError();
 }
 
-hipError_t launch_sipg_trace(const double* x, int nv, const CoefP& cf, double* trace, const Geo& g,
-                             const double* tab, hipStream_t s) {
-  SISDC_DISPATCH(g, trace_dim_p, x, nv, cf, trace, g, tab, s);
+template <typename T>
+static hipError_t sipg_trace_t(const T* x, int nv, const CoefT<T>& cf, T* trace, const Geo& g, const T* tab,
+                               hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (trace_dim_p<T, 2, PP>(x, nv, cf, trace, g, tab, s))); }
+  if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (trace_dim_p<T, 3, PP>(x, nv, cf, trace, g, tab, s))); }
+  return hipErrorInvalidValue;
 }
 
-template <int DIM, int P>
-static hipError_t apply_dim_p(const double* x, double* out, int nv, const CoefP& cf, const double* trace,
-                              double alpha, double beta, double ctau, const Geo& g, const double* tab,
-                              const double* dotv, double* part, const int* done_gen, int id, hipStream_t s) {
+template <typename T, int DIM, int P>
+static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta,
+                              T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen,
+                              int id, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
   const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
-  hipLaunchKernelGGL((k_sipg_apply<DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha, beta,
-                     ctau, g, tab, dotv, part, done_gen, id);
+  hipLaunchKernelGGL((k_sipg_apply<T, DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha,
+                     beta, ctau, g, tab, dotv, part, done_gen, id);
   return hipGetLastError();
 }
 
-hipError_t launch_sipg_apply(const double* x, double* out, int nv, const CoefP& cf, const double* trace,
-                             double alpha, double beta, double ctau, const Geo& g, const double* tab,
-                             const double* dotv, double* part, const int* done_gen, int id, hipStream_t s) {
-  SISDC_DISPATCH(g, apply_dim_p, x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv, part, done_gen, id, s);
+template <typename T>
+static hipError_t sipg_apply_t(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta,
+                               T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen,
+                               int id, hipStream_t s) {
+  if (g.dim == 2) {
+    SISDC_DISPATCH_P(g.P, return (apply_dim_p<T, 2, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
+                                                         part, done_gen, id, s)));
+  }
+  if (g.dim == 3) {
+    SISDC_DISPATCH_P(g.P, return (apply_dim_p<T, 3, PP>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv,
+                                                         part, done_gen, id, s)));
+  }
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_sipg(const double* x, double* out, int nv, const CoefP& cf, double* trace, double alpha,
-                       double beta, double ctau, const Geo& g, const double* tab, hipStream_t s) {
-  hipError_t e = launch_sipg_trace(x, nv, cf, trace, g, tab, s);
-  if (e != hipSuccess) return e;
-  return launch_sipg_apply(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, nullptr, nullptr, nullptr, 0, s);
-}
-
-template <int DIM, int P>
-static hipError_t diag_dim_p(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
-                             const double* tab, hipStream_t s) {
+template <typename T, int DIM, int P>
+static hipError_t diag_dim_p(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,
+                             hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_helm_diag<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf, dtm,
-                     ctau, g, tab);
+  hipLaunchKernelGGL((k_helm_diag<T, DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf,
+                     dtm, ctau, g, tab);
   return hipGetLastError();
 }
 
-hipError_t launch_helm_diag(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
-                            const double* tab, hipStream_t s) {
-  SISDC_DISPATCH(g, diag_dim_p, diag, nv, cf, dtm, ctau, g, tab, s);
+template <typename T>
+static hipError_t helm_diag_t(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,
+                              hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<T, 2, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
+  if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (diag_dim_p<T, 3, PP>(diag, nv, cf, dtm, ctau, g, tab, s))); }
+  return hipErrorInvalidValue;
 }
 
-template <int DIM, int P>
-static hipError_t cg_start_dim_p(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab,
+template <typename T, int DIM, int P>
+static hipError_t cg_start_dim_p(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,
                                  hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_cg_start<DIM, P>), dim3(std::min(elem_tiles<DIM, P>(g), kElemCap)), dim3(L::NT), 0, s, cg,
-                     nv, vs, cf, g, tab);
+  hipLaunchKernelGGL((k_cg_start<T, DIM, P>), dim3(std::min(elem_tiles<DIM, P>(g), kElemCap)), dim3(L::NT), 0, s,
+                     cg, nv, vs, cf, g, tab);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_start(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab,
-                           hipStream_t s) {
-  SISDC_DISPATCH(g, cg_start_dim_p, cg, nv, cf, g, tab, s);
+template <typename T>
+static hipError_t cg_start_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,
+                             hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (cg_start_dim_p<T, 2, PP>(cg, nv, cf, g, tab, s))); }
+  if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (cg_start_dim_p<T, 3, PP>(cg, nv, cf, g, tab, s))); }
+  return hipErrorInvalidValue;
 }
 
-template <int DIM, int P>
-static hipError_t cg_iter_dim_p(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab, int it,
-                                int id, hipStream_t s) {
+template <typename T, int DIM, int P>
+static hipError_t cg_iter_dim_p(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,
+                                int it, int id, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
   const int nb = std::min(elem_tiles<DIM, P>(g), kElemCap);
-  hipLaunchKernelGGL((k_cg_iter<DIM, P>), dim3(nb), dim3(L::NT), 0, s, cg, nv, vs, cf, g, tab, it, id, nb);
+  hipLaunchKernelGGL((k_cg_iter<T, DIM, P>), dim3(nb), dim3(L::NT), 0, s, cg, nv, vs, cf, g, tab, it, id, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_iter(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab, int it,
-                          int id, hipStream_t s) {
-  SISDC_DISPATCH(g, cg_iter_dim_p, cg, nv, cf, g, tab, it, id, s);
+template <typename T>
+static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab, int it,
+                            int id, hipStream_t s) {
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (cg_iter_dim_p<T, 2, PP>(cg, nv, cf, g, tab, it, id, s))); }
+  if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (cg_iter_dim_p<T, 3, PP>(cg, nv, cf, g, tab, it, id, s))); }
+  return hipErrorInvalidValue;
 }
+
+#define SISDC_PRECISION_LAUNCHERS(T)                                                                            \
+  hipError_t launch_sipg_trace(const T* x, int nv, const CoefT<T>& cf, T* trace, const Geo& g, const T* tab,     \
+                               hipStream_t s) {                                                                 \
+    return sipg_trace_t<T>(x, nv, cf, trace, g, tab, s);                                                        \
+  }                                                                                                             \
+  hipError_t launch_sipg_apply(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta, \
+                               T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen, \
+                               int id, hipStream_t s) {                                                         \
+    return sipg_apply_t<T>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, dotv, part, done_gen, id, s);      \
+  }                                                                                                             \
+  hipError_t launch_sipg(const T* x, T* out, int nv, const CoefT<T>& cf, T* trace, T alpha, T beta, T ctau,     \
+                         const Geo& g, const T* tab, hipStream_t s) {                                           \
+    hipError_t e = sipg_trace_t<T>(x, nv, cf, trace, g, tab, s);                                                \
+    if (e != hipSuccess) return e;                                                                              \
+    return sipg_apply_t<T>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, nullptr, nullptr, nullptr, 0, s);  \
+  }                                                                                                             \
+  hipError_t launch_helm_diag(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,    \
+                              hipStream_t s) {                                                                  \
+    return helm_diag_t<T>(diag, nv, cf, dtm, ctau, g, tab, s);                                                  \
+  }                                                                                                             \
+  hipError_t launch_cg_start(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,     \
+                             hipStream_t s) {                                                                   \
+    return cg_start_t<T>(cg, nv, cf, g, tab, s);                                                                \
+  }                                                                                                             \
+  hipError_t launch_cg_iter(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,      \
+                            int it, int id, hipStream_t s) {                                                    \
+    return cg_iter_t<T>(cg, nv, cf, g, tab, it, id, s);                                                         \
+  }
+
+SISDC_PRECISION_LAUNCHERS(double)
+SISDC_PRECISION_LAUNCHERS(float)
 
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
@@ -792,6 +889,24 @@ hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim,
                                  const double* A, hipStream_t s) {
   hipLaunchKernelGGL(k_space_transfer, dim3((unsigned)((long)nv * E)), dim3(256), 0, s, in, out, dim, n1i, n1o,
                      E, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
+                             hipStream_t s) {
+  const int nb = blocks_for(n, 256, kElemCap);
+  hipLaunchKernelGGL(k_resid_cast, dim3(nb), dim3(256), 0, s, b, Ax, r32, n, part);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, part, nb, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f2d, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, x, e, n);
   return hipGetLastError();
 }
 

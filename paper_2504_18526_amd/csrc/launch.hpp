@@ -15,26 +15,39 @@ constexpr int kElemCap = 512;
 
 hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
                        hipStream_t s);
-// face traces of (D grad x)
-hipError_t launch_sipg_trace(const double* x, int nv, const CoefP& cf, double* trace, const Geo& g,
-                             const double* tab, hipStream_t s);
-// out = alpha M x + beta K_D x from the traces of x; part != NULL stores the
-// block partials of (out, dotv); done_gen != NULL skips when *done_gen == id
-hipError_t launch_sipg_apply(const double* x, double* out, int nv, const CoefP& cf, const double* trace,
-                             double alpha, double beta, double ctau, const Geo& g, const double* tab,
-                             const double* dotv, double* part, const int* done_gen, int id, hipStream_t s);
-// trace pass + apply pass
-hipError_t launch_sipg(const double* x, double* out, int nv, const CoefP& cf, double* trace, double alpha,
-                       double beta, double ctau, const Geo& g, const double* tab, hipStream_t s);
-hipError_t launch_helm_diag(double* diag, int nv, const CoefP& cf, double dtm, double ctau, const Geo& g,
-                            const double* tab, hipStream_t s);
-hipError_t launch_cg_start(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab,
-                           hipStream_t s);
-hipError_t launch_cg_iter(const CGState& cg, int nv, const CoefP& cf, const Geo& g, const double* tab, int it,
-                          int id, hipStream_t s);
+// The SIPG and PCG launchers exist for double (FP64 path) and float (the
+// inner solves of the mixed-precision path).
+#define SISDC_DECLARE_PRECISION_LAUNCHERS(T)                                                                    \
+  /* face traces of (D grad x) */                                                                               \
+  hipError_t launch_sipg_trace(const T* x, int nv, const CoefT<T>& cf, T* trace, const Geo& g, const T* tab,     \
+                               hipStream_t s);                                                                  \
+  /* out = alpha M x + beta K_D x from the traces of x; part != NULL stores the block partials of (out, dotv); \
+     done_gen != NULL skips when *done_gen == id */                                                             \
+  hipError_t launch_sipg_apply(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta, \
+                               T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen, \
+                               int id, hipStream_t s);                                                          \
+  /* trace pass + apply pass */                                                                                 \
+  hipError_t launch_sipg(const T* x, T* out, int nv, const CoefT<T>& cf, T* trace, T alpha, T beta, T ctau,     \
+                         const Geo& g, const T* tab, hipStream_t s);                                            \
+  hipError_t launch_helm_diag(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,    \
+                              hipStream_t s);                                                                   \
+  hipError_t launch_cg_start(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,     \
+                             hipStream_t s);                                                                    \
+  hipError_t launch_cg_iter(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,      \
+                            int it, int id, hipStream_t s);
+
+SISDC_DECLARE_PRECISION_LAUNCHERS(double)
+SISDC_DECLARE_PRECISION_LAUNCHERS(float)
+
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s);
 hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
                                  const double* A, hipStream_t s);
+// mixed precision: FP64 -> FP32 copy; r32 = b - Ax with (r,r), (b,b) summed
+// into tot[0..1] (FP64); x += e
+hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);
+hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
+                             hipStream_t s);
+hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s);
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
                             hipStream_t s);
 // Persistent PCG: one cooperative launch per solve (pcg_persistent.hip).

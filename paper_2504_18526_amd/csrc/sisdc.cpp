@@ -40,6 +40,13 @@ struct Err {
 
 void fail(int code, const std::string& m) { throw Err{code, m}; }
 
+float* falloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&p, n * sizeof(float)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+  return (float*)p;
+}
+
 double* dalloc(size_t n) {
   void* p = nullptr;
   if (n == 0) n = 1;
@@ -70,6 +77,10 @@ struct Level {
   double* fz = nullptr;        // face values exchanged by the persistent PCG (2 buffers)
   double* ft = nullptr;        // face traces exchanged by the persistent PCG (2 buffers)
   bool persistent = false;     // solves run as one cooperative launch
+  // FP32 copies and work vectors of the mixed-precision inner solves
+  float* tab32 = nullptr;
+  float *ub32 = nullptr, *r32 = nullptr, *e32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
+        *cs32 = nullptr, *cw32 = nullptr, *diag32 = nullptr, *trace32 = nullptr;
   bool stale = true;
   double stored_dt = -1.0;
   bool has_g = false;
@@ -96,6 +107,10 @@ struct sisdc_handle {
   std::vector<Transfer> tr;
   double* partials = nullptr;  // CG partial sums: gam (3 cap), rr (2 cap), del, bbp (cap each)
   double* alpha = nullptr;     // 2 CG step lengths
+  float* partials32 = nullptr; // FP32 CG partial sums (7 cap)
+  float* alpha32 = nullptr;
+  double* ir_tot = nullptr;    // (r,r), (b,b) of the FP64 residual of iterative refinement
+  double* hir_tot = nullptr;   // pinned mirror
   int* done_gen = nullptr;     // id of the last converged solve
   CGRes* res = nullptr;        // device result record
   CGRes* hres = nullptr;       // pinned host mirror of res ...
@@ -223,26 +238,45 @@ void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double*
 }
 
 // ------------------------------------------------------------------ PCG
-CGState cg_state(sisdc_handle* h, Level& L, const double* b, double* x, double rtol) {
-  CGState cg{};
+// Work buffers of one precision for the multi-kernel PCG.
+template <typename T>
+struct CGBufs {
+  T *r, *z, *p, *s, *w, *diag, *trace;
+  const T* tab;
+  T* partials;
+  T* alpha;
+};
+
+CGBufs<double> bufs64(sisdc_handle* h, Level& L) {
+  return CGBufs<double>{L.cr, L.cz, L.cp, L.cs, L.cw, L.diag, L.trace, L.tab, h->partials, h->alpha};
+}
+
+CGBufs<float> bufs32(sisdc_handle* h, Level& L) {
+  return CGBufs<float>{L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32, L.tab32, h->partials32,
+                       h->alpha32};
+}
+
+template <typename T>
+CGStateT<T> cg_state(sisdc_handle* h, const CGBufs<T>& B, const T* b, T* x, double rtol) {
+  CGStateT<T> cg{};
   cg.x = x;
-  cg.r = L.cr;
-  cg.z = L.cz;
-  cg.p = L.cp;
-  cg.s = L.cs;
-  cg.w = L.cw;
-  cg.trace = L.trace;
+  cg.r = B.r;
+  cg.z = B.z;
+  cg.p = B.p;
+  cg.s = B.s;
+  cg.w = B.w;
+  cg.trace = B.trace;
   cg.b = b;
-  cg.diag = L.diag;
+  cg.diag = B.diag;
   cg.cap = kElemCap;
-  cg.gam = h->partials;
-  cg.rr = h->partials + 3 * kElemCap;
-  cg.del = h->partials + 5 * kElemCap;
-  cg.bbp = h->partials + 6 * kElemCap;
-  cg.alpha = h->alpha;
+  cg.gam = B.partials;
+  cg.rr = B.partials + 3 * kElemCap;
+  cg.del = B.partials + 5 * kElemCap;
+  cg.bbp = B.partials + 6 * kElemCap;
+  cg.alpha = B.alpha;
   cg.done_gen = h->done_gen;
   cg.res = h->res;
-  cg.tol2 = rtol * rtol;
+  cg.tol2 = (T)(rtol * rtol);
   return cg;
 }
 
@@ -323,33 +357,37 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   return true;
 }
 
-sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
-                           double rtol, int maxit) {
+// Multi-kernel Jacobi-PCG (Chronopoulos-Gear form) in precision T; x holds
+// the initial guess on entry.  Iterations are enqueued in batches; the host
+// reads the convergence record once per batch.  Returns the iterations, the
+// convergence flag and the final relative (recurred) residual.
+template <typename T>
+sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const CoefT<T>& cf, T dtm, const T* b, T* x,
+                           double rtol, int maxit, bool x_is_zero) {
   hipStream_t s = h->stream;
-  // the pipelined persistent form is used for production tolerances only
-  if (L.persistent && rtol >= kPersistentMinRtol && persistent_solve(h, L, cf, dtm, b, x, rtol, maxit)) {
-    sisdc_solve_stats r{};
-    r.iters = -1;  // collected later by drain()
-    r.converged = 1;
-    return r;
-  }
   const int id = ++h->solve_id;
-  CGState cg = cg_state(h, L, b, x, rtol);
-  HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dtm, h->ctau, L.g, L.tab, s));
-  HIPCHECK(launch_sipg(x, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, s));  // A x0
-  HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
-  HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cz, cg.del, nullptr, 0,
-                             s));
+  const T ctau = (T)h->ctau, one = (T)1;
+  CGStateT<T> cg = cg_state<T>(h, B, b, x, rtol);
+  HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
+  if (x_is_zero) {  // start from x = 0, so A x0 = 0
+    HIPCHECK(hipMemsetAsync(x, 0, L.vlen * sizeof(T), s));
+    HIPCHECK(hipMemsetAsync(B.w, 0, L.vlen * sizeof(T), s));
+  } else {
+    HIPCHECK(launch_sipg(x, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, s));  // A x0
+  }
+  HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, B.tab, s));
+  HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del, (const int*)nullptr,
+                             0, s));
   int chunk = std::max(2, L.last_iters + 1);
   int it = 0;
   bool converged = false;
   while (true) {
     const int stop = std::min(maxit + 1, it + chunk);  // iteration kernel `it` checks the residual after it updates
     for (; it < stop; ++it) {
-      HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, L.tab, it, id, s));
+      HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
       if (it < maxit)
-        HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, L.cz, cg.del,
-                                   h->done_gen, id, s));
+        HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
+                                   (const int*)h->done_gen, id, s));
     }
     HIPCHECK(hipMemcpyAsync(h->hres, h->res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(h->hdone, h->done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -368,7 +406,74 @@ sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dt
   r.converged = converged;
   if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
   L.last_iters = std::max(1, r.iters);
-  account(h, r.iters, r.converged, rel);
+  return r;
+}
+
+CoefT<float> coef32(sisdc_handle* h, Level& L, const CoefP& cf) {
+  CoefT<float> c{};
+  c.c = (float)cf.c;
+  for (int d = 0; d < 3; ++d) c.v[d] = (float)cf.v[d];
+  c.nu = (float)cf.nu;
+  c.ub = nullptr;
+  if (cf.ub) {
+    HIPCHECK(launch_cast_f(cf.ub, L.ub32, L.vs, h->stream));  // the coefficient state is one scalar field
+    c.ub = L.ub32;
+  }
+  return c;
+}
+
+// Mixed precision (FP64 iterative refinement around FP32 PCG):
+//   r = b - A x (FP64); stop when ||r|| <= rtol ||b||; solve A e = r in FP32
+//   to a relative tolerance max(inner_rtol, rtol ||b|| / (2 ||r||)); x += e.
+sisdc_solve_stats mixed_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                              double rtol, int maxit) {
+  hipStream_t s = h->stream;
+  const CoefT<float> cf32 = coef32(h, L, cf);
+  CGBufs<float> B = bufs32(h, L);
+  sisdc_solve_stats out{};
+  int total = 0, rounds = 0;
+  double rel = 0.0;
+  bool converged = false;
+  const double inner = h->meth.inner_rtol > 0.0 ? h->meth.inner_rtol : 1e-5;
+  while (true) {
+    HIPCHECK(launch_sipg(x, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, s));
+    HIPCHECK(launch_resid_cast(b, L.cw, L.r32, L.vlen, h->partials, h->ir_tot, s));
+    HIPCHECK(hipMemcpyAsync(h->hir_tot, h->ir_tot, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double rr = h->hir_tot[0], bb = h->hir_tot[1];
+    rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
+    if (rr <= rtol * rtol * bb) {
+      converged = true;
+      break;
+    }
+    if (total >= maxit || rounds >= 20) break;
+    const double tol_in = std::max(inner, 0.5 * rtol * std::sqrt(bb / rr));
+    sisdc_solve_stats ri = cg_multi<float>(h, L, B, cf32, (float)dtm, L.r32, L.e32, tol_in, maxit - total, true);
+    total += ri.iters;
+    rounds += 1;
+    HIPCHECK(launch_add_f2d(x, L.e32, L.vlen, s));
+  }
+  out.iters = total;
+  out.converged = converged;
+  out.rel_residual = rel;
+  h->st.ir_rounds += rounds;
+  account(h, total, converged, rel);
+  return out;
+}
+
+sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                           double rtol, int maxit) {
+  if (h->meth.precision == SISDC_MIXED) return mixed_solve(h, L, cf, dtm, b, x, rtol, maxit);
+  // the pipelined persistent form is used for production tolerances only
+  if (L.persistent && rtol >= kPersistentMinRtol && persistent_solve(h, L, cf, dtm, b, x, rtol, maxit)) {
+    sisdc_solve_stats r{};
+    r.iters = -1;  // collected later by drain()
+    r.converged = 1;
+    return r;
+  }
+  sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, rtol, maxit, false);
+  account(h, r.iters, r.converged, r.rel_residual);
   return r;
 }
 
@@ -728,6 +833,21 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
   L.fz = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
+  if (h->meth.precision == SISDC_MIXED) {
+    std::vector<float> t32(tab.begin(), tab.end());
+    L.tab32 = falloc(t32.size());
+    HIPCHECK(hipMemcpy(L.tab32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    L.ub32 = falloc(L.vs);
+    L.r32 = falloc(n);
+    L.e32 = falloc(n);
+    L.cr32 = falloc(n);
+    L.cz32 = falloc(n);
+    L.cp32 = falloc(n);
+    L.cs32 = falloc(n);
+    L.cw32 = falloc(n);
+    L.diag32 = falloc(n);
+    L.trace32 = falloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
+  }
   L.ft = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
   HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
@@ -737,6 +857,9 @@ void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
                     L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft};
   for (double* p : ptrs)
+    if (p) (void)hipFree(p);
+  float* fptrs[] = {L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32};
+  for (float* p : fptrs)
     if (p) (void)hipFree(p);
 }
 
@@ -776,7 +899,7 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
-  if (m->precision != SISDC_FP64) fail(SISDC_EINVAL, "precision");
+  if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
   if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL) fail(SISDC_EINVAL, "cg_variant");
 }
 
@@ -852,6 +975,11 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
     for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1]);
     h->partials = dalloc((size_t)7 * kElemCap);
+    h->ir_tot = dalloc(2);
+    void* pf = nullptr;
+    if (hipMalloc(&pf, 7 * kElemCap * sizeof(float) + 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->partials32 = (float*)pf;
+    h->alpha32 = h->partials32 + 7 * kElemCap;
     h->alpha = dalloc(2);
     void* pi = nullptr;
     if (hipMalloc(&pi, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
@@ -866,6 +994,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hres = (CGRes*)hp;
     h->hdone = (int*)((char*)hp + 128);
     h->hlam = (double*)((char*)hp + 192);
+    h->hir_tot = (double*)((char*)hp + 208);
     h->lam_dev = dalloc(1);
     h->pcap = 1024;
     h->ppart = dalloc((size_t)8 * h->pcap + 8);
@@ -907,6 +1036,8 @@ int sisdc_destroy(sisdc_handle* h) {
   }
   if (h->partials) (void)hipFree(h->partials);
   if (h->alpha) (void)hipFree(h->alpha);
+  if (h->partials32) (void)hipFree(h->partials32);
+  if (h->ir_tot) (void)hipFree(h->ir_tot);
   if (h->done_gen) (void)hipFree(h->done_gen);
   if (h->res) (void)hipFree(h->res);
   if (h->hres) (void)hipHostFree(h->hres);
@@ -1171,17 +1302,17 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     lincomb(h, L, L.b, {{1.0, x}}, {1});
     HIPCHECK(hipMemsetAsync(L.t2, 0, L.vlen * sizeof(double), s));
     const int id = ++h->solve_id;
-    CGState cg = cg_state(h, L, L.b, L.t2, 0.0);
+    CGState cg = cg_state<double>(h, bufs64(h, L), L.b, L.t2, 0.0);
     HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
     HIPCHECK(launch_sipg(L.t2, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, s));
     HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
-    HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del, nullptr,
-                               0, s));
+    HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
+                               (const int*)nullptr, 0, s));
     auto once = [&]() {
       switch (kernel) {
         case SISDC_K_SIPG_APPLY:
           HIPCHECK(launch_sipg_apply(L.cz, L.t1, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
-                                     h->done_gen, id, s));
+                                     (const int*)h->done_gen, id, s));
           break;
         case SISDC_K_SIPG_TRACE: HIPCHECK(launch_sipg_trace(L.cz, L.nv, cf, L.t3, L.g, L.tab, s)); break;
         case SISDC_K_CONV: conv(h, L, x, L.t1); break;

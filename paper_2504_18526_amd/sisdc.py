@@ -19,7 +19,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 EQ_CONVDIFF, EQ_BURGERS, EQ_EULER = 0, 1, 2
 SI2, SI1 = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
-FP64 = 0
+FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL = 0, 1
 OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT = range(8)
 
@@ -46,13 +46,15 @@ class Method(ctypes.Structure):
                 ("n_coarse_sweeps", ctypes.c_int), ("post_sweep", ctypes.c_int),
                 ("n_iter", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
-                ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("fine_sweeps", ctypes.c_int), ("solves", ctypes.c_int),
                 ("cg_iters", ctypes.c_longlong), ("cg_iters_max", ctypes.c_int),
-                ("not_converged", ctypes.c_int), ("max_rel_residual", ctypes.c_double)]
+                ("not_converged", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
+                ("ir_rounds", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -158,7 +160,8 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4):
 
 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
-                n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO):
+                n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
+                inner_rtol=0.0):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -174,6 +177,7 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.c_tau = c_tau
     m.precision = precision
     m.cg_variant = cg_variant
+    m.inner_rtol = inner_rtol
     return m
 
 

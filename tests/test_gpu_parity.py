@@ -333,3 +333,74 @@ def test_persistent_steps(S, case):
         u = stepper(u)
         sv.get_state(out)
         assert rel_l2(host(out), u) < 1e-8, (case, k)
+
+
+# ---------------------------------------------------------------- mixed precision
+# FP32 inner PCG inside FP64 iterative refinement.  With the outer FP64
+# residual driven to 1e-12 the result must match the FP64 oracle to 1e-10
+# relative L2 per solve and per step (the bar for the mixed form).
+RTOL_MIXED = 1e-12
+
+
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[5]])
+def test_mixed_solve(S, eq, dim, n, P):
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], rtol=RTOL_MIXED, precision=S.MIXED)
+    rng = np.random.default_rng(100 + P)
+    Ub = random_state(phys, lv.mesh, rng)
+    params = phys.step_params(Ub)
+    if params is not None:
+        sv.set_state(dev(Ub.ravel()))
+        sv.update_step_params()
+    dtm = 0.05
+    Dc = lv.coef(Ub, dtm, params)
+    b = rng.standard_normal(lv.shape())
+    x = dev(np.zeros(b.size))
+    st = sv.helmholtz_solve(0, dtm, dev(b.ravel()), x,
+                            coef_state=dev(Ub[:1].ravel()) if eq == "burgers" else None,
+                            rtol=RTOL_MIXED, maxit=4000)
+    assert st["converged"]
+    xg = host(x).reshape(b.shape)
+    res = b - lv.dg.helmholtz(Dc, dtm, xg)
+    assert np.linalg.norm(res) <= 1.0001 * RTOL_MIXED * np.linalg.norm(b)
+    xo = lv.solve(Dc, dtm, b, np.zeros_like(b))
+    assert rel_l2(xg, xo) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["convdiff_sl", "burgers_2l_cascade", "euler_3l_fmg"])
+def test_mixed_steps(S, case):
+    if case == "convdiff_sl":
+        args = dict(eq="convdiff", dim=2, n=(3, 4), Ps=[4], Ms=[3], n_iter=4)
+        dt = 1.686e-2
+    elif case == "burgers_2l_cascade":
+        args = dict(eq="burgers", dim=2, n=(4, 3), Ps=[8, 4], Ms=[5, 3], n_iter=3, nu=5e-3,
+                    start=S.START_CASCADE)
+        dt = 5e-3
+    else:
+        args = dict(eq="euler", dim=2, n=(4, 4), Ps=[6, 4, 2], Ms=[5, 3, 2], n_iter=2,
+                    start=S.START_FMG, lo=[0, 0], hi=[10, 10])
+        dt = 0.1
+    eq, dim = args["eq"], args["dim"]
+    phys, levels, sv = make_pair(S, eq, dim, args["n"], args["Ps"], args["Ms"], lo=args.get("lo"),
+                                 hi=args.get("hi"), nu=args.get("nu", 0.01), n_iter=args["n_iter"],
+                                 start=args.get("start", S.START_CASCADE), rtol=RTOL_MIXED,
+                                 precision=S.MIXED)
+    fine = levels[0]
+    if eq == "euler":
+        from paper_2504_18526_amd.inputs import isentropic_vortex
+        u = isentropic_vortex(fine.coords())
+    else:
+        u = smooth_state(phys, fine, np.random.default_rng(110))
+    if len(levels) == 1:
+        stepper = lambda v: osdc.sdc_step(fine, v, dt, args["n_iter"])
+    else:
+        start = {S.START_CASCADE: "cascade", S.START_FMG: "fmg"}[args["start"]]
+        ml = MLSDC(list(reversed(levels)), n_coarse=2, start=start, cycles=args["n_iter"], post_sweep=True)
+        stepper = lambda v: ml.step(v, dt)
+    sv.set_state(dev(u.ravel()))
+    out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    for k in range(2):
+        st = sv.step(dt)
+        assert st["not_converged"] == 0 and st["ir_rounds"] >= st["solves"]
+        u = stepper(u)
+        sv.get_state(out)
+        assert rel_l2(host(out), u) < 1e-10, (case, k)
