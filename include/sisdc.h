@@ -114,6 +114,8 @@ typedef struct {
   int not_converged;      /* solves that hit cg_maxit                       */
   double max_rel_residual;/* largest final relative residual                */
   int ir_rounds;          /* SISDC_MIXED: FP32 inner solves (refinement rounds) */
+  int net_guesses;        /* learned initial guesses computed               */
+  int net_rejected;       /* ... of which discarded (residual did not drop) */
 } sisdc_stats;
 
 typedef struct {
@@ -228,6 +230,42 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
  *   SISDC_K_CG_UPDATE   the CG vector update with its two dot products */
 enum { SISDC_K_SIPG_APPLY = 0, SISDC_K_SIPG_TRACE = 1, SISDC_K_CONV = 2, SISDC_K_CG_UPDATE = 3 };
 int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, int reps, double* avg_us);
+
+/* Learned initial guess of a level's Helmholtz solves: an element-local MLP
+ * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)
+ * row of the initial residual r0 = b - A x0 scaled to unit norm; its output,
+ * scaled back, corrects x0.  The corrected x0 is kept only if it lowers
+ * |b - A x0| (decided on the device; rejections are counted in the stats),
+ * and PCG always follows to the same tolerance, so the network changes the
+ * initial guess only.  Not part of the paper's method.
+ *   sisdc_net_init     allocate; weights (2u - 1) sqrt(6 / fan_in) with u from
+ *                      SplitMix64(seed) in parameter order, biases 0; Adam
+ *                      state zero.  max_batch bounds training batches and
+ *                      forward calls, max_rows the harvested rows.
+ *   sisdc_net_get_params / set_params   flat FP32 parameters: W1 (H x n), b1,
+ *                      W2 (H x H), b2, W3 (n x H), b3, row-major [out][in].
+ *   sisdc_net_forward  y = N(x) for `rows` rows; bf16 != 0 rounds weights and
+ *                      layer inputs to bfloat16 (nearest even), FP32 accumulate.
+ *   sisdc_net_train_step  one Adam step (lr, beta 0.9 / 0.999, eps 1e-8) on the
+ *                      loss 1/(2 rows) sum |N(x) - t|^2 in FP32; returns it.
+ *   sisdc_net_grad     the same loss and its gradient (flat layout), no update.
+ *   sisdc_net_harvest  on = 1: every later solve of the level appends rows
+ *                      (r0 / |r0|, (x* - x0) / |r0|) until max_rows; 0: stop;
+ *                      -1: stop and clear.  rows_out: rows held.
+ *   sisdc_net_train    epochs over the harvested rows in order, batches of
+ *                      `batch`; loss: mean loss of the last epoch.
+ *   sisdc_net_use      on = 1: apply the network before every solve.   */
+int sisdc_net_init(sisdc_handle* h, int level, int hidden, unsigned long long seed, int max_batch, int max_rows);
+int sisdc_net_get_params(sisdc_handle* h, int level, float* theta, int mem, long long* n_params);
+int sisdc_net_set_params(sisdc_handle* h, int level, const float* theta, int mem);
+int sisdc_net_forward(sisdc_handle* h, int level, const float* x, int rows, float* y, int mem, int bf16);
+int sisdc_net_train_step(sisdc_handle* h, int level, const float* x, const float* t, int rows, double lr,
+                         double* loss, int mem);
+int sisdc_net_grad(sisdc_handle* h, int level, const float* x, const float* t, int rows, float* grad,
+                   double* loss, int mem);
+int sisdc_net_harvest(sisdc_handle* h, int level, int on, int* rows_out);
+int sisdc_net_train(sisdc_handle* h, int level, int epochs, int batch, double lr, double* loss);
+int sisdc_net_use(sisdc_handle* h, int level, int on);
 
 #ifdef __cplusplus
 }

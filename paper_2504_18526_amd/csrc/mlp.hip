@@ -1,0 +1,278 @@
+// Element-local MLP of the learned PCG initial guess: GEMMs on the matrix
+// cores (FP32 MFMA for training, BF16 MFMA with FP32 accumulation for
+// inference), fused bias + ReLU epilogues, the backward pass and Adam.
+//
+// Rows are (element, component) pairs: a nodal vector [var][elem][node] is
+// already a row-major [rows x n] matrix with n = (P+1)^d.
+//
+// Network: z1 = W1 x + b1, a1 = relu(z1), z2 = W2 a1 + b2, a2 = relu(z2),
+// y = W3 a2 + b3; flat parameters W1 (H x n), b1, W2 (H x H), b2, W3 (n x H),
+// b3, row-major [out][in].
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "mlp.hpp"
+
+namespace sisdc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (relu).  op(A)(i,k) =
+// transA ? A[k*lda + i] : A[i*lda + k]; op(B)(k,j) = transB ? B[j*ldb + k] :
+// B[k*ldb + j].  One wave computes a 32 x 32 tile of C as 2 x 2 MFMA 16 x 16
+// blocks; out-of-range operands read as 0 and out-of-range results are not
+// stored.  BF16: operands rounded to bfloat16 on load, FP32 accumulation.
+//
+// MFMA operand layout (lane l of 64): 16x16x4 f32: A(row l%16, k l/16),
+// B(k l/16, col l%16); 16x16x16 bf16: A(row l%16, k 4(l/16)+i), B(k
+// 4(l/16)+i, col l%16), i = 0..3; result lane l, register j: row 4(l/16)+j,
+// col l%16.
+template <bool BF16>
+__global__ void __launch_bounds__(64)
+k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
+       int transB, float* __restrict__ C, int ldc, const float* __restrict__ bias, int relu) {
+  const int l = threadIdx.x;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  floatx4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto ldA = [&](int i, int k) -> float {
+    if (i >= M || k >= K) return 0.f;
+    return transA ? A[(long)k * lda + i] : A[(long)i * lda + k];
+  };
+  auto ldB = [&](int k, int j) -> float {
+    if (k >= K || j >= N) return 0.f;
+    return transB ? B[(long)j * ldb + k] : B[(long)k * ldb + j];
+  };
+  const int r = l % 16, q = l / 16;
+  if constexpr (!BF16) {
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      float av[2], bv[2];
+      for (int a = 0; a < 2; ++a) av[a] = ldA(i0 + 16 * a + r, k0 + q);
+      for (int b = 0; b < 2; ++b) bv[b] = ldB(k0 + q, j0 + 16 * b + r);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      shortx4 av[2], bv[2];
+      for (int a = 0; a < 2; ++a)
+        for (int t = 0; t < 4; ++t) av[a][t] = to_bf16(ldA(i0 + 16 * a + r, k0 + 4 * q + t));
+      for (int b = 0; b < 2; ++b)
+        for (int t = 0; t < 4; ++t) bv[b][t] = to_bf16(ldB(k0 + 4 * q + t, j0 + 16 * b + r));
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + 16 * a + 4 * q + jj, j = j0 + 16 * b + r;
+        if (i < M && j < N) {
+          float v = acc[a][b][jj];
+          if (bias) v += bias[j];
+          if (relu) v = fmaxf(v, 0.f);
+          C[(long)i * ldc + j] = v;
+        }
+      }
+}
+
+// dY = (Y - T) / B; per-block partial sums of (Y - T)^2
+__global__ void k_loss_grad(const float* __restrict__ Y, const float* __restrict__ T, float* __restrict__ dY, long n,
+                            float invB, double* part) {
+  __shared__ double sred[16];
+  double a = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float d = Y[i] - T[i];
+    dY[i] = d * invB;
+    a += (double)d * (double)d;
+  }
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0) sred[wid] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sred[w];
+    part[blockIdx.x] = s;
+  }
+}
+
+// dZ = dA * (Z > 0)
+__global__ void k_relu_back(const float* __restrict__ dA, const float* __restrict__ Z, float* __restrict__ dZ, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dZ[i] = Z[i] > 0.f ? dA[i] : 0.f;
+}
+
+// out[j] = sum over rows r (in order) of X[r * ld + j]
+__global__ void k_colsum(const float* __restrict__ X, int rows, int cols, int ld, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += X[(long)r * ld + j];
+  out[j] = s;
+}
+
+// Adam step k (1-based) on a flat parameter vector
+__global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+                       long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// Row norms of r (FP64) and the normalised rows as FP32: X = r / |r|.
+// One wave per row.
+__global__ void k_row_normalise(const double* __restrict__ r, int rows, int n, float* __restrict__ X,
+                                double* __restrict__ nrm) {
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const double* rr = r + (long)row * n;
+  double s = 0.0;
+  for (int k = lane; k < n; k += 64) s += rr[k] * rr[k];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const double nr = sqrt(s);
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int k = lane; k < n; k += 64) X[(long)row * n + k] = (float)(rr[k] * inv);
+  if (lane == 0) nrm[row] = nr;
+}
+
+// xnew = x + |r_row| * Y  (the network's correction, scaled back)
+__global__ void k_guess_update(const double* __restrict__ x, const float* __restrict__ Y, const double* __restrict__ nrm,
+                               int rows, int n, double* __restrict__ xnew) {
+  const long tot = (long)rows * n;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x)
+    xnew[i] = x[i] + nrm[i / n] * (double)Y[i];
+}
+
+// keep the guess only if it lowered the residual: tot_old[0] = |b - A x|^2,
+// tot_new[0] = |b - A xnew|^2; count rejections in *rejected
+__global__ void k_guess_select(double* __restrict__ x, const double* __restrict__ xnew, long n,
+                               const double* __restrict__ tot_old, const double* __restrict__ tot_new, int* rejected) {
+  const bool take = tot_new[0] < tot_old[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !take) rejected[0] += 1;
+  if (!take) return;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = xnew[i];
+}
+
+// harvest rows: X[row] = r0_row / |r0_row|, T[row] = (x - x0)_row / |r0_row|
+__global__ void k_harvest(const double* __restrict__ r0, const double* __restrict__ x, const double* __restrict__ x0,
+                          const double* __restrict__ nrm, int rows, int n, float* __restrict__ X,
+                          float* __restrict__ T) {
+  const long tot = (long)rows * n;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+    const double nr = nrm[i / n];
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    X[i] = (float)(r0[i] * inv);
+    T[i] = (float)((x[i] - x0[i]) * inv);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int gblocks(long n) {
+  long b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int transA, const float* B, int ldb, int transB,
+                       float* C, int ldc, const float* bias, int relu, int bf16, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((N + 31) / 32, (M + 31) / 32);
+  if (bf16)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(64), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias, relu);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(64), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
+                       relu);
+  return hipGetLastError();
+}
+
+// Forward pass of `rows` rows: Z1, A1, Z2, A2 (each rows x H) and Y (rows x n)
+hipError_t mlp_forward(const MlpShape& sh, const float* theta, const float* X, int rows, float* Z1, float* A1,
+                       float* Z2, float* A2, float* Y, int bf16, hipStream_t s) {
+  const int n = sh.n, H = sh.H;
+  const float *W1 = theta, *b1 = W1 + (long)H * n, *W2 = b1 + H, *b2 = W2 + (long)H * H, *W3 = b2 + H,
+              *b3 = W3 + (long)n * H;
+  hipError_t e;
+  if (Z1) {
+    if ((e = launch_gemm(rows, H, n, X, n, 0, W1, n, 1, Z1, H, b1, 0, bf16, s)) != hipSuccess) return e;
+    if ((e = launch_gemm(rows, H, n, X, n, 0, W1, n, 1, A1, H, b1, 1, bf16, s)) != hipSuccess) return e;
+    if ((e = launch_gemm(rows, H, H, A1, H, 0, W2, H, 1, Z2, H, b2, 0, bf16, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_gemm(rows, H, n, X, n, 0, W1, n, 1, A1, H, b1, 1, bf16, s)) != hipSuccess) return e;
+  }
+  if ((e = launch_gemm(rows, H, H, A1, H, 0, W2, H, 1, A2, H, b2, 1, bf16, s)) != hipSuccess) return e;
+  return launch_gemm(rows, n, H, A2, H, 0, W3, H, 1, Y, n, b3, 0, bf16, s);
+}
+
+// Loss partials, gradient into g (flat, same layout as theta); work buffers
+// dY (rows x n), dA, dZ (rows x H).  FP32 throughout.
+hipError_t mlp_backward(const MlpShape& sh, const float* theta, const float* X, const float* T, int rows,
+                        const float* Z1, const float* A1, const float* Z2, const float* A2, const float* Y, float* dY,
+                        float* dA, float* dZ, float* g, double* loss_part, hipStream_t s) {
+  const int n = sh.n, H = sh.H;
+  const float *W2 = theta + (long)H * n + H, *W3 = W2 + (long)H * H + H;
+  float *dW1 = g, *db1 = dW1 + (long)H * n, *dW2 = db1 + H, *db2 = dW2 + (long)H * H, *dW3 = db2 + H,
+        *db3 = dW3 + (long)n * H;
+  const long ny = (long)rows * n, nh = (long)rows * H;
+  hipLaunchKernelGGL(k_loss_grad, dim3(64), dim3(256), 0, s, Y, T, dY, ny, 1.f / rows, loss_part);
+  hipError_t e;
+  if ((e = launch_gemm(n, H, rows, dY, n, 1, A2, H, 0, dW3, H, nullptr, 0, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256), dim3(256), 0, s, dY, rows, n, n, db3);
+  if ((e = launch_gemm(rows, H, n, dY, n, 0, W3, H, 0, dA, H, nullptr, 0, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relu_back, dim3(gblocks(nh)), dim3(256), 0, s, dA, Z2, dZ, nh);
+  if ((e = launch_gemm(H, H, rows, dZ, H, 1, A1, H, 0, dW2, H, nullptr, 0, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ, rows, H, H, db2);
+  if ((e = launch_gemm(rows, H, H, dZ, H, 0, W2, H, 0, dA, H, nullptr, 0, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_relu_back, dim3(gblocks(nh)), dim3(256), 0, s, dA, Z1, dZ, nh);
+  if ((e = launch_gemm(H, n, rows, dZ, H, 1, X, n, 0, dW1, n, nullptr, 0, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dZ, rows, H, H, db1);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* th, float* m, float* v, const float* g, long n, float lr, int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(gblocks(n)), dim3(256), 0, s, th, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_normalise(const double* r, int rows, int n, float* X, double* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, r, rows, n, X, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_guess_update(const double* x, const float* Y, const double* nrm, int rows, int n, double* xnew,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_update, dim3(gblocks((long)rows * n)), dim3(256), 0, s, x, Y, nrm, rows, n, xnew);
+  return hipGetLastError();
+}
+
+hipError_t launch_guess_select(double* x, const double* xnew, long n, const double* tot_old, const double* tot_new,
+                               int* rejected, hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_select, dim3(gblocks(n)), dim3(256), 0, s, x, xnew, n, tot_old, tot_new, rejected);
+  return hipGetLastError();
+}
+
+hipError_t launch_harvest(const double* r0, const double* x, const double* x0, const double* nrm, int rows, int n,
+                          float* X, float* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_harvest, dim3(gblocks((long)rows * n)), dim3(256), 0, s, r0, x, x0, nrm, rows, n, X, T);
+  return hipGetLastError();
+}
+
+}  // namespace sisdc

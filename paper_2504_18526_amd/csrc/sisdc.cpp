@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,6 +20,7 @@
 #include "../../include/sisdc.h"
 #include "common.hpp"
 #include "launch.hpp"
+#include "mlp.hpp"
 #include "tables.hpp"
 
 using namespace sisdc;
@@ -81,6 +83,23 @@ struct Level {
   float* tab32 = nullptr;
   float *ub32 = nullptr, *r32 = nullptr, *e32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
         *cs32 = nullptr, *cw32 = nullptr, *diag32 = nullptr, *trace32 = nullptr;
+  // learned initial guess (element-local MLP), see sisdc_net_*
+  struct Net {
+    bool on = false;          // initialised
+    bool use = false;         // apply before every solve of this level
+    bool harvest = false;     // record (r0, x* - x0) rows of every solve
+    MlpShape sh{};
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    int max_batch = 0, max_rows = 0, rows = 0, step = 0;
+    float *Xd = nullptr, *Td = nullptr;                          // harvested rows
+    float *Z1 = nullptr, *A1 = nullptr, *Z2 = nullptr, *A2 = nullptr, *Y = nullptr, *dY = nullptr,
+          *dA = nullptr, *dZ = nullptr;                          // training work (max_batch rows)
+    float *Xi = nullptr, *A1i = nullptr, *A2i = nullptr, *Yi = nullptr;  // inference work (E * nv rows)
+    double *nrm = nullptr, *xnew = nullptr, *x0h = nullptr, *r0h = nullptr;
+    float *Xs = nullptr, *Ts = nullptr;                          // staging of caller rows
+    double* lossp = nullptr;                                     // loss partials, 64 per batch
+    int loss_cap = 0;                                            // batches the loss buffer holds
+  } net;
   bool stale = true;
   double stored_dt = -1.0;
   bool has_g = false;
@@ -110,6 +129,10 @@ struct sisdc_handle {
   float* partials32 = nullptr; // FP32 CG partial sums (7 cap)
   float* alpha32 = nullptr;
   double* ir_tot = nullptr;    // (r,r), (b,b) of the FP64 residual of iterative refinement
+  double* gtot = nullptr;      // residual norms before / after a learned guess (2 x 2)
+  int* nrej = nullptr;         // learned guesses rejected (device counter)
+  int* hnrej = nullptr;        // pinned mirror
+  int nrej_seen = 0;
   double* hir_tot = nullptr;   // pinned mirror
   int* done_gen = nullptr;     // id of the last converged solve
   CGRes* res = nullptr;        // device result record
@@ -297,7 +320,15 @@ void account(sisdc_handle* h, int iters, bool converged, double rel) {
 
 // Collect the result records of persistent solves enqueued since the last
 // collection (one stream synchronisation).
+void drain_rejections(sisdc_handle* h) {
+  HIPCHECK(hipMemcpyAsync(h->hnrej, h->nrej, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->st.net_rejected += *h->hnrej - h->nrej_seen;
+  h->nrej_seen = *h->hnrej;
+}
+
 void drain(sisdc_handle* h) {
+  if (h->st.net_guesses > 0) drain_rejections(h);
   if (h->ring_n == 0) return;
   HIPCHECK(hipMemcpyAsync(h->hring, h->ring, h->ring_n * sizeof(CGRes), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
@@ -462,8 +493,66 @@ sisdc_solve_stats mixed_solve(sisdc_handle* h, Level& L, const CoefP& cf, double
   return out;
 }
 
+// ------------------------------------------------------------------ learned guess
+// r = b - A x into out (FP64), with (r,r), (b,b) into tot[0..1] on the device
+void residual64(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, const double* x, double* out,
+                double* tot) {
+  HIPCHECK(launch_sipg(x, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, h->stream));
+  if (out) lincomb(h, L, out, {{1.0, b}, {-1.0, L.cw}});
+  if (tot) {
+    if (!L.r32) fail(SISDC_EDEVICE, "internal: FP32 staging missing");
+    HIPCHECK(launch_resid_cast(b, L.cw, L.r32, L.vlen, h->partials, tot, h->stream));
+  }
+}
+
+// x0 <- x0 + |r0_row| N(r0_row / |r0_row|) for every (element, component)
+// row, kept only if |b - A x0| decreases (decided on the device).
+void learned_guess(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x) {
+  auto& N = L.net;
+  hipStream_t s = h->stream;
+  const int rows = L.nv * L.E;
+  residual64(h, L, cf, dtm, b, x, N.r0h, h->gtot);
+  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, N.Xi, N.nrm, s));
+  HIPCHECK(mlp_forward(N.sh, N.theta, N.Xi, rows, nullptr, N.A1i, nullptr, N.A2i, N.Yi, 1, s));
+  HIPCHECK(launch_guess_update(x, N.Yi, N.nrm, rows, L.np, N.xnew, s));
+  residual64(h, L, cf, dtm, b, N.xnew, nullptr, h->gtot + 2);
+  HIPCHECK(launch_guess_select(x, N.xnew, L.vlen, h->gtot, h->gtot + 2, h->nrej, s));
+  h->st.net_guesses += 1;
+}
+
+// record r0 = b - A x0 and x0 before a solve (harvest)
+void harvest_before(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, const double* x) {
+  auto& N = L.net;
+  residual64(h, L, cf, dtm, b, x, N.r0h, nullptr);
+  copy_d2d(h, N.x0h, x, L.vlen);
+}
+
+// append the rows (r0 / |r0|, (x* - x0) / |r0|) of the finished solve
+void harvest_after(sisdc_handle* h, Level& L, const double* x) {
+  auto& N = L.net;
+  const int rows = L.nv * L.E;
+  if (N.rows + rows > N.max_rows) return;
+  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, N.Xi, N.nrm, h->stream));
+  HIPCHECK(launch_harvest(N.r0h, x, N.x0h, N.nrm, rows, L.np, N.Xd + (long)N.rows * L.np, N.Td + (long)N.rows * L.np,
+                          h->stream));
+  N.rows += rows;
+}
+
+sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                                double rtol, int maxit);
+
 sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                            double rtol, int maxit) {
+  const bool harvest = L.net.on && L.net.harvest && L.net.rows < L.net.max_rows;
+  if (harvest) harvest_before(h, L, cf, dtm, b, x);
+  if (L.net.on && L.net.use) learned_guess(h, L, cf, dtm, b, x);
+  sisdc_solve_stats r = cg_solve_core(h, L, cf, dtm, b, x, rtol, maxit);
+  if (harvest) harvest_after(h, L, x);
+  return r;
+}
+
+sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                                double rtol, int maxit) {
   if (h->meth.precision == SISDC_MIXED) return mixed_solve(h, L, cf, dtm, b, x, rtol, maxit);
   // the pipelined persistent form is used for production tolerances only
   if (L.persistent && rtol >= kPersistentMinRtol && persistent_solve(h, L, cf, dtm, b, x, rtol, maxit)) {
@@ -833,12 +922,12 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
   L.fz = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
+  L.r32 = falloc(n);  // FP32 staging of residuals (mixed solves, learned guess)
   if (h->meth.precision == SISDC_MIXED) {
     std::vector<float> t32(tab.begin(), tab.end());
     L.tab32 = falloc(t32.size());
     HIPCHECK(hipMemcpy(L.tab32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
     L.ub32 = falloc(L.vs);
-    L.r32 = falloc(n);
     L.e32 = falloc(n);
     L.cr32 = falloc(n);
     L.cz32 = falloc(n);
@@ -858,7 +947,13 @@ void free_level(Level& L) {
                     L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
-  float* fptrs[] = {L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32};
+  float* fptrs[] = {L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32,
+                    L.net.theta, L.net.m, L.net.v, L.net.g, L.net.Xd, L.net.Td, L.net.Z1, L.net.A1, L.net.Z2,
+                    L.net.A2, L.net.Y, L.net.dY, L.net.dA, L.net.dZ, L.net.Xi, L.net.A1i, L.net.A2i, L.net.Yi,
+                    L.net.Xs, L.net.Ts};
+  double* dptrs[] = {L.net.nrm, L.net.xnew, L.net.x0h, L.net.r0h, L.net.lossp};
+  for (double* p : dptrs)
+    if (p) (void)hipFree(p);
   for (float* p : fptrs)
     if (p) (void)hipFree(p);
 }
@@ -946,6 +1041,47 @@ int guard(F&& f) {
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------------ network helpers
+// SplitMix64 (Vigna): k-th output of the generator seeded with `seed`.
+uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void net_free(Level& L) {
+  auto& N = L.net;
+  float* f[] = {N.theta, N.m, N.v, N.g, N.Xd, N.Td, N.Z1, N.A1, N.Z2, N.A2, N.Y, N.dY, N.dA, N.dZ, N.Xi, N.A1i,
+                N.A2i, N.Yi, N.Xs, N.Ts};
+  for (float* p : f)
+    if (p) (void)hipFree(p);
+  double* d[] = {N.nrm, N.xnew, N.x0h, N.r0h, N.lossp};
+  for (double* p : d)
+    if (p) (void)hipFree(p);
+  N = Level::Net{};
+}
+
+// one Adam step on rows X, T (device, FP32); loss partials into lossp
+void net_train_batch(sisdc_handle* h, Level& L, const float* X, const float* T, int rows, double lr, double* lossp) {
+  auto& N = L.net;
+  hipStream_t s = h->stream;
+  HIPCHECK(mlp_forward(N.sh, N.theta, X, rows, N.Z1, N.A1, N.Z2, N.A2, N.Y, 0, s));
+  HIPCHECK(mlp_backward(N.sh, N.theta, X, T, rows, N.Z1, N.A1, N.Z2, N.A2, N.Y, N.dY, N.dA, N.dZ, N.g, lossp, s));
+  N.step += 1;
+  HIPCHECK(launch_adam(N.theta, N.m, N.v, N.g, N.sh.params(), (float)lr, N.step, s));
+}
+
+Level::Net& net_of(sisdc_handle* h, int level) {
+  Level& L = level_at(h, level);
+  if (!L.net.on) fail(SISDC_ESTATE, "sisdc_net_init must come first for this level");
+  return L.net;
+}
+
+}  // namespace
+
 // ==================================================================== C ABI
 extern "C" {
 
@@ -976,6 +1112,11 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1]);
     h->partials = dalloc((size_t)7 * kElemCap);
     h->ir_tot = dalloc(2);
+    h->gtot = dalloc(4);
+    void* pn = nullptr;
+    if (hipMalloc(&pn, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->nrej = (int*)pn;
+    HIPCHECK(hipMemset(h->nrej, 0, 64));
     void* pf = nullptr;
     if (hipMalloc(&pf, 7 * kElemCap * sizeof(float) + 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
     h->partials32 = (float*)pf;
@@ -995,6 +1136,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hdone = (int*)((char*)hp + 128);
     h->hlam = (double*)((char*)hp + 192);
     h->hir_tot = (double*)((char*)hp + 208);
+    h->hnrej = (int*)((char*)hp + 240);
     h->lam_dev = dalloc(1);
     h->pcap = 1024;
     h->ppart = dalloc((size_t)8 * h->pcap + 8);
@@ -1028,7 +1170,10 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
 int sisdc_destroy(sisdc_handle* h) {
   if (!h) return SISDC_OK;
   (void)hipDeviceSynchronize();
-  for (auto& L : h->lv) free_level(L);
+  for (auto& L : h->lv) {
+    net_free(L);
+    free_level(L);
+  }
   for (auto& T : h->tr) {
     if (T.Ix) (void)hipFree(T.Ix);
     if (T.Px) (void)hipFree(T.Px);
@@ -1038,6 +1183,8 @@ int sisdc_destroy(sisdc_handle* h) {
   if (h->alpha) (void)hipFree(h->alpha);
   if (h->partials32) (void)hipFree(h->partials32);
   if (h->ir_tot) (void)hipFree(h->ir_tot);
+  if (h->gtot) (void)hipFree(h->gtot);
+  if (h->nrej) (void)hipFree(h->nrej);
   if (h->done_gen) (void)hipFree(h->done_gen);
   if (h->res) (void)hipFree(h->res);
   if (h->hres) (void)hipHostFree(h->hres);
@@ -1332,6 +1479,185 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_us = 1000.0 * ms / reps;
+  });
+}
+
+int sisdc_net_init(sisdc_handle* h, int level, int hidden, unsigned long long seed, int max_batch, int max_rows) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (hidden < 1 || max_batch < 1 || max_rows < 0) fail(SISDC_EINVAL, "hidden, max_batch >= 1, max_rows >= 0");
+    net_free(L);
+    auto& N = L.net;
+    N.sh = MlpShape{L.np, hidden};
+    N.max_batch = max_batch;
+    N.max_rows = max_rows;
+    const long P = N.sh.params();
+    const int n = L.np, H = hidden;
+    std::vector<float> th(P, 0.0f);
+    // weights (2u - 1) sqrt(6 / fan_in), u from SplitMix64; biases 0
+    long pos = 0;
+    uint64_t k = 0;
+    auto fill = [&](long cnt, int fan_in) {
+      const double sc = std::sqrt(6.0 / fan_in);
+      for (long i = 0; i < cnt; ++i) {
+        const double u = (double)(splitmix64(seed, k++) >> 11) * (1.0 / 9007199254740992.0);
+        th[pos + i] = (float)((2.0 * u - 1.0) * sc);
+      }
+      pos += cnt;
+    };
+    fill((long)H * n, n);
+    pos += H;
+    fill((long)H * H, H);
+    pos += H;
+    fill((long)n * H, H);
+    N.theta = falloc(P);
+    N.m = falloc(P);
+    N.v = falloc(P);
+    N.g = falloc(P);
+    HIPCHECK(hipMemcpy(N.theta, th.data(), P * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemset(N.m, 0, P * sizeof(float)));
+    HIPCHECK(hipMemset(N.v, 0, P * sizeof(float)));
+    const long B = max_batch, rows = (long)L.nv * L.E;
+    N.Z1 = falloc(B * H);
+    N.A1 = falloc(B * H);
+    N.Z2 = falloc(B * H);
+    N.A2 = falloc(B * H);
+    N.Y = falloc(B * n);
+    N.dY = falloc(B * n);
+    N.dA = falloc(B * H);
+    N.dZ = falloc(B * H);
+    N.Xs = falloc(B * n);
+    N.Ts = falloc(B * n);
+    N.Xi = falloc(rows * n);
+    N.A1i = falloc(rows * H);
+    N.A2i = falloc(rows * H);
+    N.Yi = falloc(rows * n);
+    N.nrm = dalloc(rows);
+    N.xnew = dalloc(L.vlen);
+    N.x0h = dalloc(L.vlen);
+    N.r0h = dalloc(L.vlen);
+    N.Xd = falloc(std::max<long>(1, (long)max_rows * n));
+    N.Td = falloc(std::max<long>(1, (long)max_rows * n));
+    N.loss_cap = std::max(1, max_rows) + 1;
+    N.lossp = dalloc((size_t)64 * N.loss_cap);
+    N.on = true;
+  });
+}
+
+int sisdc_net_get_params(sisdc_handle* h, int level, float* theta, int mem, long long* n) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    if (n) *n = N.sh.params();
+    if (!theta) return;
+    HIPCHECK(hipMemcpyAsync(theta, N.theta, N.sh.params() * sizeof(float),
+                            mem == SISDC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  });
+}
+
+int sisdc_net_set_params(sisdc_handle* h, int level, const float* theta, int mem) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    if (!theta) fail(SISDC_EINVAL, "null parameters");
+    HIPCHECK(hipMemcpyAsync(N.theta, theta, N.sh.params() * sizeof(float),
+                            mem == SISDC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  });
+}
+
+int sisdc_net_forward(sisdc_handle* h, int level, const float* X, int rows, float* Y, int mem, int bf16) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    if (!X || !Y || rows < 1 || rows > N.max_batch) fail(SISDC_EINVAL, "rows must be 1..max_batch");
+    const long cnt = (long)rows * N.sh.n;
+    const auto kin = mem == SISDC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const auto kout = mem == SISDC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIPCHECK(hipMemcpyAsync(N.Xs, X, cnt * sizeof(float), kin, h->stream));
+    HIPCHECK(mlp_forward(N.sh, N.theta, N.Xs, rows, nullptr, N.A1, nullptr, N.A2, N.Y, bf16 ? 1 : 0, h->stream));
+    HIPCHECK(hipMemcpyAsync(Y, N.Y, cnt * sizeof(float), kout, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  });
+}
+
+int sisdc_net_train_step(sisdc_handle* h, int level, const float* X, const float* T, int rows, double lr, double* loss,
+                         int mem) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    auto& N = net_of(h, level);
+    if (!X || !T || rows < 1 || rows > N.max_batch) fail(SISDC_EINVAL, "rows must be 1..max_batch");
+    const long cnt = (long)rows * N.sh.n;
+    const auto kin = mem == SISDC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIPCHECK(hipMemcpyAsync(N.Xs, X, cnt * sizeof(float), kin, h->stream));
+    HIPCHECK(hipMemcpyAsync(N.Ts, T, cnt * sizeof(float), kin, h->stream));
+    net_train_batch(h, L, N.Xs, N.Ts, rows, lr, N.lossp);
+    std::vector<double> lp(64);
+    HIPCHECK(hipMemcpyAsync(lp.data(), N.lossp, 64 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    double acc = 0.0;
+    for (double v : lp) acc += v;
+    if (loss) *loss = 0.5 * acc / rows;
+  });
+}
+
+int sisdc_net_grad(sisdc_handle* h, int level, const float* X, const float* T, int rows, float* grad, double* loss,
+                   int mem) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    if (!X || !T || !grad || rows < 1 || rows > N.max_batch) fail(SISDC_EINVAL, "rows must be 1..max_batch");
+    const long cnt = (long)rows * N.sh.n;
+    const auto kin = mem == SISDC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const auto kout = mem == SISDC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipStream_t s = h->stream;
+    HIPCHECK(hipMemcpyAsync(N.Xs, X, cnt * sizeof(float), kin, s));
+    HIPCHECK(hipMemcpyAsync(N.Ts, T, cnt * sizeof(float), kin, s));
+    HIPCHECK(mlp_forward(N.sh, N.theta, N.Xs, rows, N.Z1, N.A1, N.Z2, N.A2, N.Y, 0, s));
+    HIPCHECK(mlp_backward(N.sh, N.theta, N.Xs, N.Ts, rows, N.Z1, N.A1, N.Z2, N.A2, N.Y, N.dY, N.dA, N.dZ, N.g,
+                          N.lossp, s));
+    HIPCHECK(hipMemcpyAsync(grad, N.g, N.sh.params() * sizeof(float), kout, s));
+    std::vector<double> lp(64);
+    HIPCHECK(hipMemcpyAsync(lp.data(), N.lossp, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (double v : lp) acc += v;
+    if (loss) *loss = 0.5 * acc / rows;
+  });
+}
+
+int sisdc_net_harvest(sisdc_handle* h, int level, int on, int* rows_out) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    N.harvest = on != 0;
+    if (on < 0) N.rows = 0;  // negative: clear the harvested rows
+    if (rows_out) *rows_out = N.rows;
+  });
+}
+
+int sisdc_net_train(sisdc_handle* h, int level, int epochs, int batch, double lr, double* loss) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    auto& N = net_of(h, level);
+    if (epochs < 1 || batch < 1 || batch > N.max_batch) fail(SISDC_EINVAL, "epochs >= 1, batch in 1..max_batch");
+    if (N.rows < 1) fail(SISDC_ESTATE, "no harvested rows");
+    const int nb = (N.rows + batch - 1) / batch;
+    if (nb > N.loss_cap) fail(SISDC_EINVAL, "batch too small for the loss buffer");
+    for (int ep = 0; ep < epochs; ++ep)
+      for (int b = 0; b < nb; ++b) {
+        const int r0 = b * batch, rows = std::min(batch, N.rows - r0);
+        net_train_batch(h, L, N.Xd + (long)r0 * N.sh.n, N.Td + (long)r0 * N.sh.n, rows, lr, N.lossp + 64 * (long)b);
+      }
+    std::vector<double> lp((size_t)64 * nb);
+    HIPCHECK(hipMemcpyAsync(lp.data(), N.lossp, lp.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    double acc = 0.0;
+    for (double v : lp) acc += v;
+    if (loss) *loss = 0.5 * acc / N.rows;  // mean loss of the last epoch
+  });
+}
+
+int sisdc_net_use(sisdc_handle* h, int level, int on) {
+  return guard([&] {
+    auto& N = net_of(h, level);
+    N.use = on != 0;
   });
 }
 

@@ -29,6 +29,8 @@ EXPORTS = [
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
+    "sisdc_net_init", "sisdc_net_get_params", "sisdc_net_set_params", "sisdc_net_forward",
+    "sisdc_net_train_step", "sisdc_net_grad", "sisdc_net_harvest", "sisdc_net_train", "sisdc_net_use",
 ]
 K_SIPG_APPLY, K_SIPG_TRACE, K_CONV, K_CG_UPDATE = 0, 1, 2, 3
 
@@ -54,7 +56,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("fine_sweeps", ctypes.c_int), ("solves", ctypes.c_int),
                 ("cg_iters", ctypes.c_longlong), ("cg_iters_max", ctypes.c_int),
                 ("not_converged", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
-                ("ir_rounds", ctypes.c_int)]
+                ("ir_rounds", ctypes.c_int), ("net_guesses", ctypes.c_int), ("net_rejected", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +94,15 @@ def load():
         "sisdc_apply": ([P, I, I, D, P, P, P, I], I),
         "sisdc_collocation_residual": ([P, I, D, P, I], I),
         "sisdc_profile_kernel": ([P, I, I, D, I, ctypes.POINTER(D)], I),
+        "sisdc_net_init": ([P, I, I, ctypes.c_ulonglong, I, I], I),
+        "sisdc_net_get_params": ([P, I, P, I, ctypes.POINTER(ctypes.c_longlong)], I),
+        "sisdc_net_set_params": ([P, I, P, I], I),
+        "sisdc_net_forward": ([P, I, P, I, P, I, I], I),
+        "sisdc_net_train_step": ([P, I, P, P, I, D, ctypes.POINTER(D), I], I),
+        "sisdc_net_grad": ([P, I, P, P, I, P, ctypes.POINTER(D), I], I),
+        "sisdc_net_harvest": ([P, I, I, ctypes.POINTER(I)], I),
+        "sisdc_net_train": ([P, I, I, I, D, ctypes.POINTER(D)], I),
+        "sisdc_net_use": ([P, I, I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -121,18 +132,18 @@ def _check(rc):
         raise SisdcError(rc, lib().sisdc_last_error().decode())
 
 
-def _ptr(a, writable=False):
-    """(pointer, mem) of a torch tensor or numpy array (contiguous, float64)."""
+def _ptr(a, writable=False, dtype="float64"):
+    """(pointer, mem) of a torch tensor or numpy array (contiguous, of dtype)."""
     if a is None:
         return None, MEM_DEVICE
     if hasattr(a, "data_ptr"):
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
-        if str(a.dtype) != "torch.float64":
-            raise ValueError("tensor must be float64")
+        if str(a.dtype) != "torch." + dtype:
+            raise ValueError("tensor must be " + dtype)
         return ctypes.c_void_p(a.data_ptr()), (MEM_DEVICE if a.is_cuda else MEM_HOST)
-    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
-        raise ValueError("numpy array must be C-contiguous float64")
+    if not isinstance(a, np.ndarray) or a.dtype != np.dtype(dtype) or not a.flags.c_contiguous:
+        raise ValueError("numpy array must be C-contiguous " + dtype)
     if writable and not a.flags.writeable:
         raise ValueError("output array is read-only")
     return ctypes.c_void_p(a.ctypes.data), MEM_HOST
@@ -292,6 +303,56 @@ class Solver:
         us = ctypes.c_double()
         _check(self._lib.sisdc_profile_kernel(self.h, kernel, level, dt_m, reps, ctypes.byref(us)))
         return us.value
+
+    # ---- learned initial guess (element-local MLP) ----
+    def net_init(self, level, hidden, seed=0, max_batch=4096, max_rows=65536):
+        _check(self._lib.sisdc_net_init(self.h, level, hidden, seed, max_batch, max_rows))
+
+    def net_params(self, level):
+        n = ctypes.c_longlong()
+        _check(self._lib.sisdc_net_get_params(self.h, level, None, MEM_HOST, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.float32)
+        _check(self._lib.sisdc_net_get_params(self.h, level, out.ctypes.data_as(ctypes.c_void_p), MEM_HOST,
+                                              ctypes.byref(n)))
+        return out
+
+    def net_set_params(self, level, theta):
+        p, mem = _ptr(theta, dtype="float32")
+        _check(self._lib.sisdc_net_set_params(self.h, level, p, mem))
+
+    def net_forward(self, level, X, Y, bf16=False):
+        px, mem = _ptr(X, dtype="float32")
+        py, _ = _ptr(Y, True, dtype="float32")
+        _check(self._lib.sisdc_net_forward(self.h, level, px, X.shape[0], py, mem, 1 if bf16 else 0))
+        return Y
+
+    def net_train_step(self, level, X, T, lr):
+        px, mem = _ptr(X, dtype="float32")
+        pt, _ = _ptr(T, dtype="float32")
+        loss = ctypes.c_double()
+        _check(self._lib.sisdc_net_train_step(self.h, level, px, pt, X.shape[0], lr, ctypes.byref(loss), mem))
+        return loss.value
+
+    def net_grad(self, level, X, T, G):
+        px, mem = _ptr(X, dtype="float32")
+        pt, _ = _ptr(T, dtype="float32")
+        pg, _ = _ptr(G, True, dtype="float32")
+        loss = ctypes.c_double()
+        _check(self._lib.sisdc_net_grad(self.h, level, px, pt, X.shape[0], pg, ctypes.byref(loss), mem))
+        return loss.value
+
+    def net_harvest(self, level, on):
+        rows = ctypes.c_int()
+        _check(self._lib.sisdc_net_harvest(self.h, level, int(on), ctypes.byref(rows)))
+        return rows.value
+
+    def net_train(self, level, epochs, batch, lr):
+        loss = ctypes.c_double()
+        _check(self._lib.sisdc_net_train(self.h, level, epochs, batch, lr, ctypes.byref(loss)))
+        return loss.value
+
+    def net_use(self, level, on):
+        _check(self._lib.sisdc_net_use(self.h, level, 1 if on else 0))
 
     def collocation_residual(self, level, dt, out):
         p, mem = _ptr(out, True)
