@@ -233,8 +233,8 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
 
 /* Learned initial guess of a level's Helmholtz solves: an element-local MLP
  * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)
- * row of the initial residual r0 = b - A x0 scaled to unit norm; its output,
- * scaled back, corrects x0.  The corrected x0 is kept only if it lowers
+ * row of the mass-scaled initial residual z0 = M^-1 (b - A x0), normalised to
+ * unit norm; its output, times |z0_row|, corrects x0.  The corrected x0 is kept only if it lowers
  * |b - A x0| (decided on the device; rejections are counted in the stats),
  * and PCG always follows to the same tolerance, so the network changes the
  * initial guess only.  Not part of the paper's method.
@@ -250,7 +250,7 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
  *                      loss 1/(2 rows) sum |N(x) - t|^2 in FP32; returns it.
  *   sisdc_net_grad     the same loss and its gradient (flat layout), no update.
  *   sisdc_net_harvest  on = 1: every later solve of the level appends rows
- *                      (r0 / |r0|, (x* - x0) / |r0|) until max_rows; 0: stop;
+ *                      (z0 / |z0|, (x* - x0) / |z0|) until max_rows; 0: stop;
  *                      -1: stop and clear.  rows_out: rows held.
  *   sisdc_net_train    epochs over the harvested rows in order, batches of
  *                      `batch`; loss: mean loss of the last epoch.

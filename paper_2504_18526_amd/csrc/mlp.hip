@@ -136,24 +136,28 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __r
   }
 }
 
-// Row norms of r (FP64) and the normalised rows as FP32: X = r / |r|.
+// Mass-scaled rows z = M^-1 r (mw: the n diagonal mass entries of an
+// element), their norms |z| (FP64) and the normalised rows X = z / |z| (FP32).
 // One wave per row.
-__global__ void k_row_normalise(const double* __restrict__ r, int rows, int n, float* __restrict__ X,
-                                double* __restrict__ nrm) {
+__global__ void k_row_normalise(const double* __restrict__ r, int rows, int n, const double* __restrict__ mw,
+                                float* __restrict__ X, double* __restrict__ nrm) {
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
   if (row >= rows) return;
   const double* rr = r + (long)row * n;
   double s = 0.0;
-  for (int k = lane; k < n; k += 64) s += rr[k] * rr[k];
+  for (int k = lane; k < n; k += 64) {
+    const double z = rr[k] / mw[k];
+    s += z * z;
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   const double nr = sqrt(s);
   const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-  for (int k = lane; k < n; k += 64) X[(long)row * n + k] = (float)(rr[k] * inv);
+  for (int k = lane; k < n; k += 64) X[(long)row * n + k] = (float)(rr[k] / mw[k] * inv);
   if (lane == 0) nrm[row] = nr;
 }
 
-// xnew = x + |r_row| * Y  (the network's correction, scaled back)
+// xnew = x + |z_row| * Y  (the network's correction, scaled back)
 __global__ void k_guess_update(const double* __restrict__ x, const float* __restrict__ Y, const double* __restrict__ nrm,
                                int rows, int n, double* __restrict__ xnew) {
   const long tot = (long)rows * n;
@@ -171,15 +175,16 @@ __global__ void k_guess_select(double* __restrict__ x, const double* __restrict_
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = xnew[i];
 }
 
-// harvest rows: X[row] = r0_row / |r0_row|, T[row] = (x - x0)_row / |r0_row|
+// harvest rows: X[row] = z0_row / |z0_row|, T[row] = (x - x0)_row / |z0_row|,
+// z0 = M^-1 r0
 __global__ void k_harvest(const double* __restrict__ r0, const double* __restrict__ x, const double* __restrict__ x0,
-                          const double* __restrict__ nrm, int rows, int n, float* __restrict__ X,
-                          float* __restrict__ T) {
+                          const double* __restrict__ nrm, int rows, int n, const double* __restrict__ mw,
+                          float* __restrict__ X, float* __restrict__ T) {
   const long tot = (long)rows * n;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
     const double nr = nrm[i / n];
     const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-    X[i] = (float)(r0[i] * inv);
+    X[i] = (float)(r0[i] / mw[i % n] * inv);
     T[i] = (float)((x[i] - x0[i]) * inv);
   }
 }
@@ -252,8 +257,9 @@ hipError_t launch_adam(float* th, float* m, float* v, const float* g, long n, fl
   return hipGetLastError();
 }
 
-hipError_t launch_row_normalise(const double* r, int rows, int n, float* X, double* nrm, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, r, rows, n, X, nrm);
+hipError_t launch_row_normalise(const double* r, int rows, int n, const double* mw, float* X, double* nrm,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_row_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, r, rows, n, mw, X, nrm);
   return hipGetLastError();
 }
 
@@ -270,8 +276,8 @@ hipError_t launch_guess_select(double* x, const double* xnew, long n, const doub
 }
 
 hipError_t launch_harvest(const double* r0, const double* x, const double* x0, const double* nrm, int rows, int n,
-                          float* X, float* T, hipStream_t s) {
-  hipLaunchKernelGGL(k_harvest, dim3(gblocks((long)rows * n)), dim3(256), 0, s, r0, x, x0, nrm, rows, n, X, T);
+                          const double* mw, float* X, float* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_harvest, dim3(gblocks((long)rows * n)), dim3(256), 0, s, r0, x, x0, nrm, rows, n, mw, X, T);
   return hipGetLastError();
 }
 

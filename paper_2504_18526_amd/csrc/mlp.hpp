@@ -19,12 +19,14 @@ hipError_t mlp_backward(const MlpShape& sh, const float* theta, const float* X, 
                         const float* Z1, const float* A1, const float* Z2, const float* A2, const float* Y, float* dY,
                         float* dA, float* dZ, float* g, double* loss_part, hipStream_t s);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, long n, float lr, int step, hipStream_t s);
-hipError_t launch_row_normalise(const double* r, int rows, int n, float* X, double* nrm, hipStream_t s);
+// z = M^-1 r per row (mw: the element's diagonal mass), |z| and z / |z|
+hipError_t launch_row_normalise(const double* r, int rows, int n, const double* mw, float* X, double* nrm,
+                                hipStream_t s);
 hipError_t launch_guess_update(const double* x, const float* Y, const double* nrm, int rows, int n, double* xnew,
                                hipStream_t s);
 hipError_t launch_guess_select(double* x, const double* xnew, long n, const double* tot_old, const double* tot_new,
                                int* rejected, hipStream_t s);
 hipError_t launch_harvest(const double* r0, const double* x, const double* x0, const double* nrm, int rows, int n,
-                          float* X, float* T, hipStream_t s);
+                          const double* mw, float* X, float* T, hipStream_t s);
 
 }  // namespace sisdc

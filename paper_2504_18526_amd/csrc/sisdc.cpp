@@ -505,14 +505,15 @@ void residual64(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const do
   }
 }
 
-// x0 <- x0 + |r0_row| N(r0_row / |r0_row|) for every (element, component)
-// row, kept only if |b - A x0| decreases (decided on the device).
+// x0 <- x0 + |z0_row| N(z0_row / |z0_row|), z0 = M^-1 (b - A x0), for every
+// (element, component) row, kept only if |b - A x0| decreases (decided on
+// the device).
 void learned_guess(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x) {
   auto& N = L.net;
   hipStream_t s = h->stream;
   const int rows = L.nv * L.E;
   residual64(h, L, cf, dtm, b, x, N.r0h, h->gtot);
-  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, N.Xi, N.nrm, s));
+  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, L.mw, N.Xi, N.nrm, s));
   HIPCHECK(mlp_forward(N.sh, N.theta, N.Xi, rows, nullptr, N.A1i, nullptr, N.A2i, N.Yi, 1, s));
   HIPCHECK(launch_guess_update(x, N.Yi, N.nrm, rows, L.np, N.xnew, s));
   residual64(h, L, cf, dtm, b, N.xnew, nullptr, h->gtot + 2);
@@ -527,14 +528,14 @@ void harvest_before(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, cons
   copy_d2d(h, N.x0h, x, L.vlen);
 }
 
-// append the rows (r0 / |r0|, (x* - x0) / |r0|) of the finished solve
+// append the rows (z0 / |z0|, (x* - x0) / |z0|), z0 = M^-1 r0, of the finished solve
 void harvest_after(sisdc_handle* h, Level& L, const double* x) {
   auto& N = L.net;
   const int rows = L.nv * L.E;
   if (N.rows + rows > N.max_rows) return;
-  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, N.Xi, N.nrm, h->stream));
-  HIPCHECK(launch_harvest(N.r0h, x, N.x0h, N.nrm, rows, L.np, N.Xd + (long)N.rows * L.np, N.Td + (long)N.rows * L.np,
-                          h->stream));
+  HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, L.mw, N.Xi, N.nrm, h->stream));
+  HIPCHECK(launch_harvest(N.r0h, x, N.x0h, N.nrm, rows, L.np, L.mw, N.Xd + (long)N.rows * L.np,
+                          N.Td + (long)N.rows * L.np, h->stream));
   N.rows += rows;
 }
 
