@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reps", type=int, default=400, help="launches timed for the roofline kernel")
+    ap.add_argument("--variant-steps", type=int, default=50,
+                    help="steps timed for each of the mixed / learned variants (0: skip them)")
     return ap.parse_args()
 
 
@@ -67,6 +69,66 @@ print(json.dumps({{"seconds": el, "steps": {nsteps}, "rel_l2_step1": err}}))
     if out.returncode != 0:
         raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
     return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates):
+    """Plain FP64 vs mixed precision vs the learned initial guess (and both),
+    each from the same state after the same warm-up, same PCG tolerance.
+    The network of each level is trained on rows harvested from the plain
+    solves of the warm-up steps (its training time is reported, not timed)."""
+    import time
+    import torch
+    out = {}
+    ref = None
+    for name, prec, learned in (("plain_fp64", S.FP64, False), ("mixed", S.MIXED, False),
+                                ("learned_fp64", S.FP64, True), ("learned_mixed", S.MIXED, True)):
+        meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+                             post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
+                             cg_maxit=1000, precision=prec)
+        sv = S.Solver(prob, meth, stream=stream.cuda_stream)
+        sv.set_state(u0)
+        train_s = 0.0
+        if learned:
+            for lvl in range(len(w["P"])):
+                sv.net_init(lvl, 64, seed=1 + lvl, max_batch=2048, max_rows=65536)
+                sv.net_harvest(lvl, 1)
+        for _ in range(2):
+            sv.step(dt)
+        if learned:
+            t0 = time.perf_counter()
+            for lvl in range(len(w["P"])):
+                sv.net_harvest(lvl, 0)
+                sv.net_train(lvl, 20, 512, 1e-3)
+                sv.net_use(lvl, 1)
+            torch.cuda.synchronize()
+            train_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        its, rej, rounds = 0, 0, 0
+        for _ in range(nsteps):
+            st = sv.step(dt)
+            its += st["cg_iters"]
+            rej += st["net_rejected"]
+            rounds += st["ir_rounds"]
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / nsteps
+        fin = torch.empty_like(u0)
+        sv.get_state(fin)
+        if ref is None:
+            ref = fin.clone()
+        diff = float(torch.linalg.norm(fin - ref) / torch.linalg.norm(ref))
+        out[name] = {"ms_per_step": ms, "dof_updates_per_s": dof_updates / (ms / 1000.0),
+                     "cg_iters_per_step": its / nsteps, "rel_l2_vs_plain": diff,
+                     "rejected_guesses": rej, "ir_rounds_per_step": rounds / nsteps, "train_s": train_s}
+        sv.close()
+    base = out["plain_fp64"]["ms_per_step"]
+    for k in out:
+        out[k]["speedup_vs_plain"] = base / out[k]["ms_per_step"]
+    out["steps"] = nsteps
+    return out
 
 
 def main():
@@ -139,6 +201,10 @@ def main():
                 "kernel": "k_sipg_apply<2,8> (CG matvec)", "avg_launch_us": round(us, 3),
                 "algo_bytes_per_launch": int(algo_bytes)}
 
+    variants = None
+    if a.variant_steps > 0:
+        variants = run_variants(S, w, prob, stream, ud, dt, a.variant_steps, dof_updates)
+
     cpu = None
     if not a.no_cpu_baseline:
         with tempfile.TemporaryDirectory() as td:
@@ -165,6 +231,7 @@ def main():
                    "wall_s": wall},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(rec), flush=True)
     sv.close()
