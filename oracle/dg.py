@@ -18,7 +18,14 @@ every term is a functional of the weighting function w_h.
                       + sum_f int tau [x][w],
             [x] = x^- - x^+ along n = n^-, tau = C_tau (P+1)^2 kappa_f / h_d,
             kappa_f = max(n.D^- n, n.D^+ n) per face node (reading).
-* frhs      F(u) = C(u) - K_{nu I} u for the scalar equations, C(u) for Euler.
+* visc      V(u): weak viscous term of Navier-Stokes by the first Bassi-Rebay
+            scheme (reading: the paper defers F_d to its companion paper):
+            lifted gradients G = grad q + M^-1 sum_faces E^T J_f W_f ({q} - q^-) n
+            of q = (v, T), nodal viscous fluxes f_v(u, G), then
+            V = int w div f_v + sum_faces int w ({f_v} - f_v^-).n, central
+            averages on both sides.
+* frhs      F(u) = C(u) - K_{nu I} u for the scalar equations, C(u) for Euler,
+            C(u) + V(u) for Navier-Stokes.
 
 Integrals use the GLL nodes of each element (collocated quadrature).
 """
@@ -125,11 +132,44 @@ class DG:
             Dc[d, d] = self.phys.nu
         return Dc
 
+    def lifted_gradients(self, U):
+        """BR1 gradients G[e][j] = d q_j / dx_e of q = (v, T) per node."""
+        phys, mesh = self.phys, self.mesh
+        q = phys.primitive_q(U)
+        G = [[None] * q.shape[0] for _ in range(self.dim)]
+        for e in range(self.dim):
+            ge = (2.0 / mesh.h[e]) * self.deriv(q, e)
+            for side in (-1, 1):
+                q_in, q_out = self.face(q, e, side)
+                # (J_f w_f / (J w)) at the face node equals (2 / h_e) / w_face
+                w_face = self.ref.w[0 if side < 0 else self.P]
+                self.face_add(ge, (2.0 / mesh.h[e]) / w_face * 0.5 * (q_out - q_in) * side, e, side)
+            for j in range(q.shape[0]):
+                G[e][j] = ge[j]
+        return G
+
+    def visc(self, U):
+        """V(u): weak BR1 viscous term (Navier-Stokes)."""
+        phys, mesh = self.phys, self.mesh
+        G = self.lifted_gradients(U)
+        Fv = [phys.viscous_flux(U, G, d) for d in range(self.dim)]
+        vol = np.zeros_like(U)
+        for d in range(self.dim):
+            vol += (2.0 / mesh.h[d]) * self.deriv(Fv[d], d)
+        out = self.Wm * vol
+        for d in range(self.dim):
+            for side in (-1, 1):
+                f_in, f_out = self.face(Fv[d], d, side)
+                self.face_add(out, self.Wf[d] * 0.5 * side * (f_out - f_in), d, side)
+        return out
+
     def frhs(self, U):
         """F(u) = F_c + F_d (eq. collocation:radau-iia:full), weak form."""
         out = self.conv(U)
         if not self.phys.system and self.phys.nu != 0.0:
             out = out - self.sipg(self.nu_tensor(), U)
+        if getattr(self.phys, "mu", 0.0) != 0.0:
+            out = out + self.visc(U)
         return out
 
     def helmholtz(self, Dc, dtm, X):

@@ -127,3 +127,51 @@ class Euler:
         for i in range(self.dim):
             Dc[i, i] = kap
         return Dc
+
+
+class NavierStokes(Euler):
+    """Compressible Navier-Stokes (Sec. 2, "Euler and Navier-Stokes
+    equations", written for d dimensions): constant dynamic viscosity mu,
+    Prandtl number Pr, perfect gas with gas constant R.
+
+    Viscous flux in direction d:  (0, tau_1d, ..., tau_Dd,
+    sum_k v_k tau_kd + lam_T dT/dx_d), with the Newtonian stress
+    tau_ij = mu (dv_j/dx_i + dv_i/dx_j) - 2/3 mu delta_ij div v and the heat
+    conductivity lam_T = mu c_p / Pr, c_p = gamma R / (gamma - 1).  In 1-D
+    this is the paper's f_d = (0, 4/3 eta v_x, 4/3 eta v v_x + lambda T_x).
+
+    Implicit coefficient (reading for systems): kappa_m = (dt_m/2) lam*^2 +
+    max(4 mu / (3 rho_min), gamma mu / (Pr rho_min)), lam* and rho_min taken
+    over the nodes of the step's initial value.
+    """
+
+    def __init__(self, dim, gamma, mu, Pr, R=1.0):
+        super().__init__(dim, gamma, R)
+        self.mu = float(mu)
+        self.Pr = float(Pr)
+        self.cp = self.gamma * self.R / (self.gamma - 1.0)
+        self.lam_T = self.mu * self.cp / self.Pr
+
+    def step_params(self, U0):
+        lam = max(float(np.max(self.speed(U0, d))) for d in range(self.dim))
+        rho_min = float(np.min(U0[0]))
+        visc = max(4.0 * self.mu / (3.0 * rho_min), self.gamma * self.mu / (self.Pr * rho_min))
+        return {"lam": lam, "visc": visc}
+
+    def primitive_q(self, U):
+        """q = (v_1, ..., v_D, T), the variables whose gradients enter f_d."""
+        rho, v, p = self.primitive(U)
+        return np.stack(v + [p / (rho * self.R)])
+
+    def viscous_flux(self, U, G, d):
+        """f_v,d from the state U and the gradients G[e][j] = d q_j / dx_e."""
+        D = self.dim
+        rho, v, p = self.primitive(U)
+        div = sum(G[k][k] for k in range(D))
+        tau_d = [self.mu * (G[i][d] + G[d][i]) - (2.0 / 3.0 * self.mu * div if i == d else 0.0)
+                 for i in range(D)]
+        F = np.zeros_like(U)
+        for i in range(D):
+            F[1 + i] = tau_d[i]
+        F[D + 1] = sum(v[k] * tau_d[k] for k in range(D)) + self.lam_T * G[d][D]
+        return F

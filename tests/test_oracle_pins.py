@@ -375,3 +375,59 @@ def test_euler_vortex_transport_and_conservation():
     err = np.sqrt(np.sum(lv.dg.Wm * (u - ue) ** 2) / np.sum(lv.dg.Wm * ue ** 2))
     assert err < 2e-3, err
     assert np.max(np.abs(lv.dg.integral(u) - m0)) < 1e-12 * np.max(np.abs(m0))
+
+
+# ---------------------------------------------------------------- Navier-Stokes
+from oracle.physics import NavierStokes
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ns_viscous_term_spectral_shear(dim):
+    """Shear flow u = sin y, rho = 1, T const: the viscous term is
+    mu d2u/dy2 = -mu sin y (x-momentum) and mu (u_y^2 + u u_yy) (energy)."""
+    mu = 0.05
+    ph = NavierStokes(dim, 1.4, mu, 0.71)
+    n = (2, 3) if dim == 2 else (2, 3, 2)
+    ref = RefElement(7)
+    mesh = Mesh(n, [0.0] * dim, [2 * np.pi] * dim, 7)
+    dg = DG(ref, mesh, ph)
+    xs = mesh.node_coords(ref.x)
+    y = xs[1]
+    rho = np.ones_like(y)
+    u = np.sin(y)
+    p = 10.0 + 0 * y
+    comps = [rho, rho * u] + [0 * y] * (dim - 1) + [p / 0.4 + 0.5 * rho * u * u]
+    U = np.stack(comps)
+    V = dg.visc(U) / dg.Wm
+    assert np.max(np.abs(V[1] + mu * np.sin(y))) < 5e-5
+    assert np.max(np.abs(V[dim + 1] - mu * (np.cos(y) ** 2 - np.sin(y) ** 2))) < 5e-4
+    assert np.max(np.abs(V[0])) == 0.0
+
+
+def test_ns_viscous_term_conservative_and_constant():
+    ph = NavierStokes(2, 1.4, 0.02, 0.71)
+    ref, mesh, dg = _level(ph, (3, 2), 4)
+    rng = np.random.default_rng(8)
+    U = np.ones(mesh.shape(4))
+    U[0] += 0.1 * rng.random(U[0].shape)
+    U[1:3] = 0.2 * rng.standard_normal(U[1:3].shape)
+    U[3] = 3.0 + 0.1 * rng.random(U[0].shape)
+    V = dg.visc(U)
+    assert np.max(np.abs(V.reshape(4, -1).sum(axis=1))) < 1e-14 * np.abs(V).max() * V[0].size
+    Uc = np.ones(mesh.shape(4)) * np.array([1.0, 0.3, -0.2, 2.5]).reshape(4, 1, 1, 1, 1)
+    assert np.max(np.abs(dg.visc(Uc))) < 1e-14
+
+
+def test_ns_taylor_green_step_conserves_and_dissipates():
+    from paper_2504_18526_amd.inputs import taylor_green
+    ph = NavierStokes(3, 1.4, 1.0 / 100.0, 0.71)
+    lv = sdc.DGLevel(ph, (2, 2, 2), [0, 0, 0], [2 * np.pi] * 3, 3, 2, rtol=1e-14)
+    x = lv.coords()
+    u = taylor_green(x, mach=0.1)
+    m0 = lv.dg.integral(u)
+    ke = lambda U: lv.dg.integral((0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])[None])[0]
+    k0 = ke(u)
+    for _ in range(2):
+        u = sdc.sdc_step(lv, u, 2e-3, 2)
+    assert np.max(np.abs(lv.dg.integral(u) - m0)) < 1e-12 * np.max(np.abs(m0))
+    assert ke(u) < k0
