@@ -60,7 +60,9 @@ enum { SISDC_MEM_HOST = 0, SISDC_MEM_DEVICE = 1 };
 typedef enum {
   SISDC_EQ_CONVDIFF = 0, /* u_t + div(a u) = nu lap u           (Sec. 2)   */
   SISDC_EQ_BURGERS = 1,  /* u_t + div(u^2/2 (1,..,1)) = nu lap u (Sec. 2)  */
-  SISDC_EQ_EULER = 2     /* compressible Euler, perfect gas      (Sec. 2)  */
+  SISDC_EQ_EULER = 2,    /* compressible Euler, perfect gas      (Sec. 2)  */
+  SISDC_EQ_NS = 3        /* compressible Navier-Stokes, constant mu, Pr;
+                            viscous term by BR1 lifting          (Sec. 2)  */
 } sisdc_eq;
 
 enum { SISDC_SI2 = 0, SISDC_SI1 = 1 };                 /* Sec. 3            */
@@ -81,7 +83,10 @@ typedef struct {
   int eq;              /* sisdc_eq                                          */
   double a[3];         /* convection velocity (CONVDIFF)                    */
   double nu;           /* diffusivity (CONVDIFF, BURGERS)                   */
-  double gamma;        /* ratio of specific heats (EULER)                   */
+  double gamma;        /* ratio of specific heats (EULER, NS)               */
+  double mu;           /* dynamic viscosity (NS)                            */
+  double Pr;           /* Prandtl number (NS)                               */
+  double R;            /* gas constant (EULER, NS; <= 0 means 1)            */
 } sisdc_problem;
 
 typedef struct {
@@ -160,10 +165,12 @@ int sisdc_set_fas(sisdc_handle* h, int level, const double* g, int mem);
 /* The fine solution at t+dt (u_{M}) after the last sisdc_step. */
 int sisdc_get_state(sisdc_handle* h, double* u, int mem);
 
-/* Per-step parameter of the systems' implicit term: lam* = max over the
- * nodes of max_d(|v_d| + c) of the current fine u_0 (EULER; 0 otherwise).
- * Computed on the device at the start of every step; this call computes it
- * from the current fine u_0 and stores it for the next sweeps. */
+/* Per-step parameter of the systems' implicit term kappa_m I: lam* = max
+ * over the nodes of max_d(|v_d| + c) of the current fine u_0 (EULER, NS; 0
+ * otherwise), and for NS rho_min; kappa_m = (dt_m/2) lam*^2 (+ max(4 mu /
+ * (3 rho_min), gamma mu / (Pr rho_min)) for NS).  Computed on the device at
+ * the start of every step; this call computes it from the current fine u_0
+ * and stores it for the next sweeps. */
 int sisdc_update_step_params(sisdc_handle* h, double* lam_out);
 
 /* One time step of length dt from the stored fine u_0 (Sec. 3 and 4):

@@ -17,12 +17,15 @@ struct Geo {
 };
 
 // Equation parameters.
-enum { EQ_CONVDIFF = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
+enum { EQ_CONVDIFF = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_NS = 3 };
 struct EqP {
   int eq, nv;
   double a[3];
   double nu;
   double gamma;
+  double mu;     // dynamic viscosity (Navier-Stokes)
+  double lam_T;  // heat conductivity mu c_p / Pr
+  double R;      // gas constant
 };
 
 // Implicit coefficient D_ij = c w^2 v_i v_j + nu delta_ij, w = ub[node] or 1,

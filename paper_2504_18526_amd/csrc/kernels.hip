@@ -209,6 +209,178 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
   for (int v = 0; v < NV; ++v) out[v * vs + (long)e * NP + n] = acc[v];
 }
 
+// ---------------------------------------------------------------- viscous (NS)
+// q = (v_1, ..., v_D, T) of a conservative state
+template <int DIM>
+__device__ __forceinline__ void prim_q(const EqP& q, const double (&u)[DIM + 2], double (&out)[DIM + 1]) {
+  const double ir = 1.0 / u[0];
+  double ke = 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    out[k] = u[1 + k] * ir;
+    ke += u[1 + k] * out[k];
+  }
+  const double p = (q.gamma - 1.0) * (u[DIM + 1] - 0.5 * ke);
+  out[DIM] = p * ir / q.R;
+}
+
+// viscous flux in direction d from the state and the gradients G[e][j] = dq_j/dx_e
+template <int DIM>
+__device__ __forceinline__ void visc_flux(const EqP& q, int d, const double (&u)[DIM + 2],
+                                          const double (&G)[DIM][DIM + 1], double (&f)[DIM + 2]) {
+  const double ir = 1.0 / u[0];
+  double div = 0.0;
+  for (int k = 0; k < DIM; ++k) div += G[k][k];
+  f[0] = 0.0;
+  double work = 0.0;
+  for (int i = 0; i < DIM; ++i) {
+    const double tau = q.mu * (G[i][d] + G[d][i]) - (i == d ? 2.0 / 3.0 * q.mu * div : 0.0);
+    f[1 + i] = tau;
+    work += u[1 + i] * ir * tau;
+  }
+  f[DIM + 1] = work + q.lam_T * G[d][DIM];
+}
+
+// BR1 lifted gradients at a node: grad q from the LDS tiles sq (component j
+// at sq[j * EPB * NP]) plus (2/h_d) / w_face * ({q} - q^-) n_d at face nodes.
+template <int DIM, int P>
+__device__ __forceinline__ void lifted_grad(const double* sq, int le, int n, const int (&ii)[3], const double* sD,
+                                            const double* sw, const Geo& g, const EqP& q, const double* u, long vs,
+                                            int e, const double (&qo)[DIM + 1], double (&G)[DIM][DIM + 1]) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  for (int d = 0; d < DIM; ++d) {
+    const int st = L::stride(d);
+    for (int j = 0; j <= DIM; ++j) {
+      const double* row = &sq[(j * EPB + le) * NP + n - ii[d] * st];
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+      G[d][j] = g.rh2[d] * s;
+    }
+  }
+  for (int d = 0; d < DIM; ++d)
+    for (int side = 0; side < 2; ++side) {
+      if (ii[d] != (side ? P : 0)) continue;
+      const double sgn = side ? 1.0 : -1.0;
+      const int nb = neighbour(g, e, d, side ? 1 : -1);
+      const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
+      double uo[DIM + 2], qn[DIM + 1];
+      for (int v = 0; v < DIM + 2; ++v) uo[v] = u[v * vs + (long)nb * NP + nn];
+      prim_q<DIM>(q, uo, qn);
+      const double lift = g.rh2[d] / sw[ii[d]] * 0.5 * sgn;
+      for (int j = 0; j <= DIM; ++j) G[d][j] += lift * (qn[j] - qo[j]);
+    }
+}
+
+// Pass 1 of the viscous term: the viscous fluxes f_v,d at face nodes,
+// trace[v][e][d][side][f].
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_visc_trace(const double* __restrict__ u, double* __restrict__ trace, Geo g, EqP q, const double* __restrict__ tab,
+             long vs) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sq[(DIM + 1) * EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  double uu[NV], qo[DIM + 1];
+  for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
+  prim_q<DIM>(q, uu, qo);
+  if (act)
+    for (int j = 0; j <= DIM; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+  __syncthreads();
+  if (!act) return;
+  bool face = false;
+  for (int d = 0; d < DIM; ++d) face = face || ii[d] == 0 || ii[d] == P;
+  if (!face) return;
+  double G[DIM][DIM + 1];
+  lifted_grad<DIM, P>(sq, le, n, ii, sD, sw, g, q, u, vs, e, qo, G);
+  for (int d = 0; d < DIM; ++d) {
+    const bool lo = ii[d] == 0, hi = ii[d] == P;
+    if (!lo && !hi) continue;
+    double f[NV];
+    visc_flux<DIM>(q, d, uu, G, f);
+    for (int v = 0; v < NV; ++v) {
+      const long base = (((long)v * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
+      if (lo) trace[base] = f[v];
+      if (hi) trace[base + NF] = f[v];
+    }
+  }
+}
+
+// Pass 2: out += V(u) = J w sum_d (2/h_d) D_d f_v,d + sum_faces J_f w_f
+// ({f_v} - f_v^-).n  (accumulated onto out, which holds C(u)).
+template <int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ trace, Geo g, EqP q,
+             const double* __restrict__ tab, long vs) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2;
+  __shared__ double sD[N1 * N1], sw[N1];
+  __shared__ double sq[(DIM + 1) * EPB * NP];
+  __shared__ double sf[NV * EPB * NP];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = (le < EPB) && (e < g.E);
+  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
+  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  double uu[NV], qo[DIM + 1];
+  for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
+  prim_q<DIM>(q, uu, qo);
+  if (act)
+    for (int j = 0; j <= DIM; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+  __syncthreads();
+  double G[DIM][DIM + 1];
+  if (act) lifted_grad<DIM, P>(sq, le, n, ii, sD, sw, g, q, u, vs, e, qo, G);
+  double acc[NV];
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int d = 0; d < DIM; ++d) {
+    if (act) {
+      double f[NV];
+      visc_flux<DIM>(q, d, uu, G, f);
+      for (int v = 0; v < NV; ++v) sf[(v * EPB + le) * NP + n] = f[v];
+    }
+    __syncthreads();
+    if (act) {
+      const int st = L::stride(d);
+      for (int v = 1; v < NV; ++v) {
+        const double* row = &sf[(v * EPB + le) * NP + n - ii[d] * st];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
+        acc[v] += g.rh2[d] * s;
+      }
+    }
+    __syncthreads();
+  }
+  if (!act) return;
+  double wn = 1.0;
+  for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  for (int v = 0; v < NV; ++v) acc[v] *= g.J * wn;
+  for (int d = 0; d < DIM; ++d)
+    for (int side = 0; side < 2; ++side) {
+      if (ii[d] != (side ? P : 0)) continue;
+      const double sgn = side ? 1.0 : -1.0;
+      const int nb = neighbour(g, e, d, side ? 1 : -1);
+      double f[NV];
+      visc_flux<DIM>(q, d, uu, G, f);
+      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
+      for (int v = 1; v < NV; ++v) {
+        const double fnb = trace[(((long)v * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + face_index<DIM, N1>(d, ii)];
+        acc[v] += jfwf * 0.5 * sgn * (fnb - f[v]);
+      }
+    }
+  for (int v = 1; v < NV; ++v) out[v * vs + (long)e * NP + n] += acc[v];
+}
+
 // ---------------------------------------------------------------- SIPG
 template <typename T>
 __device__ __forceinline__ T coef_w2(const CoefT<T>& cf, long idx) {
@@ -652,40 +824,66 @@ __global__ void k_add_f2d(double* __restrict__ x, const float* __restrict__ e, l
     x[i] += (double)e[i];
 }
 
-// Per-block maxima of max_d (|v_d| + c) (Euler); reduced by k_max_partials.
+// Per-block maxima of max_d (|v_d| + c) and minima of rho (Euler /
+// Navier-Stokes) into part[b] and part[kElemCap + b]; reduced by
+// k_maxmin_partials.
 template <int DIM>
 __global__ void k_euler_lam(const double* __restrict__ u, long vs, EqP q, double* part) {
   constexpr int NV = DIM + 2;
-  __shared__ double sm[16];
-  double m = 0.0;
+  __shared__ double sm[16], sr[16];
+  double m = 0.0, rmin = 1e300;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vs; i += (long)gridDim.x * blockDim.x) {
     double uu[NV];
     for (int v = 0; v < NV; ++v) uu[v] = u[v * vs + i];
     for (int d = 0; d < DIM; ++d) m = fmax(m, wave_speed<NV>(q, d, uu));
+    rmin = fmin(rmin, uu[0]);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-  if (lane == 0) sm[wid] = m;
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_down(m, off, 64));
+    rmin = fmin(rmin, __shfl_down(rmin, off, 64));
+  }
+  if (lane == 0) {
+    sm[wid] = m;
+    sr[wid] = rmin;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s = fmax(s, sm[w]);
+    double s = 0.0, r = 1e300;
+    for (int w = 0; w < nw; ++w) {
+      s = fmax(s, sm[w]);
+      r = fmin(r, sr[w]);
+    }
     part[blockIdx.x] = s;
+    part[kElemCap + blockIdx.x] = r;
   }
 }
 
-__global__ void k_max_partials(const double* __restrict__ part, int n, double* result) {
-  __shared__ double sm[16];
-  double m = 0.0;
-  for (int b = threadIdx.x; b < n; b += blockDim.x) m = fmax(m, part[b]);
+__global__ void k_maxmin_partials(const double* __restrict__ part, int n, double* result) {
+  __shared__ double sm[16], sr[16];
+  double m = 0.0, rmin = 1e300;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    m = fmax(m, part[b]);
+    rmin = fmin(rmin, part[kElemCap + b]);
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-  if (lane == 0) sm[wid] = m;
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_down(m, off, 64));
+    rmin = fmin(rmin, __shfl_down(rmin, off, 64));
+  }
+  if (lane == 0) {
+    sm[wid] = m;
+    sr[wid] = rmin;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s = fmax(s, sm[w]);
-    *result = s;
+    double s = 0.0, r = 1e300;
+    for (int w = 0; w < nw; ++w) {
+      s = fmax(s, sm[w]);
+      r = fmin(r, sr[w]);
+    }
+    result[0] = s;
+    result[1] = r;
   }
 }
 
@@ -880,6 +1078,22 @@ static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, c
 SISDC_PRECISION_LAUNCHERS(double)
 SISDC_PRECISION_LAUNCHERS(float)
 
+template <int DIM, int P>
+static hipError_t visc_dim_p(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
+                             hipStream_t s) {
+  using L = EL<DIM, P>;
+  const long vs = (long)g.E * L::NP;
+  hipLaunchKernelGGL((k_visc_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, trace, g, q, tab, vs);
+  hipLaunchKernelGGL((k_visc_apply<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, trace, g, q, tab,
+                     vs);
+  return hipGetLastError();
+}
+
+hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
+                       hipStream_t s) {
+  SISDC_DISPATCH(g, visc_dim_p, u, out, trace, g, q, tab, s);
+}
+
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
   return hipGetLastError();
@@ -917,7 +1131,7 @@ hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, dou
     hipLaunchKernelGGL(k_euler_lam<2>, dim3(nb), dim3(256), 0, s, u, vs, q, part);
   else
     hipLaunchKernelGGL(k_euler_lam<3>, dim3(nb), dim3(256), 0, s, u, vs, q, part);
-  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, part, nb, result);
+  hipLaunchKernelGGL(k_maxmin_partials, dim3(1), dim3(256), 0, s, part, nb, result);
   return hipGetLastError();
 }
 

@@ -39,6 +39,9 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
 SISDC_DECLARE_PRECISION_LAUNCHERS(double)
 SISDC_DECLARE_PRECISION_LAUNCHERS(float)
 
+// out += V(u), the BR1 viscous term of Navier-Stokes (trace pass + apply pass)
+hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
+                       hipStream_t s);
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s);
 hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
                                  const double* A, hipStream_t s);
@@ -48,6 +51,7 @@ hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);
 hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
                              hipStream_t s);
 hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s);
+// result[0] = max over nodes of max_d (|v_d| + c), result[1] = min rho
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
                             hipStream_t s);
 // Persistent PCG: one cooperative launch per solve (pcg_persistent.hip).

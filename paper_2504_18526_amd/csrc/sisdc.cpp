@@ -154,6 +154,7 @@ struct sisdc_handle {
   double* io = nullptr;      // staging for host pointers, (Mmax+1) x vlen_max
   size_t io_len = 0;
   double lam = 0.0;
+  double visc = 0.0;           // viscous bound added to kappa_m (NS)
   bool have_state = false;
   double ctau = 2.0;
   sisdc_stats st{};
@@ -224,9 +225,9 @@ CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
       c.nu = h->eq.nu;
       c.ub = ub;
       break;
-    default:  // systems: kappa_m I, kappa_m = (dt_m / 2) lam*^2
+    default:  // systems: kappa_m I, kappa_m = (dt_m / 2) lam*^2 (+ viscous bound, NS)
       c.c = 0.0;
-      c.nu = 0.5 * dtm * h->lam * h->lam;
+      c.nu = 0.5 * dtm * h->lam * h->lam + h->visc;
       c.ub = nullptr;
   }
   (void)L;
@@ -248,16 +249,20 @@ void sipg(sisdc_handle* h, const Level& L, const CoefP& cf, const double* x, dou
   HIPCHECK(launch_sipg(x, out, L.nv, cf, L.trace, alpha, beta, h->ctau, L.g, L.tab, h->stream));
 }
 
-bool has_physical_diffusion(sisdc_handle* h) { return h->eq.eq != EQ_EULER && h->eq.nu != 0.0; }
+bool is_system(sisdc_handle* h) { return h->eq.eq == EQ_EULER || h->eq.eq == EQ_NS; }
+bool has_physical_diffusion(sisdc_handle* h) { return !is_system(h) && h->eq.nu != 0.0; }
 
-// f = F(u) = C(u) - K_nu u  (scalars), C(u) (Euler); Cu = C(u) precomputed
+// f = F(u) = C(u) - K_nu u (scalars), C(u) (Euler), C(u) + V(u) (NS);
+// Cu = C(u) precomputed
 void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double* Cu, double* f) {
   if (has_physical_diffusion(h)) {
     sipg(h, L, coef_nu(h), u, L.t3, 0.0, 1.0);
     lincomb(h, L, f, {{1.0, Cu}, {-1.0, L.t3}});
-  } else if (f != Cu) {
-    copy_d2d(h, f, Cu, L.vlen);
+    return;
   }
+  if (f != Cu) copy_d2d(h, f, Cu, L.vlen);
+  if (h->eq.eq == EQ_NS && h->eq.mu != 0.0)
+    HIPCHECK(launch_visc(u, f, L.trace, L.g, h->eq, L.tab, h->stream));
 }
 
 // ------------------------------------------------------------------ PCG
@@ -802,12 +807,22 @@ void set_level_initial(sisdc_handle* h) {
 }
 
 void update_lam(sisdc_handle* h) {
-  if (h->eq.eq != EQ_EULER) { h->lam = 0.0; return; }
+  if (!is_system(h)) {
+    h->lam = 0.0;
+    h->visc = 0.0;
+    return;
+  }
   Level& L = h->lv[0];
   HIPCHECK(launch_euler_lam(L.um(0), L.vs, h->eq, L.g.dim, h->partials, h->lam_dev, h->stream));
-  HIPCHECK(hipMemcpyAsync(h->hlam, h->lam_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->hlam, h->lam_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  h->lam = *h->hlam;
+  h->lam = h->hlam[0];
+  h->visc = 0.0;
+  if (h->eq.eq == EQ_NS) {
+    const double rmin = h->hlam[1];
+    if (!(rmin > 0.0)) fail(SISDC_ENONFINITE, "non-positive density in the state");
+    h->visc = std::max(4.0 * h->eq.mu / (3.0 * rmin), h->eq.gamma * h->eq.mu / (h->prob.Pr * rmin));
+  }
 }
 
 void do_step(sisdc_handle* h, double dt) {
@@ -982,9 +997,11 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
     if (p->n_elem[d] < 1) fail(SISDC_EINVAL, "n_elem must be >= 1");
     if (!(p->hi[d] > p->lo[d])) fail(SISDC_EINVAL, "hi must exceed lo");
   }
-  if (p->eq < SISDC_EQ_CONVDIFF || p->eq > SISDC_EQ_EULER) fail(SISDC_EINVAL, "unknown equation");
-  if (p->eq == SISDC_EQ_EULER && !(p->gamma > 1.0)) fail(SISDC_EINVAL, "gamma must exceed 1");
-  if (p->eq != SISDC_EQ_EULER && !(p->nu >= 0.0)) fail(SISDC_EINVAL, "nu must be >= 0");
+  if (p->eq < SISDC_EQ_CONVDIFF || p->eq > SISDC_EQ_NS) fail(SISDC_EINVAL, "unknown equation");
+  const bool sys = p->eq == SISDC_EQ_EULER || p->eq == SISDC_EQ_NS;
+  if (sys && !(p->gamma > 1.0)) fail(SISDC_EINVAL, "gamma must exceed 1");
+  if (!sys && !(p->nu >= 0.0)) fail(SISDC_EINVAL, "nu must be >= 0");
+  if (p->eq == SISDC_EQ_NS && (!(p->mu >= 0.0) || !(p->Pr > 0.0))) fail(SISDC_EINVAL, "NS needs mu >= 0, Pr > 0");
   if (m->n_levels < 1 || m->n_levels > 3) fail(SISDC_EINVAL, "n_levels must be 1..3");
   for (int l = 0; l < m->n_levels; ++l) {
     if (m->P[l] < 1 || m->P[l] > kMaxP) fail(SISDC_EINVAL, "P must be 1..8");
@@ -1103,10 +1120,14 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->stream = (hipStream_t)hip_stream;
     h->ctau = meth->c_tau > 0.0 ? meth->c_tau : 2.0;
     h->eq.eq = prob->eq;
-    h->eq.nv = prob->eq == SISDC_EQ_EULER ? prob->dim + 2 : 1;
+    const bool sys = prob->eq == SISDC_EQ_EULER || prob->eq == SISDC_EQ_NS;
+    h->eq.nv = sys ? prob->dim + 2 : 1;
     for (int d = 0; d < 3; ++d) h->eq.a[d] = d < prob->dim ? prob->a[d] : 0.0;
-    h->eq.nu = prob->eq == SISDC_EQ_EULER ? 0.0 : prob->nu;
+    h->eq.nu = sys ? 0.0 : prob->nu;
     h->eq.gamma = prob->gamma;
+    h->eq.R = prob->R > 0.0 ? prob->R : 1.0;
+    h->eq.mu = prob->eq == SISDC_EQ_NS ? prob->mu : 0.0;
+    h->eq.lam_T = prob->eq == SISDC_EQ_NS ? prob->mu * (prob->gamma * h->eq.R / (prob->gamma - 1.0)) / prob->Pr : 0.0;
     h->lv.resize(meth->n_levels);
     for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
@@ -1136,9 +1157,9 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hres = (CGRes*)hp;
     h->hdone = (int*)((char*)hp + 128);
     h->hlam = (double*)((char*)hp + 192);
-    h->hir_tot = (double*)((char*)hp + 208);
-    h->hnrej = (int*)((char*)hp + 240);
-    h->lam_dev = dalloc(1);
+    h->hir_tot = (double*)((char*)hp + 208 + 16);
+    h->hnrej = (int*)((char*)hp + 248);
+    h->lam_dev = dalloc(2);
     h->pcap = 1024;
     h->ppart = dalloc((size_t)8 * h->pcap + 8);
     HIPCHECK(hipMemset(h->ppart, 0, ((size_t)8 * h->pcap + 8) * sizeof(double)));

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsisdc.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
-EQ_CONVDIFF, EQ_BURGERS, EQ_EULER = 0, 1, 2
+EQ_CONVDIFF, EQ_BURGERS, EQ_EULER, EQ_NS = 0, 1, 2, 3
 SI2, SI1 = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64, MIXED = 0, 1
@@ -39,7 +39,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int * 3),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("eq", ctypes.c_int), ("a", ctypes.c_double * 3),
-                ("nu", ctypes.c_double), ("gamma", ctypes.c_double)]
+                ("nu", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("mu", ctypes.c_double), ("Pr", ctypes.c_double), ("R", ctypes.c_double)]
 
 
 class Method(ctypes.Structure):
@@ -156,7 +157,7 @@ def _mem_of(*arrays):
     return mems.pop() if mems else MEM_HOST
 
 
-def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4):
+def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, Pr=0.71, R=1.0):
     p = Problem()
     p.dim = dim
     for d in range(3):
@@ -167,6 +168,9 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4):
     p.eq = eq
     p.nu = nu
     p.gamma = gamma
+    p.mu = mu
+    p.Pr = Pr
+    p.R = R
     return p
 
 

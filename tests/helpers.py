@@ -3,7 +3,7 @@ an oracle level (CPU, FP64) and once as a libsisdc handle (GPU)."""
 import numpy as np
 
 from oracle import sdc as osdc
-from oracle.physics import ConvDiff, Burgers, Euler
+from oracle.physics import ConvDiff, Burgers, Euler, NavierStokes
 
 
 def rel_l2(a, b):
@@ -13,17 +13,22 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+NS_MU, NS_PR = 0.02, 0.71
+
+
 def oracle_phys(eq, dim, a=(1.0, 0.5, 0.25), nu=0.01, gamma=1.4):
     if eq == "convdiff":
         return ConvDiff(list(a[:dim]), nu)
     if eq == "burgers":
         return Burgers(dim, nu)
+    if eq == "ns":
+        return NavierStokes(dim, gamma, NS_MU, NS_PR)
     return Euler(dim, gamma)
 
 
 def lib_problem(S, eq, dim, n, lo, hi, a=(1.0, 0.5, 0.25), nu=0.01, gamma=1.4):
-    code = {"convdiff": S.EQ_CONVDIFF, "burgers": S.EQ_BURGERS, "euler": S.EQ_EULER}[eq]
-    return S.make_problem(dim, n, lo, hi, code, a=a[:dim], nu=nu, gamma=gamma)
+    code = {"convdiff": S.EQ_CONVDIFF, "burgers": S.EQ_BURGERS, "euler": S.EQ_EULER, "ns": S.EQ_NS}[eq]
+    return S.make_problem(dim, n, lo, hi, code, a=a[:dim], nu=nu, gamma=gamma, mu=NS_MU, Pr=NS_PR)
 
 
 def random_state(phys, mesh, rng, amp=1.0):

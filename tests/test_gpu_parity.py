@@ -56,6 +56,8 @@ OPS = [
     ("burgers", 3, (2, 3, 2), 2),
     ("euler", 3, (2, 2, 3), 3),
     ("burgers", 2, (1, 3), 5),
+    ("ns", 2, (3, 4), 5),
+    ("ns", 3, (2, 3, 2), 4),
 ]
 
 
@@ -226,7 +228,8 @@ def test_vcycle_two_levels(S):
 
 
 @pytest.mark.parametrize("variant", ["auto", "multi"])
-@pytest.mark.parametrize("case", ["convdiff_sl", "burgers_2l_cascade", "euler_3l_fmg", "convdiff_3d_2l"])
+@pytest.mark.parametrize("case", ["convdiff_sl", "burgers_2l_cascade", "euler_3l_fmg", "convdiff_3d_2l",
+                                  "ns_3d_2l"])
 def test_steps(S, case, variant):
     if case == "convdiff_sl":
         args = dict(eq="convdiff", dim=2, n=(3, 4), Ps=[4], Ms=[3], n_iter=4)
@@ -239,10 +242,14 @@ def test_steps(S, case, variant):
         args = dict(eq="euler", dim=2, n=(4, 4), Ps=[6, 4, 2], Ms=[5, 3, 2], n_iter=2,
                     start=S.START_FMG, lo=[0, 0], hi=[10, 10])
         dt, nsteps = 0.1, 2
-    else:
+    elif case == "convdiff_3d_2l":
         args = dict(eq="convdiff", dim=3, n=(2, 2, 3), Ps=[3, 2], Ms=[3, 2], n_iter=2,
                     start=S.START_CASCADE)
         dt, nsteps = 0.01, 2
+    else:
+        args = dict(eq="ns", dim=3, n=(2, 3, 2), Ps=[4, 2], Ms=[3, 2], n_iter=2,
+                    start=S.START_CASCADE, lo=[0, 0, 0], hi=[2 * np.pi] * 3)
+        dt, nsteps = 4e-3, 2
     eq, dim = args["eq"], args["dim"]
     phys, levels, sv = make_pair(S, eq, dim, args["n"], args["Ps"], args["Ms"], lo=args.get("lo"),
                                  hi=args.get("hi"), nu=args.get("nu", 0.01), n_iter=args["n_iter"],
@@ -253,6 +260,9 @@ def test_steps(S, case, variant):
     if eq == "euler":
         from paper_2504_18526_amd.inputs import isentropic_vortex
         u = isentropic_vortex(fine.coords())
+    elif eq == "ns":
+        from paper_2504_18526_amd.inputs import taylor_green
+        u = taylor_green(fine.coords(), mach=0.1)
     else:
         u = smooth_state(phys, fine, rng)
     if len(levels) == 1:
