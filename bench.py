@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--reps", type=int, default=400, help="launches timed for the roofline kernel")
     ap.add_argument("--variant-steps", type=int, default=50,
                     help="steps timed for each of the mixed / learned variants (0: skip them)")
+    ap.add_argument("--workload", default="burgers",
+                    help="burgers (default: the two-level Burgers workload), convdiff, euler, ns")
     return ap.parse_args()
 
 
@@ -48,13 +50,20 @@ def cpu_baseline(w, u0_path, gpu_step1_path, nsteps):
 import sys, time, json, numpy as np
 sys.path.insert(0, {ROOT!r})
 from oracle.sdc import DGLevel, MLSDC
-from oracle.physics import Burgers
+from oracle.physics import Burgers, ConvDiff, Euler, NavierStokes
 w = {json.dumps({k: v for k, v in w.items()})}
-ph = Burgers(w['dim'], w['nu'])
+if w['eq'] == 'burgers':
+    ph = Burgers(w['dim'], w['nu'])
+elif w['eq'] == 'convdiff':
+    ph = ConvDiff(list(w['a'][:w['dim']]), w['nu'])
+elif w['eq'] == 'euler':
+    ph = Euler(w['dim'], w['gamma'])
+else:
+    ph = NavierStokes(w['dim'], w['gamma'], w['mu'], w['Pr'])
 lv = [DGLevel(ph, w['n_elem'], w['lo'], w['hi'], P, M, rtol=w['cg_rtol']) for P, M in zip(w['P'], w['M'])]
 ml = MLSDC(list(reversed(lv)), n_coarse=w['n_coarse'], start=w['start'], cycles=w['cycles'],
            post_sweep=bool(w['post_sweep']))
-u = np.load({u0_path!r}).reshape(lv[0].mesh.shape(1))
+u = np.load({u0_path!r}).reshape(lv[0].mesh.shape(ph.nv))
 g1 = np.load({gpu_step1_path!r}).reshape(u.shape)
 t = time.perf_counter()
 for k in range({nsteps}):
@@ -71,7 +80,7 @@ print(json.dumps({{"seconds": el, "steps": {nsteps}, "rel_l2_step1": err}}))
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
-def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates):
+def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates, start):
     """Plain FP64 vs mixed precision vs the learned initial guess (and both),
     each from the same state after the same warm-up, same PCG tolerance.
     The network of each level is trained on rows harvested from the plain
@@ -82,7 +91,7 @@ def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates):
     ref = None
     for name, prec, learned in (("plain_fp64", S.FP64, False), ("mixed", S.MIXED, False),
                                 ("learned_fp64", S.FP64, True), ("learned_mixed", S.MIXED, True)):
-        meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+        meth = S.make_method(w["P"], w["M"], start=start, n_coarse_sweeps=w["n_coarse"],
                              post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
                              cg_maxit=1000, precision=prec)
         sv = S.Solver(prob, meth, stream=stream.cuda_stream)
@@ -140,20 +149,36 @@ def main():
     import torch
     from paper_2504_18526_amd import sisdc as S
     from paper_2504_18526_amd.inputs import burgers_field
-    from paper_2504_18526_amd.workloads import burgers_2level, fine_sweeps_per_step
+    from paper_2504_18526_amd.workloads import fine_sweeps_per_step
 
-    w = burgers_2level()
+    from paper_2504_18526_amd.inputs import convdiff_field, isentropic_vortex, taylor_green
+    from paper_2504_18526_amd.workloads import WORKLOADS, systems_dt
+    w = WORKLOADS[a.workload]()
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    prob = S.make_problem(w["dim"], w["n_elem"], w["lo"], w["hi"], S.EQ_BURGERS, nu=w["nu"])
-    meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+    eqc = {"convdiff": S.EQ_CONVDIFF, "burgers": S.EQ_BURGERS, "euler": S.EQ_EULER, "ns": S.EQ_NS}[w["eq"]]
+    prob = S.make_problem(w["dim"], w["n_elem"], w["lo"], w["hi"], eqc, a=w.get("a", (0.0, 0.0, 0.0)),
+                          nu=w.get("nu", 0.0), gamma=w.get("gamma", 1.4), mu=w.get("mu", 0.0),
+                          Pr=w.get("Pr", 0.71))
+    start = {"cascade": S.START_CASCADE, "fmg": S.START_FMG}[w["start"]]
+    meth = S.make_method(w["P"], w["M"], start=start, n_coarse_sweeps=w["n_coarse"],
                          post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
                          cg_maxit=1000)
     sv = S.Solver(prob, meth, stream=stream.cuda_stream)
     E, Np, nv, M = sv.level_info(0)
     x = sv.coords(0)
-    u0 = burgers_field([x[d] for d in range(w["dim"])], seed=w["seed"], kmax=w["kmax"]).reshape(1, E, Np)
-    u0 = np.ascontiguousarray(u0)
+    xs = [x[d] for d in range(w["dim"])]
+    if w["eq"] == "burgers":
+        u0 = burgers_field(xs, seed=w["seed"], kmax=w["kmax"])[None]
+    elif w["eq"] == "convdiff":
+        u0 = convdiff_field(xs, seed=w["seed"], kmax=w["kmax"])[None]
+    elif w["eq"] == "euler":
+        u0 = isentropic_vortex(xs)
+    else:
+        u0 = taylor_green(xs, mach=w["mach"])
+    u0 = np.ascontiguousarray(u0.reshape(nv, E, Np))
+    if "dt" not in w:
+        w["dt"] = systems_dt(w, u0)
     ud = torch.from_numpy(u0).to(dev)
     sv.set_state(ud)
     dt = w["dt"]
@@ -192,18 +217,19 @@ def main():
     # with its fused dot product, fine level, at the first substep
     dtm = dt / M  # a representative substep length
     us = sv.profile_kernel(S.K_SIPG_APPLY, 0, dtm, reps=a.reps)
-    nf = 9  # (P+1)^(d-1) face nodes at P = 8, d = 2
-    bytes_per_dof = 8.0 * (3.0 + 2 * w["dim"] * nf / Np)  # read p, read u_b, write Ap, read neighbour traces
+    nf = (w["P"][0] + 1) ** (w["dim"] - 1)  # face nodes per element face
+    reads_ub = 1.0 if w["eq"] == "burgers" else 0.0   # the coefficient state (Burgers only)
+    bytes_per_dof = 8.0 * (2.0 + reads_ub + 2 * w["dim"] * nf / Np)  # read p (+ u_b), write Ap, neighbour traces
     algo_bytes = bytes_per_dof * E * Np * nv
     achieved = algo_bytes / (us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sipg_apply<2,8> (CG matvec)", "avg_launch_us": round(us, 3),
+                "kernel": f"k_sipg_apply<{w['dim']},{w['P'][0]}> (CG matvec)", "avg_launch_us": round(us, 3),
                 "algo_bytes_per_launch": int(algo_bytes)}
 
     variants = None
     if a.variant_steps > 0:
-        variants = run_variants(S, w, prob, stream, ud, dt, a.variant_steps, dof_updates)
+        variants = run_variants(S, w, prob, stream, ud, dt, a.variant_steps, dof_updates, start)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -224,7 +250,7 @@ def main():
         "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded Fourier initial data)",
-        "config": {"workload": w["name"], "global_batch": 1, "seq_len": None, "parallelism": "none",
+        "config": {"workload": w["name"], "levels_P": w["P"], "levels_M": w["M"], "global_batch": 1, "seq_len": None, "parallelism": "none",
                    "dt": dt, "fine_dof": E * Np * nv, "fine_sweeps_per_step": sweeps,
                    "cg_iters_per_step": tot["cg_iters"] / a.steps, "solves_per_step": tot["solves"] / a.steps,
                    "not_converged": tot["not_converged"], "max_rel_residual": tot["max_rel_residual"],

@@ -52,3 +52,55 @@ def fine_sweeps_per_step(w):
     if len(w["P"]) == 1:
         return 1 + w["cycles"]
     return w["cycles"] + (1 if w["post_sweep"] else 0)
+
+
+def euler_3level():
+    """Three-level SI-MLSDC, 2-D Euler isentropic vortex on [0,10]^2 (eps = 5,
+    background Mach 0.5 along +x, gamma = 1.4): 64 x 64 elements, P 6/4/2,
+    M 5/3/2, FMG start, 3 V-cycles + post-sweep, N_c = 2, CFL = 4 with lam =
+    max over nodes of sum_d (|v_d| + c) of u0, 40 steps."""
+    return dict(
+        name="euler2d_vortex_mlsdc_64x64_P6-4-2_M5-3-2",
+        eq="euler", dim=2, n_elem=(64, 64), lo=(0.0, 0.0), hi=(10.0, 10.0), gamma=1.4,
+        P=[6, 4, 2], M=[5, 3, 2], start="fmg", cycles=3, n_coarse=2, post_sweep=1,
+        cfl=4.0, steps=40, cg_rtol=1e-10,
+    )
+
+
+def ns_2level():
+    """Two-level SI-MLSDC, 3-D compressible Navier-Stokes Taylor-Green
+    vortex on [0, 2 pi]^3: 16^3 hexahedra, P 7/3, M 4/2, Re = 1600 (mu =
+    1/1600 with rho0 = V0 = L = 1), Ma = 0.1, Pr = 0.71, gamma = 1.4, R = 1;
+    cascade start, 3 V-cycles + post-sweep, N_c = 2, CFL = 8 with the
+    acoustic lam = max sum_d (|v_d| + c), 10 steps."""
+    return dict(
+        name="ns3d_taylor_green_mlsdc_16^3_P7-3_M4-2",
+        eq="ns", dim=3, n_elem=(16, 16, 16), lo=(0.0, 0.0, 0.0), hi=(6.283185307179586,) * 3,
+        gamma=1.4, mu=1.0 / 1600.0, Pr=0.71, mach=0.1,
+        P=[7, 3], M=[4, 2], start="cascade", cycles=3, n_coarse=2, post_sweep=1,
+        cfl=8.0, steps=10, cg_rtol=1e-10,
+    )
+
+
+def systems_dt(w, u0):
+    """dt from the CFL number for the Euler / Navier-Stokes workloads:
+    lam = max over nodes of sum_d (|v_d| + c) of the initial state u0
+    (conservative variables [var][...])."""
+    import numpy as np
+    g = w["gamma"]
+    dim = w["dim"]
+    rho = u0[0]
+    v = [u0[1 + d] / rho for d in range(dim)]
+    p = (g - 1.0) * (u0[dim + 1] - 0.5 * rho * sum(vd * vd for vd in v))
+    c = np.sqrt(g * p / rho)
+    lam = float(np.max(sum(np.abs(vd) + c for vd in v)))
+    h = (w["hi"][0] - w["lo"][0]) / w["n_elem"][0]
+    return cfl_dt(w["cfl"], h, w["P"][0], lam)
+
+
+WORKLOADS = {
+    "convdiff": convdiff_1level,
+    "burgers": burgers_2level,
+    "euler": euler_3level,
+    "ns": ns_2level,
+}
