@@ -7,9 +7,12 @@ post-sweep, every implicit system solved by PCG to a relative residual of
 1e-10.  Metric: fine-level DOF-updates/s =
 nodes_fine * n_var * M_fine * fine_sweeps_per_step / (s / step).
 
-Prints one JSON line with the contract fields plus `roofline` (the CG
-matvec kernel, timed with HIP events on the solver's stream) and
-`cpu_baseline` (the CPU oracle on a bounded sample, rank 0, N = 1).
+Prints one JSON line with the contract fields plus `roofline` and
+`cpu_baseline` (the CPU oracle on a bounded sample, rank 0, N = 1).  The
+roofline kernel is the persistent fine-level PCG (one launch per Helmholtz
+solve), timed with HIP events on the solver's stream around each of its
+launches in the timed steps; where a level runs the multi-kernel PCG it is
+the CG matvec pass, timed over back-to-back launches.
 """
 import argparse
 import json
@@ -24,6 +27,39 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the roofline kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
+#   bench.py --no-cpu-baseline --variant-steps 0
+# averaged over that kernel's dispatches and scaled by what the same counters
+# read for a 256 MiB device copy (FETCH_SIZE reads half of the bytes a copy
+# moves, WRITE_SIZE all of them).  A figure holds only for the kernel sources
+# it was taken on (SHA-256 prefix of the files that build the kernel).
+COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+MEASURED_TRAFFIC = {}
+TRAFFIC_SOURCES = {
+    "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "launch.hpp", "xcd.hpp"],
+    "k_sipg_apply": ["kernels.hip", "common.hpp", "launch.hpp", "xcd.hpp"],
+}
+
+
+def kernel_source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    base = kernel.split("<")[0]
+    for f in TRAFFIC_SOURCES[base]:
+        with open(os.path.join(ROOT, "paper_2504_18526_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """Counter-measured HBM bytes per launch, or None when there is no
+    measurement for this kernel source."""
+    rec = MEASURED_TRAFFIC.get((workload, kernel))
+    if rec is None or rec["src"] != kernel_source_digest(kernel):
+        return None
+    return int(1024 * (rec["fetch_kib"] * COUNTER_SCALE["FETCH_SIZE"] + rec["write_kib"] * COUNTER_SCALE["WRITE_SIZE"]))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,6 +71,8 @@ def parse():
     ap.add_argument("--reps", type=int, default=400, help="launches timed for the roofline kernel")
     ap.add_argument("--variant-steps", type=int, default=50,
                     help="steps timed for each of the mixed / learned variants (0: skip them)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="burgers",
                     help="burgers (default: the two-level Burgers workload), convdiff, euler, ns")
     return ap.parse_args()
@@ -155,6 +193,12 @@ def main():
     from paper_2504_18526_amd.workloads import WORKLOADS, systems_dt
     w = WORKLOADS[a.workload]()
     dev = torch.device("cuda:0")
+    if a.copy_probe_mb > 0:
+        src = torch.empty(a.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.Stream(device=dev)
     eqc = {"convdiff": S.EQ_CONVDIFF, "burgers": S.EQ_BURGERS, "euler": S.EQ_EULER, "ns": S.EQ_NS}[w["eq"]]
     prob = S.make_problem(w["dim"], w["n_elem"], w["lo"], w["hi"], eqc, a=w.get("a", (0.0, 0.0, 0.0)),
@@ -192,6 +236,7 @@ def main():
             sv.get_state(out)
             step1 = out.cpu().numpy()
 
+    sv.pcg_timing(True)  # events around every persistent PCG launch of the timed steps
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -213,19 +258,42 @@ def main():
     dof_updates = E * Np * nv * M * sweeps
     value = dof_updates / (ms_step / 1000.0)
 
-    # roofline of the dominant kernel: the CG matvec pass (M + dt_m K_D) p
-    # with its fused dot product, fine level, at the first substep
-    dtm = dt / M  # a representative substep length
+    # roofline of the dominant kernel
+    pcg_n, pcg_it, pcg_us = sv.pcg_timing_get(0)
+    sv.pcg_timing(False)
+    fine_dof = E * Np * nv
+    # the CG matvec pass (M + dt_m K_D) p with its fused dot product, fine
+    # level, at a representative substep (separate launches, HIP events)
+    dtm = dt / M
     us = sv.profile_kernel(S.K_SIPG_APPLY, 0, dtm, reps=a.reps)
     nf = (w["P"][0] + 1) ** (w["dim"] - 1)  # face nodes per element face
     reads_ub = 1.0 if w["eq"] == "burgers" else 0.0   # the coefficient state (Burgers only)
     bytes_per_dof = 8.0 * (2.0 + reads_ub + 2 * w["dim"] * nf / Np)  # read p (+ u_b), write Ap, neighbour traces
-    algo_bytes = bytes_per_dof * E * Np * nv
-    achieved = algo_bytes / (us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_sipg_apply<{w['dim']},{w['P'][0]}> (CG matvec)", "avg_launch_us": round(us, 3),
-                "algo_bytes_per_launch": int(algo_bytes)}
+    mv_bytes = bytes_per_dof * fine_dof
+    mv_name = f"k_sipg_apply<{w['dim']},{w['P'][0]}>"
+    matvec = {"kernel": mv_name + " (CG matvec)", "avg_launch_us": round(us, 3),
+              "algo_bytes_per_launch": int(mv_bytes),
+              "achieved_GBs": round(mv_bytes / (us * 1e-6) / 1e9, 1)}
+    if pcg_n > 0:
+        # the persistent PCG: one launch = one whole fine-level Helmholtz solve.
+        # Algorithmic bytes of a streaming PCG: 5 FP64 words per DOF to set up
+        # a solve and 11 per iteration (fused matvec / dot / update).
+        name = f"k_pcg_persistent<{w['dim']},{w['P'][0]},{nv}>"
+        algo = 8.0 * fine_dof * (5.0 * pcg_n + 11.0 * pcg_it)
+        achieved = algo / (pcg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(w["name"], name),
+                    "kernel": name + " (whole fine-level PCG solve)",
+                    "avg_launch_us": round(pcg_us / pcg_n, 3), "launches": pcg_n,
+                    "iters_per_launch": round(pcg_it / pcg_n, 3),
+                    "algo_bytes_per_launch": int(algo / pcg_n), "matvec": matvec}
+    else:
+        roofline = {"bound": "hbm", "achieved": matvec["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(matvec["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(w["name"], mv_name),
+                    "kernel": matvec["kernel"], "avg_launch_us": matvec["avg_launch_us"],
+                    "algo_bytes_per_launch": matvec["algo_bytes_per_launch"]}
 
     variants = None
     if a.variant_steps > 0:

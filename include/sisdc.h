@@ -238,6 +238,20 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
 enum { SISDC_K_SIPG_APPLY = 0, SISDC_K_SIPG_TRACE = 1, SISDC_K_CONV = 2, SISDC_K_CG_UPDATE = 3 };
 int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, int reps, double* avg_us);
 
+/* Measurement hook for the persistent PCG (one cooperative launch per
+ * Helmholtz solve, used for levels whose tiles are co-resident and for
+ * tolerances >= 1e-11).  With on = 1 the handle records a pair of HIP events
+ * on its stream around every persistent launch and accumulates, per level,
+ * the launches, the CG iterations they report and the event time between
+ * each pair; switching on clears the sums.  on = 0 stops recording (the sums
+ * are kept).  Results of launches still in flight are collected first, so
+ * both calls synchronise the handle's stream. */
+int sisdc_pcg_timing(sisdc_handle* h, int on);
+/* The sums of sisdc_pcg_timing for one level: launches, iterations and total
+ * event time in microseconds (any output pointer may be NULL). */
+int sisdc_pcg_timing_get(sisdc_handle* h, int level, long long* launches, long long* iters,
+                         double* total_us);
+
 /* Learned initial guess of a level's Helmholtz solves: an element-local MLP
  * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)
  * row of the mass-scaled initial residual z0 = M^-1 (b - A x0), normalised to

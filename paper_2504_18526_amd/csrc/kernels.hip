@@ -17,6 +17,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "xcd.hpp"
 
 namespace sisdc {
 
@@ -151,7 +152,7 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sf[EPB * NV * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
@@ -283,7 +284,7 @@ k_visc_trace(const double* __restrict__ u, double* __restrict__ trace, Geo g, Eq
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sq[(DIM + 1) * EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
@@ -326,7 +327,7 @@ k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const doubl
   __shared__ double sq[(DIM + 1) * EPB * NP];
   __shared__ double sf[NV * EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
@@ -434,7 +435,7 @@ k_sipg_trace(const T* __restrict__ x, int nv, long vs, CoefT<T> cf, T* __restric
   __shared__ T sD[N1 * N1];
   __shared__ T sx[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   int ii[3];
@@ -477,7 +478,9 @@ k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, Coef
   const T pen = ctau * (T)(N1 * N1);
   const int ntiles = (g.E + EPB - 1) / EPB;
   T dacc = T(0.0);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  int tile0, tile1;
+  tile_range(ntiles, tile0, tile1);
+  for (int tile = tile0; tile < tile1; ++tile) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
@@ -564,7 +567,7 @@ k_helm_diag(T* __restrict__ diag, int nv, long vs, CoefT<T> cf, T dtm, T ctau, G
   __shared__ T sD[N1 * N1], sw[N1];
   __shared__ T sc[EPB * NP];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
   for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
@@ -631,7 +634,9 @@ k_cg_start(CGStateT<T> cg, int nv, long vs, CoefT<T> cf, Geo g, const T* __restr
   decomp<DIM, N1>(n, ii);
   const int ntiles = (g.E + EPB - 1) / EPB;
   T a[3] = {T(0.0), T(0.0), T(0.0)};
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  int tile0, tile1;
+  tile_range(ntiles, tile0, tile1);
+  for (int tile = tile0; tile < tile1; ++tile) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
@@ -709,7 +714,9 @@ k_cg_iter(CGStateT<T> cg, int nv, long vs, CoefT<T> cf, Geo g, const T* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) cg.alpha[it % 2] = alpha;
   const int ntiles = (g.E + EPB - 1) / EPB;
   T a[2] = {T(0.0), T(0.0)};
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  int tile0, tile1;
+  tile_range(ntiles, tile0, tile1);
+  for (int tile = tile0; tile < tile1; ++tile) {
     const int e = tile * EPB + le;
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;

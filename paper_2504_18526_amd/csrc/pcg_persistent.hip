@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "xcd.hpp"
 
 namespace sisdc {
 
@@ -151,7 +152,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   __shared__ double sc[EPB * NP];
   __shared__ int s_ok;
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
   const long vs = (long)g.E * NP;
   const long own = (long)e * NP + n;

@@ -148,6 +148,12 @@ struct sisdc_handle {
   CGRes* hring = nullptr;      // pinned host mirror
   int ring_n = 0;              // records in flight
   std::vector<std::pair<int, int>> ring_meta;  // (level, maxit) per record
+  // event timing of the persistent PCG launches (sisdc_pcg_timing)
+  bool ptime = false;
+  std::vector<hipEvent_t> pev;   // 2 per ring record: before / after the launch
+  std::vector<char> ring_timed;  // per record: events recorded
+  std::vector<double> pt_us;     // per level: summed event time (us) ...
+  std::vector<long long> pt_n, pt_it;  // ... launches and iterations
   double* lam_dev = nullptr;
   double* hlam = nullptr;      // pinned
   double* state = nullptr;
@@ -345,11 +351,20 @@ void drain(sisdc_handle* h) {
     const double rel = r.bb > 0.0 ? std::sqrt(r.rr / r.bb) : 0.0;
     if (!std::isfinite(rel)) nonfinite = true;
     account(h, r.it, conv, rel);
-    Level& L = h->lv[h->ring_meta[i].first];
+    const int li = h->ring_meta[i].first;
+    Level& L = h->lv[li];
     L.last_iters = std::max(1, r.it);
+    if (h->ring_timed[i]) {
+      float ms = 0.0f;
+      HIPCHECK(hipEventElapsedTime(&ms, h->pev[2 * i], h->pev[2 * i + 1]));
+      h->pt_us[li] += 1000.0 * ms;
+      h->pt_n[li] += 1;
+      h->pt_it[li] += r.it;
+    }
   }
   h->ring_n = 0;
   h->ring_meta.clear();
+  h->ring_timed.clear();
   if (aborted) {
     HIPCHECK(hipMemsetAsync(h->bar, 0, 512, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
@@ -382,12 +397,16 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   HIPCHECK(hipGetDevice(&dev));
   HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const int max_blocks = pcg_persistent_blocks_per_cu(L.g, L.nv) * ncu;
+  const int slot = h->ring_n;
+  if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot], h->stream));
   hipError_t e = launch_pcg_persistent(a, L.nv, cf, L.g, L.tab, max_blocks, h->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     L.persistent = false;
     return false;
   }
+  if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot + 1], h->stream));
+  h->ring_timed.push_back(h->ptime ? 1 : 0);
   h->ring_meta.emplace_back((int)(&L - h->lv.data()), maxit);
   h->ring_n += 1;
   return true;
@@ -1215,6 +1234,7 @@ int sisdc_destroy(sisdc_handle* h) {
   if (h->bar) (void)hipFree(h->bar);
   if (h->ring) (void)hipFree(h->ring);
   if (h->hring) (void)hipHostFree(h->hring);
+  for (hipEvent_t ev : h->pev) (void)hipEventDestroy(ev);
   if (h->state) (void)hipFree(h->state);
   if (h->io) (void)hipFree(h->io);
   delete h;
@@ -1456,6 +1476,34 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
     if (!out) fail(SISDC_EINVAL, "null output");
     colloc_residual(h, L, dt, L.r, nullptr);
     dev_out(h, out, L.r, (long)L.M * L.vlen, mem);
+  });
+}
+
+int sisdc_pcg_timing(sisdc_handle* h, int on) {
+  return guard([&] {
+    if (!h) fail(SISDC_EINVAL, "null handle");
+    drain(h);  // records launched before this call keep their own setting
+    if (on && h->pev.empty()) {
+      h->pev.resize(2 * kRing, nullptr);
+      for (auto& ev : h->pev) HIPCHECK(hipEventCreate(&ev));
+    }
+    if (on) {
+      h->pt_us.assign(h->lv.size(), 0.0);
+      h->pt_n.assign(h->lv.size(), 0);
+      h->pt_it.assign(h->lv.size(), 0);
+    }
+    h->ptime = on != 0;
+  });
+}
+
+int sisdc_pcg_timing_get(sisdc_handle* h, int level, long long* launches, long long* iters, double* total_us) {
+  return guard([&] {
+    level_at(h, level);
+    drain(h);
+    const bool have = (size_t)level < h->pt_us.size();
+    if (launches) *launches = have ? h->pt_n[level] : 0;
+    if (iters) *iters = have ? h->pt_it[level] : 0;
+    if (total_us) *total_us = have ? h->pt_us[level] : 0.0;
   });
 }
 

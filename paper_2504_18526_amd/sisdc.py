@@ -29,6 +29,7 @@ EXPORTS = [
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
+    "sisdc_pcg_timing", "sisdc_pcg_timing_get",
     "sisdc_net_init", "sisdc_net_get_params", "sisdc_net_set_params", "sisdc_net_forward",
     "sisdc_net_train_step", "sisdc_net_grad", "sisdc_net_harvest", "sisdc_net_train", "sisdc_net_use",
 ]
@@ -95,6 +96,9 @@ def load():
         "sisdc_apply": ([P, I, I, D, P, P, P, I], I),
         "sisdc_collocation_residual": ([P, I, D, P, I], I),
         "sisdc_profile_kernel": ([P, I, I, D, I, ctypes.POINTER(D)], I),
+        "sisdc_pcg_timing": ([P, I], I),
+        "sisdc_pcg_timing_get": ([P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(D)], I),
         "sisdc_net_init": ([P, I, I, ctypes.c_ulonglong, I, I], I),
         "sisdc_net_get_params": ([P, I, P, I, ctypes.POINTER(ctypes.c_longlong)], I),
         "sisdc_net_set_params": ([P, I, P, I], I),
@@ -307,6 +311,17 @@ class Solver:
         us = ctypes.c_double()
         _check(self._lib.sisdc_profile_kernel(self.h, kernel, level, dt_m, reps, ctypes.byref(us)))
         return us.value
+
+    def pcg_timing(self, on):
+        """Start (clearing the sums) or stop event timing of the persistent PCG launches."""
+        _check(self._lib.sisdc_pcg_timing(self.h, 1 if on else 0))
+
+    def pcg_timing_get(self, level):
+        """(launches, CG iterations, total event time in us) of the persistent
+        PCG launches on a level since timing was switched on."""
+        n, it, us = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_double()
+        _check(self._lib.sisdc_pcg_timing_get(self.h, level, ctypes.byref(n), ctypes.byref(it), ctypes.byref(us)))
+        return n.value, it.value, us.value
 
     # ---- learned initial guess (element-local MLP) ----
     def net_init(self, level, hidden, seed=0, max_batch=4096, max_rows=65536):
