@@ -15,8 +15,12 @@
 // therefore deterministic, and no atomics are used.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "common.hpp"
 #include "launch.hpp"
+#include "gll_const.hpp"
 #include "xcd.hpp"
 
 namespace sisdc {
@@ -554,6 +558,307 @@ k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, Coef
   }
 }
 
+// ---------------------------------------------------------------- SIPG, isotropic, hexahedra
+// K_D x for an isotropic coefficient D = nu I that is constant on the level
+// (the systems' kappa_m I; a scalar problem without convection) on
+// hexahedra with (P+1)^2 dividing 64.  With D isotropic the flux along axis
+// d involves only the derivative along d, so the operator splits into three
+// one-dimensional problems: for each axis, gradient, flux, the face terms
+// of the two faces normal to that axis and the transposed contraction act
+// on the P+1 nodes of a grid line.  The neighbour's face flux is the
+// derivative of the neighbour's own line, so no face-trace pass is needed.
+//
+// A group of (P+1)^2 lanes owns one (component, element) pair; for every
+// axis in turn lane l of the group holds, in registers, the line through
+// (a, b) = (l mod (P+1), l div (P+1)) along that axis, and the lines of the
+// two neighbours across the faces it ends on (loaded from global memory:
+// all three line layouts are coalesced).  The contributions of the three
+// axes are summed in an LDS region of the group (rows padded to P+2 to
+// spread the banks).  A group lies inside one wave, so the LDS exchange
+// needs no workgroup barrier; waves work on their own pairs.
+//
+// The operand is x, or x scaled node by node by isc[n] (isc holds NP values,
+// the same for every element and component: the inverse Jacobi diagonal of
+// an isotropic operator).  out = alpha M x + beta K_D x; with part != NULL
+// the block partial of (out, operand) is stored in part[blockIdx.x];
+// done_gen (nullable): skip when *done_gen == id.
+template <int P>
+struct ISO {
+  static constexpr int N1 = P + 1, NP = N1 * N1 * N1, LG = N1 * N1, GW = 64 / LG;
+  static constexpr int WAVES = P >= 7 ? 16 : 4;       // waves per workgroup
+  static constexpr int NT = 64 * WAVES, GPB = GW * WAVES;  // threads, groups per workgroup
+  static constexpr int SY = N1 + 1, SZ = N1 * SY, REG = N1 * SZ;  // padded LDS region of a group
+  static_assert(64 % LG == 0, "the lane groups must tile a wave");
+};
+
+// node index of position k on the grid line along axis D through (a, b)
+template <int D, int N1>
+__device__ __forceinline__ int line_node(int k, int a, int b) {
+  return D == 0 ? k + N1 * (a + N1 * b) : (D == 1 ? a + N1 * (k + N1 * b) : a + N1 * (b + N1 * k));
+}
+
+// Orders the LDS accesses of a wave: stores issued before are seen by the
+// loads of every lane of the wave issued after.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The operand on the line (a, b) along D of element e (component base xc),
+// scaled by the LDS table sc when `scaled`.
+// A line along axis 0 is contiguous and 16-byte aligned when 16 / sizeof(T)
+// divides P+1 (vectors start 256-byte aligned, an element holds (P+1)^3
+// values): it is then read with 16-byte loads, which touch a quarter (FP64)
+// of the cache lines per instruction that 8-byte loads at a lane stride of
+// P+1 values would.
+template <typename T, int P, int D>
+__device__ __forceinline__ void load_line(const T* __restrict__ xc, int e, int a, int b, const T* sc, bool scaled,
+                                          T (&v)[P + 1]) {
+  constexpr int N1 = P + 1, NP = N1 * N1 * N1;
+  constexpr int VW = 16 / (int)sizeof(T);  // values per 16-byte load
+  const T* const xe = xc + (long)e * NP;
+  if constexpr (D == 0 && N1 % VW == 0) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    const V* const lv = reinterpret_cast<const V*>(xe + line_node<0, N1>(0, a, b));
+#pragma unroll
+    for (int q = 0; q < N1 / VW; ++q) {
+      const V t = lv[q];
+      const T* const tt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) v[q * VW + i] = tt[i];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) v[k] = xe[line_node<D, N1>(k, a, b)];
+  }
+  if (scaled) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) v[k] *= sc[line_node<D, N1>(k, a, b)];
+  }
+}
+
+// Axis D of the isotropic apply on the line (a, b) of element e: xl holds
+// the operand on the line; r[k] receives the volume and face terms of line
+// node k.
+// f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>):
+// loop indices that are constant expressions.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// D[k][j] and w[k] of degree P as literal constants of type T
+template <typename T, int P, int K, int J>
+__device__ __forceinline__ constexpr T gll_d() {
+  constexpr T v = (T)kGLL<P>.D[K][J];
+  return v;
+}
+template <typename T, int P, int K>
+__device__ __forceinline__ constexpr T gll_w() {
+  constexpr T v = (T)kGLL<P>.w[K];
+  return v;
+}
+
+template <typename T, int P, int D>
+__device__ __forceinline__ void iso_axis(const T* __restrict__ xc, const T* sc, bool scaled,
+                                         const T (&xl)[P + 1], T (&r)[P + 1], int nbm, int nbp, int a, int b,
+                                         const Geo& g, T nu, T pen, T wab) {
+  constexpr int N1 = P + 1;
+  const T rh = (T)g.rh2[D], J = (T)g.J;
+  T q[N1], Q[N1];
+  static_for<N1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    T s = T(0.0);
+    static_for<N1>([&](auto jc) { s += gll_d<T, P, k, decltype(jc)::value>() * xl[decltype(jc)::value]; });
+    q[k] = nu * rh * s;  // flux along D
+    Q[k] = J * wab * gll_w<T, P, k>() * q[k];
+  });
+  const T jfwf = J * rh * wab;
+  const T tau = pen * nu * T(0.5) * rh;
+  static_for<2>([&](auto sidec) {
+    constexpr int side = decltype(sidec)::value;
+    constexpr int ke = side ? P : 0;   // this element's node on the face
+    constexpr int kn = side ? 0 : P;   // the neighbour's node on the face
+    const T sgn = side ? T(1.0) : -T(1.0);
+    T nl[N1];
+    load_line<T, P, D>(xc, side ? nbp : nbm, a, b, sc, scaled, nl);
+    T sn = T(0.0);
+    static_for<N1>([&](auto jc) { sn += gll_d<T, P, kn, decltype(jc)::value>() * nl[decltype(jc)::value]; });
+    const T qn = T(0.5) * sgn * (q[ke] + nu * rh * sn);
+    const T jump = xl[ke] - nl[kn];
+    r[ke] += jfwf * (-qn + tau * jump);
+    Q[ke] -= T(0.5) * jfwf * jump * sgn * nu;
+  });
+  static_for<N1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    T s = T(0.0);
+    static_for<N1>([&](auto jc) { s += gll_d<T, P, decltype(jc)::value, k>() * Q[decltype(jc)::value]; });
+    r[k] += rh * s;
+  });
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__((ISO<P>::NT))
+k_sipg_apply_iso3(const T* __restrict__ x, const T* __restrict__ isc, T* __restrict__ out, int nv, long vs, T nu,
+                  T alpha, T beta, T ctau, Geo g, const T* __restrict__ tab, T* part,
+                  const int* __restrict__ done_gen, int id) {
+  using I = ISO<P>;
+  constexpr int N1 = I::N1, LG = I::LG, SY = I::SY, SZ = I::SZ, REG = I::REG;
+  if (done_gen != nullptr && *done_gen == id) return;
+  __shared__ T sR[I::GPB * REG];
+  // one group per wave (P = 7): the pair, its element and its neighbours are
+  // wave-uniform and live in scalar registers
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int grp = I::GW == 1 ? 0 : lane / LG, l = lane - grp * LG;
+  const int a = l % N1, b = l / N1;
+  T* const R = &sR[(wave * I::GW + grp) * REG];
+  const T* const w = tab + N1 * N1;  // GLL weights (runtime table: lane-dependent index)
+  const T pen = ctau * (T)(N1 * N1), J = (T)g.J;
+  const T wab[3] = {w[b] * w[a], w[a] * w[b], w[a] * w[b]};  // line weights w_a w_b per axis
+  __shared__ T sc[I::NP];  // operand scale per node
+  const bool scaled = isc != nullptr;
+  if (scaled)
+    for (int k = threadIdx.x; k < I::NP; k += blockDim.x) sc[k] = isc[k];
+  __syncthreads();
+  const long npairs = (long)nv * g.E;
+  const long lb = xcd_block(blockIdx.x, gridDim.x);
+  const long p0 = lb * npairs / gridDim.x, p1 = (lb + 1) * npairs / gridDim.x;
+  T dacc = T(0.0);
+  for (long p = p0 + wave * I::GW + grp; p < p1; p += I::GPB) {
+    const int c = (int)(p / g.E), e = (int)(p - (long)c * g.E);
+    const int ex = e % g.ne[0], ey = (e / g.ne[0]) % g.ne[1], ez = e / (g.ne[0] * g.ne[1]);
+    const int sx = 1, sy = g.ne[0], sz = g.ne[0] * g.ne[1];
+    // neighbours across the faces normal to each axis (periodic)
+    const int nbm0 = e + (ex > 0 ? -sx : (g.ne[0] - 1) * sx), nbp0 = e + (ex < g.ne[0] - 1 ? sx : -(g.ne[0] - 1) * sx);
+    const int nbm1 = e + (ey > 0 ? -sy : (g.ne[1] - 1) * sy), nbp1 = e + (ey < g.ne[1] - 1 ? sy : -(g.ne[1] - 1) * sy);
+    const int nbm2 = e + (ez > 0 ? -sz : (g.ne[2] - 1) * sz), nbp2 = e + (ez < g.ne[2] - 1 ? sz : -(g.ne[2] - 1) * sz);
+    const T* const xc = x + c * vs;
+    T xl[N1], r[N1];
+    load_line<T, P, 0>(xc, e, a, b, sc, scaled, xl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    iso_axis<T, P, 0>(xc, sc, scaled, xl, r, nbm0, nbp0, a, b, g, nu, pen, wab[0]);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) R[k + SY * a + SZ * b] = r[k];
+    wave_lds_fence();
+    load_line<T, P, 1>(xc, e, a, b, sc, scaled, xl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    iso_axis<T, P, 1>(xc, sc, scaled, xl, r, nbm1, nbp1, a, b, g, nu, pen, wab[1]);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) R[a + SY * k + SZ * b] += r[k];
+    wave_lds_fence();
+    load_line<T, P, 2>(xc, e, a, b, sc, scaled, xl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    iso_axis<T, P, 2>(xc, sc, scaled, xl, r, nbm2, nbp2, a, b, g, nu, pen, wab[2]);
+    const T jab = J * w[a] * w[b];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const T val = alpha * jab * w[k] * xl[k] + beta * (r[k] + R[a + SY * b + SZ * k]);
+      out[c * vs + (long)e * I::NP + line_node<2, N1>(k, a, b)] = val;
+      dacc += val * xl[k];
+    }
+    wave_lds_fence();  // the next pair's stores follow these loads
+  }
+  if (part != nullptr) {
+    const T v1[1] = {dacc};
+    T* const pp[1] = {part};
+    block_partials<T, 1>(v1, pp);
+  }
+}
+
+// NP-periodic inverse of the Jacobi diagonal of an isotropic operator (the
+// diagonal is the same for every element and component): idg[n] = 1/diag[n].
+template <typename T>
+__global__ void k_inv_table(const T* __restrict__ diag, T* __restrict__ idg, int np) {
+  for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < np; n += gridDim.x * blockDim.x) idg[n] = T(1.0) / diag[n];
+}
+
+// Jacobi-PCG (Chronopoulos-Gear) for the isotropic operator, streaming form:
+// z = r idg is never stored (the matvec scales r itself), so an iteration
+// moves r, w, p, s, x in and r, p, s, x out, with no face traces.  Same
+// partial-sum protocol and stopping test as k_cg_start / k_cg_iter; blocks
+// take contiguous ranges of the flattened vectors.
+template <typename T, int NP>
+__global__ void __launch_bounds__(1024) k_cg_start_iso(CGStateT<T> cg, const T* __restrict__ idg, long n) {
+  T a[3] = {T(0.0), T(0.0), T(0.0)};
+  const long lb = xcd_block(blockIdx.x, gridDim.x);
+  const long i0 = lb * n / gridDim.x, i1 = (lb + 1) * n / gridDim.x;
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const T bi = cg.b[i];
+    const T ri = bi - cg.w[i];
+    const T zi = ri * idg[i & (NP - 1)];
+    cg.r[i] = ri;
+    a[0] += ri * zi;
+    a[1] += ri * ri;
+    a[2] += bi * bi;
+  }
+  T* const pp[3] = {cg.gam, cg.rr, cg.bbp};
+  block_partials<T, 3>(a, pp);
+}
+
+template <typename T, int NP>
+__global__ void __launch_bounds__(1024)
+k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id, int nparts) {
+  if (*cg.done_gen == id) return;
+  const int cap = cg.cap;
+  T tot[5];
+  {
+    const T* const pr[5] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.del,
+                            cg.rr + (it % 2) * cap, cg.bbp};
+    sum_partials<T, 5>(pr, nparts, tot);
+  }
+  const T gi = tot[0], gprev = tot[1], di = tot[2], rri = tot[3], bb = tot[4];
+  const T thresh = cg.tol2 * bb;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cg.res->rr = rri;
+    cg.res->bb = bb;
+    cg.res->thresh = thresh;
+    cg.res->it_last = it;
+  }
+  if (rri <= thresh || !(rri == rri)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cg.res->it = it;
+      *cg.done_gen = id;
+    }
+    return;
+  }
+  T beta = T(0.0), alpha;
+  if (it == 0) {
+    alpha = gi / di;
+  } else {
+    beta = gi / gprev;
+    alpha = gi / (di - beta * gi / cg.alpha[(it + 1) % 2]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg.alpha[it % 2] = alpha;
+  T a[2] = {T(0.0), T(0.0)};
+  const long lb = xcd_block(blockIdx.x, gridDim.x);
+  const long i0 = lb * n / gridDim.x, i1 = (lb + 1) * n / gridDim.x;
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const T ig = idg[i & (NP - 1)];
+    const T r0 = cg.r[i], wi = cg.w[i];
+    const T z0 = r0 * ig;
+    const T pi = it == 0 ? z0 : z0 + beta * cg.p[i];
+    const T si = it == 0 ? wi : wi + beta * cg.s[i];
+    cg.p[i] = pi;
+    cg.s[i] = si;
+    cg.x[i] += alpha * pi;
+    const T ri = r0 - alpha * si;
+    cg.r[i] = ri;
+    const T zi = ri * ig;
+    a[0] += ri * zi;
+    a[1] += ri * ri;
+  }
+  T* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
+  block_partials<T, 2>(a, pp);
+}
+
 // Jacobi diagonal of M + dt_m K_D (volume terms with d = d' and the face
 // terms of the node itself); any positive diagonal gives the same solution.
 template <typename T, int DIM, int P>
@@ -972,13 +1277,31 @@ static hipError_t sipg_trace_t(const T* x, int nv, const CoefT<T>& cf, T* trace,
   return hipErrorInvalidValue;
 }
 
+// The isotropic hexahedral kernel serves D = nu I (no convective part, no
+// coefficient state) for the degrees whose line groups tile a wave.
+template <typename T>
+static bool iso_coef(const CoefT<T>& cf) {
+  return cf.ub == nullptr && cf.v[0] == T(0.0) && cf.v[1] == T(0.0) && cf.v[2] == T(0.0);
+}
+
 template <typename T, int DIM, int P>
 static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta,
                               T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen,
                               int id, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
+  // the partial count must equal the grid of the CG kernels that sum them
   const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
+  if constexpr (DIM == 3 && (P == 1 || P == 3 || P == 7)) {
+    if (iso_coef(cf) && (part == nullptr || dotv == x)) {
+      using I = ISO<P>;
+      const long groups = ((long)nv * g.E + I::GPB - 1) / I::GPB;
+      const int nbi = part ? nb : (int)std::min<long>(std::max<long>(groups, 1), 8192);
+      hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nbi), dim3(I::NT), 0, s, x, (const T*)nullptr, out, nv, vs,
+                         cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_sipg_apply<T, DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha,
                      beta, ctau, g, tab, dotv, part, done_gen, id);
   return hipGetLastError();
@@ -1053,6 +1376,54 @@ static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, c
   return hipErrorInvalidValue;
 }
 
+// Isotropic hexahedral path: D = nu I constant on the level, dim 3, P in {1, 3, 7}.
+template <typename T>
+static bool iso_path_t(const Geo& g, const CoefT<T>& cf) {
+  return g.dim == 3 && (g.P == 1 || g.P == 3 || g.P == 7) && iso_coef(cf);
+}
+
+#define SISDC_DISPATCH_ISO(P_, BODY)                 \
+  switch (P_) {                                      \
+    case 1: { constexpr int PP = 1; BODY; } break;  \
+    case 3: { constexpr int PP = 3; BODY; } break;  \
+    case 7: { constexpr int PP = 7; BODY; } break;  \
+    default: return hipErrorInvalidValue;            \
+  }
+
+// grid of the isotropic CG kernels: the same partial count as the matvec
+template <int P>
+static int iso_grid(const Geo& g) {
+  return std::min(elem_tiles<3, P>(g), kElemCap);
+}
+
+template <typename T, int P>
+static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha, T beta,
+                              T ctau, const Geo& g, const T* tab, T* part, const int* done_gen, int id,
+                              hipStream_t s) {
+  using I = ISO<P>;
+  const long vs = (long)g.E * I::NP;
+  hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(iso_grid<P>(g)), dim3(I::NT), 0, s, x, isc, out, nv, vs, cf.nu,
+                     alpha, beta, ctau, g, tab, part, done_gen, id);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+static hipError_t cg_start_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {
+  constexpr int NP = (P + 1) * (P + 1) * (P + 1);
+  hipLaunchKernelGGL((k_cg_start_iso<T, NP>), dim3(iso_grid<P>(g)), dim3(1024), 0, s, cg, idg,
+                     (long)nv * g.E * NP);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,
+                                hipStream_t s) {
+  constexpr int NP = (P + 1) * (P + 1) * (P + 1);
+  const int nb = iso_grid<P>(g);
+  hipLaunchKernelGGL((k_cg_iter_iso<T, NP>), dim3(nb), dim3(1024), 0, s, cg, idg, (long)nv * g.E * NP, it, id, nb);
+  return hipGetLastError();
+}
+
 #define SISDC_PRECISION_LAUNCHERS(T)                                                                            \
   hipError_t launch_sipg_trace(const T* x, int nv, const CoefT<T>& cf, T* trace, const Geo& g, const T* tab,     \
                                hipStream_t s) {                                                                 \
@@ -1065,8 +1436,10 @@ static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, c
   }                                                                                                             \
   hipError_t launch_sipg(const T* x, T* out, int nv, const CoefT<T>& cf, T* trace, T alpha, T beta, T ctau,     \
                          const Geo& g, const T* tab, hipStream_t s) {                                           \
-    hipError_t e = sipg_trace_t<T>(x, nv, cf, trace, g, tab, s);                                                \
-    if (e != hipSuccess) return e;                                                                              \
+    if (!iso_path_t<T>(g, cf)) { /* the isotropic kernel needs no trace pass */                                 \
+      hipError_t e = sipg_trace_t<T>(x, nv, cf, trace, g, tab, s);                                              \
+      if (e != hipSuccess) return e;                                                                            \
+    }                                                                                                           \
     return sipg_apply_t<T>(x, out, nv, cf, trace, alpha, beta, ctau, g, tab, nullptr, nullptr, nullptr, 0, s);  \
   }                                                                                                             \
   hipError_t launch_helm_diag(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,    \
@@ -1080,6 +1453,30 @@ static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, c
   hipError_t launch_cg_iter(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,      \
                             int it, int id, hipStream_t s) {                                                    \
     return cg_iter_t<T>(cg, nv, cf, g, tab, it, id, s);                                                         \
+  }                                                                                                             \
+  bool sipg_iso_path(const Geo& g, const CoefT<T>& cf) { return iso_path_t<T>(g, cf); }                         \
+  hipError_t launch_inv_table(const T* diag, T* idg, int np, hipStream_t s) {                                   \
+    hipLaunchKernelGGL((k_inv_table<T>), dim3((np + 255) / 256), dim3(256), 0, s, diag, idg, np);               \
+    return hipGetLastError();                                                                                   \
+  }                                                                                                             \
+  hipError_t launch_sipg_apply_iso(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha,       \
+                                   T beta, T ctau, const Geo& g, const T* tab, T* part, const int* done_gen,    \
+                                   int id, hipStream_t s) {                                                     \
+    if (!iso_path_t<T>(g, cf)) return hipErrorInvalidValue;                                                     \
+    SISDC_DISPATCH_ISO(g.P, return (apply_iso_p<T, PP>(x, isc, out, nv, cf, alpha, beta, ctau, g, tab, part,    \
+                                                       done_gen, id, s)));                                      \
+    return hipErrorInvalidValue;                                                                                \
+  }                                                                                                             \
+  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {    \
+    if (g.dim != 3) return hipErrorInvalidValue;                                                                \
+    SISDC_DISPATCH_ISO(g.P, return (cg_start_iso_p<T, PP>(cg, idg, nv, g, s)));                                 \
+    return hipErrorInvalidValue;                                                                                \
+  }                                                                                                             \
+  hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
+                                hipStream_t s) {                                                                \
+    if (g.dim != 3) return hipErrorInvalidValue;                                                                \
+    SISDC_DISPATCH_ISO(g.P, return (cg_iter_iso_p<T, PP>(cg, idg, nv, g, it, id, s)));                          \
+    return hipErrorInvalidValue;                                                                                \
   }
 
 SISDC_PRECISION_LAUNCHERS(double)

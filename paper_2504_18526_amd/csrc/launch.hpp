@@ -34,7 +34,18 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
   hipError_t launch_cg_start(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,     \
                              hipStream_t s);                                                                    \
   hipError_t launch_cg_iter(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,      \
-                            int it, int id, hipStream_t s);
+                            int it, int id, hipStream_t s);                                                     \
+  /* Isotropic hexahedral path (D = nu I constant on the level, dim 3, P in {1, 3, 7}): the matvec computes    \
+     the neighbours' face fluxes itself (no trace pass) and may scale its operand node by node by isc (NP       \
+     values); the streaming CG kernels never store z = r idg (idg: NP-periodic inverse Jacobi diagonal). */      \
+  bool sipg_iso_path(const Geo& g, const CoefT<T>& cf);                                                         \
+  hipError_t launch_inv_table(const T* diag, T* idg, int np, hipStream_t s);                                    \
+  hipError_t launch_sipg_apply_iso(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha,       \
+                                   T beta, T ctau, const Geo& g, const T* tab, T* part, const int* done_gen,    \
+                                   int id, hipStream_t s);                                                      \
+  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s);     \
+  hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
+                                hipStream_t s);
 
 SISDC_DECLARE_PRECISION_LAUNCHERS(double)
 SISDC_DECLARE_PRECISION_LAUNCHERS(float)

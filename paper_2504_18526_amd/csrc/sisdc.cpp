@@ -74,6 +74,7 @@ struct Level {
   double* r = nullptr;    // M x vlen, residual
   double* q = nullptr;    // M x vlen, quadrature
   double *b = nullptr, *y = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  double* idg = nullptr;        // NP-periodic inverse Jacobi diagonal (isotropic path)
   double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cs = nullptr, *cw = nullptr;
   double* trace = nullptr;
   double* fz = nullptr;        // face values exchanged by the persistent PCG (2 buffers)
@@ -83,6 +84,7 @@ struct Level {
   float* tab32 = nullptr;
   float *ub32 = nullptr, *r32 = nullptr, *e32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
         *cs32 = nullptr, *cw32 = nullptr, *diag32 = nullptr, *trace32 = nullptr;
+  float* idg32 = nullptr;
   // learned initial guess (element-local MLP), see sisdc_net_*
   struct Net {
     bool on = false;          // initialised
@@ -279,15 +281,16 @@ struct CGBufs {
   const T* tab;
   T* partials;
   T* alpha;
+  T* idg;
 };
 
 CGBufs<double> bufs64(sisdc_handle* h, Level& L) {
-  return CGBufs<double>{L.cr, L.cz, L.cp, L.cs, L.cw, L.diag, L.trace, L.tab, h->partials, h->alpha};
+  return CGBufs<double>{L.cr, L.cz, L.cp, L.cs, L.cw, L.diag, L.trace, L.tab, h->partials, h->alpha, L.idg};
 }
 
 CGBufs<float> bufs32(sisdc_handle* h, Level& L) {
   return CGBufs<float>{L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32, L.tab32, h->partials32,
-                       h->alpha32};
+                       h->alpha32, L.idg32};
 }
 
 template <typename T>
@@ -424,25 +427,41 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
   const T ctau = (T)h->ctau, one = (T)1;
   CGStateT<T> cg = cg_state<T>(h, B, b, x, rtol);
   HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
+  // isotropic hexahedral levels: streaming CG, z = r / diag formed inside the matvec
+  const bool iso = sipg_iso_path(L.g, cf);
+  if (iso) HIPCHECK(launch_inv_table(B.diag, B.idg, L.np, s));
   if (x_is_zero) {  // start from x = 0, so A x0 = 0
     HIPCHECK(hipMemsetAsync(x, 0, L.vlen * sizeof(T), s));
     HIPCHECK(hipMemsetAsync(B.w, 0, L.vlen * sizeof(T), s));
   } else {
     HIPCHECK(launch_sipg(x, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, s));  // A x0
   }
-  HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, B.tab, s));
-  HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del, (const int*)nullptr,
-                             0, s));
+  if (iso) {
+    HIPCHECK(launch_cg_start_iso(cg, B.idg, L.nv, L.g, s));
+    HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
+                                   (const int*)nullptr, 0, s));
+  } else {
+    HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, B.tab, s));
+    HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
+                               (const int*)nullptr, 0, s));
+  }
   int chunk = std::max(2, L.last_iters + 1);
   int it = 0;
   bool converged = false;
   while (true) {
     const int stop = std::min(maxit + 1, it + chunk);  // iteration kernel `it` checks the residual after it updates
     for (; it < stop; ++it) {
-      HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
-      if (it < maxit)
-        HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
-                                   (const int*)h->done_gen, id, s));
+      if (iso) {
+        HIPCHECK(launch_cg_iter_iso(cg, B.idg, L.nv, L.g, it, id, s));
+        if (it < maxit)
+          HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
+                                         (const int*)h->done_gen, id, s));
+      } else {
+        HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
+        if (it < maxit)
+          HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
+                                     (const int*)h->done_gen, id, s));
+      }
     }
     HIPCHECK(hipMemcpyAsync(h->hres, h->res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(h->hdone, h->done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -956,6 +975,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cs = dalloc(n);
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
+  L.idg = dalloc(L.np);
   L.fz = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
   L.r32 = falloc(n);  // FP32 staging of residuals (mixed solves, learned guess)
   if (h->meth.precision == SISDC_MIXED) {
@@ -971,6 +991,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
     L.cw32 = falloc(n);
     L.diag32 = falloc(n);
     L.trace32 = falloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
+    L.idg32 = falloc(L.np);
   }
   L.ft = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
@@ -979,10 +1000,10 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
 
 void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
-                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft};
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft, L.idg};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
-  float* fptrs[] = {L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32,
+  float* fptrs[] = {L.idg32, L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32,
                     L.net.theta, L.net.m, L.net.v, L.net.g, L.net.Xd, L.net.Td, L.net.Z1, L.net.A1, L.net.Z2,
                     L.net.A2, L.net.Y, L.net.dY, L.net.dA, L.net.dZ, L.net.Xi, L.net.A1i, L.net.A2i, L.net.Yi,
                     L.net.Xs, L.net.Ts};
@@ -1520,20 +1541,37 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     HIPCHECK(hipMemsetAsync(L.t2, 0, L.vlen * sizeof(double), s));
     const int id = ++h->solve_id;
     CGState cg = cg_state<double>(h, bufs64(h, L), L.b, L.t2, 0.0);
+    // the kernels the PCG of this level runs (isotropic hexahedral path or general path)
+    const bool iso = sipg_iso_path(L.g, cf);
     HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
+    if (iso) HIPCHECK(launch_inv_table(L.diag, L.idg, L.np, s));
     HIPCHECK(launch_sipg(L.t2, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, s));
-    HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
-    HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
-                               (const int*)nullptr, 0, s));
+    if (iso) {
+      HIPCHECK(launch_cg_start_iso(cg, L.idg, L.nv, L.g, s));
+      HIPCHECK(launch_sipg_apply_iso(L.cr, L.idg, L.cw, L.nv, cf, 1.0, dt_m, h->ctau, L.g, L.tab, cg.del,
+                                     (const int*)nullptr, 0, s));
+    } else {
+      HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, L.tab, s));
+      HIPCHECK(launch_sipg_apply(L.cz, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
+                                 (const int*)nullptr, 0, s));
+    }
     auto once = [&]() {
       switch (kernel) {
         case SISDC_K_SIPG_APPLY:
-          HIPCHECK(launch_sipg_apply(L.cz, L.t1, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
-                                     (const int*)h->done_gen, id, s));
+          if (iso)
+            HIPCHECK(launch_sipg_apply_iso(L.cr, L.idg, L.t1, L.nv, cf, 1.0, dt_m, h->ctau, L.g, L.tab, cg.del,
+                                           (const int*)h->done_gen, id, s));
+          else
+            HIPCHECK(launch_sipg_apply(L.cz, L.t1, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, L.cz, cg.del,
+                                       (const int*)h->done_gen, id, s));
           break;
-        case SISDC_K_SIPG_TRACE: HIPCHECK(launch_sipg_trace(L.cz, L.nv, cf, L.t3, L.g, L.tab, s)); break;
+        case SISDC_K_SIPG_TRACE: HIPCHECK(launch_sipg_trace(L.cz, L.nv, cf, L.trace, L.g, L.tab, s)); break;
         case SISDC_K_CONV: conv(h, L, x, L.t1); break;
-        default: HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, L.tab, 0, id, s));
+        default:
+          if (iso)
+            HIPCHECK(launch_cg_iter_iso(cg, L.idg, L.nv, L.g, 0, id, s));
+          else
+            HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, L.tab, 0, id, s));
       }
     };
     once();

@@ -58,6 +58,8 @@ OPS = [
     ("burgers", 2, (1, 3), 5),
     ("ns", 2, (3, 4), 5),
     ("ns", 3, (2, 3, 2), 4),
+    ("ns", 3, (2, 1, 2), 7),
+    ("euler", 3, (3, 2, 2), 1),
 ]
 
 
@@ -98,8 +100,25 @@ def test_sipg_and_helmholtz_apply(S, eq, dim, n, P):
     assert rel_l2(host(out), lv.dg.helmholtz(Dc, dtm, X)) < TOL
 
 
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[5], OPS[10], ("convdiff", 2, (3, 2), 2)])
+def test_profile_hooks(S, eq, dim, n, P):
+    """The measurement hooks run on levels whose face-trace array is larger
+    than a nodal vector (3-D P <= 4, 2-D P <= 2), and leave the operators
+    intact."""
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3])
+    rng = np.random.default_rng(40 + P)
+    U = random_state(phys, lv.mesh, rng)
+    sv.set_state(dev(U.ravel()))
+    for k in (S.K_SIPG_APPLY, S.K_SIPG_TRACE, S.K_CONV, S.K_CG_UPDATE):
+        assert sv.profile_kernel(k, 0, 0.01, reps=3) > 0.0
+    torch.cuda.synchronize()
+    out = torch.empty(U.size, dtype=torch.float64, device="cuda")
+    sv.apply(S.OP_CONV, 0, dev(U.ravel()), out)
+    assert rel_l2(host(out), lv.conv(U)) < TOL
+
+
 @pytest.mark.parametrize("variant", ["auto", "multi"])
-@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[4], OPS[5]])
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[4], OPS[5], OPS[9], OPS[10]])
 def test_helmholtz_solve(S, eq, dim, n, P, variant):
     cgv = S.CG_AUTO if variant == "auto" else S.CG_MULTI_KERNEL
     phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], cg_variant=cgv)
@@ -352,7 +371,7 @@ def test_persistent_steps(S, case):
 RTOL_MIXED = 1e-12
 
 
-@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[5]])
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[5], OPS[9]])
 def test_mixed_solve(S, eq, dim, n, P):
     phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], rtol=RTOL_MIXED, precision=S.MIXED)
     rng = np.random.default_rng(100 + P)
