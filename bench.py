@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 MEASURED_TRAFFIC = {}
 TRAFFIC_SOURCES = {
-    "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "launch.hpp", "xcd.hpp"],
-    "k_sipg_apply": ["kernels.hip", "common.hpp", "launch.hpp", "xcd.hpp"],
+    "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],
+    "k_sipg_apply": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
 }
 
 
