@@ -77,7 +77,7 @@ struct PCGArgs {
   double* x;       // in: initial guess, out: solution
   double* fz;      // face values of the exchanged vector, 2 x [c][e][dim][side][f]
   double* ft;      // face traces of (D grad .),      2 x [c][e][dim][side][f]
-  double* part;    // barrier records: cap records of 8 doubles, then the broadcast record
+  double* part;    // barrier records: 2 (barrier parity) x cap records of 8 doubles
   unsigned* bar;
   CGRes* res;      // result record of this solve
   double tol2;

@@ -320,12 +320,15 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     const double bi = act ? a.b[c * vs + own] : 0.0;
     bb_l += bi * bi;
   }
-  double* rec = a.part;
+  // barrier records, double-buffered by barrier parity: a workgroup rewrites
+  // its record of barrier k only at barrier k + 2, after every workgroup has
+  // passed barrier k + 1 and so has finished reading the records of k
+  auto rec = [&]() { return a.part + (long)(gen & 1u) * 8 * a.cap; };
   unsigned* abort_w = &a.bar[64];
   double epoch = a.epoch0;
   // barrier with K reduced values; advances the epoch and the face-buffer parity
   auto barrier1 = [&](const double (&v)[1], double (&tt)[1]) -> bool {
-    const bool r = sync_reduce<1>(v, tt, rec, abort_w, epoch, a.spin_limit, &s_ok);
+    const bool r = sync_reduce<1>(v, tt, rec(), abort_w, epoch, a.spin_limit, &s_ok);
     epoch += 1.0;
     gen += 1u;
     return r;
@@ -364,7 +367,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     publish(m);
     const double v4[4] = {g_l, d_l, r_l, bb < 0.0 ? bb_l : 0.0};
     double tt[4];
-    ok = sync_reduce<4>(v4, tt, rec, abort_w, epoch, a.spin_limit, &s_ok);
+    ok = sync_reduce<4>(v4, tt, rec(), abort_w, epoch, a.spin_limit, &s_ok);
     epoch += 1.0;
     gen += 1u;
     if (!ok) break;

@@ -142,7 +142,7 @@ struct sisdc_handle {
   int* hdone = nullptr;        // ... and of done_gen
   int solve_id = 0;
   // persistent PCG
-  double* ppart = nullptr;     // barrier records of the persistent PCG (8 x pcap + 8)
+  double* ppart = nullptr;     // barrier records of the persistent PCG (2 x 8 x pcap)
   double epoch = 0.0;          // last barrier epoch handed out
   int pcap = 0;
   unsigned* bar = nullptr;     // grid barrier words
@@ -1201,8 +1201,8 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hnrej = (int*)((char*)hp + 248);
     h->lam_dev = dalloc(2);
     h->pcap = 1024;
-    h->ppart = dalloc((size_t)8 * h->pcap + 8);
-    HIPCHECK(hipMemset(h->ppart, 0, ((size_t)8 * h->pcap + 8) * sizeof(double)));
+    h->ppart = dalloc((size_t)2 * 8 * h->pcap);
+    HIPCHECK(hipMemset(h->ppart, 0, (size_t)2 * 8 * h->pcap * sizeof(double)));
     void* pb = nullptr;
     if (hipMalloc(&pb, 512) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
     h->bar = (unsigned*)pb;
