@@ -68,7 +68,8 @@ def measured_traffic(workload, kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200; the batch workload: its 20 steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,7 +79,8 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="burgers",
-                    help="burgers (default: the two-level Burgers workload), convdiff, euler, ns")
+                    help="burgers (default: the two-level Burgers workload), convdiff, euler, ns, "
+                         "batch (64 independent instances)")
     return ap.parse_args()
 
 
@@ -120,6 +122,147 @@ print(json.dumps({{"seconds": el, "steps": {nsteps}, "rel_l2_step1": err}}))
     if out.returncode != 0:
         raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
     return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline_batch(inst, budget_s=15.0):
+    """The CPU oracle (one thread) on a bounded sample of the batch: one step
+    of each instance, smallest first, until the budget is spent."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    order = sorted(range(len(inst)), key=lambda i: inst[i]["n_elem"][0] ** 2 * (inst[i]["P"][0] + 1) ** 2)
+    code = f"""
+import sys, time, json, numpy as np
+sys.path.insert(0, {ROOT!r})
+from oracle.sdc import DGLevel, MLSDC
+from oracle.physics import Burgers, ConvDiff
+from paper_2504_18526_amd.inputs import burgers_field, convdiff_field
+inst = {json.dumps([inst[i] for i in order])}
+done, tot, dofu = [], 0.0, 0.0
+for w in inst:
+    ph = Burgers(2, w['nu']) if w['eq'] == 'burgers' else ConvDiff(list(w['a'][:2]), w['nu'])
+    lv = [DGLevel(ph, w['n_elem'], w['lo'], w['hi'], P, M, rtol=w['cg_rtol']) for P, M in zip(w['P'], w['M'])]
+    ml = MLSDC(list(reversed(lv)), n_coarse=w['n_coarse'], start=w['start'], cycles=w['cycles'],
+               post_sweep=bool(w['post_sweep']))
+    xs = lv[0].coords()
+    f = convdiff_field if w['eq'] == 'convdiff' else burgers_field
+    u = f([xs[0], xs[1]], seed=w['seed'], kmax=w['kmax'])[None]
+    t = time.perf_counter()
+    ml.step(u, w['dt'])
+    tot += time.perf_counter() - t
+    n1 = w['P'][0] + 1
+    dofu += w['n_elem'][0] * w['n_elem'][1] * n1 * n1 * w['M'][0] * (w['cycles'] + w['post_sweep'])
+    done.append(w['name'])
+    if tot > {budget_s}:
+        break
+print(json.dumps({{"seconds": tot, "dof_updates": dofu, "instances": done}}))
+"""
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def main_batch(a, w):
+    """The batched serving-shape workload: every instance stepped by the
+    batch API (one handle and stream per instance), tuned by the library's
+    autotuner first; whole-batch steps timed by the host clock between
+    device synchronisations (the instances run on many streams)."""
+    import numpy as np
+    import torch
+    from paper_2504_18526_amd import sisdc as S
+    from paper_2504_18526_amd.inputs import burgers_field, convdiff_field
+    from paper_2504_18526_amd.workloads import fine_sweeps_per_step
+    inst = w["instances"]
+    steps = a.steps if a.steps is not None else w["steps"]
+    dev = torch.device("cuda:0")
+    probs, meths = [], []
+    for wi in inst:
+        eqc = S.EQ_CONVDIFF if wi["eq"] == "convdiff" else S.EQ_BURGERS
+        probs.append(S.make_problem(2, wi["n_elem"], wi["lo"], wi["hi"], eqc, a=wi["a"][:2], nu=wi["nu"]))
+        meths.append(S.make_method(wi["P"], wi["M"], start=S.START_CASCADE, n_coarse_sweeps=wi["n_coarse"],
+                                   post_sweep=wi["post_sweep"], n_iter=wi["cycles"], cg_rtol=wi["cg_rtol"],
+                                   cg_maxit=2000, precision=S.MIXED if wi["precision"] == "mixed" else S.FP64))
+    batch = S.Batch(probs, meths)
+    dof_updates, fine_dof = 0.0, 0
+    for i, wi in enumerate(inst):
+        m = batch[i]
+        E, Np, nv, M = m.level_info(0)
+        x = m.coords(0)
+        f = convdiff_field if wi["eq"] == "convdiff" else burgers_field
+        u0 = np.ascontiguousarray(f([x[0], x[1]], seed=wi["seed"], kmax=wi["kmax"])[None].reshape(nv, E, Np))
+        m.set_state(torch.from_numpy(u0).to(dev))
+        dof_updates += E * Np * nv * M * fine_sweeps_per_step(wi)
+        fine_dof += E * Np * nv
+    dts = [wi["dt"] for wi in inst]
+    t0 = time.perf_counter()
+    threads, variants = batch.tune(dts)
+    tune_s = time.perf_counter() - t0
+    step1 = None
+    for k in range(max(1, a.warmup)):
+        batch.step(dts)
+        if k == 0:
+            step1 = []
+            for i in range(len(inst)):
+                E, Np, nv, M = batch[i].level_info(0)
+                out = torch.empty(nv * E * Np, dtype=torch.float64, device=dev)
+                batch[i].get_state(out)
+                step1.append(out.cpu().numpy())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = {"cg_iters": 0, "solves": 0, "not_converged": 0, "ir_rounds": 0}
+    for _ in range(steps):
+        for st in batch.step(dts):
+            for k in tot:
+                tot[k] += st[k]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1000.0 * wall / steps
+    value = dof_updates / (ms_step / 1000.0)
+
+    # roofline: the multi-kernel PCG kernels of the largest instance
+    big = max(range(len(inst)), key=lambda i: inst[i]["n_elem"][0] ** 2 * (inst[i]["P"][0] + 1) ** 2)
+    wb = inst[big]
+    Eb, Npb, nvb, Mb = batch[big].level_info(0)
+    nf = wb["P"][0] + 1
+    traces = 4 * nf / Npb
+    reads_ub = 1.0 if wb["eq"] == "burgers" else 0.0
+    kern = {}
+    for key, kid, name, words in (
+            ("matvec", S.K_SIPG_APPLY, f"k_sipg_apply<2,{wb['P'][0]}>", 2.0 + reads_ub + traces),
+            ("update", S.K_CG_UPDATE, f"k_cg_iter<2,{wb['P'][0]}>", 12.0 + reads_ub + traces)):
+        us = batch[big].profile_kernel(kid, 0, wb["dt"] / Mb, reps=a.reps)
+        nbytes = 8.0 * words * Eb * Npb * nvb
+        kern[key] = {"kernel": name, "avg_launch_us": round(us, 3), "algo_bytes_per_launch": int(nbytes),
+                     "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+    dom = max(kern.values(), key=lambda k: k["avg_launch_us"])
+    other = kern["update"] if dom is kern["matvec"] else kern["matvec"]
+    roofline = {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom["kernel"] + f" (largest instance, {wb['n_elem'][0]}^2 elements)",
+                "avg_launch_us": dom["avg_launch_us"], "algo_bytes_per_launch": dom["algo_bytes_per_launch"],
+                "other": other}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        r = cpu_baseline_batch(inst)
+        cpu = {"value": r["dof_updates"] / r["seconds"], "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"one step of each of the {len(r['instances'])} smallest instances, {r['seconds']:.1f} s"}
+    rec = {
+        "metric": "fine-level DOF-updates/s (s/step at fixed PCG tolerance 1e-10)",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (FP32 inner PCG)", "data": "synthetic (seeded Fourier initial data)",
+        "config": {"workload": w["name"], "instances": len(inst), "fine_dof": fine_dof, "global_batch": len(inst),
+                   "seq_len": None, "parallelism": "none", "host_threads": threads,
+                   "persistent_instances": int(sum(1 for v in variants if v == S.CG_AUTO)) if threads == 1 else 0,
+                   "tune_s": round(tune_s, 2), "cg_iters_per_step": tot["cg_iters"] / steps,
+                   "ir_rounds_per_step": tot["ir_rounds"] / steps, "not_converged": tot["not_converged"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    batch.close()
 
 
 def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates, start):
@@ -196,6 +339,10 @@ def main():
     from paper_2504_18526_amd.inputs import convdiff_field, isentropic_vortex, taylor_green
     from paper_2504_18526_amd.workloads import WORKLOADS, systems_dt
     w = WORKLOADS[a.workload]()
+    if w["eq"] == "batch":
+        return main_batch(a, w)
+    if a.steps is None:
+        a.steps = 200
     dev = torch.device("cuda:0")
     if a.copy_probe_mb > 0:
         src = torch.empty(a.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)

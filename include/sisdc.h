@@ -24,7 +24,11 @@
  *              handle owns every level and work buffer.
  *   Streams    the handle is bound to one hipStream_t at creation (NULL: the
  *              null stream); every call is stream-ordered and returns after
- *              its work has completed (calls synchronise the stream).
+ *              its work has completed (calls synchronise the stream).  The
+ *              library accesses caller device buffers on the handle's
+ *              stream: work on other streams that produces an input (or
+ *              still uses an output buffer) must be complete before the
+ *              call.
  *   Threads    one handle is used by one thread at a time.
  *   Levels     level index 0 is the FINEST level, n_levels-1 the coarsest
  *              (the paper numbers levels the other way, l = 1 coarsest).
@@ -287,6 +291,40 @@ int sisdc_net_grad(sisdc_handle* h, int level, const float* x, const float* t, i
 int sisdc_net_harvest(sisdc_handle* h, int level, int on, int* rows_out);
 int sisdc_net_train(sisdc_handle* h, int level, int epochs, int batch, double lr, double* loss);
 int sisdc_net_use(sisdc_handle* h, int level, int on);
+
+/* ---- Batches of independent instances ----
+ * n instances (problem i, method i), each with its own handle and its own
+ * HIP stream created by the batch, so the kernels of different instances
+ * overlap on the device.  The host work of a batch step is spread over a
+ * number of host threads (instance i on thread i mod threads; default
+ * min(n, 8)).  With more than one thread every instance runs the
+ * multi-kernel PCG (persistent launches of different streams are not known
+ * to be co-resident); with one thread the instances run one after the other,
+ * each with the PCG form of its method (or the tuner's choice).  Instances
+ * are independent: a batch step gives every instance the result of
+ * sisdc_step on its own, up to the PCG tolerance.
+ *
+ * sisdc_batch_handle gives the handle of instance i for the per-instance
+ * calls (sisdc_set_state, sisdc_get_state, sisdc_level_info, ...); the batch
+ * owns it (do not destroy it).  sisdc_batch_step steps every instance by
+ * its dt[i] and fills st[i] (st may be NULL); on failure the message names
+ * the first failing instance, and the other instances have still been
+ * stepped.  sisdc_batch_tune is the batch's autotuner: from the current
+ * states (which it restores) it times one step of every instance with the
+ * persistent and with the multi-kernel PCG and keeps the faster for
+ * one-thread stepping, then times whole batch steps with 1, 2, 4, 8 and 16
+ * host threads and keeps the fastest; threads_out and variants_out[n]
+ * (SISDC_CG_*, the one-thread choices) receive the choices (either may be
+ * NULL).  It needs a state on every instance and allocates
+ * one fine-level state copy per instance while it runs. */
+typedef struct sisdc_batch sisdc_batch;
+int sisdc_batch_create(int n, const sisdc_problem* probs, const sisdc_method* meths, sisdc_batch** out);
+int sisdc_batch_destroy(sisdc_batch* b);
+int sisdc_batch_size(const sisdc_batch* b, int* n);
+int sisdc_batch_handle(sisdc_batch* b, int i, sisdc_handle** h);
+int sisdc_batch_set_threads(sisdc_batch* b, int threads);
+int sisdc_batch_step(sisdc_batch* b, const double* dt, sisdc_stats* st);
+int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out);
 
 #ifdef __cplusplus
 }

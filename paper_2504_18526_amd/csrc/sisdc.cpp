@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -1767,6 +1769,240 @@ int sisdc_net_use(sisdc_handle* h, int level, int on) {
     auto& N = net_of(h, level);
     N.use = on != 0;
   });
+}
+
+// ------------------------------------------------------------------ batches
+// Independent instances stepped together.  Every instance has its own handle
+// and its own HIP stream, so the kernels of different instances overlap on
+// the device; the host work (launches, the waits of the multi-kernel PCG and
+// of the step's end) is spread over `threads` host threads, instance i on
+// thread i mod threads.
+}  // extern "C"
+
+// Cooperative (persistent PCG) launches of different streams are not known
+// to be co-resident with each other, so with more than one host thread every
+// instance runs the multi-kernel PCG; with one thread the instances run one
+// after the other and each uses its own PCG choice (`variant`).
+struct sisdc_batch {
+  std::vector<sisdc_handle*> h;
+  std::vector<hipStream_t> streams;
+  std::vector<int> variant;  // PCG form of each instance when stepped by one thread
+  int threads = 1;
+};
+
+namespace {
+
+// f(i) for every instance on the batch's host threads; the first failing
+// instance's code and message become the caller's.
+template <class F>
+int batch_run(sisdc_batch* b, F&& f) {
+  const int n = (int)b->h.size();
+  const int T = std::max(1, std::min(b->threads, n));
+  std::vector<int> rc(n, SISDC_OK);
+  std::vector<std::string> msg(n);
+  auto work = [&](int t) {
+    for (int i = t; i < n; i += T) {
+      rc[i] = f(i);
+      if (rc[i] != SISDC_OK) msg[i] = sisdc_last_error();
+    }
+  };
+  if (T == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> pool;
+    pool.reserve(T);
+    for (int t = 0; t < T; ++t) pool.emplace_back(work, t);
+    for (auto& th : pool) th.join();
+  }
+  for (int i = 0; i < n; ++i)
+    if (rc[i] != SISDC_OK) {
+      g_last_error = "instance " + std::to_string(i) + ": " + msg[i];
+      return rc[i];
+    }
+  g_last_error.clear();
+  return SISDC_OK;
+}
+
+// Select the PCG form of every level of a handle (SISDC_CG_AUTO lets levels
+// whose tiles fit use the persistent kernel).
+void set_cg_variant(sisdc_handle* h, int variant) {
+  h->meth.cg_variant = variant;
+  for (auto& L : h->lv) L.persistent = variant == SISDC_CG_AUTO && elem_tile_count(L.g) <= h->pcap;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sisdc_batch_create(int n, const sisdc_problem* probs, const sisdc_method* meths, sisdc_batch** out) {
+  if (!out) {
+    g_last_error = "null output pointer";
+    return SISDC_EINVAL;
+  }
+  *out = nullptr;
+  if (n < 1 || !probs || !meths) {
+    g_last_error = "n >= 1 and problem / method arrays required";
+    return SISDC_EINVAL;
+  }
+  sisdc_batch* b = new (std::nothrow) sisdc_batch();
+  if (!b) {
+    g_last_error = "host allocation failed";
+    return SISDC_ENOMEM;
+  }
+  for (int i = 0; i < n; ++i) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      sisdc_batch_destroy(b);
+      g_last_error = "instance " + std::to_string(i) + ": hipStreamCreateWithFlags failed";
+      return SISDC_EDEVICE;
+    }
+    b->streams.push_back(s);
+    sisdc_handle* h = nullptr;
+    const int rc = sisdc_create(&probs[i], &meths[i], (void*)s, &h);
+    if (rc != SISDC_OK) {
+      const std::string m = "instance " + std::to_string(i) + ": " + g_last_error;
+      sisdc_batch_destroy(b);
+      g_last_error = m;
+      return rc;
+    }
+    b->h.push_back(h);
+    b->variant.push_back(meths[i].cg_variant);
+  }
+  b->threads = std::min(n, 8);
+  *out = b;
+  return SISDC_OK;
+}
+
+int sisdc_batch_destroy(sisdc_batch* b) {
+  if (!b) return SISDC_OK;
+  for (sisdc_handle* h : b->h) sisdc_destroy(h);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+  return SISDC_OK;
+}
+
+int sisdc_batch_size(const sisdc_batch* b, int* n) {
+  if (!b || !n) {
+    g_last_error = "null batch or output pointer";
+    return SISDC_EINVAL;
+  }
+  *n = (int)b->h.size();
+  return SISDC_OK;
+}
+
+int sisdc_batch_handle(sisdc_batch* b, int i, sisdc_handle** h) {
+  if (!b || !h || i < 0 || i >= (int)b->h.size()) {
+    g_last_error = "null pointer or instance out of range";
+    return SISDC_EINVAL;
+  }
+  *h = b->h[i];
+  return SISDC_OK;
+}
+
+int sisdc_batch_set_threads(sisdc_batch* b, int threads) {
+  if (!b || threads < 1 || threads > 64) {
+    g_last_error = "threads in 1..64 required";
+    return SISDC_EINVAL;
+  }
+  b->threads = threads;
+  return SISDC_OK;
+}
+
+int sisdc_batch_step(sisdc_batch* b, const double* dt, sisdc_stats* st) {
+  if (!b || !dt) {
+    g_last_error = "null batch or dt";
+    return SISDC_EINVAL;
+  }
+  const bool concurrent = std::min(b->threads, (int)b->h.size()) > 1;
+  for (size_t i = 0; i < b->h.size(); ++i) set_cg_variant(b->h[i], concurrent ? SISDC_CG_MULTI_KERNEL : b->variant[i]);
+  return batch_run(b, [&](int i) { return sisdc_step(b->h[i], 0.0, dt[i], st ? &st[i] : nullptr); });
+}
+
+// Autotuner: per instance, the PCG form for one-thread stepping (persistent
+// where it fits, or multi-kernel), then the number of host threads for the
+// whole batch (more than one thread runs every instance with the
+// multi-kernel PCG), each by the wall time of one step from the same state,
+// which is restored afterwards.
+int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out) {
+  if (!b || !dt) {
+    g_last_error = "null batch or dt";
+    return SISDC_EINVAL;
+  }
+  const int n = (int)b->h.size();
+  std::vector<double*> saved(n, nullptr);
+  auto release = [&]() {
+    for (double* p : saved)
+      if (p) (void)hipFree(p);
+  };
+  for (int i = 0; i < n; ++i) {
+    sisdc_handle* h = b->h[i];
+    if (!h->have_state) {
+      release();
+      g_last_error = "instance " + std::to_string(i) + ": sisdc_set_state must precede sisdc_batch_tune";
+      return SISDC_ESTATE;
+    }
+    if (hipMalloc(&saved[i], h->lv[0].vlen * sizeof(double)) != hipSuccess) {
+      release();
+      g_last_error = "hipMalloc failed";
+      return SISDC_ENOMEM;
+    }
+    if (hipMemcpyAsync(saved[i], h->state, h->lv[0].vlen * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      release();
+      g_last_error = "state copy failed";
+      return SISDC_EDEVICE;
+    }
+  }
+  auto restore = [&](int i) { return sisdc_set_state(b->h[i], saved[i], SISDC_MEM_DEVICE); };
+  auto now = []() { return std::chrono::steady_clock::now(); };
+  auto secs = [](auto a, auto c) { return std::chrono::duration<double>(c - a).count(); };
+  int rc = SISDC_OK;
+  for (int i = 0; i < n && rc == SISDC_OK; ++i) {
+    sisdc_handle* h = b->h[i];
+    const int original = h->meth.cg_variant;
+    double best = 1e300;
+    int pick = original;
+    for (int v : {SISDC_CG_AUTO, SISDC_CG_MULTI_KERNEL}) {
+      set_cg_variant(h, v);
+      if ((rc = sisdc_step(h, 0.0, dt[i], nullptr)) != SISDC_OK) break;  // warm-up of this form
+      if ((rc = restore(i)) != SISDC_OK) break;
+      const auto t0 = now();
+      if ((rc = sisdc_step(h, 0.0, dt[i], nullptr)) != SISDC_OK) break;
+      const double tv = secs(t0, now());
+      if ((rc = restore(i)) != SISDC_OK) break;
+      if (tv < best) {
+        best = tv;
+        pick = v;
+      }
+    }
+    set_cg_variant(h, pick);
+    b->variant[i] = pick;
+    if (variants_out) variants_out[i] = pick;
+  }
+  if (rc == SISDC_OK) {
+    double best = 1e300;
+    int pick = b->threads;
+    for (int T : {1, 2, 4, 8, 16}) {
+      if (T > n && T != 1) continue;
+      b->threads = T;
+      const auto t0 = now();
+      if ((rc = sisdc_batch_step(b, dt, nullptr)) != SISDC_OK) break;
+      const double tv = secs(t0, now());
+      for (int i = 0; i < n && rc == SISDC_OK; ++i) rc = restore(i);
+      if (rc != SISDC_OK) break;
+      if (tv < best) {
+        best = tv;
+        pick = T;
+      }
+    }
+    b->threads = pick;
+    if (threads_out) *threads_out = pick;
+  }
+  const std::string m = g_last_error;
+  release();
+  g_last_error = rc == SISDC_OK ? std::string() : m;
+  return rc;
 }
 
 }  // extern "C"

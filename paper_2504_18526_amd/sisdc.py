@@ -30,6 +30,8 @@ EXPORTS = [
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
     "sisdc_pcg_timing", "sisdc_pcg_timing_get",
+    "sisdc_batch_create", "sisdc_batch_destroy", "sisdc_batch_size", "sisdc_batch_handle",
+    "sisdc_batch_set_threads", "sisdc_batch_step", "sisdc_batch_tune",
     "sisdc_net_init", "sisdc_net_get_params", "sisdc_net_set_params", "sisdc_net_forward",
     "sisdc_net_train_step", "sisdc_net_grad", "sisdc_net_harvest", "sisdc_net_train", "sisdc_net_use",
 ]
@@ -97,6 +99,13 @@ def load():
         "sisdc_collocation_residual": ([P, I, D, P, I], I),
         "sisdc_profile_kernel": ([P, I, I, D, I, ctypes.POINTER(D)], I),
         "sisdc_pcg_timing": ([P, I], I),
+        "sisdc_batch_create": ([I, P, P, ctypes.POINTER(P)], I),
+        "sisdc_batch_destroy": ([P], I),
+        "sisdc_batch_size": ([P, ctypes.POINTER(I)], I),
+        "sisdc_batch_handle": ([P, I, ctypes.POINTER(P)], I),
+        "sisdc_batch_set_threads": ([P, I], I),
+        "sisdc_batch_step": ([P, P, P], I),
+        "sisdc_batch_tune": ([P, P, ctypes.POINTER(I), P], I),
         "sisdc_pcg_timing_get": ([P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(D)], I),
         "sisdc_net_init": ([P, I, I, ctypes.c_ulonglong, I, I], I),
@@ -146,6 +155,11 @@ def _ptr(a, writable=False, dtype="float64"):
             raise ValueError("tensor must be contiguous")
         if str(a.dtype) != "torch." + dtype:
             raise ValueError("tensor must be " + dtype)
+        if a.is_cuda:
+            # the library reads and writes device buffers on its own stream:
+            # work queued on the caller's current stream must finish first
+            import torch
+            torch.cuda.current_stream(a.device).synchronize()
         return ctypes.c_void_p(a.data_ptr()), (MEM_DEVICE if a.is_cuda else MEM_HOST)
     if not isinstance(a, np.ndarray) or a.dtype != np.dtype(dtype) or not a.flags.c_contiguous:
         raise ValueError("numpy array must be C-contiguous " + dtype)
@@ -377,3 +391,78 @@ class Solver:
         p, mem = _ptr(out, True)
         _check(self._lib.sisdc_collocation_residual(self.h, level, dt, p, mem))
         return out
+
+
+class _Member(Solver):
+    """A batch instance's handle (owned by the batch: never destroyed here)."""
+
+    def __init__(self, batch, h, problem, method):
+        self._lib = lib()
+        self.h = h
+        self._batch = batch  # keeps the batch alive
+        self.problem = problem
+        self.method = method
+        self.dim = problem.dim
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Independent instances stepped together (sisdc_batch_*)."""
+
+    def __init__(self, problems, methods):
+        self._lib = lib()
+        n = len(problems)
+        if n != len(methods) or n < 1:
+            raise ValueError("one method per problem, at least one instance")
+        self._probs = (Problem * n)(*problems)
+        self._meths = (Method * n)(*methods)
+        b = ctypes.c_void_p()
+        _check(self._lib.sisdc_batch_create(n, ctypes.cast(self._probs, ctypes.c_void_p),
+                                            ctypes.cast(self._meths, ctypes.c_void_p), ctypes.byref(b)))
+        self.b = b
+        self.n = n
+        self.members = []
+        for i in range(n):
+            h = ctypes.c_void_p()
+            _check(self._lib.sisdc_batch_handle(self.b, i, ctypes.byref(h)))
+            self.members.append(_Member(self, h, problems[i], methods[i]))
+
+    def close(self):
+        if self.b:
+            for m in self.members:
+                m.h = None
+            self._lib.sisdc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        return self.members[i]
+
+    def set_threads(self, threads):
+        _check(self._lib.sisdc_batch_set_threads(self.b, threads))
+
+    def step(self, dts):
+        dt = (ctypes.c_double * self.n)(*[float(d) for d in dts])
+        st = (Stats * self.n)()
+        _check(self._lib.sisdc_batch_step(self.b, ctypes.cast(dt, ctypes.c_void_p), ctypes.cast(st, ctypes.c_void_p)))
+        return [s.as_dict() for s in st]
+
+    def tune(self, dts):
+        """Autotune the PCG form of every instance and the host thread count;
+        returns (threads, [variant per instance])."""
+        dt = (ctypes.c_double * self.n)(*[float(d) for d in dts])
+        th = ctypes.c_int()
+        var = (ctypes.c_int * self.n)()
+        _check(self._lib.sisdc_batch_tune(self.b, ctypes.cast(dt, ctypes.c_void_p), ctypes.byref(th),
+                                          ctypes.cast(var, ctypes.c_void_p)))
+        return th.value, list(var)

@@ -98,9 +98,46 @@ def systems_dt(w, u0):
     return cfl_dt(w["cfl"], h, w["P"][0], lam)
 
 
+def batch_instances(n=64, base_seed=0):
+    """Batched serving-shape run: n independent 2-D instances on [0,1]^2,
+    instance i drawn with numpy.random.default_rng(base_seed + i):
+    elements m x m with m = round(exp U[ln 8, ln 64]); P uniform in 3..8;
+    M uniform in {3, 4, 5}; nu log-uniform in [1e-3, 1e-1]; even i
+    convection-diffusion (a = (1, 0.5), u0 as in the one-level workload),
+    odd i Burgers (u0 as in the two-level workload); two levels with
+    P_c = ceil(P/2), M_c = floor(M/2) + 1 (the paper's coarsening rule);
+    cascade start, 3 V-cycles + post-sweep, N_c = 2, CFL = 1, 20 steps,
+    mixed precision with FP64 refinement, PCG to 1e-10."""
+    import math
+    import numpy as np
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(base_seed + i)
+        m = int(round(math.exp(rng.uniform(math.log(8.0), math.log(64.0)))))
+        P = int(rng.integers(3, 9))
+        M = int(rng.integers(3, 6))
+        nu = float(math.exp(rng.uniform(math.log(1e-3), math.log(1e-1))))
+        eq = "convdiff" if i % 2 == 0 else "burgers"
+        lam = 1.5 if eq == "convdiff" else 2.0
+        out.append(dict(
+            name=f"instance{i}", eq=eq, dim=2, n_elem=(m, m), lo=(0.0, 0.0), hi=(1.0, 1.0), nu=nu,
+            a=(1.0, 0.5, 0.0), P=[P, (P + 1) // 2], M=[M, M // 2 + 1], start="cascade", cycles=3, n_coarse=2,
+            post_sweep=1, dt=cfl_dt(1.0, 1.0 / m, P, lam), steps=20, seed=base_seed + i,
+            kmax=4 if eq == "convdiff" else 6, cg_rtol=1e-10, precision="mixed",
+        ))
+    return out
+
+
+def batch_64():
+    """The 64-instance batch as one workload record (instances in `instances`)."""
+    inst = batch_instances(64)
+    return dict(name="batch2d_64_instances_mlsdc_mixed", eq="batch", dim=2, instances=inst, steps=20)
+
+
 WORKLOADS = {
     "convdiff": convdiff_1level,
     "burgers": burgers_2level,
     "euler": euler_3level,
     "ns": ns_2level,
+    "batch": batch_64,
 }

@@ -1,0 +1,128 @@
+"""Batches of independent instances (sisdc_batch_*), through the C ABI.
+
+Instances of different equations, sizes, degrees and node counts are stepped
+together and compared with the CPU oracle stepping each instance on its own
+(1e-12 for FP64, 1e-10 for mixed precision), and with the same instance
+stepped through its own handle outside a batch (the reductions are
+deterministic, so the results agree bit for bit).  The autotuner must leave
+every state as it found it.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.sdc import DGLevel, MLSDC
+from helpers import rel_l2, oracle_phys, lib_problem, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_18526_amd import sisdc
+    return sisdc
+
+
+# (eq, n_elem, P, M, nu, dt): two-level instances (P_c = ceil(P/2), M_c = floor(M/2) + 1)
+INSTANCES = [
+    ("convdiff", (3, 4), 4, 3, 0.02, 1.0e-2),
+    ("burgers", (4, 3), 6, 4, 5e-3, 4.0e-3),
+    ("convdiff", (2, 5), 3, 5, 0.05, 8.0e-3),
+    ("burgers", (5, 2), 8, 3, 1e-2, 3.0e-3),
+    ("convdiff", (1, 3), 5, 4, 0.01, 1.2e-2),
+]
+
+
+def build(S, precision, rtol):
+    probs, meths, orc, dts = [], [], [], []
+    for eq, n, P, M, nu, dt in INSTANCES:
+        Ps, Ms = [P, (P + 1) // 2], [M, M // 2 + 1]
+        lo, hi = [0.0, 0.0], [1.0, 1.25]
+        probs.append(lib_problem(S, eq, 2, n, lo, hi, nu=nu))
+        meths.append(S.make_method(Ps, Ms, start=S.START_CASCADE, n_iter=2, cg_rtol=rtol, cg_maxit=5000,
+                                   precision=precision))
+        phys = oracle_phys(eq, 2, nu=nu)
+        levels = [DGLevel(phys, n, lo, hi, p, m, rtol=1e-14) for p, m in zip(Ps, Ms)]
+        orc.append((phys, levels))
+        dts.append(dt)
+    return probs, meths, orc, dts
+
+
+def initial_states(orc):
+    out = []
+    for i, (phys, levels) in enumerate(orc):
+        out.append(smooth_state(phys, levels[0], np.random.default_rng(100 + i)))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_batch_steps_match_oracle_and_single_handles(S, mode):
+    precision = S.FP64 if mode == "fp64" else S.MIXED
+    rtol, tol = (1e-14, 1e-12) if mode == "fp64" else (1e-12, 1e-10)
+    probs, meths, orc, dts = build(S, precision, rtol)
+    u0 = initial_states(orc)
+    batch = S.Batch(probs, meths)
+    batch.set_threads(3)
+    singles = [S.Solver(p, m) for p, m in zip(probs, meths)]
+    for i, u in enumerate(u0):
+        batch[i].set_state(torch.from_numpy(u.ravel().copy()).cuda())
+        singles[i].set_state(torch.from_numpy(u.ravel().copy()).cuda())
+    ref = [u.copy() for u in u0]
+    for k in range(2):
+        stats = batch.step(dts)
+        for i, (phys, levels) in enumerate(orc):
+            assert stats[i]["fine_sweeps"] == 3
+            singles[i].step(dts[i])
+            ml = MLSDC(list(reversed(levels)), n_coarse=2, start="cascade", cycles=2, post_sweep=True)
+            ref[i] = ml.step(ref[i], dts[i])
+            out = torch.empty(u0[i].size, dtype=torch.float64, device="cuda")
+            batch[i].get_state(out)
+            one = torch.empty_like(out)
+            singles[i].get_state(one)
+            got = out.cpu().numpy()
+            assert np.array_equal(got, one.cpu().numpy()), (mode, k, i)
+            assert rel_l2(got, ref[i]) < tol, (mode, k, i)
+    for s in singles:
+        s.close()
+    batch.close()
+
+
+def test_batch_tune_restores_state_and_keeps_results(S):
+    probs, meths, orc, dts = build(S, S.FP64, 1e-14)
+    u0 = initial_states(orc)
+    batch = S.Batch(probs, meths)
+    for i, u in enumerate(u0):
+        batch[i].set_state(torch.from_numpy(u.ravel().copy()).cuda())
+    threads, variants = batch.tune(dts)
+    assert threads in (1, 2, 4, 8, 16)
+    assert all(v in (S.CG_AUTO, S.CG_MULTI_KERNEL) for v in variants)
+    for i, u in enumerate(u0):  # the tuner restored every state
+        out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+        batch[i].get_state(out)
+        assert np.array_equal(out.cpu().numpy(), u.ravel())
+    batch.step(dts)
+    for i, (phys, levels) in enumerate(orc):
+        ml = MLSDC(list(reversed(levels)), n_coarse=2, start="cascade", cycles=2, post_sweep=True)
+        ref = ml.step(u0[i], dts[i])
+        out = torch.empty(u0[i].size, dtype=torch.float64, device="cuda")
+        batch[i].get_state(out)
+        assert rel_l2(out.cpu().numpy(), ref) < 1e-12, i
+    batch.close()
+
+
+def test_batch_errors_name_the_instance(S):
+    probs, meths, orc, dts = build(S, S.FP64, 1e-14)
+    meths[2].P[0] = 12  # degree out of range for instance 2
+    with pytest.raises(S.SisdcError, match="instance 2"):
+        S.Batch(probs, meths)
+    probs, meths, orc, dts = build(S, S.FP64, 1e-14)
+    batch = S.Batch(probs, meths)
+    u0 = initial_states(orc)
+    for i in (0, 1, 3, 4):  # instance 2 has no state
+        batch[i].set_state(torch.from_numpy(u0[i].ravel().copy()).cuda())
+    with pytest.raises(S.SisdcError, match="instance 2"):
+        batch.step(dts)
+    batch.close()
