@@ -433,3 +433,51 @@ def test_mixed_steps(S, case):
         u = stepper(u)
         sv.get_state(out)
         assert rel_l2(host(out), u) < 1e-10, (case, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", ["auto", "multi"])
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[1], OPS[9]])
+def test_zero_rhs_solve(S, eq, dim, n, P, variant, precision):
+    """Degenerate solve: b = 0 from x0 = 0 returns x = 0 without iterating."""
+    cgv = S.CG_AUTO if variant == "auto" else S.CG_MULTI_KERNEL
+    prec = S.FP64 if precision == "fp64" else S.MIXED
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], cg_variant=cgv, precision=prec)
+    rng = np.random.default_rng(50 + P)
+    Ub = random_state(phys, lv.mesh, rng)
+    if phys.step_params(Ub) is not None:
+        sv.set_state(dev(Ub.ravel()))
+        sv.update_step_params()
+    b = np.zeros(lv.shape())
+    x = dev(np.zeros(b.size))
+    st = sv.helmholtz_solve(0, 0.05, dev(b.ravel()), x,
+                            coef_state=dev(Ub[:1].ravel()) if eq == "burgers" else None, rtol=1e-10, maxit=100)
+    assert st["converged"]
+    assert st["iters"] == 0
+    assert float(torch.abs(x).max()) == 0.0
+
+
+@pytest.mark.parametrize("eq,dim,n,Ps,Ms", [("convdiff", 2, (3, 2), [4, 2], [3, 2]),
+                                             ("burgers", 2, (2, 3), [5, 3], [4, 2]),
+                                             ("euler", 2, (3, 3), [4], [3]),
+                                             ("ns", 3, (2, 1, 2), [3, 2], [3, 2])])
+def test_constant_state_is_steady(S, eq, dim, n, Ps, Ms):
+    """A constant state is an exact steady solution of every equation (all
+    fluxes constant, all jumps zero): one full step leaves it unchanged."""
+    phys, levels, sv = make_pair(S, eq, dim, n, Ps, Ms, rtol=1e-12, n_iter=2)
+    fine = levels[0]
+    shp = fine.shape()
+    if phys.nv == 1:
+        U = np.full(shp, 0.7)
+    else:
+        U = np.empty(shp)
+        rho, v, p = 1.3, [0.2, -0.1, 0.05][:dim], 0.9
+        U[0] = rho
+        for k in range(dim):
+            U[1 + k] = rho * v[k]
+        U[dim + 1] = p / (phys.gamma - 1.0) + 0.5 * rho * sum(vk * vk for vk in v)
+    sv.set_state(dev(U.ravel()))
+    sv.step(1e-3 if dim == 2 else 5e-4)
+    out = torch.empty(U.size, dtype=torch.float64, device="cuda")
+    sv.get_state(out)
+    assert rel_l2(host(out), U) < 1e-13
