@@ -124,7 +124,7 @@ typedef struct {
   double max_rel_residual;/* largest final relative residual                */
   int ir_rounds;          /* SISDC_MIXED: FP32 inner solves (refinement rounds) */
   int net_guesses;        /* learned initial guesses computed               */
-  int net_rejected;       /* ... of which discarded (residual did not drop) */
+  int net_rejected;       /* ... of which refused (no positive step)        */
 } sisdc_stats;
 
 typedef struct {
@@ -259,10 +259,12 @@ int sisdc_pcg_timing_get(sisdc_handle* h, int level, long long* launches, long l
 /* Learned initial guess of a level's Helmholtz solves: an element-local MLP
  * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)
  * row of the mass-scaled initial residual z0 = M^-1 (b - A x0), normalised to
- * unit norm; its output, times |z0_row|, corrects x0.  The corrected x0 is kept only if it lowers
- * |b - A x0| (decided on the device; rejections are counted in the stats),
- * and PCG always follows to the same tolerance, so the network changes the
- * initial guess only.  Not part of the paper's method.
+ * unit norm; its output, times |z0_row|, is a correction delta, and x0
+ * moves along it by the step that minimises the A-norm of the error,
+ * alpha = (delta, r0) / (delta, A delta) (decided on the device; a step that
+ * is not positive is refused and counted in the stats).  PCG always follows
+ * to the same tolerance, so the network changes the initial guess only, and
+ * never raises the error's A-norm.  Not part of the paper's method.
  *   sisdc_net_init     allocate; weights (2u - 1) sqrt(6 / fan_in) with u from
  *                      SplitMix64(seed) in parameter order, biases 0; Adam
  *                      state zero.  max_batch bounds training batches and

@@ -1130,6 +1130,18 @@ __global__ void k_sum2(const double* __restrict__ part, int n, double* tot) {
   }
 }
 
+// block partials of (a, b) -> part[blk] and (a, c) -> part[kElemCap + blk]
+__global__ void k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                       long n, double* part) {
+  double v[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    v[0] += a[i] * b[i];
+    v[1] += a[i] * c[i];
+  }
+  double* const pp[2] = {part, part + kElemCap};
+  block_partials<double, 2>(v, pp);
+}
+
 // x += (double) e
 __global__ void k_add_f2d(double* __restrict__ x, const float* __restrict__ e, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -1519,6 +1531,14 @@ hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long
                              hipStream_t s) {
   const int nb = blocks_for(n, 256, kElemCap);
   hipLaunchKernelGGL(k_resid_cast, dim3(nb), dim3(256), 0, s, b, Ax, r32, n, part);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, part, nb, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(const double* a, const double* b, const double* c, long n, double* part, double* tot,
+                       hipStream_t s) {
+  const int nb = blocks_for(n, 256, kElemCap);
+  hipLaunchKernelGGL(k_dot2, dim3(nb), dim3(256), 0, s, a, b, c, n, part);
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, part, nb, tot);
   return hipGetLastError();
 }

@@ -62,6 +62,9 @@ hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);
 hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
                              hipStream_t s);
 hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s);
+// tot[0] = (a, b), tot[1] = (a, c) (deterministic partial sums in part)
+hipError_t launch_dot2(const double* a, const double* b, const double* c, long n, double* part, double* tot,
+                       hipStream_t s);
 // result[0] = max over nodes of max_d (|v_d| + c), result[1] = min rho
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
                             hipStream_t s);

@@ -158,21 +158,26 @@ __global__ void k_row_normalise(const double* __restrict__ r, int rows, int n, c
 }
 
 // xnew = x + |z_row| * Y  (the network's correction, scaled back)
-__global__ void k_guess_update(const double* __restrict__ x, const float* __restrict__ Y, const double* __restrict__ nrm,
-                               int rows, int n, double* __restrict__ xnew) {
+// the network's correction of every row: delta = |z0_row| Y_row
+__global__ void k_guess_delta(const float* __restrict__ Y, const double* __restrict__ nrm, int rows, int n,
+                              double* __restrict__ delta) {
   const long tot = (long)rows * n;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x)
-    xnew[i] = x[i] + nrm[i / n] * (double)Y[i];
+    delta[i] = nrm[i / n] * (double)Y[i];
 }
 
-// keep the guess only if it lowered the residual: tot_old[0] = |b - A x|^2,
-// tot_new[0] = |b - A xnew|^2; count rejections in *rejected
-__global__ void k_guess_select(double* __restrict__ x, const double* __restrict__ xnew, long n,
-                               const double* __restrict__ tot_old, const double* __restrict__ tot_new, int* rejected) {
-  const bool take = tot_new[0] < tot_old[0];
+// x += alpha delta with the step that minimises the A-norm of the error
+// along delta: alpha = (delta, r0) / (delta, A delta) from dots[0..1]; the
+// error's A-norm then drops by (delta, r0)^2 / (delta, A delta).  A step
+// that is not positive and finite is refused (counted in *rejected).
+__global__ void k_guess_step(double* __restrict__ x, const double* __restrict__ delta, long n,
+                             const double* __restrict__ dots, int* rejected) {
+  const double alpha = dots[1] > 0.0 ? dots[0] / dots[1] : 0.0;
+  const bool take = alpha > 0.0 && alpha < 1e300;
   if (blockIdx.x == 0 && threadIdx.x == 0 && !take) rejected[0] += 1;
   if (!take) return;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = xnew[i];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] += alpha * delta[i];
 }
 
 // harvest rows: X[row] = z0_row / |z0_row|, T[row] = (x - x0)_row / |z0_row|,
@@ -263,15 +268,14 @@ hipError_t launch_row_normalise(const double* r, int rows, int n, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_guess_update(const double* x, const float* Y, const double* nrm, int rows, int n, double* xnew,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_guess_update, dim3(gblocks((long)rows * n)), dim3(256), 0, s, x, Y, nrm, rows, n, xnew);
+hipError_t launch_guess_delta(const float* Y, const double* nrm, int rows, int n, double* delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_delta, dim3(gblocks((long)rows * n)), dim3(256), 0, s, Y, nrm, rows, n, delta);
   return hipGetLastError();
 }
 
-hipError_t launch_guess_select(double* x, const double* xnew, long n, const double* tot_old, const double* tot_new,
-                               int* rejected, hipStream_t s) {
-  hipLaunchKernelGGL(k_guess_select, dim3(gblocks(n)), dim3(256), 0, s, x, xnew, n, tot_old, tot_new, rejected);
+hipError_t launch_guess_step(double* x, const double* delta, long n, const double* dots, int* rejected,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_guess_step, dim3(gblocks(n)), dim3(256), 0, s, x, delta, n, dots, rejected);
   return hipGetLastError();
 }
 

@@ -22,10 +22,11 @@ hipError_t launch_adam(float* th, float* m, float* v, const float* g, long n, fl
 // z = M^-1 r per row (mw: the element's diagonal mass), |z| and z / |z|
 hipError_t launch_row_normalise(const double* r, int rows, int n, const double* mw, float* X, double* nrm,
                                 hipStream_t s);
-hipError_t launch_guess_update(const double* x, const float* Y, const double* nrm, int rows, int n, double* xnew,
-                               hipStream_t s);
-hipError_t launch_guess_select(double* x, const double* xnew, long n, const double* tot_old, const double* tot_new,
-                               int* rejected, hipStream_t s);
+// delta = |z0_row| Y_row; x += alpha delta, alpha = dots[0] / dots[1] =
+// (delta, r0) / (delta, A delta) when positive (else refused, counted)
+hipError_t launch_guess_delta(const float* Y, const double* nrm, int rows, int n, double* delta, hipStream_t s);
+hipError_t launch_guess_step(double* x, const double* delta, long n, const double* dots, int* rejected,
+                             hipStream_t s);
 hipError_t launch_harvest(const double* r0, const double* x, const double* x0, const double* nrm, int rows, int n,
                           const double* mw, float* X, float* T, hipStream_t s);
 

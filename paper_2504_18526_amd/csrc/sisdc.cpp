@@ -133,7 +133,7 @@ struct sisdc_handle {
   float* partials32 = nullptr; // FP32 CG partial sums (7 cap)
   float* alpha32 = nullptr;
   double* ir_tot = nullptr;    // (r,r), (b,b) of the FP64 residual of iterative refinement
-  double* gtot = nullptr;      // residual norms before / after a learned guess (2 x 2)
+  double* gtot = nullptr;      // (delta, r0), (delta, A delta) of a learned guess
   int* nrej = nullptr;         // learned guesses rejected (device counter)
   int* hnrej = nullptr;        // pinned mirror
   int nrej_seen = 0;
@@ -550,19 +550,23 @@ void residual64(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const do
   }
 }
 
-// x0 <- x0 + |z0_row| N(z0_row / |z0_row|), z0 = M^-1 (b - A x0), for every
-// (element, component) row, kept only if |b - A x0| decreases (decided on
+// The network proposes, for every (element, component) row, the correction
+// delta_row = |z0_row| N(z0_row / |z0_row|), z0 = M^-1 (b - A x0); the guess
+// moves along delta by the step that minimises the A-norm of the error,
+// x0 <- x0 + alpha delta, alpha = (delta, r0) / (delta, A delta), so it can
+// only lower that norm (a step that is not positive is refused; decided on
 // the device).
 void learned_guess(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x) {
   auto& N = L.net;
   hipStream_t s = h->stream;
   const int rows = L.nv * L.E;
-  residual64(h, L, cf, dtm, b, x, N.r0h, h->gtot);
+  residual64(h, L, cf, dtm, b, x, N.r0h, nullptr);
   HIPCHECK(launch_row_normalise(N.r0h, rows, L.np, L.mw, N.Xi, N.nrm, s));
   HIPCHECK(mlp_forward(N.sh, N.theta, N.Xi, rows, nullptr, N.A1i, nullptr, N.A2i, N.Yi, 1, s));
-  HIPCHECK(launch_guess_update(x, N.Yi, N.nrm, rows, L.np, N.xnew, s));
-  residual64(h, L, cf, dtm, b, N.xnew, nullptr, h->gtot + 2);
-  HIPCHECK(launch_guess_select(x, N.xnew, L.vlen, h->gtot, h->gtot + 2, h->nrej, s));
+  HIPCHECK(launch_guess_delta(N.Yi, N.nrm, rows, L.np, N.xnew, s));
+  HIPCHECK(launch_sipg(N.xnew, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, s));  // A delta
+  HIPCHECK(launch_dot2(N.xnew, N.r0h, L.cw, L.vlen, h->partials, h->gtot, s));
+  HIPCHECK(launch_guess_step(x, N.xnew, L.vlen, h->gtot, h->nrej, s));
   h->st.net_guesses += 1;
 }
 
