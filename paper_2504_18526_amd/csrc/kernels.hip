@@ -725,11 +725,18 @@ k_sipg_apply_iso3(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
   if (scaled)
     for (int k = threadIdx.x; k < I::NP; k += blockDim.x) sc[k] = isc[k];
   __syncthreads();
+  // Every XCD takes one contiguous range of pairs (a slab of elements); its
+  // workgroups interleave over that range group by group, so the pairs in
+  // flight on an XCD at any time are a compact window and the neighbour
+  // lines they read were loaded into that XCD's L2 by the same window.
   const long npairs = (long)nv * g.E;
-  const long lb = xcd_block(blockIdx.x, gridDim.x);
-  const long p0 = lb * npairs / gridDim.x, p1 = (lb + 1) * npairs / gridDim.x;
+  const int G = gridDim.x, xcd = blockIdx.x % kXcd, per = G / kXcd, rem = G % kXcd;
+  const long kx = per + (xcd < rem ? 1 : 0);                  // workgroups of this XCD
+  const long lb0 = (long)xcd * per + (xcd < rem ? xcd : rem); // its first logical id
+  const long xs = lb0 * npairs / G, xe = (lb0 + kx) * npairs / G;
+  const long k = blockIdx.x / kXcd;                           // rank among them
   T dacc = T(0.0);
-  for (long p = p0 + wave * I::GW + grp; p < p1; p += I::GPB) {
+  for (long p = xs + k * I::GPB + wave * I::GW + grp; p < xe; p += kx * I::GPB) {
     const int c = (int)(p / g.E), e = (int)(p - (long)c * g.E);
     const int ex = e % g.ne[0], ey = (e / g.ne[0]) % g.ne[1], ez = e / (g.ne[0] * g.ne[1]);
     const int sx = 1, sy = g.ne[0], sz = g.ne[0] * g.ne[1];
@@ -805,16 +812,19 @@ __global__ void __launch_bounds__(1024) k_cg_start_iso(CGStateT<T> cg, const T* 
 
 template <typename T, int NP>
 __global__ void __launch_bounds__(1024)
-k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id, int nparts) {
+k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id, int nparts, int ndel) {
   if (*cg.done_gen == id) return;
   const int cap = cg.cap;
-  T tot[5];
+  T tot[4], dtot[1];
   {
-    const T* const pr[5] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.del,
-                            cg.rr + (it % 2) * cap, cg.bbp};
-    sum_partials<T, 5>(pr, nparts, tot);
+    // this kernel's own partials (nparts), and the matvec's (w, z) partials (ndel)
+    const T* const pr[4] = {cg.gam + (it % 3) * cap, cg.gam + ((it + 2) % 3) * cap, cg.rr + (it % 2) * cap,
+                            cg.bbp};
+    sum_partials<T, 4>(pr, nparts, tot);
+    const T* const pd[1] = {cg.del};
+    sum_partials<T, 1>(pd, ndel, dtot);
   }
-  const T gi = tot[0], gprev = tot[1], di = tot[2], rri = tot[3], bb = tot[4];
+  const T gi = tot[0], gprev = tot[1], di = dtot[0], rri = tot[2], bb = tot[3];
   const T thresh = cg.tol2 * bb;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cg.res->rr = rri;
@@ -1305,10 +1315,10 @@ static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, co
   // the partial count must equal the grid of the CG kernels that sum them
   const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
   if constexpr (DIM == 3 && (P == 1 || P == 3 || P == 7)) {
-    if (iso_coef(cf) && (part == nullptr || dotv == x)) {
+    if (iso_coef(cf) && part == nullptr) {  // the isotropic CG calls launch_sipg_apply_iso
       using I = ISO<P>;
       const long groups = ((long)nv * g.E + I::GPB - 1) / I::GPB;
-      const int nbi = part ? nb : (int)std::min<long>(std::max<long>(groups, 1), 8192);
+      const int nbi = (int)std::min<long>(std::max<long>(groups, 1), 8192);
       hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nbi), dim3(I::NT), 0, s, x, (const T*)nullptr, out, nv, vs,
                          cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
       return hipGetLastError();
@@ -1408,14 +1418,33 @@ static int iso_grid(const Geo& g) {
   return std::min(elem_tiles<3, P>(g), kElemCap);
 }
 
+// Grid of the isotropic matvec: the workgroups that are resident at once
+// (so that each XCD's interleaved window of pairs is the one in flight),
+// at most kElemCap (partial sums) and at most one per lane group needed.
+template <typename T, int P>
+static int iso_apply_grid(const Geo& g, int nv) {
+  using I = ISO<P>;
+  static const int resident = [] {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sipg_apply_iso3<T, P>, I::NT, 0) !=
+            hipSuccess)
+      return kElemCap;
+    return std::max(1, per_cu * ncu);
+  }();
+  const long groups = ((long)nv * g.E + I::GPB - 1) / I::GPB;
+  return (int)std::max<long>(1, std::min<long>({(long)resident, (long)kElemCap, groups}));
+}
+
 template <typename T, int P>
 static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha, T beta,
                               T ctau, const Geo& g, const T* tab, T* part, const int* done_gen, int id,
                               hipStream_t s) {
   using I = ISO<P>;
   const long vs = (long)g.E * I::NP;
-  hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(iso_grid<P>(g)), dim3(I::NT), 0, s, x, isc, out, nv, vs, cf.nu,
-                     alpha, beta, ctau, g, tab, part, done_gen, id);
+  hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(iso_apply_grid<T, P>(g, nv)), dim3(I::NT), 0, s, x, isc, out,
+                     nv, vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
   return hipGetLastError();
 }
 
@@ -1432,7 +1461,8 @@ static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, con
                                 hipStream_t s) {
   constexpr int NP = (P + 1) * (P + 1) * (P + 1);
   const int nb = iso_grid<P>(g);
-  hipLaunchKernelGGL((k_cg_iter_iso<T, NP>), dim3(nb), dim3(1024), 0, s, cg, idg, (long)nv * g.E * NP, it, id, nb);
+  hipLaunchKernelGGL((k_cg_iter_iso<T, NP>), dim3(nb), dim3(1024), 0, s, cg, idg, (long)nv * g.E * NP, it, id, nb,
+                     iso_apply_grid<T, P>(g, nv));
   return hipGetLastError();
 }
 

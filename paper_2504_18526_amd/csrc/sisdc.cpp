@@ -1542,8 +1542,10 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     hipStream_t s = h->stream;
     CoefP cf = coef_for(h, L, dt_m, L.um(0));
     const double* x = L.M >= 1 ? L.um(1) : L.um(0);
-    // a CG state on the level's data: b = M u_1, x0 = 0, never converging (rtol = 0)
-    lincomb(h, L, L.b, {{1.0, x}}, {1});
+    // a CG state on the level's data: b = M u_1 + diag (never zero), x0 = 0,
+    // never converging (rtol = 0)
+    HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
+    lincomb(h, L, L.b, {{1.0, x}, {1.0, L.diag}}, {1, 0});
     HIPCHECK(hipMemsetAsync(L.t2, 0, L.vlen * sizeof(double), s));
     const int id = ++h->solve_id;
     CGState cg = cg_state<double>(h, bufs64(h, L), L.b, L.t2, 0.0);
