@@ -850,15 +850,21 @@ k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id,
   T a[2] = {T(0.0), T(0.0)};
   const long lb = xcd_block(blockIdx.x, gridDim.x);
   const long i0 = lb * n / gridDim.x, i1 = (lb + 1) * n / gridDim.x;
+  // x is updated every second iteration, with both steps at once:
+  // x += alpha_{it-1} p_{it-1} + alpha_it p_it (p_{it-1} is read anyway);
+  // k_cg_fix_iso adds a last pending step after the loop.
+  const bool odd = (it & 1) != 0;
+  const T aprev = odd ? cg.alpha[(it + 1) % 2] : T(0.0);
   for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const T ig = idg[i & (NP - 1)];
     const T r0 = cg.r[i], wi = cg.w[i];
     const T z0 = r0 * ig;
-    const T pi = it == 0 ? z0 : z0 + beta * cg.p[i];
+    const T pold = it == 0 ? T(0.0) : cg.p[i];
+    const T pi = z0 + beta * pold;
     const T si = it == 0 ? wi : wi + beta * cg.s[i];
     cg.p[i] = pi;
     cg.s[i] = si;
-    cg.x[i] += alpha * pi;
+    if (odd) cg.x[i] += aprev * pold + alpha * pi;
     const T ri = r0 - alpha * si;
     cg.r[i] = ri;
     const T zi = ri * ig;
@@ -867,6 +873,19 @@ k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id,
   }
   T* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
   block_partials<T, 2>(a, pp);
+}
+
+// After the loop of k_cg_iter_iso: if the last iteration that updated the
+// vectors (L) was even, x still lacks alpha_L p_L; add it.  L is read from
+// the result record (the converged iteration - 1, else the last launched).
+template <typename T>
+__global__ void k_cg_fix_iso(CGStateT<T> cg, long n, int id) {
+  const bool done = *cg.done_gen == id;
+  const int L = done ? cg.res->it - 1 : cg.res->it_last;
+  if (L < 0 || (L & 1)) return;
+  const T al = cg.alpha[L % 2];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    cg.x[i] += al * cg.p[i];
 }
 
 // Jacobi diagonal of M + dt_m K_D (volume terms with d = d' and the face
@@ -1519,6 +1538,10 @@ static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, con
     if (g.dim != 3) return hipErrorInvalidValue;                                                                \
     SISDC_DISPATCH_ISO(g.P, return (cg_iter_iso_p<T, PP>(cg, idg, nv, g, it, id, s)));                          \
     return hipErrorInvalidValue;                                                                                \
+  }                                                                                                             \
+  hipError_t launch_cg_fix_iso(const CGStateT<T>& cg, long n, int id, hipStream_t s) {                          \
+    hipLaunchKernelGGL((k_cg_fix_iso<T>), dim3(blocks_for(n, 256, 2048)), dim3(256), 0, s, cg, n, id);          \
+    return hipGetLastError();                                                                                   \
   }
 
 SISDC_PRECISION_LAUNCHERS(double)

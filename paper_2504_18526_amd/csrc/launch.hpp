@@ -45,7 +45,9 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
                                    int id, hipStream_t s);                                                      \
   hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s);     \
   hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
-                                hipStream_t s);
+                                hipStream_t s);                                                                 \
+  /* the streaming CG updates x every second iteration; this adds the step still pending after its loop */     \
+  hipError_t launch_cg_fix_iso(const CGStateT<T>& cg, long n, int id, hipStream_t s);
 
 SISDC_DECLARE_PRECISION_LAUNCHERS(double)
 SISDC_DECLARE_PRECISION_LAUNCHERS(float)

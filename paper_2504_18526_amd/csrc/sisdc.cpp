@@ -475,6 +475,7 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
     if (it > maxit) break;
     chunk = 8;
   }
+  if (iso) HIPCHECK(launch_cg_fix_iso(cg, L.vlen, id, s));
   sisdc_solve_stats r{};
   r.iters = converged ? h->hres->it : maxit;
   const double rel = h->hres->bb > 0.0 ? std::sqrt(h->hres->rr / h->hres->bb) : 0.0;
