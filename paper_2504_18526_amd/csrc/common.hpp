@@ -74,7 +74,8 @@ using CGState = CGStateT<double>;
 // device-scope (L2 write-through) stores and loads; bar[64] is the abort word.
 struct PCGArgs {
   const double* b;
-  double* x;       // in: initial guess, out: solution
+  double* x;       // out: solution
+  const double* x0;  // in: initial guess (may equal x)
   double* fz;      // face values of the exchanged vector, 2 x [c][e][dim][side][f]
   double* ft;      // face traces of (D grad .),      2 x [c][e][dim][side][f]
   double* part;    // barrier records: 2 (barrier parity) x cap records of 8 doubles

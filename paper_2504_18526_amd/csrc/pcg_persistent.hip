@@ -311,7 +311,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // vectors of the pipelined iteration (Ghysels-Vanroose, preconditioned)
   double x[NV], r[NV], u[NV], w[NV], m[NV], nn[NV], zv[NV], q[NV], s[NV], p[NV];
   for (int c = 0; c < NV; ++c) {
-    x[c] = act ? a.x[c * vs + own] : 0.0;
+    x[c] = act ? a.x0[c * vs + own] : 0.0;
     zv[c] = q[c] = s[c] = p[c] = 0.0;
   }
   const double idg = act ? 1.0 / dg : 0.0;

@@ -380,11 +380,12 @@ void drain(sisdc_handle* h) {
 }
 
 bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
-                      double rtol, int maxit) {
+                      double rtol, int maxit, const double* x0 = nullptr) {
   if (h->ring_n >= kRing) drain(h);
   PCGArgs a{};
   a.b = b;
   a.x = x;
+  a.x0 = x0 ? x0 : x;
   a.fz = L.fz;
   a.ft = L.ft;
   a.part = h->ppart;
@@ -617,8 +618,21 @@ sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, doub
   return r;
 }
 
-sisdc_solve_stats solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x) {
-  return cg_solve(h, L, cf, dtm, b, x, h->meth.cg_rtol, h->meth.cg_maxit);
+// Solve with the initial guess x0 (x0 == x: x holds it).  The persistent
+// PCG reads x0 and writes x itself; the other forms start from a copy.
+sisdc_solve_stats solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
+                        const double* x0) {
+  const double rtol = h->meth.cg_rtol;
+  const bool plain = !(L.net.on && (L.net.use || L.net.harvest)) && h->meth.precision != SISDC_MIXED;
+  if (x0 != x && plain && L.persistent && rtol >= kPersistentMinRtol &&
+      persistent_solve(h, L, cf, dtm, b, x, rtol, h->meth.cg_maxit, x0)) {
+    sisdc_solve_stats r{};
+    r.iters = -1;  // collected later by drain()
+    r.converged = 1;
+    return r;
+  }
+  if (x0 != x) copy_d2d(h, x, x0, L.vlen);
+  return cg_solve(h, L, cf, dtm, b, x, rtol, h->meth.cg_maxit);
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -659,13 +673,11 @@ void predictor(sisdc_handle* h, Level& L, double dt) {
     conv(h, L, ua, L.t1);
     lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
     double* y = si1 ? L.um(m) : L.y;
-    copy_d2d(h, y, ua, L.vlen);
-    solve(h, L, cf, dtm, L.b, y);
+    solve(h, L, cf, dtm, L.b, y, ua);
     if (!si1) {
       conv(h, L, y, L.t1);
       lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
-      copy_d2d(h, L.um(m), y, L.vlen);
-      solve(h, L, cf, dtm, L.b, L.um(m));
+      solve(h, L, cf, dtm, L.b, L.um(m), y);
     }
   }
   L.stale = true;
@@ -695,8 +707,7 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
     else
       lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0});
     double* y = si1 ? L.unm(m) : L.y;
-    copy_d2d(h, y, L.um(m), n);
-    solve(h, L, cf, dtm, L.b, y);
+    solve(h, L, cf, dtm, L.b, y, L.um(m));
     if (!si1) {
       // stage 2: M u^k_m = M u^k_{m-1} + q_m + g_m + H(y,u^k_{m-1},u^k_m) - H(u^{k-1}_m,u^{k-1}_{m-1},u^{k-1}_m)
       conv(h, L, y, L.t1);
@@ -704,8 +715,7 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
         lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0});
       else
         lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0});
-      copy_d2d(h, L.unm(m), y, n);
-      solve(h, L, cf, dtm, L.b, L.unm(m));
+      solve(h, L, cf, dtm, L.b, L.unm(m), y);
     }
     // stored terms of the new iterate at node m
     double* Cm = L.Cnew + (long)m * n;
