@@ -107,9 +107,10 @@ typedef struct {
   double c_tau;        /* SIPG penalty factor C_tau (tau = C_tau (P+1)^2 kappa / h) */
   int precision;       /* SISDC_FP64 or SISDC_MIXED                         */
   int cg_variant;      /* SISDC_CG_AUTO: one cooperative launch per solve
-                          (pipelined PCG) when the level's elements fit on the
-                          GPU at once and rtol >= 1e-11, else the multi-kernel
-                          form; SISDC_CG_MULTI_KERNEL: always the multi-kernel
+                          (pipelined PCG) for scalar equations when the
+                          level's elements fit on the GPU at once and
+                          rtol >= 1e-11, else the multi-kernel form;
+                          SISDC_CG_MULTI_KERNEL: always the multi-kernel
                           form                                              */
   double inner_rtol;   /* SISDC_MIXED: relative tolerance of each FP32 inner
                           solve (<= 0: 1e-5)                                */

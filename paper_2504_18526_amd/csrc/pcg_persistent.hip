@@ -449,8 +449,7 @@ template <int DIM, int P>
 static hipError_t pcg_dim_p(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
                             int max_blocks, hipStream_t s) {
   if (nv == 1) return pcg_dim_p_nv<DIM, P, 1>(a, cf, g, tab, max_blocks, s);
-  if (nv == DIM + 2) return pcg_dim_p_nv<DIM, P, DIM + 2>(a, cf, g, tab, max_blocks, s);
-  return hipErrorInvalidValue;
+  return hipErrorInvalidValue;  // systems use the multi-kernel PCG (faster there)
 }
 
 template <int DIM, int P, int NV>
@@ -465,7 +464,6 @@ static int occ_dim_p_nv() {
 template <int DIM, int P>
 static int occ_dim_p(int nv) {
   if (nv == 1) return occ_dim_p_nv<DIM, P, 1>();
-  if (nv == DIM + 2) return occ_dim_p_nv<DIM, P, DIM + 2>();
   return 0;
 }
 

@@ -379,6 +379,15 @@ void drain(sisdc_handle* h) {
   if (nonfinite) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
 }
 
+// Levels that use the persistent PCG under SISDC_CG_AUTO: scalar equations
+// whose tiles fit the partial-sum records.  For systems the per-workgroup
+// work of an iteration grows with the number of components and the
+// multi-kernel form is faster (three-level Euler workload: 54 against 84 ms
+// per step).
+bool persistent_fits(const sisdc_handle* h, const Level& L, int variant) {
+  return variant == SISDC_CG_AUTO && L.nv == 1 && elem_tile_count(L.g) <= h->pcap;
+}
+
 bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                       double rtol, int maxit, const double* x0 = nullptr) {
   if (h->ring_n >= kRing) drain(h);
@@ -1231,7 +1240,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     if (hipHostMalloc(&hrr, kRing * sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
     h->hring = (CGRes*)hrr;
     for (auto& L : h->lv)
-      L.persistent = meth->cg_variant == SISDC_CG_AUTO && elem_tile_count(L.g) <= h->pcap;
+      L.persistent = persistent_fits(h, L, meth->cg_variant);
     h->state = dalloc(h->lv[0].vlen);
     size_t io = 0;
     for (auto& L : h->lv) io = std::max(io, (size_t)(L.M + 1) * L.vlen);
@@ -1844,7 +1853,7 @@ int batch_run(sisdc_batch* b, F&& f) {
 // whose tiles fit use the persistent kernel).
 void set_cg_variant(sisdc_handle* h, int variant) {
   h->meth.cg_variant = variant;
-  for (auto& L : h->lv) L.persistent = variant == SISDC_CG_AUTO && elem_tile_count(L.g) <= h->pcap;
+  for (auto& L : h->lv) L.persistent = persistent_fits(h, L, variant);
 }
 
 }  // namespace
