@@ -780,6 +780,149 @@ k_sipg_apply_iso3(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
   }
 }
 
+// The same isotropic apply on quadrilaterals: a group of P+1 lanes owns a
+// (component, element) pair (64 / (P+1) groups per wave, the remaining lanes
+// idle), lane a holding, for each of the two axes, the line through a.
+template <int P>
+struct ISO2 {
+  static constexpr int N1 = P + 1, NP = N1 * N1, LG = N1, GW = 64 / N1;
+  static constexpr int WAVES = 8;
+  static constexpr int NT = 64 * WAVES, GPB = GW * WAVES;
+  static constexpr int SY = N1 + 1, REG = N1 * SY;  // padded LDS region of a group
+};
+
+template <int D, int N1>
+__device__ __forceinline__ int line_node2(int k, int a) {
+  return D == 0 ? k + N1 * a : a + N1 * k;
+}
+
+template <typename T, int P, int D>
+__device__ __forceinline__ void load_line2(const T* __restrict__ xc, int e, int a, const T* sc, bool scaled,
+                                           T (&v)[P + 1]) {
+  constexpr int N1 = P + 1, NP = N1 * N1;
+  const T* const xe = xc + (long)e * NP;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int n = line_node2<D, N1>(k, a);
+    v[k] = scaled ? xe[n] * sc[n] : xe[n];
+  }
+}
+
+// Axis D on the line a of element e (neighbours nbm, nbp across the faces
+// normal to D); wl = w_a, the weight of the line's other coordinate.
+template <typename T, int P, int D>
+__device__ __forceinline__ void iso_axis2(const T* __restrict__ xc, const T* sc, bool scaled, const T (&xl)[P + 1],
+                                          T (&r)[P + 1], int nbm, int nbp, int a, const Geo& g, T nu, T pen, T wl) {
+  constexpr int N1 = P + 1;
+  const T rh = (T)g.rh2[D], J = (T)g.J;
+  T q[N1], Q[N1];
+  static_for<N1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    T s = T(0.0);
+    static_for<N1>([&](auto jc) { s += gll_d<T, P, k, decltype(jc)::value>() * xl[decltype(jc)::value]; });
+    q[k] = nu * rh * s;
+    Q[k] = J * wl * gll_w<T, P, k>() * q[k];
+  });
+  const T jfwf = J * rh * wl;
+  const T tau = pen * nu * T(0.5) * rh;
+  static_for<2>([&](auto sidec) {
+    constexpr int side = decltype(sidec)::value;
+    constexpr int ke = side ? P : 0;
+    constexpr int kn = side ? 0 : P;
+    const T sgn = side ? T(1.0) : -T(1.0);
+    T nl[N1];
+    load_line2<T, P, D>(xc, side ? nbp : nbm, a, sc, scaled, nl);
+    T sn = T(0.0);
+    static_for<N1>([&](auto jc) { sn += gll_d<T, P, kn, decltype(jc)::value>() * nl[decltype(jc)::value]; });
+    const T qn = T(0.5) * sgn * (q[ke] + nu * rh * sn);
+    const T jump = xl[ke] - nl[kn];
+    r[ke] += jfwf * (-qn + tau * jump);
+    Q[ke] -= T(0.5) * jfwf * jump * sgn * nu;
+  });
+  static_for<N1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    T s = T(0.0);
+    static_for<N1>([&](auto jc) { s += gll_d<T, P, decltype(jc)::value, k>() * Q[decltype(jc)::value]; });
+    r[k] += rh * s;
+  });
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__((ISO2<P>::NT))
+k_sipg_apply_iso2(const T* __restrict__ x, const T* __restrict__ isc, T* __restrict__ out, int nv, long vs, T nu,
+                  T alpha, T beta, T ctau, Geo g, const T* __restrict__ tab, T* part,
+                  const int* __restrict__ done_gen, int id) {
+  using I = ISO2<P>;
+  constexpr int N1 = I::N1, LG = I::LG, SY = I::SY, REG = I::REG;
+  if (done_gen != nullptr && *done_gen == id) return;
+  __shared__ T sR[I::GPB * REG];
+  __shared__ T sc[I::NP];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int grp = lane / LG, a = lane - grp * LG;
+  const bool lane_on = grp < I::GW;
+  T* const R = &sR[(wave * I::GW + (lane_on ? grp : 0)) * REG];
+  const T* const w = tab + N1 * N1;
+  const T pen = ctau * (T)(N1 * N1), J = (T)g.J;
+  const T wa = w[lane_on ? a : 0];
+  const bool scaled = isc != nullptr;
+  if (scaled)
+    for (int k = threadIdx.x; k < I::NP; k += blockDim.x) sc[k] = isc[k];
+  __syncthreads();
+  const long npairs = (long)nv * g.E;
+  const int G = gridDim.x, xcd = blockIdx.x % kXcd, per = G / kXcd, rem = G % kXcd;
+  const long kx = per + (xcd < rem ? 1 : 0);
+  const long lb0 = (long)xcd * per + (xcd < rem ? xcd : rem);
+  const long xs = lb0 * npairs / G, xe = (lb0 + kx) * npairs / G;
+  const long kk = blockIdx.x / kXcd;
+  T dacc = T(0.0);
+  for (long p = xs + kk * I::GPB + wave * I::GW + grp; lane_on && p < xe; p += kx * I::GPB) {
+    const int c = (int)(p / g.E), e = (int)(p - (long)c * g.E);
+    const int ex = e % g.ne[0], ey = e / g.ne[0];
+    const int sy = g.ne[0];
+    const int nbm0 = e + (ex > 0 ? -1 : g.ne[0] - 1), nbp0 = e + (ex < g.ne[0] - 1 ? 1 : -(g.ne[0] - 1));
+    const int nbm1 = e + (ey > 0 ? -sy : (g.ne[1] - 1) * sy), nbp1 = e + (ey < g.ne[1] - 1 ? sy : -(g.ne[1] - 1) * sy);
+    const T* const xc = x + c * vs;
+    T xl[N1], r[N1];
+    load_line2<T, P, 0>(xc, e, a, sc, scaled, xl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    iso_axis2<T, P, 0>(xc, sc, scaled, xl, r, nbm0, nbp0, a, g, nu, pen, wa);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) R[k + SY * a] = r[k];
+    wave_lds_fence();
+    load_line2<T, P, 1>(xc, e, a, sc, scaled, xl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    iso_axis2<T, P, 1>(xc, sc, scaled, xl, r, nbm1, nbp1, a, g, nu, pen, wa);
+    const T ja = J * wa;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const T val = alpha * ja * w[k] * xl[k] + beta * (r[k] + R[a + SY * k]);
+      out[c * vs + (long)e * I::NP + line_node2<1, N1>(k, a)] = val;
+      dacc += val * xl[k];
+    }
+    wave_lds_fence();
+  }
+  if (part != nullptr) {
+    const T v1[1] = {dacc};
+    T* const pp[1] = {part};
+    block_partials<T, 1>(v1, pp);
+  }
+}
+
+template <typename T, int DIM, int P>
+struct IsoKernel;  // the matvec kernel, its block size and lane groups per block
+template <typename T, int P>
+struct IsoKernel<T, 3, P> {
+  static constexpr int NT = ISO<P>::NT, GPB = ISO<P>::GPB;
+  static const void* fn() { return (const void*)k_sipg_apply_iso3<T, P>; }
+};
+template <typename T, int P>
+struct IsoKernel<T, 2, P> {
+  static constexpr int NT = ISO2<P>::NT, GPB = ISO2<P>::GPB;
+  static const void* fn() { return (const void*)k_sipg_apply_iso2<T, P>; }
+};
+
 // NP-periodic inverse of the Jacobi diagonal of an isotropic operator (the
 // diagonal is the same for every element and component): idg[n] = 1/diag[n].
 template <typename T>
@@ -800,7 +943,7 @@ __global__ void __launch_bounds__(1024) k_cg_start_iso(CGStateT<T> cg, const T* 
   for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const T bi = cg.b[i];
     const T ri = bi - cg.w[i];
-    const T zi = ri * idg[i & (NP - 1)];
+    const T zi = ri * idg[i % NP];
     cg.r[i] = ri;
     a[0] += ri * zi;
     a[1] += ri * ri;
@@ -856,7 +999,7 @@ k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id,
   const bool odd = (it & 1) != 0;
   const T aprev = odd ? cg.alpha[(it + 1) % 2] : T(0.0);
   for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const T ig = idg[i & (NP - 1)];
+    const T ig = idg[i % NP];
     const T r0 = cg.r[i], wi = cg.w[i];
     const T z0 = r0 * ig;
     const T pold = it == 0 ? T(0.0) : cg.p[i];
@@ -1333,13 +1476,17 @@ static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, co
   const long vs = (long)g.E * L::NP;
   // the partial count must equal the grid of the CG kernels that sum them
   const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
-  if constexpr (DIM == 3 && (P == 1 || P == 3 || P == 7)) {
+  if constexpr (DIM == 2 || P == 1 || P == 3 || P == 7) {
     if (iso_coef(cf) && part == nullptr) {  // the isotropic CG calls launch_sipg_apply_iso
-      using I = ISO<P>;
-      const long groups = ((long)nv * g.E + I::GPB - 1) / I::GPB;
+      using K = IsoKernel<T, DIM, P>;
+      const long groups = ((long)nv * g.E + K::GPB - 1) / K::GPB;
       const int nbi = (int)std::min<long>(std::max<long>(groups, 1), 8192);
-      hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nbi), dim3(I::NT), 0, s, x, (const T*)nullptr, out, nv, vs,
-                         cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+      if constexpr (DIM == 3)
+        hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const T*)nullptr, out, nv,
+                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+      else
+        hipLaunchKernelGGL((k_sipg_apply_iso2<T, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const T*)nullptr, out, nv,
+                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
       return hipGetLastError();
     }
   }
@@ -1417,10 +1564,12 @@ static hipError_t cg_iter_t(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, c
   return hipErrorInvalidValue;
 }
 
-// Isotropic hexahedral path: D = nu I constant on the level, dim 3, P in {1, 3, 7}.
+// Isotropic path: D = nu I constant on the level; hexahedra with P in
+// {1, 3, 7} ((P+1)^2 lanes tile a wave) and quadrilaterals of any degree.
 template <typename T>
 static bool iso_path_t(const Geo& g, const CoefT<T>& cf) {
-  return g.dim == 3 && (g.P == 1 || g.P == 3 || g.P == 7) && iso_coef(cf);
+  const bool shape = (g.dim == 3 && (g.P == 1 || g.P == 3 || g.P == 7)) || (g.dim == 2 && g.P >= 1 && g.P <= 8);
+  return shape && iso_coef(cf);
 }
 
 #define SISDC_DISPATCH_ISO(P_, BODY)                 \
@@ -1431,57 +1580,68 @@ static bool iso_path_t(const Geo& g, const CoefT<T>& cf) {
     default: return hipErrorInvalidValue;            \
   }
 
+// dispatch over (dim, P) of the isotropic path; BODY uses DD and PP
+#define SISDC_DISPATCH_ISO_DIM(G_, BODY)                                                  \
+  do {                                                                                    \
+    if ((G_).dim == 3) { constexpr int DD = 3; SISDC_DISPATCH_ISO((G_).P, BODY); }        \
+    if ((G_).dim == 2) { constexpr int DD = 2; SISDC_DISPATCH_P((G_).P, BODY); }          \
+    return hipErrorInvalidValue;                                                          \
+  } while (0)
+
 // grid of the isotropic CG kernels: the same partial count as the matvec
-template <int P>
+template <int DIM, int P>
 static int iso_grid(const Geo& g) {
-  return std::min(elem_tiles<3, P>(g), kElemCap);
+  return std::min(elem_tiles<DIM, P>(g), kElemCap);
 }
 
 // Grid of the isotropic matvec: the workgroups that are resident at once
 // (so that each XCD's interleaved window of pairs is the one in flight),
 // at most kElemCap (partial sums) and at most one per lane group needed.
-template <typename T, int P>
+template <typename T, int DIM, int P>
 static int iso_apply_grid(const Geo& g, int nv) {
-  using I = ISO<P>;
+  using K = IsoKernel<T, DIM, P>;
   static const int resident = [] {
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sipg_apply_iso3<T, P>, I::NT, 0) !=
-            hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K::fn(), K::NT, 0) != hipSuccess)
       return kElemCap;
     return std::max(1, per_cu * ncu);
   }();
-  const long groups = ((long)nv * g.E + I::GPB - 1) / I::GPB;
+  const long groups = ((long)nv * g.E + K::GPB - 1) / K::GPB;
   return (int)std::max<long>(1, std::min<long>({(long)resident, (long)kElemCap, groups}));
 }
 
-template <typename T, int P>
+template <typename T, int DIM, int P>
 static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha, T beta,
                               T ctau, const Geo& g, const T* tab, T* part, const int* done_gen, int id,
                               hipStream_t s) {
-  using I = ISO<P>;
-  const long vs = (long)g.E * I::NP;
-  hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(iso_apply_grid<T, P>(g, nv)), dim3(I::NT), 0, s, x, isc, out,
-                     nv, vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+  const long vs = (long)g.E * EL<DIM, P>::NP;
+  const int nb = iso_apply_grid<T, DIM, P>(g, nv);
+  if constexpr (DIM == 3)
+    hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nb), dim3(ISO<P>::NT), 0, s, x, isc, out, nv, vs, cf.nu,
+                       alpha, beta, ctau, g, tab, part, done_gen, id);
+  else
+    hipLaunchKernelGGL((k_sipg_apply_iso2<T, P>), dim3(nb), dim3(ISO2<P>::NT), 0, s, x, isc, out, nv, vs, cf.nu,
+                       alpha, beta, ctau, g, tab, part, done_gen, id);
   return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int DIM, int P>
 static hipError_t cg_start_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {
-  constexpr int NP = (P + 1) * (P + 1) * (P + 1);
-  hipLaunchKernelGGL((k_cg_start_iso<T, NP>), dim3(iso_grid<P>(g)), dim3(1024), 0, s, cg, idg,
+  constexpr int NP = EL<DIM, P>::NP;
+  hipLaunchKernelGGL((k_cg_start_iso<T, NP>), dim3(iso_grid<DIM, P>(g)), dim3(1024), 0, s, cg, idg,
                      (long)nv * g.E * NP);
   return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int DIM, int P>
 static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,
                                 hipStream_t s) {
-  constexpr int NP = (P + 1) * (P + 1) * (P + 1);
-  const int nb = iso_grid<P>(g);
+  constexpr int NP = EL<DIM, P>::NP;
+  const int nb = iso_grid<DIM, P>(g);
   hipLaunchKernelGGL((k_cg_iter_iso<T, NP>), dim3(nb), dim3(1024), 0, s, cg, idg, (long)nv * g.E * NP, it, id, nb,
-                     iso_apply_grid<T, P>(g, nv));
+                     iso_apply_grid<T, DIM, P>(g, nv));
   return hipGetLastError();
 }
 
@@ -1524,20 +1684,15 @@ static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, con
                                    T beta, T ctau, const Geo& g, const T* tab, T* part, const int* done_gen,    \
                                    int id, hipStream_t s) {                                                     \
     if (!iso_path_t<T>(g, cf)) return hipErrorInvalidValue;                                                     \
-    SISDC_DISPATCH_ISO(g.P, return (apply_iso_p<T, PP>(x, isc, out, nv, cf, alpha, beta, ctau, g, tab, part,    \
-                                                       done_gen, id, s)));                                      \
-    return hipErrorInvalidValue;                                                                                \
+    SISDC_DISPATCH_ISO_DIM(g, return (apply_iso_p<T, DD, PP>(x, isc, out, nv, cf, alpha, beta, ctau, g, tab,    \
+                                                             part, done_gen, id, s)));                          \
   }                                                                                                             \
   hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {    \
-    if (g.dim != 3) return hipErrorInvalidValue;                                                                \
-    SISDC_DISPATCH_ISO(g.P, return (cg_start_iso_p<T, PP>(cg, idg, nv, g, s)));                                 \
-    return hipErrorInvalidValue;                                                                                \
+    SISDC_DISPATCH_ISO_DIM(g, return (cg_start_iso_p<T, DD, PP>(cg, idg, nv, g, s)));                           \
   }                                                                                                             \
   hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
                                 hipStream_t s) {                                                                \
-    if (g.dim != 3) return hipErrorInvalidValue;                                                                \
-    SISDC_DISPATCH_ISO(g.P, return (cg_iter_iso_p<T, PP>(cg, idg, nv, g, it, id, s)));                          \
-    return hipErrorInvalidValue;                                                                                \
+    SISDC_DISPATCH_ISO_DIM(g, return (cg_iter_iso_p<T, DD, PP>(cg, idg, nv, g, it, id, s)));                    \
   }                                                                                                             \
   hipError_t launch_cg_fix_iso(const CGStateT<T>& cg, long n, int id, hipStream_t s) {                          \
     hipLaunchKernelGGL((k_cg_fix_iso<T>), dim3(blocks_for(n, 256, 2048)), dim3(256), 0, s, cg, n, id);          \

@@ -60,6 +60,8 @@ OPS = [
     ("ns", 3, (2, 3, 2), 4),
     ("ns", 3, (2, 1, 2), 7),
     ("euler", 3, (3, 2, 2), 1),
+    ("euler", 2, (3, 2), 8),
+    ("ns", 2, (1, 4), 3),
 ]
 
 
@@ -118,7 +120,8 @@ def test_profile_hooks(S, eq, dim, n, P):
 
 
 @pytest.mark.parametrize("variant", ["auto", "multi"])
-@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[4], OPS[5], OPS[9], OPS[10]])
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[4], OPS[5], OPS[9], OPS[10], OPS[11],
+                                        OPS[12]])
 def test_helmholtz_solve(S, eq, dim, n, P, variant):
     cgv = S.CG_AUTO if variant == "auto" else S.CG_MULTI_KERNEL
     phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], cg_variant=cgv)
@@ -371,7 +374,7 @@ def test_persistent_steps(S, case):
 RTOL_MIXED = 1e-12
 
 
-@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[5], OPS[9]])
+@pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[5], OPS[9], OPS[11]])
 def test_mixed_solve(S, eq, dim, n, P):
     phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], rtol=RTOL_MIXED, precision=S.MIXED)
     rng = np.random.default_rng(100 + P)
