@@ -45,6 +45,7 @@ TRAFFIC_SOURCES = {
     "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],
     "k_sipg_apply": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
     "k_sipg_apply_iso3": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
+    "k_sipg_apply_iso2": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
     "k_cg_iter": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
     "k_cg_iter_iso": ["kernels.hip", "common.hpp", "xcd.hpp", "gll_const.hpp"],
 }
@@ -423,14 +424,14 @@ def main():
     dtm = dt / M
     nf = (w["P"][0] + 1) ** (w["dim"] - 1)  # face nodes per element face
     traces = 2 * w["dim"] * nf / Np         # face-trace words per DOF
-    iso = w["eq"] in ("euler", "ns") and w["dim"] == 3 and w["P"][0] in (1, 3, 7)
+    iso = w["eq"] in ("euler", "ns") and (w["dim"] == 2 or w["P"][0] in (1, 3, 7))
     if iso:
-        # isotropic hexahedral kernels: the matvec reads r (scaled in-kernel to
-        # z) and writes w; the update reads r, w, p, s and writes r, p, s, and
-        # every second iteration also x (read + write).  The timed launches
-        # repeat iteration 0, an even one: 7 words.
-        mv_words, up_words = 2.0, 7.0
-        mv_name = f"k_sipg_apply_iso3<{w['P'][0]}>"
+        # isotropic kernels: the matvec reads r (scaled in-kernel to z) and
+        # writes w; the update reads r, w, p, s and writes r, p, s, and on odd
+        # iterations also x (read + write).  The timed launches alternate odd
+        # and even iterations: 8 words on average.
+        mv_words, up_words = 2.0, 8.0
+        mv_name = f"k_sipg_apply_iso{w['dim']}<{w['P'][0]}>"
         up_name = f"k_cg_iter_iso<{Np}>"
     else:
         reads_ub = 1.0 if w["eq"] == "burgers" else 0.0  # the coefficient state (Burgers only)

@@ -239,7 +239,11 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
  *                       dot product (face traces from SISDC_K_SIPG_TRACE)
  *   SISDC_K_SIPG_TRACE  the face-flux trace pass of the SIPG operator
  *   SISDC_K_CONV        the convective operator C(u)
- *   SISDC_K_CG_UPDATE   the CG vector update with its two dot products */
+ *   SISDC_K_CG_UPDATE   the CG vector update with its two dot products
+ *                       (iteration 0 once, then iterations 1 and 2 in turn)
+ * On isotropic levels (the systems' kappa_m I) the matvec and the update are
+ * those of the streaming PCG: the matvec forms z = r / diag itself and
+ * computes the neighbours' face fluxes (no trace pass). */
 enum { SISDC_K_SIPG_APPLY = 0, SISDC_K_SIPG_TRACE = 1, SISDC_K_CONV = 2, SISDC_K_CG_UPDATE = 3 };
 int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, int reps, double* avg_us);
 
