@@ -78,7 +78,7 @@ enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
                              the node quadrature and the node updates stay
                              FP64; operators and CG vectors of the inner
                              solves are FP32 with FP32 accumulation        */
-enum { SISDC_CG_AUTO = 0, SISDC_CG_MULTI_KERNEL = 1 };
+enum { SISDC_CG_AUTO = 0, SISDC_CG_MULTI_KERNEL = 1, SISDC_CG_PERSISTENT_COOPERATIVE = 2 };
 
 typedef struct {
   int dim;             /* 2 or 3                                            */
@@ -106,12 +106,24 @@ typedef struct {
   int cg_maxit;        /* iteration cap per solve                           */
   double c_tau;        /* SIPG penalty factor C_tau (tau = C_tau (P+1)^2 kappa / h) */
   int precision;       /* SISDC_FP64 or SISDC_MIXED                         */
-  int cg_variant;      /* SISDC_CG_AUTO: one cooperative launch per solve
+  int cg_variant;      /* SISDC_CG_AUTO: one persistent launch per solve
                           (pipelined PCG) for scalar equations when the
                           level's elements fit on the GPU at once and
-                          rtol >= 1e-11, else the multi-kernel form;
+                          rtol >= 1e-11, else the multi-kernel form.  The
+                          persistent kernel is an ordinary launch whose
+                          grid fits the device at once; the library orders
+                          its persistent solves across streams and handles
+                          (each waits for the previous one, wherever it
+                          ran), so two never share the device.  Kernels of
+                          other code that wait on each other across
+                          workgroups must not run at the same time;
                           SISDC_CG_MULTI_KERNEL: always the multi-kernel
-                          form                                              */
+                          form;
+                          SISDC_CG_PERSISTENT_COOPERATIVE: as AUTO, but the
+                          persistent kernel goes through the cooperative-
+                          launch API, which checks co-residency itself and
+                          costs about 25 us more per solve (the queue hand-
+                          over before and after the kernel)               */
   double inner_rtol;   /* SISDC_MIXED: relative tolerance of each FP32 inner
                           solve (<= 0: 1e-5)                                */
 } sisdc_method;

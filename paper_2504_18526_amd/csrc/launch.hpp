@@ -70,12 +70,15 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, long n
 // result[0] = max over nodes of max_d (|v_d| + c), result[1] = min rho
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,
                             hipStream_t s);
-// Persistent PCG: one cooperative launch per solve (pcg_persistent.hip), for
-// scalar equations (nv = 1; hipErrorInvalidValue otherwise).  Fails with
+// Persistent PCG: one launch per solve (pcg_persistent.hip), for scalar
+// equations (nv = 1; hipErrorInvalidValue otherwise).  `cooperative`: through
+// the cooperative-launch API; otherwise an ordinary launch, and the caller
+// makes sure no other grid that waits across workgroups shares the device
+// (all max_blocks workgroups are then resident together).  Fails with
 // hipErrorCooperativeLaunchTooLarge when the level's tiles exceed max_blocks
 // (co-resident workgroups) or the partial-sum capacity.
 hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
-                                 int max_blocks, hipStream_t s);
+                                 int max_blocks, bool cooperative, hipStream_t s);
 int pcg_persistent_blocks_per_cu(const Geo& g, int nv);
 int elem_tile_count(const Geo& g);
 int reduce_grid(const Geo& g);

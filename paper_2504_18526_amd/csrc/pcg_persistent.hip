@@ -1,5 +1,7 @@
 // Persistent Jacobi-PCG for levels whose elements fit on the GPU at once:
-// one cooperative launch per Helmholtz solve (M + dt_m K_D) x = b.
+// one launch per Helmholtz solve (M + dt_m K_D) x = b, with a grid no larger
+// than the number of workgroups the device holds at once (from the occupancy
+// query), so every workgroup is resident while the others wait for it.
 //
 // Every workgroup owns one tile of EPB elements for the whole solve; a
 // thread owns one node and keeps the CG vectors and the Jacobi diagonal in
@@ -433,7 +435,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
 
 template <int DIM, int P, int NV>
 static hipError_t pcg_dim_p_nv(const PCGArgs& a, const CoefP& cf, const Geo& g, const double* tab, int max_blocks,
-                               hipStream_t s) {
+                               bool cooperative, hipStream_t s) {
   using L = PT<DIM, P>;
   const int nb = (g.E + L::EPB - 1) / L::EPB;
   if (nb > max_blocks || nb > a.cap) return hipErrorCooperativeLaunchTooLarge;
@@ -441,14 +443,18 @@ static hipError_t pcg_dim_p_nv(const PCGArgs& a, const CoefP& cf, const Geo& g, 
   CoefP cc = cf;
   Geo gg = g;
   const double* tt = tab;
+  if (!cooperative) {  // ordinary launch: the grid fits the device at once (nb <= max_blocks)
+    hipLaunchKernelGGL((k_pcg_persistent<DIM, P, NV>), dim3(nb), dim3(L::NT), 0, s, aa, cc, gg, tt);
+    return hipGetLastError();
+  }
   void* args[] = {&aa, &cc, &gg, &tt};
   return hipLaunchCooperativeKernel((const void*)k_pcg_persistent<DIM, P, NV>, dim3(nb), dim3(L::NT), args, 0, s);
 }
 
 template <int DIM, int P>
 static hipError_t pcg_dim_p(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
-                            int max_blocks, hipStream_t s) {
-  if (nv == 1) return pcg_dim_p_nv<DIM, P, 1>(a, cf, g, tab, max_blocks, s);
+                            int max_blocks, bool cooperative, hipStream_t s) {
+  if (nv == 1) return pcg_dim_p_nv<DIM, P, 1>(a, cf, g, tab, max_blocks, cooperative, s);
   return hipErrorInvalidValue;  // systems use the multi-kernel PCG (faster there)
 }
 
@@ -481,9 +487,9 @@ static int occ_dim_p(int nv) {
   }
 
 hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
-                                 int max_blocks, hipStream_t s) {
-  if (g.dim == 2) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<2, PP>(a, nv, cf, g, tab, max_blocks, s))); }
-  if (g.dim == 3) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<3, PP>(a, nv, cf, g, tab, max_blocks, s))); }
+                                 int max_blocks, bool cooperative, hipStream_t s) {
+  if (g.dim == 2) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<2, PP>(a, nv, cf, g, tab, max_blocks, cooperative, s))); }
+  if (g.dim == 3) { SISDC_PDISPATCH(g.P, return (pcg_dim_p<3, PP>(a, nv, cf, g, tab, max_blocks, cooperative, s))); }
   return hipErrorInvalidValue;
 }
 

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -81,7 +82,7 @@ struct Level {
   double* trace = nullptr;
   double* fz = nullptr;        // face values exchanged by the persistent PCG (2 buffers)
   double* ft = nullptr;        // face traces exchanged by the persistent PCG (2 buffers)
-  bool persistent = false;     // solves run as one cooperative launch
+  bool persistent = false;     // solves run as one persistent launch
   // FP32 copies and work vectors of the mixed-precision inner solves
   float* tab32 = nullptr;
   float *ub32 = nullptr, *r32 = nullptr, *e32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
@@ -125,6 +126,8 @@ struct sisdc_handle {
   sisdc_problem prob{};
   sisdc_method meth{};
   hipStream_t stream = nullptr;
+  int dev = 0;              // device current at creation
+  bool registered = false;  // stream entered in the persistent-solve order
   EqP eq{};
   std::vector<Level> lv;
   std::vector<Transfer> tr;
@@ -385,7 +388,56 @@ void drain(sisdc_handle* h) {
 // multi-kernel form is faster (three-level Euler workload: 54 against 84 ms
 // per step).
 bool persistent_fits(const sisdc_handle* h, const Level& L, int variant) {
-  return variant == SISDC_CG_AUTO && L.nv == 1 && elem_tile_count(L.g) <= h->pcap;
+  return (variant == SISDC_CG_AUTO || variant == SISDC_CG_PERSISTENT_COOPERATIVE) && L.nv == 1 &&
+         elem_tile_count(L.g) <= h->pcap;
+}
+
+// Order of the persistent solves on one device.  A persistent grid relies on
+// all its workgroups being resident together, so two must never compete for
+// the device: a solve launched on one stream waits (on the GPU) for the
+// latest persistent solve launched on another.  Every handle registers its
+// stream here.  While one stream is registered, stream order alone does
+// this and no event is recorded; with several, an event recorded after
+// each launch marks it (a launch made before the second stream appeared is
+// marked when first needed, by an event recorded on its stream then).
+struct PersistentOrder {
+  std::mutex m;
+  std::vector<std::pair<hipStream_t, int>> streams;  // streams of live handles, with handle counts
+  hipEvent_t done = nullptr;
+  hipStream_t last = nullptr;  // stream of the latest persistent launch
+  bool pending = false;        // that launch may still be running
+  bool marked = false;         // `done` was recorded after it
+};
+constexpr int kMaxDevices = 64;
+PersistentOrder g_porder[kMaxDevices];
+
+PersistentOrder& porder(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(SISDC_EDEVICE, "device ordinal out of range");
+  return g_porder[dev];
+}
+
+void porder_register(int dev, hipStream_t s) {
+  PersistentOrder& po = porder(dev);
+  std::lock_guard<std::mutex> lock(po.m);
+  for (auto& e : po.streams)
+    if (e.first == s) {
+      e.second += 1;
+      return;
+    }
+  po.streams.emplace_back(s, 1);
+}
+
+// The caller has synchronised the device: nothing of `s` is still running.
+void porder_unregister(int dev, hipStream_t s) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  PersistentOrder& po = g_porder[dev];
+  std::lock_guard<std::mutex> lock(po.m);
+  for (size_t i = 0; i < po.streams.size(); ++i)
+    if (po.streams[i].first == s) {
+      if (--po.streams[i].second == 0) po.streams.erase(po.streams.begin() + (long)i);
+      break;
+    }
+  if (po.pending && po.last == s) po.pending = false;
 }
 
 bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
@@ -413,12 +465,30 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const int max_blocks = pcg_persistent_blocks_per_cu(L.g, L.nv) * ncu;
   const int slot = h->ring_n;
+  const bool cooperative = h->meth.cg_variant == SISDC_CG_PERSISTENT_COOPERATIVE;
+  PersistentOrder& po = porder(h->dev);
+  std::lock_guard<std::mutex> lock(po.m);
+  const bool several = po.streams.size() > 1;
+  if (several) {
+    if (!po.done) HIPCHECK(hipEventCreateWithFlags(&po.done, hipEventDisableTiming));
+    if (po.pending && po.last != h->stream) {
+      if (!po.marked) HIPCHECK(hipEventRecord(po.done, po.last));
+      HIPCHECK(hipStreamWaitEvent(h->stream, po.done, 0));
+    }
+  }
   if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot], h->stream));
-  hipError_t e = launch_pcg_persistent(a, L.nv, cf, L.g, L.tab, max_blocks, h->stream);
+  hipError_t e = launch_pcg_persistent(a, L.nv, cf, L.g, L.tab, max_blocks, cooperative, h->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     L.persistent = false;
     return false;
+  }
+  po.last = h->stream;
+  po.pending = true;
+  po.marked = false;
+  if (several) {
+    HIPCHECK(hipEventRecord(po.done, h->stream));
+    po.marked = true;
   }
   if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot + 1], h->stream));
   h->ring_timed.push_back(h->ptime ? 1 : 0);
@@ -1079,7 +1149,9 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
-  if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL) fail(SISDC_EINVAL, "cg_variant");
+  if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL &&
+      m->cg_variant != SISDC_CG_PERSISTENT_COOPERATIVE)
+    fail(SISDC_EINVAL, "cg_variant");
 }
 
 // Caller pointer -> device pointer (host data staged through h->io).
@@ -1246,6 +1318,9 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     for (auto& L : h->lv) io = std::max(io, (size_t)(L.M + 1) * L.vlen);
     h->io_len = io;
     h->io = dalloc(io);
+    HIPCHECK(hipGetDevice(&h->dev));
+    porder_register(h->dev, h->stream);
+    h->registered = true;
   });
   if (rc != SISDC_OK) {
     if (h) sisdc_destroy(h);
@@ -1258,6 +1333,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
 int sisdc_destroy(sisdc_handle* h) {
   if (!h) return SISDC_OK;
   (void)hipDeviceSynchronize();
+  if (h->registered) porder_unregister(h->dev, h->stream);
   for (auto& L : h->lv) {
     net_free(L);
     free_level(L);
@@ -1812,10 +1888,11 @@ int sisdc_net_use(sisdc_handle* h, int level, int on) {
 // thread i mod threads.
 }  // extern "C"
 
-// Cooperative (persistent PCG) launches of different streams are not known
-// to be co-resident with each other, so with more than one host thread every
-// instance runs the multi-kernel PCG; with one thread the instances run one
-// after the other and each uses its own PCG choice (`variant`).
+// Persistent PCG solves of one device run one after another, whatever their
+// stream, so with more than one host thread every instance runs the
+// multi-kernel PCG (the instances' solves then overlap on the device); with
+// one thread the instances run one after the other and each uses its own
+// PCG choice (`variant`).
 struct sisdc_batch {
   std::vector<sisdc_handle*> h;
   std::vector<hipStream_t> streams;

@@ -20,7 +20,7 @@ EQ_CONVDIFF, EQ_BURGERS, EQ_EULER, EQ_NS = 0, 1, 2, 3
 SI2, SI1 = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64, MIXED = 0, 1
-CG_AUTO, CG_MULTI_KERNEL = 0, 1
+CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2
 OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT = range(8)
 
 EXPORTS = [

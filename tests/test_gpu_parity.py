@@ -317,9 +317,14 @@ def test_steps(S, case, variant):
 RTOL_PROD = 1e-10
 
 
+def launch_variant(S, launch):
+    return S.CG_AUTO if launch == "ordinary" else S.CG_PERSISTENT_COOPERATIVE
+
+
+@pytest.mark.parametrize("launch", ["ordinary", "cooperative"])
 @pytest.mark.parametrize("eq,dim,n,P", [OPS[0], OPS[1], OPS[2], OPS[3], OPS[6]])
-def test_persistent_solve_true_residual(S, eq, dim, n, P):
-    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], rtol=RTOL_PROD)
+def test_persistent_solve_true_residual(S, eq, dim, n, P, launch):
+    phys, (lv,), sv = make_pair(S, eq, dim, n, [P], [3], rtol=RTOL_PROD, cg_variant=launch_variant(S, launch))
     rng = np.random.default_rng(80 + P)
     Ub = random_state(phys, lv.mesh, rng)
     params = phys.step_params(Ub)
@@ -342,16 +347,18 @@ def test_persistent_solve_true_residual(S, eq, dim, n, P):
     assert rel_l2(xg, xo) < 1e-8
 
 
+@pytest.mark.parametrize("launch", ["ordinary", "cooperative"])
 @pytest.mark.parametrize("case", ["burgers_2l", "convdiff_1l"])
-def test_persistent_steps(S, case):
+def test_persistent_steps(S, case, launch):
+    cgv = launch_variant(S, launch)
     if case == "burgers_2l":
         phys, levels, sv = make_pair(S, "burgers", 2, (5, 4), [8, 4], [5, 3], nu=5e-3, rtol=RTOL_PROD,
-                                     n_iter=3, start=S.START_CASCADE)
+                                     n_iter=3, start=S.START_CASCADE, cg_variant=cgv)
         ml = MLSDC(list(reversed(levels)), n_coarse=2, start="cascade", cycles=3, post_sweep=True)
         dt = 2e-3
         stepper = lambda v: ml.step(v, dt)
     else:
-        phys, levels, sv = make_pair(S, "convdiff", 2, (7, 3), [4], [3], rtol=RTOL_PROD, n_iter=4)
+        phys, levels, sv = make_pair(S, "convdiff", 2, (7, 3), [4], [3], rtol=RTOL_PROD, n_iter=4, cg_variant=cgv)
         dt = 1.5e-2
         stepper = lambda v: osdc.sdc_step(levels[0], v, dt, 4)
     fine = levels[0]
@@ -365,6 +372,57 @@ def test_persistent_steps(S, case):
         u = stepper(u)
         sv.get_state(out)
         assert rel_l2(host(out), u) < 1e-8, (case, k)
+
+
+def test_persistent_solves_of_two_streams(S):
+    """Two handles on two streams, stepped from two host threads at once: the
+    library orders their persistent solves on the device, so neither one's
+    barrier waits for workgroups the other keeps off the device, and each
+    result equals that of the same handle stepped alone (deterministic
+    reductions: bit for bit)."""
+    import threading
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    w = [dict(n=(16, 16), P=[8, 4], M=[5, 3], dt=2e-3), dict(n=(24, 20), P=[6, 3], M=[4, 3], dt=2e-3)]
+    solvers, u0 = [], []
+    for i, c in enumerate(w):
+        phys = oracle_phys("burgers", 2, nu=5e-3)
+        lv = DGLevel(phys, c["n"], [0.0, 0.0], [1.0, 1.25], c["P"][0], c["M"][0], rtol=1e-14)
+        u0.append(smooth_state(phys, lv, np.random.default_rng(300 + i)).ravel())
+        prob = lib_problem(S, "burgers", 2, c["n"], [0.0, 0.0], [1.0, 1.25], nu=5e-3)
+        m = S.make_method(c["P"], c["M"], start=S.START_CASCADE, n_iter=3, cg_rtol=RTOL_PROD, cg_maxit=2000)
+        solvers.append([S.Solver(prob, m, stream=streams[i].cuda_stream) for _ in range(2)])
+    for i in range(2):
+        for sv in solvers[i]:
+            sv.set_state(dev(u0[i]))
+    torch.cuda.synchronize()
+    errors = []
+
+    def run(i):
+        try:
+            for _ in range(3):
+                st = solvers[i][0].step(w[i]["dt"])
+                assert st["not_converged"] == 0
+        except Exception as e:  # reported by the main thread
+            errors.append((i, e))
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for i in range(2):  # the same steps, one handle at a time
+        for _ in range(3):
+            solvers[i][1].step(w[i]["dt"])
+    for i in range(2):
+        a = torch.empty(u0[i].size, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        solvers[i][0].get_state(a)
+        solvers[i][1].get_state(b)
+        assert torch.equal(a, b), i
+    for pair in solvers:
+        for sv in pair:
+            sv.close()
 
 
 # ---------------------------------------------------------------- mixed precision
