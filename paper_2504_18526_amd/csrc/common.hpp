@@ -78,7 +78,7 @@ struct PCGArgs {
   const double* x0;  // in: initial guess (may equal x)
   double* fz;      // face values of the exchanged vector, 2 x [c][e][dim][side][f]
   double* ft;      // face traces of (D grad .),      2 x [c][e][dim][side][f]
-  double* part;    // barrier records: 2 (barrier parity) x cap records of 8 doubles
+  unsigned long long* part;  // barrier records: 2 (barrier parity) x cap records of 16 tagged words
   unsigned* bar;
   CGRes* res;      // result record of this solve
   double tol2;
@@ -87,7 +87,8 @@ struct PCGArgs {
   int maxit;
   int cap;
   long spin_limit; // polls before a barrier gives up (abort, no hang)
-  double epoch0;   // first barrier epoch of this launch (never reused)
+  unsigned tag0;   // tag of the launch's first barrier; the launch uses tag0, tag0 + 1, ...,
+                   // none of them in a record at launch time, and never 0
 };
 
 // Up to 8 vectors combined node-wise: out = sum_j c_j (m_j ? Jw : 1) x_j.

@@ -40,7 +40,7 @@ struct PT {
   static constexpr int N1 = P + 1;
   static constexpr int NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
   static constexpr int NF = DIM == 2 ? N1 : N1 * N1;
-  static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
+  static constexpr int EPB = NP >= 512 ? 1 : 512 / NP;
   static constexpr int NT = ((EPB * NP + 63) / 64) * 64;
   static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
 };
@@ -52,53 +52,99 @@ __device__ __forceinline__ double ld_dev(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double wsum(double x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+// A double moved across lanes by a DPP control (both 32-bit halves); lanes
+// whose source lies outside the pattern receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wave, in lane 63 (the other lanes hold partial
+// sums): shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row
+// broadcasts of lanes 15 and 31.  Register-to-register (DPP), no LDS; the
+// order of the additions is fixed, so every wave rounds alike.
+__device__ __forceinline__ double wsum63(double x) {
+  x += dpp_f64<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_f64<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_f64<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_f64<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
-// All-gather grid barrier with reduction (epoch = a number never used before
-// on these records).  Each workgroup stores its K block sums and then the
-// epoch in its own 64-byte record; then every workgroup waits for all records
-// to carry the epoch and sums them in workgroup order (thread t takes records
-// t, t + blockDim, ...; the same shuffle and LDS order everywhere), so all
+__device__ __forceinline__ void st_dev64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_dev64(const unsigned long long* p) {
+  return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All-gather grid barrier with reduction.  Each workgroup stores its K block
+// sums in its own record, every 64-bit word carrying 32 bits of a sum and
+// the barrier's tag (a number no record holds when the launch starts) in its
+// upper half, so a word is valid exactly when its tag matches: a reader
+// needs no separate flag and no second load, and the writer no wait between
+// the sums and a flag.  Every workgroup waits until all records carry the
+// tag and sums them in workgroup order (thread t takes records t,
+// t + blockDim, ...; the same shuffle and LDS order everywhere), so all
 // workgroups obtain the same bits.  No atomics: every word has one writer.
 // The stores a workgroup issued before the barrier (face data) complete
 // before its record is written, so after the barrier every workgroup sees
 // them.  Bounded spins: returns false (and sets the abort word) when a wait
 // exceeds spin_limit polls.
-template <int K>
-__device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], double* rec, unsigned* abort_w, double epoch,
-                            long spin_limit, int* s_ok) {
-  static_assert(K >= 1 && K <= 6, "a record holds up to 6 values");
+// `overlap` is work of the whole workgroup that needs no other workgroup's
+// data: it runs after the record is stored, while the other records arrive.
+template <int K, typename F>
+__device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned long long* rec, unsigned* abort_w,
+                            unsigned tag, long spin_limit, int* s_ok, F&& overlap) {
+  static_assert(K >= 1 && K <= 8, "a record holds up to 8 values");
   __shared__ double sred[K][16];
+  __shared__ double stot[K][16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   for (int k = 0; k < K; ++k) {
-    const double x = wsum(v[k]);
-    if (lane == 0) sred[k][wid] = x;
+    const double x = wsum63(v[k]);
+    if (lane == 63) sred[k][wid] = x;
   }
-  __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores have completed
+  if (threadIdx.x == 0) *s_ok = 1;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores (face data) have completed
   __syncthreads();
+  const unsigned long long hi = (unsigned long long)tag << 32;
   if (threadIdx.x == 0) {
-    double* my = rec + 8 * (long)blockIdx.x;
+    unsigned long long* my = rec + 16 * (long)blockIdx.x;
     for (int k = 0; k < K; ++k) {
       double sb = 0.0;
       for (int w = 0; w < nw; ++w) sb += sred[k][w];
-      st_dev(&my[k], sb);
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(sb);
+      st_dev64(&my[2 * k], hi | (bits & 0xffffffffull));
+      st_dev64(&my[2 * k + 1], hi | (bits >> 32));
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    st_dev(&my[7], epoch);
-    *s_ok = 1;
   }
-  __syncthreads();
+  overlap();
   double acc[K];
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   int ok = 1;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-    const double* rb = rec + 8 * (long)b;
+    const unsigned long long* rb = rec + 16 * (long)b;
+    unsigned long long wv[2 * K];
     long spins = 0;
-    while (ld_dev(&rb[7]) != epoch) {
-      if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > spin_limit) {
+    while (true) {
+      // poll one word; once it carries the tag, read the others (they were
+      // stored together, so they are normally there as well)
+      wv[2 * K - 1] = ld_dev64(&rb[2 * K - 1]);
+      if ((wv[2 * K - 1] >> 32) == (unsigned long long)tag) {
+        for (int j = 0; j < 2 * K - 1; ++j) wv[j] = ld_dev64(&rb[j]);
+        bool ready = true;
+        for (int j = 0; j < 2 * K - 1; ++j) ready = ready && (wv[j] >> 32) == (unsigned long long)tag;
+        if (ready) break;
+      }
+      // the abort word is read every 64th poll only: a load of it in every
+      // poll would double the time a poll takes
+      if ((++spins & 63) == 0 &&
+          (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > spin_limit)) {
         __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
@@ -106,17 +152,18 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], double* rec,
       __builtin_amdgcn_s_sleep(1);
     }
     if (!ok) break;
-    for (int k = 0; k < K; ++k) acc[k] += ld_dev(&rb[k]);
+    for (int k = 0; k < K; ++k)
+      acc[k] += __longlong_as_double((long long)((wv[2 * k + 1] << 32) | (wv[2 * k] & 0xffffffffull)));
   }
   if (!ok) *s_ok = 0;  // benign race: every writer stores 0
   for (int k = 0; k < K; ++k) {
-    const double x = wsum(acc[k]);
-    if (lane == 0) sred[k][wid] = x;
+    const double x = wsum63(acc[k]);
+    if (lane == 63) stot[k][wid] = x;
   }
   __syncthreads();
   for (int k = 0; k < K; ++k) {
     double sb = 0.0;
-    for (int w = 0; w < nw; ++w) sb += sred[k][w];
+    for (int w = 0; w < nw; ++w) sb += stot[k][w];
     tot[k] = sb;
   }
   const bool res = *s_ok != 0;
@@ -252,11 +299,16 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     }
   };
 
-  // out = M v + dt_m K_D v, v staged in LDS by publish(), neighbours' face data published
-  auto apply = [&](double (&out)[NV]) {
+  // out = M v + dt_m K_D v for v staged in LDS by publish(), in two parts:
+  // apply_local takes every term that needs no neighbour data (mass term,
+  // volume terms of both contractions) and runs while a barrier waits;
+  // apply_faces adds the interface terms once the barrier has passed and the
+  // neighbours' face data are published.
+  double qloc[NV][DIM];
+  auto apply_local = [&](double (&loc)[NV]) __attribute__((always_inline)) {
     for (int c = 0; c < NV; ++c) {
       const double* tile = &sx[(c * EPB + le) * NP];
-      double r = 0.0, xo = 0.0;
+      double xo = 0.0;
       if (act) {
         xo = tile[n];
         double gr[DIM];
@@ -270,11 +322,35 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
         }
         double vg = 0.0;
         for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
-        double qv[DIM], Qd[DIM];
         for (int d = 0; d < DIM; ++d) {
-          qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
-          Qd[d] = jw * qv[d];
+          qloc[c][d] = cw * cf.v[d] * vg + cf.nu * gr[d];
+          sQ[(le * DIM + d) * NP + n] = jw * qloc[c][d];
         }
+      }
+      __syncthreads();
+      double r = 0.0;
+      if (act) {
+        for (int d = 0; d < DIM; ++d) {
+          const int st = L::stride(d);
+          const double* row = &sQ[(le * DIM + d) * NP + n - ii[d] * st];
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < N1; ++k) s += sD[k * N1 + ii[d]] * row[k * st];
+          r += g.rh2[d] * s;
+        }
+      }
+      loc[c] = act ? jw * xo + a.dtm * r : 0.0;
+      __syncthreads();
+    }
+  };
+  auto apply_faces = [&](double (&out)[NV], const double (&loc)[NV]) __attribute__((always_inline)) {
+    for (int c = 0; c < NV; ++c) {
+      const double* tile = &sx[(c * EPB + le) * NP];
+      double r = 0.0;
+      if (act) {
+        const double xo = tile[n];
+        double Qd[DIM];
+        for (int d = 0; d < DIM; ++d) Qd[d] = 0.0;
         for (int d = 0; d < DIM; ++d)
           for (int side = 0; side < 2; ++side) {
             if (ii[d] != (side ? P : 0)) continue;
@@ -284,7 +360,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
             const double xnb = ld_dev(&a.fz[fofs + fb]);
             const double qnb = ld_dev(&a.ft[fofs + fb]);
             const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
-            const double qn = 0.5 * sgn * (qv[d] + qnb);
+            const double qn = 0.5 * sgn * (qloc[c][d] + qnb);
             const double tau = pen * fmax(dow, dnb[d][side]) * 0.5 * g.rh2[d];
             const double jump = xo - xnb;
             const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
@@ -305,7 +381,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
           r += g.rh2[d] * s;
         }
       }
-      out[c] = act ? jw * xo + a.dtm * r : 0.0;
+      out[c] = act ? loc[c] + a.dtm * r : 0.0;
       __syncthreads();
     }
   };
@@ -325,34 +401,43 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // barrier records, double-buffered by barrier parity: a workgroup rewrites
   // its record of barrier k only at barrier k + 2, after every workgroup has
   // passed barrier k + 1 and so has finished reading the records of k
-  auto rec = [&]() { return a.part + (long)(gen & 1u) * 8 * a.cap; };
+  auto rec = [&]() { return a.part + (long)(gen & 1u) * 16 * a.cap; };
   unsigned* abort_w = &a.bar[64];
-  double epoch = a.epoch0;
-  // barrier with K reduced values; advances the epoch and the face-buffer parity
-  auto barrier1 = [&](const double (&v)[1], double (&tt)[1]) -> bool {
-    const bool r = sync_reduce<1>(v, tt, rec(), abort_w, epoch, a.spin_limit, &s_ok);
-    epoch += 1.0;
+  // barrier with one reduced value, the local part of the matvec of the
+  // published vector into `loc` while it waits; advances the tag and the
+  // face-buffer parity
+  auto barrier1 = [&](const double (&v)[1], double (&tt)[1], double (&loc)[NV]) -> bool {
+    const bool r = sync_reduce<1>(v, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+                                  [&]() __attribute__((always_inline)) { apply_local(loc); });
     gen += 1u;
     return r;
   };
-  // r = b - A x, u = diag^-1 r, w = A u (also used to replace the residual)
-  auto true_residual = [&]() -> bool {
+  // r = b - A x and u = diag^-1 r (also used to replace the recurred
+  // residual); the second barrier carries the face data of u together with
+  // (r, r), so w = A u can follow (apply) without another barrier
+  double wloc[NV];
+  auto true_residual = [&](double& rr_true) -> bool {
     const double z1[1] = {0.0};
     double t1[1];
     publish(x);
-    if (!barrier1(z1, t1)) return false;
-    apply(w);
+    if (!barrier1(z1, t1, wloc)) return false;
+    apply_faces(w, wloc);
+    double t_l = 0.0;
     for (int c = 0; c < NV; ++c) {
       const double bi = act ? a.b[c * vs + own] : 0.0;
       r[c] = act ? bi - w[c] : 0.0;
       u[c] = r[c] * idg;
+      t_l += r[c] * r[c];
     }
     publish(u);
-    if (!barrier1(z1, t1)) return false;
-    apply(w);
+    const double v1[1] = {t_l};
+    if (!barrier1(v1, t1, wloc)) return false;
+    rr_true = t1[0];
     return true;
   };
-  bool ok = true_residual();
+  double rr0 = 0.0;
+  bool ok = true_residual(rr0);
+  if (ok) apply_faces(w, wloc);
   double bb = -1.0, thresh = 0.0, gprev = 0.0, aprev = 0.0, rr = 0.0;
   int it = 0, replaced = 0;
   bool converged = false;
@@ -369,8 +454,9 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     publish(m);
     const double v4[4] = {g_l, d_l, r_l, bb < 0.0 ? bb_l : 0.0};
     double tt[4];
-    ok = sync_reduce<4>(v4, tt, rec(), abort_w, epoch, a.spin_limit, &s_ok);
-    epoch += 1.0;
+    double nloc[NV];
+    ok = sync_reduce<4>(v4, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+                        [&]() __attribute__((always_inline)) { apply_local(nloc); });
     gen += 1u;
     if (!ok) break;
     if (bb < 0.0) {
@@ -382,25 +468,19 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     if (!(rr == rr)) break;
     if (rr <= thresh) {
       // confirm with the true residual; replace the recurred one if it misses
-      ok = true_residual();
+      ok = true_residual(rr);
       if (!ok) break;
-      double t_l = 0.0;
-      for (int c = 0; c < NV; ++c) t_l += r[c] * r[c];
-      const double v1[1] = {t_l};
-      double tr[1];
-      ok = barrier1(v1, tr);
-      if (!ok) break;
-      rr = tr[0];
       if (rr <= thresh) { converged = true; break; }
       // restart the recurrences from the true residual (at most 3 times)
       if (++replaced > 3 || it >= a.maxit) break;
+      apply_faces(w, wloc);
       for (int c = 0; c < NV; ++c) zv[c] = q[c] = s[c] = p[c] = 0.0;
       gprev = 0.0;
       aprev = 0.0;
       continue;
     }
     if (it >= a.maxit) break;
-    apply(nn);  // n = A m (neighbour face data published before the barrier)
+    apply_faces(nn, nloc);  // n = A m: the face terms (neighbour data published before the barrier)
     double beta = 0.0, alpha;
     if (gprev == 0.0) {
       alpha = gi / di;

@@ -147,8 +147,8 @@ struct sisdc_handle {
   int* hdone = nullptr;        // ... and of done_gen
   int solve_id = 0;
   // persistent PCG
-  double* ppart = nullptr;     // barrier records of the persistent PCG (2 x 8 x pcap)
-  double epoch = 0.0;          // last barrier epoch handed out
+  unsigned long long* ppart = nullptr;  // barrier records of the persistent PCG (2 x 16 x pcap words)
+  unsigned tag = 0;                     // last barrier tag handed out
   int pcap = 0;
   unsigned* bar = nullptr;     // grid barrier words
   CGRes* ring = nullptr;       // result records of solves not yet collected
@@ -458,8 +458,16 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   a.maxit = maxit;
   a.cap = h->pcap;
   a.spin_limit = kSpinLimit;
-  a.epoch0 = h->epoch + 1.0;
-  h->epoch += (double)(4 * maxit + 64);  // more epochs than a launch can use
+  // more tags than a launch can use (2 + maxit + 2 per residual check, at most 4 checks); when the
+  // 32-bit tags run out the records are cleared (tag 0) and the count starts again
+  const unsigned long long need = 2ull * (unsigned long long)maxit + 64ull;
+  if (need > 0x40000000ull) return false;  // such an iteration cap takes the multi-kernel form
+  if ((unsigned long long)h->tag + need >= 0xffffffffull) {
+    HIPCHECK(hipMemsetAsync(h->ppart, 0, (size_t)2 * 16 * h->pcap * sizeof(unsigned long long), h->stream));
+    h->tag = 0;
+  }
+  a.tag0 = h->tag + 1u;
+  h->tag += (unsigned)need;
   int dev = 0, ncu = 0;
   HIPCHECK(hipGetDevice(&dev));
   HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1299,8 +1307,11 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->hnrej = (int*)((char*)hp + 248);
     h->lam_dev = dalloc(2);
     h->pcap = 1024;
-    h->ppart = dalloc((size_t)2 * 8 * h->pcap);
-    HIPCHECK(hipMemset(h->ppart, 0, (size_t)2 * 8 * h->pcap * sizeof(double)));
+    void* pp = nullptr;
+    if (hipMalloc(&pp, (size_t)2 * 16 * h->pcap * sizeof(unsigned long long)) != hipSuccess)
+      fail(SISDC_ENOMEM, "hipMalloc failed");
+    h->ppart = (unsigned long long*)pp;
+    HIPCHECK(hipMemset(h->ppart, 0, (size_t)2 * 16 * h->pcap * sizeof(unsigned long long)));
     void* pb = nullptr;
     if (hipMalloc(&pb, 512) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
     h->bar = (unsigned*)pb;
