@@ -76,8 +76,8 @@ struct PCGArgs {
   const double* b;
   double* x;       // out: solution
   const double* x0;  // in: initial guess (may equal x)
-  double* fz;      // face values of the exchanged vector, 2 x [c][e][dim][side][f]
-  double* ft;      // face traces of (D grad .),      2 x [c][e][dim][side][f]
+  unsigned long long* fz;  // face values of the exchanged vector, 2 x [c][e][dim][side][f] x 2 tagged words
+  unsigned long long* ft;  // face traces of (D grad .),      2 x [c][e][dim][side][f] x 2 tagged words
   unsigned long long* part;  // barrier records: 2 (barrier parity) x cap records of 16 tagged words
   unsigned* bar;
   CGRes* res;      // result record of this solve

@@ -45,12 +45,6 @@ struct PT {
   static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
 };
 
-__device__ __forceinline__ void st_dev(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // A double moved across lanes by a DPP control (both 32-bit halves); lanes
 // whose source lies outside the pattern receive 0.
@@ -81,6 +75,16 @@ __device__ __forceinline__ void st_dev64(unsigned long long* p, unsigned long lo
 }
 __device__ __forceinline__ unsigned long long ld_dev64(const unsigned long long* p) {
   return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A double published as two words, 32 bits of it and the tag in each.
+__device__ __forceinline__ void st_tagged(unsigned long long* p, double v, unsigned long long tag_hi) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  st_dev64(p, tag_hi | (b & 0xffffffffull));
+  st_dev64(p + 1, tag_hi | (b >> 32));
+}
+__device__ __forceinline__ double untag(unsigned long long lo, unsigned long long hi) {
+  return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
 }
 
 // All-gather grid barrier with reduction.  Each workgroup stores its K block
@@ -263,11 +267,17 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
 
   // Face data are double-buffered by barrier parity: a workgroup may publish
   // the next vector while a slower neighbour still reads the previous one.
-  const long fsize = (long)NV * g.E * DIM * 2 * NF;
-  long fofs = 0;  // buffer of the last publish
+  // Every face value is stored as two words tagged with the barrier that
+  // follows the publish, so a reader can load it before that barrier has
+  // passed (while the barrier waits) and keep it if both tags match.
+  const long fsize = 2L * NV * g.E * DIM * 2 * NF;  // words per buffer
+  long fofs = 0;                                   // buffer of the last publish
+  unsigned ftag = 0;                               // its tag
   // publish: stage v in LDS, store its face values and face traces
   auto publish = [&](const double (&v)[NV]) {
     fofs = (long)(gen & 1u) * fsize;
+    ftag = a.tag0 + gen;
+    const unsigned long long tag_hi = (unsigned long long)ftag << 32;
     for (int c = 0; c < NV; ++c)
       if (act) sx[(c * EPB + le) * NP + n] = v[c];
     __syncthreads();
@@ -292,11 +302,65 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
         const bool lo = ii[d] == 0, hi = ii[d] == P;
         if (!lo && !hi) continue;
         const double qd = cw * cf.v[d] * vg + cf.nu * gr[d];
-        const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + fidx<DIM, N1>(d, ii);
-        if (lo) { st_dev(&a.ft[fofs + base], qd); st_dev(&a.fz[fofs + base], v[c]); }
-        if (hi) { st_dev(&a.ft[fofs + base + NF], qd); st_dev(&a.fz[fofs + base + NF], v[c]); }
+        const long base = 2 * ((((long)c * g.E + e) * DIM + d) * 2 * NF + fidx<DIM, N1>(d, ii) + (hi ? NF : 0));
+        st_tagged(&a.ft[fofs + base], qd, tag_hi);
+        st_tagged(&a.fz[fofs + base], v[c], tag_hi);
       }
     }
+  };
+
+  // the neighbours' face words this node needs (face value and trace, two
+  // words each, per face of the node), loaded ahead by prefetch_faces()
+  unsigned long long pf[NV][DIM][4];
+  auto face_word = [&](int c, int d) -> long {
+    const int side = ii[d] == P ? 1 : 0;
+    const int nb = nbr(g, e, d, side ? 1 : -1);
+    return fofs + 2 * ((((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + fidx<DIM, N1>(d, ii));
+  };
+  // (2-D only: in 3-D the words held across the barrier would not fit the
+  // register budget; there face_vals loads them after the barrier)
+  auto prefetch_faces = [&]() __attribute__((always_inline)) {
+    if constexpr (DIM == 3) return;
+    if (!act) return;
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (ii[d] != 0 && ii[d] != P) continue;
+        const long w = face_word(c, d);
+        pf[c][d][0] = ld_dev64(&a.fz[w]);
+        pf[c][d][1] = ld_dev64(&a.fz[w + 1]);
+        pf[c][d][2] = ld_dev64(&a.ft[w]);
+        pf[c][d][3] = ld_dev64(&a.ft[w + 1]);
+      }
+  };
+  unsigned* abort_w = &a.bar[64];
+  // after the barrier: the face value and trace of the neighbour across face
+  // d, from the prefetched words, reloaded if they were not yet published
+  // when prefetched (the barrier guarantees they are now)
+  auto face_vals = [&](int c, int d, double& xnb, double& qnb) __attribute__((always_inline)) {
+    unsigned long long w0 = 0ull, w1 = 0ull, w2 = 0ull, w3 = 0ull;  // tag 0 is never published
+    if constexpr (DIM == 2) {
+      w0 = pf[c][d][0];
+      w1 = pf[c][d][1];
+      w2 = pf[c][d][2];
+      w3 = pf[c][d][3];
+    }
+    const unsigned long long want = (unsigned long long)ftag;
+    long spins = 0;
+    while ((w0 >> 32) != want || (w1 >> 32) != want || (w2 >> 32) != want || (w3 >> 32) != want) {
+      if (++spins > a.spin_limit) {
+        __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      const long w = face_word(c, d);
+      w0 = ld_dev64(&a.fz[w]);
+      w1 = ld_dev64(&a.fz[w + 1]);
+      w2 = ld_dev64(&a.ft[w]);
+      w3 = ld_dev64(&a.ft[w + 1]);
+    }
+    xnb = untag(w0, w1);
+    qnb = untag(w2, w3);
   };
 
   // out = M v + dt_m K_D v for v staged in LDS by publish(), in two parts:
@@ -355,10 +419,8 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
           for (int side = 0; side < 2; ++side) {
             if (ii[d] != (side ? P : 0)) continue;
             const double sgn = side ? 1.0 : -1.0;
-            const int nb = nbr(g, e, d, side ? 1 : -1);
-            const long fb = (((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + fidx<DIM, N1>(d, ii);
-            const double xnb = ld_dev(&a.fz[fofs + fb]);
-            const double qnb = ld_dev(&a.ft[fofs + fb]);
+            double xnb, qnb;
+            face_vals(c, d, xnb, qnb);
             const double dow = cw * cf.v[d] * cf.v[d] + cf.nu;
             const double qn = 0.5 * sgn * (qloc[c][d] + qnb);
             const double tau = pen * fmax(dow, dnb[d][side]) * 0.5 * g.rh2[d];
@@ -402,13 +464,15 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // its record of barrier k only at barrier k + 2, after every workgroup has
   // passed barrier k + 1 and so has finished reading the records of k
   auto rec = [&]() { return a.part + (long)(gen & 1u) * 16 * a.cap; };
-  unsigned* abort_w = &a.bar[64];
   // barrier with one reduced value, the local part of the matvec of the
   // published vector into `loc` while it waits; advances the tag and the
   // face-buffer parity
   auto barrier1 = [&](const double (&v)[1], double (&tt)[1], double (&loc)[NV]) -> bool {
     const bool r = sync_reduce<1>(v, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
-                                  [&]() __attribute__((always_inline)) { apply_local(loc); });
+                                  [&]() __attribute__((always_inline)) {
+                                    apply_local(loc);
+                                    prefetch_faces();
+                                  });
     gen += 1u;
     return r;
   };
@@ -456,7 +520,10 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     double tt[4];
     double nloc[NV];
     ok = sync_reduce<4>(v4, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
-                        [&]() __attribute__((always_inline)) { apply_local(nloc); });
+                        [&]() __attribute__((always_inline)) {
+                          apply_local(nloc);
+                          prefetch_faces();
+                        });
     gen += 1u;
     if (!ok) break;
     if (bb < 0.0) {

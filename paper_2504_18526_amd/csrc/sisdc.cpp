@@ -80,8 +80,8 @@ struct Level {
   double* idg = nullptr;        // NP-periodic inverse Jacobi diagonal (isotropic path)
   double *diag = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cs = nullptr, *cw = nullptr;
   double* trace = nullptr;
-  double* fz = nullptr;        // face values exchanged by the persistent PCG (2 buffers)
-  double* ft = nullptr;        // face traces exchanged by the persistent PCG (2 buffers)
+  unsigned long long* fz = nullptr;  // tagged face values of the persistent PCG (2 buffers, 2 words each)
+  unsigned long long* ft = nullptr;  // tagged face traces of the persistent PCG (2 buffers, 2 words each)
   bool persistent = false;     // solves run as one persistent launch
   // FP32 copies and work vectors of the mixed-precision inner solves
   float* tab32 = nullptr;
@@ -1080,7 +1080,20 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
   L.idg = dalloc(L.np);
-  L.fz = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
+  if (L.nv == 1) {  // the persistent PCG serves scalar equations only
+    const size_t words = (size_t)2 * 2 * L.nv * L.E * 2 * pr.dim * g.nf;
+    void* pz = nullptr;
+    void* pt = nullptr;
+    if (hipMalloc(&pz, words * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&pt, words * sizeof(unsigned long long)) != hipSuccess) {
+      if (pz) (void)hipFree(pz);
+      fail(SISDC_ENOMEM, "hipMalloc failed");
+    }
+    L.fz = (unsigned long long*)pz;
+    L.ft = (unsigned long long*)pt;
+    HIPCHECK(hipMemset(L.fz, 0, words * sizeof(unsigned long long)));
+    HIPCHECK(hipMemset(L.ft, 0, words * sizeof(unsigned long long)));
+  }
   L.r32 = falloc(n);  // FP32 staging of residuals (mixed solves, learned guess)
   if (h->meth.precision == SISDC_MIXED) {
     std::vector<float> t32(tab.begin(), tab.end());
@@ -1097,16 +1110,17 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
     L.trace32 = falloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
     L.idg32 = falloc(L.np);
   }
-  L.ft = dalloc((size_t)2 * L.nv * L.E * 2 * pr.dim * g.nf);
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
   HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
 }
 
 void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
-                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.fz, L.ft, L.idg};
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.idg};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
+  if (L.fz) (void)hipFree(L.fz);
+  if (L.ft) (void)hipFree(L.ft);
   float* fptrs[] = {L.idg32, L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32,
                     L.net.theta, L.net.m, L.net.v, L.net.g, L.net.Xd, L.net.Td, L.net.Z1, L.net.A1, L.net.Z2,
                     L.net.A2, L.net.Y, L.net.dY, L.net.dA, L.net.dZ, L.net.Xi, L.net.A1i, L.net.A2i, L.net.Yi,
