@@ -96,10 +96,10 @@ __device__ __forceinline__ double untag(unsigned long long lo, unsigned long lon
 // tag and sums them in workgroup order (thread t takes records t,
 // t + blockDim, ...; the same shuffle and LDS order everywhere), so all
 // workgroups obtain the same bits.  No atomics: every word has one writer.
-// The stores a workgroup issued before the barrier (face data) complete
-// before its record is written, so after the barrier every workgroup sees
-// them.  Bounded spins: returns false (and sets the abort word) when a wait
-// exceeds spin_limit polls.
+// The face data carry tags of their own, so the record is not ordered after
+// them: a reader waits for a face word's tag where it uses it.  Bounded
+// spins: returns false (and sets the abort word) when a wait exceeds
+// spin_limit polls.
 // `overlap` is work of the whole workgroup that needs no other workgroup's
 // data: it runs after the record is stored, while the other records arrive.
 template <int K, typename F>
@@ -114,7 +114,6 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
     if (lane == 63) sred[k][wid] = x;
   }
   if (threadIdx.x == 0) *s_ok = 1;
-  __builtin_amdgcn_s_waitcnt(0);  // this wave's device-scope stores (face data) have completed
   __syncthreads();
   const unsigned long long hi = (unsigned long long)tag << 32;
   if (threadIdx.x == 0) {
@@ -336,8 +335,8 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   };
   unsigned* abort_w = &a.bar[64];
   // after the barrier: the face value and trace of the neighbour across face
-  // d, from the prefetched words, reloaded if they were not yet published
-  // when prefetched (the barrier guarantees they are now)
+  // d, from the prefetched words, reloaded until they carry the tag of this
+  // exchange (the neighbour has passed its publish, so they are on their way)
   auto face_vals = [&](int c, int d, double& xnb, double& qnb) __attribute__((always_inline)) {
     unsigned long long w0 = 0ull, w1 = 0ull, w2 = 0ull, w3 = 0ull;  // tag 0 is never published
     if constexpr (DIM == 2) {
