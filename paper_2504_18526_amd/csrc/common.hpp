@@ -99,4 +99,34 @@ struct LinComb {
   int n;
 };
 
+// A value moved across lanes by a DPP control (32-bit pieces); lanes whose
+// source lies outside the pattern receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave, in lane 63 (the other lanes hold partial
+// sums): shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row
+// broadcasts of lanes 15 and 31.  Register-to-register (DPP), no LDS; the
+// order of the additions is fixed, so every wave rounds alike.  Every lane
+// of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T wave_sum63(T x) {
+  x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 }  // namespace sisdc

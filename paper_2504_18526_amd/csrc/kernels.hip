@@ -61,11 +61,6 @@ __device__ __forceinline__ int neighbour(const Geo& g, int e, int d, int s) {
 }
 
 // ---------------------------------------------------------------- reductions
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-  return x;
-}
 
 // Block-wide sums of K per-thread values; thread 0 stores them in
 // part[k][blockIdx.x].  Every thread of the block must call it.
@@ -76,8 +71,8 @@ __device__ void block_partials(const T (&v)[K], T* const (&part)[K]) {
   const int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   for (int k = 0; k < K; ++k) {
-    const T x = wave_sum(v[k]);
-    if (lane == 0) sred[k][wid] = x;
+    const T x = wave_sum63(v[k]);
+    if (lane == 63) sred[k][wid] = x;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -101,8 +96,8 @@ __device__ void sum_partials(const T* const (&part)[K], int n, T (&tot)[K]) {
   for (int k = 0; k < K; ++k) {
     T a = T(0);
     for (int b = threadIdx.x; b < n; b += blockDim.x) a += part[k][b];
-    a = wave_sum(a);
-    if (lane == 0) sred[k][wid] = a;
+    a = wave_sum63(a);
+    if (lane == 63) sred[k][wid] = a;
   }
   __syncthreads();
   for (int k = 0; k < K; ++k) {

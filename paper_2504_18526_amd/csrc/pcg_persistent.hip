@@ -46,29 +46,6 @@ struct PT {
 };
 
 
-// A double moved across lanes by a DPP control (both 32-bit halves); lanes
-// whose source lies outside the pattern receive 0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum over the 64 lanes of a wave, in lane 63 (the other lanes hold partial
-// sums): shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row
-// broadcasts of lanes 15 and 31.  Register-to-register (DPP), no LDS; the
-// order of the additions is fixed, so every wave rounds alike.
-__device__ __forceinline__ double wsum63(double x) {
-  x += dpp_f64<0x111, 0xf>(x);  // row_shr:1
-  x += dpp_f64<0x112, 0xf>(x);  // row_shr:2
-  x += dpp_f64<0x114, 0xf>(x);  // row_shr:4
-  x += dpp_f64<0x118, 0xf>(x);  // row_shr:8
-  x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-  return x;
-}
 
 __device__ __forceinline__ void st_dev64(unsigned long long* p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,7 +87,7 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
   __shared__ double stot[K][16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   for (int k = 0; k < K; ++k) {
-    const double x = wsum63(v[k]);
+    const double x = wave_sum63(v[k]);
     if (lane == 63) sred[k][wid] = x;
   }
   if (threadIdx.x == 0) *s_ok = 1;
@@ -160,7 +137,7 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
   }
   if (!ok) *s_ok = 0;  // benign race: every writer stores 0
   for (int k = 0; k < K; ++k) {
-    const double x = wsum63(acc[k]);
+    const double x = wave_sum63(acc[k]);
     if (lane == 63) stot[k][wid] = x;
   }
   __syncthreads();
