@@ -456,11 +456,16 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // residual); the second barrier carries the face data of u together with
   // (r, r), so w = A u can follow (apply) without another barrier
   double wloc[NV];
+  double bb = -1.0, thresh = 0.0;  // (b, b) and rtol^2 (b, b), from the first barrier
   auto true_residual = [&](double& rr_true) -> bool {
-    const double z1[1] = {0.0};
+    const double z1[1] = {bb < 0.0 ? bb_l : 0.0};
     double t1[1];
     publish(x);
     if (!barrier1(z1, t1, wloc)) return false;
+    if (bb < 0.0) {
+      bb = t1[0];
+      thresh = a.tol2 * bb;
+    }
     apply_faces(w, wloc);
     double t_l = 0.0;
     for (int c = 0; c < NV; ++c) {
@@ -478,12 +483,12 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   double rr0 = 0.0;
   bool ok = true_residual(rr0);
   if (ok) apply_faces(w, wloc);
-  double bb = -1.0, thresh = 0.0, gprev = 0.0, aprev = 0.0, rr = 0.0;
+  double gprev = 0.0, aprev = 0.0, rr = 0.0;
   int it = 0, replaced = 0;
   bool converged = false;
   while (ok) {
-    // local (r,u), (w,u), (r,r), (b,b); m = diag^-1 w; one barrier carries
-    // the face data of m and the four sums
+    // local (r,u), (w,u), (r,r); m = diag^-1 w; one barrier carries the face
+    // data of m and the three sums
     double g_l = 0.0, d_l = 0.0, r_l = 0.0;
     for (int c = 0; c < NV; ++c) {
       g_l += r[c] * u[c];
@@ -492,20 +497,16 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
       m[c] = w[c] * idg;
     }
     publish(m);
-    const double v4[4] = {g_l, d_l, r_l, bb < 0.0 ? bb_l : 0.0};
-    double tt[4];
+    const double v3[3] = {g_l, d_l, r_l};
+    double tt[3];
     double nloc[NV];
-    ok = sync_reduce<4>(v4, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+    ok = sync_reduce<3>(v3, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
                         [&]() __attribute__((always_inline)) {
                           apply_local(nloc);
                           prefetch_faces();
                         });
     gen += 1u;
     if (!ok) break;
-    if (bb < 0.0) {
-      bb = tt[3];
-      thresh = a.tol2 * bb;
-    }
     const double gi = tt[0], di = tt[1];
     rr = tt[2];
     if (!(rr == rr)) break;
