@@ -65,7 +65,9 @@ __device__ __forceinline__ double untag(unsigned long long lo, unsigned long lon
 }
 
 // All-gather grid barrier with reduction.  Each workgroup stores its K block
-// sums in its own record, every 64-bit word carrying 32 bits of a sum and
+// sums in its own record (word j of workgroup b at rec[j * cap + b], so the
+// readers' loads of one word of consecutive records coalesce), every 64-bit
+// word carrying 32 bits of a sum and
 // the barrier's tag (a number no record holds when the launch starts) in its
 // upper half, so a word is valid exactly when its tag matches: a reader
 // needs no separate flag and no second load, and the writer no wait between
@@ -80,8 +82,8 @@ __device__ __forceinline__ double untag(unsigned long long lo, unsigned long lon
 // `overlap` is work of the whole workgroup that needs no other workgroup's
 // data: it runs after the record is stored, while the other records arrive.
 template <int K, typename F>
-__device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned long long* rec, unsigned* abort_w,
-                            unsigned tag, long spin_limit, int* s_ok, F&& overlap) {
+__device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned long long* rec, long cap,
+                            unsigned* abort_w, unsigned tag, long spin_limit, int* s_ok, F&& overlap) {
   static_assert(K >= 1 && K <= 8, "a record holds up to 8 values");
   __shared__ double sred[K][16];
   __shared__ double stot[K][16];
@@ -94,13 +96,13 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
   __syncthreads();
   const unsigned long long hi = (unsigned long long)tag << 32;
   if (threadIdx.x == 0) {
-    unsigned long long* my = rec + 16 * (long)blockIdx.x;
+    unsigned long long* my = rec + blockIdx.x;
     for (int k = 0; k < K; ++k) {
       double sb = 0.0;
       for (int w = 0; w < nw; ++w) sb += sred[k][w];
       const unsigned long long bits = (unsigned long long)__double_as_longlong(sb);
-      st_dev64(&my[2 * k], hi | (bits & 0xffffffffull));
-      st_dev64(&my[2 * k + 1], hi | (bits >> 32));
+      st_dev64(&my[(2 * k) * cap], hi | (bits & 0xffffffffull));
+      st_dev64(&my[(2 * k + 1) * cap], hi | (bits >> 32));
     }
   }
   overlap();
@@ -108,15 +110,15 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   int ok = 1;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-    const unsigned long long* rb = rec + 16 * (long)b;
+    const unsigned long long* rb = rec + b;
     unsigned long long wv[2 * K];
     long spins = 0;
     while (true) {
       // poll one word; once it carries the tag, read the others (they were
       // stored together, so they are normally there as well)
-      wv[2 * K - 1] = ld_dev64(&rb[2 * K - 1]);
+      wv[2 * K - 1] = ld_dev64(&rb[(2 * K - 1) * cap]);
       if ((wv[2 * K - 1] >> 32) == (unsigned long long)tag) {
-        for (int j = 0; j < 2 * K - 1; ++j) wv[j] = ld_dev64(&rb[j]);
+        for (int j = 0; j < 2 * K - 1; ++j) wv[j] = ld_dev64(&rb[j * cap]);
         bool ready = true;
         for (int j = 0; j < 2 * K - 1; ++j) ready = ready && (wv[j] >> 32) == (unsigned long long)tag;
         if (ready) break;
@@ -444,7 +446,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // published vector into `loc` while it waits; advances the tag and the
   // face-buffer parity
   auto barrier1 = [&](const double (&v)[1], double (&tt)[1], double (&loc)[NV]) -> bool {
-    const bool r = sync_reduce<1>(v, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+    const bool r = sync_reduce<1>(v, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
                                   [&]() __attribute__((always_inline)) {
                                     apply_local(loc);
                                     prefetch_faces();
@@ -500,7 +502,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     const double v3[3] = {g_l, d_l, r_l};
     double tt[3];
     double nloc[NV];
-    ok = sync_reduce<3>(v3, tt, rec(), abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+    ok = sync_reduce<3>(v3, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
                         [&]() __attribute__((always_inline)) {
                           apply_local(nloc);
                           prefetch_faces();
