@@ -72,8 +72,18 @@ using CGState = CGStateT<double>;
 // Arguments of the persistent (one launch per solve) PCG kernel.  Face data
 // exchanged between workgroups and the barrier records go through
 // device-scope (L2 write-through) stores and loads; bar[64] is the abort word.
+// Up to 8 vectors combined node-wise: out = sum_j c_j (m_j ? Jw : 1) x_j.
+struct LinComb {
+  const double* x[8];
+  double c[8];
+  int m[8];
+  int n;
+};
+
 struct PCGArgs {
-  const double* b;
+  const double* b;  // right-hand side, or null: then b = bl at every node
+  LinComb bl;       // the right-hand side as a combination of vectors (used when b is null)
+  const double* mw; // mass weights J w of one element's nodes (for bl's mass terms)
   double* x;       // out: solution
   const double* x0;  // in: initial guess (may equal x)
   unsigned long long* fz;  // face values of the exchanged vector, 2 x [c][e][dim][side][f] x 2 tagged words
@@ -89,14 +99,6 @@ struct PCGArgs {
   long spin_limit; // polls before a barrier gives up (abort, no hang)
   unsigned tag0;   // tag of the launch's first barrier; the launch uses tag0, tag0 + 1, ...,
                    // none of them in a record at launch time, and never 0
-};
-
-// Up to 8 vectors combined node-wise: out = sum_j c_j (m_j ? Jw : 1) x_j.
-struct LinComb {
-  const double* x[8];
-  double c[8];
-  int m[8];
-  int n;
 };
 
 // A value moved across lanes by a DPP control (32-bit pieces); lanes whose

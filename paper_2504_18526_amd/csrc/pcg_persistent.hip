@@ -433,9 +433,22 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     zv[c] = q[c] = s[c] = p[c] = 0.0;
   }
   const double idg = act ? 1.0 / dg : 0.0;
+  // the right-hand side, given or formed here from its terms (the same
+  // arithmetic as k_lincomb, so both give the same bits)
+  double bv[NV];
   double bb_l = 0.0;
   for (int c = 0; c < NV; ++c) {
-    const double bi = act ? a.b[c * vs + own] : 0.0;
+    double bi = 0.0;
+    if (act) {
+      const long i = c * vs + own;
+      if (a.b) {
+        bi = a.b[i];
+      } else {
+        const double mwn = a.mw[n];
+        for (int j = 0; j < a.bl.n; ++j) bi += a.bl.c[j] * (a.bl.m[j] ? mwn : 1.0) * a.bl.x[j][i];
+      }
+    }
+    bv[c] = bi;
     bb_l += bi * bi;
   }
   // barrier records, double-buffered by barrier parity: a workgroup rewrites
@@ -471,8 +484,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     apply_faces(w, wloc);
     double t_l = 0.0;
     for (int c = 0; c < NV; ++c) {
-      const double bi = act ? a.b[c * vs + own] : 0.0;
-      r[c] = act ? bi - w[c] : 0.0;
+      r[c] = act ? bv[c] - w[c] : 0.0;
       u[c] = r[c] * idg;
       t_l += r[c] * r[c];
     }

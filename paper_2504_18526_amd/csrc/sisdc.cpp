@@ -192,6 +192,21 @@ void lincomb(sisdc_handle* h, const Level& L, double* out, std::initializer_list
   HIPCHECK(launch_lincomb(out, lc, L.vlen, L.mw, L.np, h->stream));
 }
 
+LinComb make_lc(std::initializer_list<std::pair<double, const double*>> terms, std::initializer_list<int> mflags) {
+  LinComb lc{};
+  int k = 0;
+  auto mit = mflags.begin();
+  for (auto& t : terms) {
+    if (k >= 8) fail(SISDC_EINVAL, "lincomb: too many terms");
+    lc.x[k] = t.second;
+    lc.c[k] = t.first;
+    lc.m[k] = (mit != mflags.end()) ? *mit++ : 0;
+    ++k;
+  }
+  lc.n = k;
+  return lc;
+}
+
 void lincomb_v(sisdc_handle* h, const Level& L, double* out, const std::vector<double>& c,
                const std::vector<const double*>& x, const std::vector<int>& m) {
   // chunks of 8 terms: out = sum; later chunks accumulate onto out
@@ -440,11 +455,17 @@ void porder_unregister(int dev, hipStream_t s) {
   if (po.pending && po.last == s) po.pending = false;
 }
 
+// b null: the kernel forms the right-hand side from `bl`.
 bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
-                      double rtol, int maxit, const double* x0 = nullptr) {
+                      double rtol, int maxit, const double* x0 = nullptr, const LinComb* bl = nullptr) {
+  if (!b && !bl) fail(SISDC_EINVAL, "internal: no right-hand side");
   if (h->ring_n >= kRing) drain(h);
   PCGArgs a{};
   a.b = b;
+  if (!b) {
+    a.bl = *bl;
+    a.mw = L.mw;
+  }
   a.x = x;
   a.x0 = x0 ? x0 : x;
   a.fz = L.fz;
@@ -722,6 +743,24 @@ sisdc_solve_stats solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, 
   return cg_solve(h, L, cf, dtm, b, x, rtol, h->meth.cg_maxit);
 }
 
+// Solve with the right-hand side given as a combination of vectors: the
+// persistent PCG forms it at every node itself (no separate assembly
+// kernel); the other forms get it assembled into L.b first.
+sisdc_solve_stats solve_lc(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const LinComb& lc, double* x,
+                           const double* x0) {
+  const double rtol = h->meth.cg_rtol;
+  const bool plain = !(L.net.on && (L.net.use || L.net.harvest)) && h->meth.precision != SISDC_MIXED;
+  if (plain && L.persistent && rtol >= kPersistentMinRtol &&
+      persistent_solve(h, L, cf, dtm, nullptr, x, rtol, h->meth.cg_maxit, x0, &lc)) {
+    sisdc_solve_stats r{};
+    r.iters = -1;  // collected later by drain()
+    r.converged = 1;
+    return r;
+  }
+  HIPCHECK(launch_lincomb(L.b, lc, L.vlen, L.mw, L.np, h->stream));
+  return solve(h, L, cf, dtm, L.b, x, x0);
+}
+
 // ------------------------------------------------------------------ sweeps
 // Stored terms of the current iterate: C(u_m), m = 0..M; f(u_m) and
 // X_m = K_{D_m(u_{m-1})} u_m, m = 1..M (implementation note of Sec. 3:
@@ -758,13 +797,11 @@ void predictor(sisdc_handle* h, Level& L, double dt) {
     const double* ua = L.um(m - 1);
     CoefP cf = coef_for(h, L, dtm, ua);
     conv(h, L, ua, L.t1);
-    lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
     double* y = si1 ? L.um(m) : L.y;
-    solve(h, L, cf, dtm, L.b, y, ua);
+    solve_lc(h, L, cf, dtm, make_lc({{1.0, ua}, {dtm, L.t1}}, {1, 0}), y, ua);
     if (!si1) {
       conv(h, L, y, L.t1);
-      lincomb(h, L, L.b, {{1.0, ua}, {dtm, L.t1}}, {1, 0});
-      solve(h, L, cf, dtm, L.b, L.um(m), y);
+      solve_lc(h, L, cf, dtm, make_lc({{1.0, ua}, {dtm, L.t1}}, {1, 0}), L.um(m), y);
     }
   }
   L.stale = true;
@@ -789,20 +826,18 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
     const double* gm = g ? g + (long)(m - 1) * n : nullptr;
     CoefP cf = coef_for(h, L, dtm, ua);
     // stage 1: M y = M u^k_{m-1} + q_m + g_m + H(u^k_{m-1},u^k_{m-1},y) - H(u^{k-1}_{m-1},u^{k-1}_{m-1},u^{k-1}_m)
-    if (gm)
-      lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0});
-    else
-      lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0});
+    const LinComb b1 =
+        gm ? make_lc({{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0})
+           : make_lc({{1.0, ua}, {1.0, qm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0});
     double* y = si1 ? L.unm(m) : L.y;
-    solve(h, L, cf, dtm, L.b, y, L.um(m));
+    solve_lc(h, L, cf, dtm, b1, y, L.um(m));
     if (!si1) {
       // stage 2: M u^k_m = M u^k_{m-1} + q_m + g_m + H(y,u^k_{m-1},u^k_m) - H(u^{k-1}_m,u^{k-1}_{m-1},u^{k-1}_m)
       conv(h, L, y, L.t1);
-      if (gm)
-        lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0});
-      else
-        lincomb(h, L, L.b, {{1.0, ua}, {1.0, qm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0});
-      solve(h, L, cf, dtm, L.b, L.unm(m), y);
+      const LinComb b2 =
+          gm ? make_lc({{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0})
+             : make_lc({{1.0, ua}, {1.0, qm}, {dtm, L.t1}, {-dtm, Cold_m}, {dtm, Xm}}, {1, 0, 0, 0, 0});
+      solve_lc(h, L, cf, dtm, b2, L.unm(m), y);
     }
     // stored terms of the new iterate at node m
     double* Cm = L.Cnew + (long)m * n;
