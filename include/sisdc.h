@@ -69,7 +69,7 @@ typedef enum {
                             viscous term by BR1 lifting          (Sec. 2)  */
 } sisdc_eq;
 
-enum { SISDC_SI2 = 0, SISDC_SI1 = 1 };                 /* Sec. 3            */
+enum { SISDC_SI2 = 0, SISDC_SI1 = 1, SISDC_IMEX_EULER = 2 };  /* Sec. 3 */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
 enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
@@ -97,7 +97,11 @@ typedef struct {
   int n_levels;        /* 1..3                                              */
   int P[3];            /* polynomial degree per level (index 0 finest), 1..8 */
   int M[3];            /* Radau-right nodes per level, 1..8                 */
-  int integrator;      /* SISDC_SI2 (default) or SISDC_SI1                  */
+  int integrator;      /* SISDC_SI2 (default), SISDC_SI1, or SISDC_IMEX_EULER
+                          (eq. H_IMEX: the one-stage form with the physical
+                          diffusion alone implicit, nu I for the scalar
+                          equations; systems keep no implicit term, their
+                          substeps are explicit apart from the mass matrix) */
   int start;           /* SISDC_START_*  (multilevel only)                  */
   int n_coarse_sweeps; /* N_c, sweeps on the coarsest level per V-cycle     */
   int post_sweep;      /* final fine sweep after the last V-cycle (0/1)     */

@@ -3,7 +3,8 @@
 For a Fourier mode exp(i k x) of the convection-diffusion equation the
 operators reduce to numbers: the convective part is i lam_i, the diffusion
 lam_r (lam_r = -nu k^2, lam_i = -v k), and the implicit coefficient
-(dt_m/2) A_c^2 + A_d acts as K = (dt_m/2) lam_i^2 - lam_r.  The mass is 1.
+(dt_m/2) A_c^2 + A_d acts as K = (dt_m/2) lam_i^2 - lam_r (IMEX Euler:
+A_d alone, K = -lam_r).  The mass is 1.
 Plugging these into the same predictor / corrector / V-cycle code gives the
 stability function R(z) = u^{n+1} / u^n, z = dt (lam_r + i lam_i).
 """
@@ -30,6 +31,10 @@ class DahlquistLevel:
 
     def coef(self, ub, dtm, params):
         return 0.5 * dtm * self.lam_i ** 2 - self.lam_r
+
+    def coef_d(self, ub, dtm, params):
+        """A_d alone (IMEX Euler): the diffusion -lam_r."""
+        return -self.lam_r
 
     def K(self, c, x):
         return c * x

@@ -43,6 +43,14 @@ class ConvDiff:
                 Dc[i, j] = 0.5 * dtm * self.a[i] * self.a[j] + (self.nu if i == j else 0.0)
         return Dc
 
+    def coef_d(self, Ub, dtm, params=None):
+        """A_d alone (IMEX Euler, eq. H_IMEX): nu I at every node."""
+        shp = Ub[0].shape
+        Dc = np.zeros((self.dim, self.dim) + shp)
+        for i in range(self.dim):
+            Dc[i, i] = self.nu
+        return Dc
+
     def step_params(self, U0):
         return None
 
@@ -70,6 +78,14 @@ class Burgers:
         for i in range(self.dim):
             for j in range(self.dim):
                 Dc[i, j] = 0.5 * dtm * u2 + (self.nu if i == j else 0.0)
+        return Dc
+
+    def coef_d(self, Ub, dtm, params=None):
+        """A_d alone (IMEX Euler, eq. H_IMEX): nu I at every node."""
+        shp = Ub[0].shape
+        Dc = np.zeros((self.dim, self.dim) + shp)
+        for i in range(self.dim):
+            Dc[i, i] = self.nu
         return Dc
 
     def step_params(self, U0):
@@ -119,6 +135,14 @@ class Euler:
 
     def kappa(self, dtm, params):
         return 0.5 * dtm * params["lam"] ** 2 + params["visc"]
+
+    def coef_d(self, Ub, dtm, params):
+        """A_d alone (IMEX Euler, eq. H_IMEX): zero.  The Euler equations have
+        no diffusion; the Navier-Stokes viscous term stays explicit inside f
+        (reading), so IMEX Euler substeps of a system are explicit apart from
+        the mass matrix."""
+        shp = Ub[0].shape
+        return np.zeros((self.dim, self.dim) + shp)
 
     def coef(self, Ub, dtm, params):
         kap = self.kappa(dtm, params)

@@ -13,7 +13,11 @@ so the same code runs the DG discretisation and the scalar test equation.
 Low-order term (eq. H_SI(1)), weak form:
     H(a, b, c) = dt_m [ C(a) - K_{D_m(b)} c ],
 with D_m(b) the implicit coefficient (physics.py).  Semi-implicit systems are
-solved as (M + dt_m K_{D_m(b)}) x = rhs.
+solved as (M + dt_m K_{D_m(b)}) x = rhs.  The IMEX Euler term (eq. H_IMEX,
+scheme "eu") is the same expression with D_m(b) = A_d(b), the physical
+diffusion alone; its predictor and corrector are the one-stage forms (eqs.
+sdc:incremental_predictor_eu and DeltaH_EU), i.e. those of SI(1) with that
+coefficient.
 
 Predictor SI(2) (eq. sdc:incremental_predictor_si2):
     M y   = M u_{m-1} + H(u_{m-1}, u_{m-1}, y)
@@ -83,6 +87,9 @@ class DGLevel:
     def coef(self, ub, dtm, params):
         return self.phys.coef(ub, dtm, params)
 
+    def coef_d(self, ub, dtm, params):
+        return self.phys.coef_d(ub, dtm, params)
+
     def K(self, Dc, x):
         return self.dg.sipg(Dc, x)
 
@@ -149,21 +156,33 @@ def quadrature(lv, F, dt):
     return q
 
 
-def H(lv, a, b, c, dtm, params):
-    """Weak H^SI(a, b, c) = dt_m [C(a) - K_{D_m(b)} c]."""
-    return dtm * (lv.conv(a) - lv.K(lv.coef(b, dtm, params), c))
+def implicit_coef(lv, ub, dtm, params, scheme):
+    """D_m(u_b) of the low-order term: (dt_m/2) A_c^2 + A_d (SI, eq. H_SI(1))
+    or A_d alone (IMEX Euler, eq. H_IMEX)."""
+    if scheme == "eu":
+        return lv.coef_d(ub, dtm, params)
+    return lv.coef(ub, dtm, params)
+
+
+def one_stage(scheme):
+    return scheme in ("si1", "eu")
+
+
+def H(lv, a, b, c, dtm, params, scheme="si2"):
+    """Weak H(a, b, c) = dt_m [C(a) - K_{D_m(b)} c]."""
+    return dtm * (lv.conv(a) - lv.K(implicit_coef(lv, b, dtm, params, scheme), c))
 
 
 def predictor(lv, u0, dt, params, scheme="si2"):
-    """SI(1) / SI(2) predictor sweep: returns [u_0, u_1, ..., u_M]."""
+    """SI(1) / SI(2) / IMEX Euler predictor sweep: returns [u_0, u_1, ..., u_M]."""
     U = [u0]
     dts = substeps(lv, dt)
     for m in range(1, lv.tt.M + 1):
         dtm = dts[m - 1]
         ua = U[m - 1]
-        Dc = lv.coef(ua, dtm, params)
+        Dc = implicit_coef(lv, ua, dtm, params, scheme)
         y = lv.solve(Dc, dtm, lv.mass(ua) + dtm * lv.conv(ua), ua)
-        if scheme == "si1":
+        if one_stage(scheme):
             U.append(y)
             continue
         U.append(lv.solve(Dc, dtm, lv.mass(ua) + dtm * lv.conv(y), y))
@@ -171,7 +190,7 @@ def predictor(lv, u0, dt, params, scheme="si2"):
 
 
 def sweep(lv, U, dt, params, g=None, scheme="si2"):
-    """One incremental SI(1)/SI(2) corrector sweep (Alg. 1 with N = 1)."""
+    """One incremental SI(1)/SI(2)/IMEX Euler corrector sweep (Alg. 1 with N = 1)."""
     M = lv.tt.M
     dts = substeps(lv, dt)
     F = [None] + [lv.frhs(U[i]) for i in range(1, M + 1)]
@@ -179,17 +198,17 @@ def sweep(lv, U, dt, params, g=None, scheme="si2"):
     Unew = [U[0]]
     for m in range(1, M + 1):
         dtm = dts[m - 1]
-        h1_old = H(lv, U[m - 1], U[m - 1], U[m], dtm, params)
+        h1_old = H(lv, U[m - 1], U[m - 1], U[m], dtm, params, scheme)
         ua = Unew[m - 1]
-        Dc = lv.coef(ua, dtm, params)
+        Dc = implicit_coef(lv, ua, dtm, params, scheme)
         base = lv.mass(ua) + q[m]
         if g is not None:
             base = base + g[m]
         y = lv.solve(Dc, dtm, base + dtm * lv.conv(ua) - h1_old, U[m])
-        if scheme == "si1":
+        if one_stage(scheme):
             Unew.append(y)
             continue
-        h2_old = H(lv, U[m], U[m - 1], U[m], dtm, params)
+        h2_old = H(lv, U[m], U[m - 1], U[m], dtm, params, scheme)
         Unew.append(lv.solve(Dc, dtm, base + dtm * lv.conv(y) - h2_old, y))
     return Unew
 

@@ -240,6 +240,12 @@ void copy_d2d(sisdc_handle* h, double* dst, const double* src, long n) {
 
 CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
   CoefP c{};
+  if (h->meth.integrator == SISDC_IMEX_EULER) {  // eq. H_IMEX: A_d alone
+    c.nu = (h->eq.eq == EQ_EULER || h->eq.eq == EQ_NS) ? 0.0 : h->eq.nu;
+    (void)L;
+    (void)ub;
+    return c;
+  }
   switch (h->eq.eq) {
     case EQ_CONVDIFF:
       c.c = 0.5 * dtm;
@@ -791,7 +797,7 @@ void quadrature(sisdc_handle* h, Level& L, double dt) {
 }
 
 void predictor(sisdc_handle* h, Level& L, double dt) {
-  const bool si1 = h->meth.integrator == SISDC_SI1;
+  const bool si1 = h->meth.integrator != SISDC_SI2;  // one-stage forms: SI(1), IMEX Euler
   for (int m = 1; m <= L.M; ++m) {
     const double dtm = dt * L.dtau[m - 1];
     const double* ua = L.um(m - 1);
@@ -809,7 +815,7 @@ void predictor(sisdc_handle* h, Level& L, double dt) {
 
 // One incremental SI(1)/SI(2) corrector sweep (Alg. 1 with N = 1).
 void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
-  const bool si1 = h->meth.integrator == SISDC_SI1;
+  const bool si1 = h->meth.integrator != SISDC_SI2;  // one-stage forms: SI(1), IMEX Euler
   ensure_stored(h, L, dt);
   quadrature(h, L, dt);
   const long n = L.vlen;
@@ -1201,7 +1207,8 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
     if (m->M[l] < 1 || m->M[l] > 8) fail(SISDC_EINVAL, "M must be 1..8");
     if (l > 0 && m->P[l] > m->P[l - 1]) fail(SISDC_EINVAL, "coarser levels need P <= finer P");
   }
-  if (m->integrator != SISDC_SI2 && m->integrator != SISDC_SI1) fail(SISDC_EINVAL, "integrator");
+  if (m->integrator != SISDC_SI2 && m->integrator != SISDC_SI1 && m->integrator != SISDC_IMEX_EULER)
+    fail(SISDC_EINVAL, "integrator");
   if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsisdc.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 EQ_CONVDIFF, EQ_BURGERS, EQ_EULER, EQ_NS = 0, 1, 2, 3
-SI2, SI1 = 0, 1
+SI2, SI1, IMEX_EULER = 0, 1, 2
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2

@@ -431,3 +431,60 @@ def test_ns_taylor_green_step_conserves_and_dissipates():
         u = sdc.sdc_step(lv, u, 2e-3, 2)
     assert np.max(np.abs(lv.dg.integral(u) - m0)) < 1e-12 * np.max(np.abs(m0))
     assert ke(u) < k0
+
+
+# ---------------------------------------------------------------- IMEX Euler (eqs. H_IMEX, DeltaH_EU)
+def test_imex_euler_single_substep_closed_form():
+    """M = 1: the predictor is one IMEX Euler step, convection explicit and
+    diffusion implicit: R = (1 + i z_i) / (1 - z_r) (dt = 1)."""
+    for z in (-0.4 + 0.7j, -3.0 - 2.0j, -0.05 + 1.5j):
+        r = (1 + 1j * z.imag) / (1 - z.real)
+        assert abs(dahlquist.amplification_sdc(z, 1, 0, "eu") - r) < 1e-15
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_imex_euler_sdc_converges_to_radau_iia_pade(M):
+    # the sweeps change the low-order term only, so their fixed point is the
+    # same collocation solution as that of SI(1) / SI(2)
+    for z in (-0.3 + 0.2j, -0.5 + 0.5j, -1.0 + 0.3j):
+        R = dahlquist.amplification_sdc(z, M, 80, "eu")
+        assert abs(R - pade(z, M - 1, M)) < 1e-12
+
+
+def test_imex_euler_gains_one_order_per_sweep():
+    M = 4
+    d = np.exp(1j * 0.7)
+    for k in range(0, 4):
+        p = min(k + 1, 2 * M - 1)
+        e1 = abs(dahlquist.amplification_sdc(0.02 * d, M, k, "eu") - np.exp(0.02 * d))
+        e2 = abs(dahlquist.amplification_sdc(0.01 * d, M, k, "eu") - np.exp(0.01 * d))
+        assert np.log2(e1 / e2) > p + 1 - 0.3, k
+
+
+def test_imex_euler_predictor_is_explicit_euler_for_the_euler_equations():
+    """The Euler equations have no diffusion (A_d = 0), so each IMEX Euler
+    substep is u_m = u_{m-1} + dt_m M^-1 C(u_{m-1})."""
+    phys = Euler(2, 1.4)
+    lv = sdc.DGLevel(phys, (3, 3), [0, 0], [10, 10], 4, 3, rtol=1e-14)
+    u = isentropic_vortex(lv.coords())
+    params = phys.step_params(u)
+    dt = 0.05
+    U = sdc.predictor(lv, u, dt, params, "eu")
+    ref = u
+    for m, dtm in enumerate(sdc.substeps(lv, dt), start=1):
+        ref = ref + dtm * lv.dg.conv(ref) / lv.dg.Wm
+        assert np.max(np.abs(U[m] - ref)) < 1e-12 * np.max(np.abs(ref)), m
+
+
+def test_imex_euler_diffusion_substep_damps_fourier_mode():
+    """Pure diffusion (a = 0): one IMEX Euler substep divides a Fourier mode
+    sin(2 pi k x) by 1 + dt nu (2 pi k)^2, up to the spectral error of the
+    discrete operator."""
+    nu, k, dt = 0.05, 2, 0.02
+    phys = ConvDiff([0.0, 0.0], nu)
+    lv = sdc.DGLevel(phys, (4, 4), [0, 0], [1, 1], 8, 1, rtol=1e-14)
+    x = lv.coords()
+    u0 = np.sin(2 * np.pi * k * x[0])[None]
+    U = sdc.predictor(lv, u0, dt, None, "eu")
+    g = 1.0 / (1.0 + dt * nu * (2 * np.pi * k) ** 2)
+    assert np.max(np.abs(U[1] - g * u0)) < 1e-6
