@@ -70,6 +70,7 @@ typedef enum {
 } sisdc_eq;
 
 enum { SISDC_SI2 = 0, SISDC_SI1 = 1, SISDC_IMEX_EULER = 2 };  /* Sec. 3 */
+enum { SISDC_PROJ_INTERP = 0, SISDC_PROJ_L2 = 1 };                /* Sec. 4 */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
 enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
@@ -130,6 +131,11 @@ typedef struct {
                           over before and after the kernel)               */
   double inner_rtol;   /* SISDC_MIXED: relative tolerance of each FP32 inner
                           solve (<= 0: 1e-5)                                */
+  int projection;      /* P_x, the fine-to-coarse solution transfer (Sec. 4,
+                          "MLSDC transfer operators"): SISDC_PROJ_INTERP
+                          (embedded interpolation, default) or SISDC_PROJ_L2
+                          (L^2 projection onto each element's coarse
+                          polynomials, (I^T W_f I)^-1 I^T W_f per axis)     */
 } sisdc_method;
 
 typedef struct {

@@ -110,13 +110,25 @@ class DGLevel:
 
 class SpaceTransfer:
     """p-coarsening transfer between two DG levels on the same mesh:
-    I_x (coarse -> fine), P_x (fine -> coarse, embedded interpolation) and
-    R_x = I_x^T, each the 1-D Lagrange matrix applied along every axis."""
+    I_x (coarse -> fine), P_x (fine -> coarse) and R_x = I_x^T, each a 1-D
+    matrix applied along every axis.  P_x (Sec. 4, "MLSDC transfer
+    operators", eq. projection_int and the choice that follows it) is either
+    embedded interpolation (the coarse nodal values of the fine polynomial)
+    or the L^2 projection onto the coarse polynomials of each element:
+    P = (I^T W_f I)^-1 I^T W_f per axis, with W_f the fine GLL weights (the
+    fine quadrature integrates the coarse mass matrix exactly for P_c < P_f;
+    the element Jacobian cancels)."""
 
-    def __init__(self, fine, coarse):
+    def __init__(self, fine, coarse, projection="interp"):
         self.fine, self.coarse = fine, coarse
         self.I1 = lagrange_matrix(coarse.ref.x, fine.ref.x)     # (Pf+1, Pc+1)
-        self.P1 = lagrange_matrix(fine.ref.x, coarse.ref.x)     # (Pc+1, Pf+1)
+        if projection == "interp":
+            self.P1 = lagrange_matrix(fine.ref.x, coarse.ref.x)     # (Pc+1, Pf+1)
+        elif projection == "l2":
+            Wf = np.diag(fine.ref.w)
+            self.P1 = np.linalg.solve(self.I1.T @ Wf @ self.I1, self.I1.T @ Wf)
+        else:
+            raise ValueError(projection)
 
     def _apply(self, X, A):
         mesh = self.fine.mesh
@@ -227,10 +239,10 @@ def collocation_residual(lv, U, dt):
 class Transfer:
     """Space-time transfer between level l (fine) and l-1 (coarse)."""
 
-    def __init__(self, fine, coarse, space=None):
+    def __init__(self, fine, coarse, space=None, projection="interp"):
         self.fine, self.coarse = fine, coarse
         self.It, self.Pt, self.Rt = time_transfer(fine.tt, coarse.tt)
-        self.space = space if space is not None else SpaceTransfer(fine, coarse)
+        self.space = space if space is not None else SpaceTransfer(fine, coarse, projection)
 
     def interp(self, Uc):
         """(I_t (x) I_x) on nodes 1..M_c -> nodes 1..M_f (index 0: None)."""
@@ -274,11 +286,12 @@ class MLSDC:
     """SI-MLSDC on levels[0] (l = 1, coarsest) .. levels[L-1] (l = L)."""
 
     def __init__(self, levels, transfers=None, scheme="si2", n_coarse=2,
-                 start="cascade", cycles=3, post_sweep=True, c_fmg=1):
+                 start="cascade", cycles=3, post_sweep=True, c_fmg=1, projection="interp"):
         self.levels = levels
         self.L = len(levels)
         if transfers is None:
-            transfers = [None] + [Transfer(levels[i], levels[i - 1]) for i in range(1, self.L)]
+            transfers = [None] + [Transfer(levels[i], levels[i - 1], projection=projection)
+                                  for i in range(1, self.L)]
         self.tr = transfers            # tr[i]: between levels[i] and levels[i-1]
         self.scheme = scheme
         self.n_coarse = n_coarse

@@ -1173,9 +1173,44 @@ void free_level(Level& L) {
     if (p) (void)hipFree(p);
 }
 
-void build_transfer(Transfer& T, const Level& F, const Level& Cc) {
+// L^2 projection onto the coarse polynomials of an element, one axis:
+// P = (I^T W_f I)^-1 I^T W_f (n1c x n1f), the coarse mass by the fine GLL
+// quadrature (exact for Pc < Pf); Gaussian elimination with partial pivoting.
+std::vector<double> l2_projection(const std::vector<double>& I, const std::vector<double>& wf, int n1f, int n1c) {
+  std::vector<double> A(n1c * n1c, 0.0), B(n1c * n1f, 0.0);
+  for (int a = 0; a < n1c; ++a) {
+    for (int b = 0; b < n1c; ++b)
+      for (int i = 0; i < n1f; ++i) A[a * n1c + b] += I[i * n1c + a] * wf[i] * I[i * n1c + b];
+    for (int i = 0; i < n1f; ++i) B[a * n1f + i] = I[i * n1c + a] * wf[i];
+  }
+  for (int k = 0; k < n1c; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n1c; ++r)
+      if (std::fabs(A[r * n1c + k]) > std::fabs(A[piv * n1c + k])) piv = r;
+    if (A[piv * n1c + k] == 0.0) fail(SISDC_EINVAL, "singular coarse mass matrix");
+    if (piv != k) {
+      for (int c = 0; c < n1c; ++c) std::swap(A[k * n1c + c], A[piv * n1c + c]);
+      for (int c = 0; c < n1f; ++c) std::swap(B[k * n1f + c], B[piv * n1f + c]);
+    }
+    for (int r = k + 1; r < n1c; ++r) {
+      const double f = A[r * n1c + k] / A[k * n1c + k];
+      for (int c = k; c < n1c; ++c) A[r * n1c + c] -= f * A[k * n1c + c];
+      for (int c = 0; c < n1f; ++c) B[r * n1f + c] -= f * B[k * n1f + c];
+    }
+  }
+  for (int k = n1c - 1; k >= 0; --k)
+    for (int c = 0; c < n1f; ++c) {
+      double v = B[k * n1f + c];
+      for (int j = k + 1; j < n1c; ++j) v -= A[k * n1c + j] * B[j * n1f + c];
+      B[k * n1f + c] = v / A[k * n1c + k];
+    }
+  return B;
+}
+
+void build_transfer(Transfer& T, const Level& F, const Level& Cc, int projection) {
   std::vector<double> I = lagrange(Cc.xg, F.xg);   // (n1f x n1c)
-  std::vector<double> P = lagrange(F.xg, Cc.xg);   // (n1c x n1f)
+  std::vector<double> P = projection == SISDC_PROJ_L2 ? l2_projection(I, F.wg, F.n1, Cc.n1)
+                                                      : lagrange(F.xg, Cc.xg);  // (n1c x n1f)
   std::vector<double> R(Cc.n1 * F.n1);
   for (int i = 0; i < F.n1; ++i)
     for (int j = 0; j < Cc.n1; ++j) R[j * F.n1 + i] = I[i * Cc.n1 + j];
@@ -1209,6 +1244,7 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   }
   if (m->integrator != SISDC_SI2 && m->integrator != SISDC_SI1 && m->integrator != SISDC_IMEX_EULER)
     fail(SISDC_EINVAL, "integrator");
+  if (m->projection != SISDC_PROJ_INTERP && m->projection != SISDC_PROJ_L2) fail(SISDC_EINVAL, "projection");
   if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
@@ -1333,7 +1369,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->lv.resize(meth->n_levels);
     for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
-    for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1]);
+    for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1], meth->projection);
     h->partials = dalloc((size_t)7 * kElemCap);
     h->ir_tot = dalloc(2);
     h->gtot = dalloc(4);

@@ -488,3 +488,28 @@ def test_imex_euler_diffusion_substep_damps_fourier_mode():
     U = sdc.predictor(lv, u0, dt, None, "eu")
     g = 1.0 / (1.0 + dt * nu * (2 * np.pi * k) ** 2)
     assert np.max(np.abs(U[1] - g * u0)) < 1e-6
+
+
+# ---------------------------------------------------------------- L^2 projection (Sec. 4, P_l)
+@pytest.mark.parametrize("dim,Pf,Pc", [(2, 8, 4), (2, 6, 3), (3, 5, 2)])
+def test_l2_projection_properties(dim, Pf, Pc):
+    """P = L^2 projection onto the coarse polynomials: it reproduces every
+    coarse field (P I = 1), conserves the integral, and leaves a remainder
+    orthogonal to the coarse space under the fine quadrature."""
+    phys = ConvDiff([1.0] * dim, 0.01)
+    n = (2, 3) if dim == 2 else (2, 1, 2)
+    lf = sdc.DGLevel(phys, n, [0.0] * dim, [1.0] * dim, Pf, 2)
+    lc = sdc.DGLevel(phys, n, [0.0] * dim, [1.0] * dim, Pc, 2)
+    tr = sdc.SpaceTransfer(lf, lc, projection="l2")
+    rng = np.random.default_rng(7)
+    vc = rng.standard_normal(lc.shape())
+    np.testing.assert_allclose(tr.P(tr.I(vc)), vc, atol=1e-12)
+    uf = rng.standard_normal(lf.shape())
+    assert abs(lc.dg.integral(tr.P(uf))[0] - lf.dg.integral(uf)[0]) < 1e-12 * np.abs(uf).sum()
+    rem = uf - tr.I(tr.P(uf))
+    # (I^T W_f) rem = 0, element by element: the coarse moments of the remainder vanish
+    mom = tr.R(lf.dg.Wm * rem)
+    assert np.max(np.abs(mom)) < 1e-12
+    # embedded interpolation is not conservative in general (so the check above has teeth)
+    ti = sdc.SpaceTransfer(lf, lc, projection="interp")
+    assert abs(lc.dg.integral(ti.P(uf))[0] - lf.dg.integral(uf)[0]) > 1e-6
