@@ -234,6 +234,69 @@ def collocation_residual(lv, U, dt):
 
 
 # --------------------------------------------------------------------------
+# non-incremental (zero-to-node) form (Sec. 3 "Non-incremental SDC method",
+# Sec. 4 "Non-incremental multilevel SDC method")
+# --------------------------------------------------------------------------
+def quadrature0n(lv, F, dt):
+    """q0n_m = dt sum_i w0n_{m,i} f_i (eq. cm:non-incremental)."""
+    W = dt * lv.tt.w0n
+    M = lv.tt.M
+    q = [None]
+    for m in range(M):
+        acc = 0.0
+        for i in range(M):
+            acc = acc + W[m, i] * F[i + 1]
+        q.append(acc)
+    return q
+
+
+def sweep0n(lv, U, dt, params, g0n=None, scheme="si2"):
+    """One zero-to-node sweep (eq. sdc:non-incremental; with the FAS term of
+    eq. ml-sdc:non-incremental:matrix):
+        M u^k_m = M u_0 + q0n_m + g0n_m + sum_{i<=m} DeltaH^k_i,
+    the deltas the same as in the incremental form.  The SI(2) stage keeps
+    its incremental definition (the paper states it only in that form), with
+    the node's share g0n_m - g0n_{m-1} of the FAS term (reading)."""
+    M = lv.tt.M
+    dts = substeps(lv, dt)
+    F = [None] + [lv.frhs(U[i]) for i in range(1, M + 1)]
+    q0 = quadrature0n(lv, F, dt)
+    qn = quadrature(lv, F, dt)
+    Unew = [U[0]]
+    acc = 0.0                                     # sum of the deltas of nodes 1..m-1
+    base0 = lv.mass(U[0])
+    for m in range(1, M + 1):
+        dtm = dts[m - 1]
+        ua = Unew[m - 1]
+        Dc = implicit_coef(lv, ua, dtm, params, scheme)
+        g_m = g0n[m] if g0n is not None else 0.0
+        g_prev = g0n[m - 1] if (g0n is not None and m > 1) else 0.0
+        h1_old = H(lv, U[m - 1], U[m - 1], U[m], dtm, params, scheme)
+        rhs0 = base0 + q0[m] + g_m + acc
+        if one_stage(scheme):
+            # DeltaH_m = H(ua, ua, u_m) - h1_old, implicit in u_m
+            um = lv.solve(Dc, dtm, rhs0 + dtm * lv.conv(ua) - h1_old, U[m])
+            acc = acc + H(lv, ua, ua, um, dtm, params, scheme) - h1_old
+            Unew.append(um)
+            continue
+        stage = lv.mass(ua) + qn[m] + (g_m - g_prev)
+        y = lv.solve(Dc, dtm, stage + dtm * lv.conv(ua) - h1_old, U[m])
+        h2_old = H(lv, U[m], U[m - 1], U[m], dtm, params, scheme)
+        um = lv.solve(Dc, dtm, rhs0 + dtm * lv.conv(y) - h2_old, y)
+        acc = acc + H(lv, y, ua, um, dtm, params, scheme) - h2_old
+        Unew.append(um)
+    return Unew
+
+
+def collocation_residual0n(lv, U, dt):
+    """F0n_m(u) = M (u_m - u_0) - q0n_m(u), m = 1..M (eq. cm:non-incremental:matrix)."""
+    M = lv.tt.M
+    F = [None] + [lv.frhs(U[i]) for i in range(1, M + 1)]
+    q = quadrature0n(lv, F, dt)
+    return [None] + [lv.mass(U[m] - U[0]) - q[m] for m in range(1, M + 1)]
+
+
+# --------------------------------------------------------------------------
 # space-time transfers
 # --------------------------------------------------------------------------
 class Transfer:
@@ -286,8 +349,12 @@ class MLSDC:
     """SI-MLSDC on levels[0] (l = 1, coarsest) .. levels[L-1] (l = L)."""
 
     def __init__(self, levels, transfers=None, scheme="si2", n_coarse=2,
-                 start="cascade", cycles=3, post_sweep=True, c_fmg=1, projection="interp"):
+                 start="cascade", cycles=3, post_sweep=True, c_fmg=1, projection="interp",
+                 formulation="incremental"):
         self.levels = levels
+        if formulation not in ("incremental", "nonincremental"):
+            raise ValueError(formulation)
+        self.nonincremental = formulation == "nonincremental"
         self.L = len(levels)
         if transfers is None:
             transfers = [None] + [Transfer(levels[i], levels[i - 1], projection=projection)
@@ -315,7 +382,11 @@ class MLSDC:
             self.u0[i - 1] = self.tr[i].space.P(self.u0[i])
 
     def sdc_sweep(self, i, dt, g):
-        self.U[i] = sweep(self.levels[i], self.U[i], dt, self.params, g, self.scheme)
+        sw = sweep0n if self.nonincremental else sweep
+        self.U[i] = sw(self.levels[i], self.U[i], dt, self.params, g, self.scheme)
+
+    def residual_op(self, lv, U, dt):
+        return (collocation_residual0n if self.nonincremental else collocation_residual)(lv, U, dt)
 
     def vcycle(self, top, dt):
         """Alg. 2 on levels[0..top]; the top level has g = 0."""
@@ -323,13 +394,13 @@ class MLSDC:
         for i in range(top, 0, -1):
             lv, lc, tr = self.levels[i], self.levels[i - 1], self.tr[i]
             self.sdc_sweep(i, dt, self.g[i])                          # pre-sweep
-            Fl = collocation_residual(lv, self.U[i], dt)
+            Fl = self.residual_op(lv, self.U[i], dt)
             r = [None] + [(self.g[i][m] if self.g[i] is not None else 0.0) - Fl[m]
                           for m in range(1, lv.tt.M + 1)]             # residual
             v = tr.project(self.U[i])                                 # restriction
             v[0] = self.u0[i - 1]
             self.v[i - 1] = v
-            Fc = collocation_residual(lc, v, dt)
+            Fc = self.residual_op(lc, v, dt)
             Rr = tr.restrict(r)
             self.g[i - 1] = [None] + [Fc[m] + Rr[m] for m in range(1, lc.tt.M + 1)]
             self.U[i - 1] = list(v)

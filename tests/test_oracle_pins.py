@@ -513,3 +513,53 @@ def test_l2_projection_properties(dim, Pf, Pc):
     # embedded interpolation is not conservative in general (so the check above has teeth)
     ti = sdc.SpaceTransfer(lf, lc, projection="interp")
     assert abs(lc.dg.integral(ti.P(uf))[0] - lf.dg.integral(uf)[0]) > 1e-6
+
+
+# ---------------------------------------------------------------- non-incremental form (Sec. 3 and 4)
+@pytest.mark.parametrize("scheme", ["si2", "si1", "eu"])
+def test_nonincremental_sdc_equals_incremental(scheme):
+    """Single level: the zero-to-node sweep equals the node-to-node one by
+    recursion (Sec. 3 "Non-incremental SDC method")."""
+    lv = dahlquist.DahlquistLevel(-0.7, 0.9, 4)
+    U = sdc.predictor(lv, np.complex128(1.0), 1.0, None, scheme)
+    for _ in range(3):
+        a = sdc.sweep(lv, U, 1.0, None, None, scheme)
+        b = sdc.sweep0n(lv, U, 1.0, None, None, scheme)
+        assert max(abs(x - y) for x, y in zip(a[1:], b[1:])) < 1e-14
+        U = a
+
+
+def test_nonincremental_mlsdc_converges_to_radau_iia_pade():
+    for start in ("predictor", "cascade", "fmg"):
+        for z in (-0.5 + 0.3j, -1.0 - 0.5j):
+            ml = dahlquist.mlsdc(z.real, z.imag, [3, 5, 7], cycles=40, start=start, formulation="nonincremental")
+            assert abs(complex(ml.step(np.complex128(1.0), 1.0)) - pade(z, 6, 7)) < 1e-12
+
+
+def test_nonincremental_mlsdc_is_incremental_with_cumulated_restriction():
+    """Writing g0n = C g and r0n = C r (C the lower-triangular ones matrix of
+    the node sums), the zero-to-node MLSDC is the node-to-node one with the
+    time restriction C_c^-1 R_t C_f instead of R_t; the two forms are not
+    equivalent because R_t C_f != C_c R_t (Sec. 4 "Non-equivalence")."""
+
+    class CumulatedTransfer(sdc.Transfer):
+        def restrict(self, rf):
+            Mf, Mc = self.fine.tt.M, self.coarse.tt.M
+            Cf, Cc = np.tril(np.ones((Mf, Mf))), np.tril(np.ones((Mc, Mc)))
+            Reff = np.linalg.inv(Cc) @ self.It.T @ Cf
+            xs = [self.space.R(rf[i]) for i in range(1, Mf + 1)]
+            return [None] + [sum(Reff[j, i] * xs[i] for i in range(Mf)) for j in range(Mc)]
+
+    z = -0.8 + 0.6j
+    for start in ("predictor", "cascade", "fmg"):
+        levels = [dahlquist.DahlquistLevel(z.real, z.imag, M) for M in (3, 5, 7)]
+        tr = [None] + [CumulatedTransfer(levels[i], levels[i - 1], space=dahlquist._Identity())
+                       for i in range(1, 3)]
+        inc = sdc.MLSDC(levels, tr, cycles=2, start=start)
+        zn = dahlquist.mlsdc(z.real, z.imag, [3, 5, 7], cycles=2, start=start, formulation="nonincremental")
+        plain = dahlquist.mlsdc(z.real, z.imag, [3, 5, 7], cycles=2, start=start)
+        a = complex(inc.step(np.complex128(1.0), 1.0))
+        b = complex(zn.step(np.complex128(1.0), 1.0))
+        c = complex(plain.step(np.complex128(1.0), 1.0))
+        assert abs(a - b) < 1e-14, start
+        assert abs(b - c) > 1e-10, start  # not equivalent to the incremental form
