@@ -71,6 +71,7 @@ typedef enum {
 
 enum { SISDC_SI2 = 0, SISDC_SI1 = 1, SISDC_IMEX_EULER = 2 };  /* Sec. 3 */
 enum { SISDC_PROJ_INTERP = 0, SISDC_PROJ_L2 = 1 };                /* Sec. 4 */
+enum { SISDC_INCREMENTAL = 0, SISDC_NONINCREMENTAL = 1 };        /* Sec. 3, 4 */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
 enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
@@ -136,6 +137,12 @@ typedef struct {
                           (embedded interpolation, default) or SISDC_PROJ_L2
                           (L^2 projection onto each element's coarse
                           polynomials, (I^T W_f I)^-1 I^T W_f per axis)     */
+  int formulation;     /* SISDC_INCREMENTAL (node-to-node, default) or
+                          SISDC_NONINCREMENTAL (zero-to-node, Sec. 4
+                          "Non-incremental multilevel SDC method"): equal
+                          on one level; with several levels the FAS terms
+                          and residuals are node sums, so the residual
+                          restriction in time becomes C_c^-1 I_t^T C_f    */
 } sisdc_method;
 
 typedef struct {

@@ -118,6 +118,8 @@ struct Transfer {  // between level i (fine) and i+1 (coarse)
   double* Px = nullptr;  // (n1c x n1f) fine -> coarse
   double* Rx = nullptr;  // (n1c x n1f) = Ix^T
   std::vector<double> It, Pt;  // It: (Mf x Mc), Pt: (Mc x Mf)
+  std::vector<double> Rt;      // (Mc x Mf) time restriction of residuals: I_t^T, or
+                               // C_c^-1 I_t^T C_f for the non-incremental form
 };
 
 }  // namespace
@@ -908,7 +910,7 @@ void restrict_fas(sisdc_handle* h, int i, double dt) {
     std::vector<double> c;
     std::vector<const double*> x;
     for (int i2 = 0; i2 < F.M; ++i2) {
-      c.push_back(T.It[i2 * Cc.M + mc]);
+      c.push_back(T.Rt[mc * F.M + i2]);
       x.push_back(F.r + (long)i2 * F.vlen);
     }
     lincomb_v(h, F, F.t1, c, x, {});
@@ -1207,7 +1209,7 @@ std::vector<double> l2_projection(const std::vector<double>& I, const std::vecto
   return B;
 }
 
-void build_transfer(Transfer& T, const Level& F, const Level& Cc, int projection) {
+void build_transfer(Transfer& T, const Level& F, const Level& Cc, int projection, int formulation) {
   std::vector<double> I = lagrange(Cc.xg, F.xg);   // (n1f x n1c)
   std::vector<double> P = projection == SISDC_PROJ_L2 ? l2_projection(I, F.wg, F.n1, Cc.n1)
                                                       : lagrange(F.xg, Cc.xg);  // (n1c x n1f)
@@ -1222,6 +1224,25 @@ void build_transfer(Transfer& T, const Level& F, const Level& Cc, int projection
   HIPCHECK(hipMemcpy(T.Rx, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice));
   T.It = lagrange(Cc.tau, F.tau);  // (Mf x Mc)
   T.Pt = lagrange(F.tau, Cc.tau);  // (Mc x Mf)
+  // Residual restriction in time.  The non-incremental (zero-to-node) form
+  // (Sec. 4, eq. ml-sdc:non-incremental:matrix) restricts the node sums
+  // r0n = C_f r and its coarse FAS term is g0n = C_c g, C the lower-
+  // triangular matrix of ones; in node-to-node variables that is the
+  // restriction C_c^-1 I_t^T C_f: row mc of I_t^T C_f minus row mc - 1.
+  const int Mf = F.M, Mc = Cc.M;
+  std::vector<double> RC(Mc * Mf, 0.0);  // I_t^T C_f: sum over fine nodes k >= i of It[k][j]
+  for (int j = 0; j < Mc; ++j)
+    for (int i = 0; i < Mf; ++i) {
+      double acc = 0.0;
+      for (int k = i; k < Mf; ++k) acc += T.It[k * Mc + j];
+      RC[j * Mf + i] = acc;
+    }
+  T.Rt.assign(Mc * Mf, 0.0);
+  for (int j = 0; j < Mc; ++j)
+    for (int i = 0; i < Mf; ++i)
+      T.Rt[j * Mf + i] = formulation == SISDC_NONINCREMENTAL
+                             ? RC[j * Mf + i] - (j > 0 ? RC[(j - 1) * Mf + i] : 0.0)
+                             : T.It[i * Mc + j];
 }
 
 void validate(const sisdc_problem* p, const sisdc_method* m) {
@@ -1245,6 +1266,7 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->integrator != SISDC_SI2 && m->integrator != SISDC_SI1 && m->integrator != SISDC_IMEX_EULER)
     fail(SISDC_EINVAL, "integrator");
   if (m->projection != SISDC_PROJ_INTERP && m->projection != SISDC_PROJ_L2) fail(SISDC_EINVAL, "projection");
+  if (m->formulation != SISDC_INCREMENTAL && m->formulation != SISDC_NONINCREMENTAL) fail(SISDC_EINVAL, "formulation");
   if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
@@ -1369,7 +1391,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->lv.resize(meth->n_levels);
     for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
-    for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1], meth->projection);
+    for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1], meth->projection, meth->formulation);
     h->partials = dalloc((size_t)7 * kElemCap);
     h->ir_tot = dalloc(2);
     h->gtot = dalloc(4);

@@ -418,6 +418,58 @@ def test_l2_projection_steps(S, case):
                                rtol=1e-12, atol=1e-12)
 
 
+# ---------------------------------------------------------------- non-incremental MLSDC
+@pytest.mark.parametrize("case", ["burgers_2l_cascade", "convdiff_3l_fmg", "euler_3l_fmg", "ns_3d_2l"])
+def test_nonincremental_steps(S, case):
+    """Zero-to-node MLSDC (Sec. 4): the library's cumulated time restriction
+    against the oracle's literal zero-to-node sweeps, residuals and FAS
+    terms.  The result differs from the node-to-node form's (the two are not
+    equivalent), by far more than the tolerance."""
+    if case == "burgers_2l_cascade":
+        args = dict(eq="burgers", dim=2, n=(4, 3), Ps=[8, 4], Ms=[5, 3], n_iter=2, nu=5e-3, start=S.START_CASCADE)
+        dt = 5e-3
+    elif case == "convdiff_3l_fmg":
+        args = dict(eq="convdiff", dim=2, n=(3, 4), Ps=[6, 4, 2], Ms=[5, 3, 2], n_iter=1, start=S.START_FMG)
+        dt = 2e-2
+    elif case == "euler_3l_fmg":
+        args = dict(eq="euler", dim=2, n=(4, 4), Ps=[6, 4, 2], Ms=[5, 3, 2], n_iter=1, start=S.START_FMG,
+                    lo=[0, 0], hi=[10, 10])
+        dt = 0.1
+    else:
+        args = dict(eq="ns", dim=3, n=(2, 3, 2), Ps=[4, 2], Ms=[3, 2], n_iter=1, start=S.START_CASCADE,
+                    lo=[0, 0, 0], hi=[2 * np.pi] * 3)
+        dt = 4e-3
+    eq, dim = args["eq"], args["dim"]
+    name = {S.START_CASCADE: "cascade", S.START_FMG: "fmg"}[args["start"]]
+    res = {}
+    for form in ("nonincremental", "incremental"):
+        phys, levels, sv = make_pair(S, eq, dim, args["n"], args["Ps"], args["Ms"], lo=args.get("lo"),
+                                     hi=args.get("hi"), nu=args.get("nu", 0.01), n_iter=args["n_iter"],
+                                     start=args["start"],
+                                     formulation=S.NONINCREMENTAL if form == "nonincremental" else S.INCREMENTAL)
+        fine = levels[0]
+        if eq == "euler":
+            from paper_2504_18526_amd.inputs import isentropic_vortex
+            u = isentropic_vortex(fine.coords())
+        elif eq == "ns":
+            from paper_2504_18526_amd.inputs import taylor_green
+            u = taylor_green(fine.coords(), mach=0.1)
+        else:
+            u = smooth_state(phys, fine, np.random.default_rng(73))
+        ml = MLSDC(list(reversed(levels)), n_coarse=2, start=name, cycles=args["n_iter"], post_sweep=True,
+                   formulation=form)
+        sv.set_state(dev(u.ravel()))
+        out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+        st = sv.step(dt)
+        ref = ml.step(u, dt)
+        sv.get_state(out)
+        assert st["not_converged"] == 0
+        assert rel_l2(host(out), ref) < TOL, (case, form)
+        res[form] = host(out)
+        sv.close()
+    assert rel_l2(res["nonincremental"], res["incremental"]) > 1e3 * TOL, case
+
+
 # ---------------------------------------------------------------- persistent PCG
 # The one-launch pipelined PCG runs at production tolerances (rtol >= 1e-11).
 # Its iterates differ from the oracle's exact solve by at most about
