@@ -72,6 +72,7 @@ typedef enum {
 enum { SISDC_SI2 = 0, SISDC_SI1 = 1, SISDC_IMEX_EULER = 2 };  /* Sec. 3 */
 enum { SISDC_PROJ_INTERP = 0, SISDC_PROJ_L2 = 1 };                /* Sec. 4 */
 enum { SISDC_INCREMENTAL = 0, SISDC_NONINCREMENTAL = 1 };        /* Sec. 3, 4 */
+enum { SISDC_NODES_RADAU_RIGHT = 0, SISDC_NODES_LOBATTO = 1 };  /* Sec. 3 */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
        SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
 enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
@@ -143,6 +144,10 @@ typedef struct {
                           on one level; with several levels the FAS terms
                           and residuals are node sums, so the residual
                           restriction in time becomes C_c^-1 I_t^T C_f    */
+  int nodes;           /* collocation nodes in time (Sec. 3): SISDC_NODES_
+                          RADAU_RIGHT (default; Radau IIA, order 2M - 1) or
+                          SISDC_NODES_LOBATTO (both end points, tau_1 = 0 so
+                          u_1 = u_0; Lobatto IIIA, order 2M - 2; M >= 2)    */
 } sisdc_method;
 
 typedef struct {

@@ -15,10 +15,10 @@ from . import sdc
 
 
 class DahlquistLevel:
-    def __init__(self, lam_r, lam_i, M):
+    def __init__(self, lam_r, lam_i, M, nodes="radau"):
         self.lam_r = float(lam_r)
         self.lam_i = float(lam_i)
-        self.tt = TimeTable(M)
+        self.tt = TimeTable(M, nodes)
 
     def mass(self, x):
         return x
@@ -54,16 +54,16 @@ class _Identity:
         return x
 
 
-def mlsdc(lam_r, lam_i, Ms, **kw):
-    levels = [DahlquistLevel(lam_r, lam_i, M) for M in Ms]
+def mlsdc(lam_r, lam_i, Ms, nodes="radau", **kw):
+    levels = [DahlquistLevel(lam_r, lam_i, M, nodes) for M in Ms]
     tr = [None] + [sdc.Transfer(levels[i], levels[i - 1], space=_Identity())
                    for i in range(1, len(levels))]
     return sdc.MLSDC(levels, tr, **kw)
 
 
-def amplification_sdc(z, M, sweeps, scheme="si2"):
+def amplification_sdc(z, M, sweeps, scheme="si2", nodes="radau"):
     """R(z) of single-level SDC with `sweeps` corrector sweeps, dt = 1."""
-    lv = DahlquistLevel(z.real, z.imag, M)
+    lv = DahlquistLevel(z.real, z.imag, M, nodes)
     return complex(sdc.sdc_step(lv, np.complex128(1.0), 1.0, sweeps, scheme))
 
 

@@ -57,15 +57,16 @@ from . import solve as _solve
 # levels
 # --------------------------------------------------------------------------
 class DGLevel:
-    """One space-time level: DG-SEM of degree P on a mesh, M Radau nodes."""
+    """One space-time level: DG-SEM of degree P on a mesh, M Radau-right (or
+    Lobatto) nodes."""
 
     def __init__(self, phys, n_elem, lo, hi, P, M, c_tau=2.0, rtol=1e-14,
-                 maxit=20000, solver="cg"):
+                 maxit=20000, solver="cg", nodes="radau"):
         self.phys = phys
         self.ref = RefElement(P)
         self.mesh = Mesh(n_elem, lo, hi, P)
         self.dg = DG(self.ref, self.mesh, phys, c_tau)
-        self.tt = TimeTable(M)
+        self.tt = TimeTable(M, nodes)
         self.rtol = rtol
         self.maxit = maxit
         self.solver = solver

@@ -1,9 +1,11 @@
-"""Radau-right collocation in time (Sec. 3, "Single-level collocation and SDC
-methods"; Sec. 4, "MLSDC transfer operators").
+"""Collocation in time (Sec. 3, "Single-level collocation and SDC methods";
+Sec. 4, "MLSDC transfer operators").
 
-* nodes   : t_m = t + tau_m dt, m = 1..M, tau_M = 1 (Radau right: the left end
-            point t_0 is not a collocation node).  tau are the roots of
-            P_M(x) - P_{M-1}(x) mapped from [-1, 1] to [0, 1].
+* nodes   : t_m = t + tau_m dt, m = 1..M, tau_M = 1.  Radau right (the
+            default): the left end point t_0 is not a collocation node; tau
+            are the roots of P_M(x) - P_{M-1}(x) mapped from [-1, 1] to
+            [0, 1].  Lobatto: both end points are nodes (tau_1 = 0, so
+            u_1 = u_0); tau are the M Gauss-Lobatto points.
 * w^nn    : incremental (node-to-node) weights, eq. (nn_weights):
             w^nn_{m,i} = (1/dt) int_{t_{m-1}}^{t_m} l_i(t) dt, with l_i the
             Lagrange basis on t_1..t_M and t_0 = t.
@@ -37,6 +39,17 @@ def radau_right_nodes(M):
     return (r + 1.0) / 2.0
 
 
+def lobatto_nodes(M):
+    """Lobatto IIIA nodes on [0, 1]: the M Gauss-Lobatto-Legendre points."""
+    if M < 2:
+        raise ValueError("M >= 2 required for Lobatto nodes")
+    from .element import gll_nodes_weights
+    x, _ = gll_nodes_weights(M - 1)
+    t = (np.asarray(x) + 1.0) / 2.0
+    t[0], t[-1] = 0.0, 1.0
+    return t
+
+
 def _gauss_legendre(n):
     x, w = npleg.leggauss(n)
     return x, w
@@ -67,11 +80,17 @@ def zero_to_node_weights(Wnn):
 
 
 class TimeTable:
-    """Collocation tables for M Radau-right nodes on the unit interval."""
+    """Collocation tables for M Radau-right (or Lobatto) nodes on the unit
+    interval."""
 
-    def __init__(self, M):
+    def __init__(self, M, nodes="radau"):
         self.M = int(M)
-        self.tau = radau_right_nodes(self.M)
+        if nodes == "radau":
+            self.tau = radau_right_nodes(self.M)
+        elif nodes == "lobatto":
+            self.tau = lobatto_nodes(self.M)
+        else:
+            raise ValueError(nodes)
         self.wnn = nn_weights(self.tau)
         self.w0n = zero_to_node_weights(self.wnn)
         # substep lengths (fractions of dt): dtau_m = tau_m - tau_{m-1}
@@ -83,7 +102,7 @@ class TimeTable:
 
 
 def time_transfer(tt_fine, tt_coarse):
-    """(I_t, P_t, R_t) between two Radau-right node sets (Sec. 4)."""
+    """(I_t, P_t, R_t) between two node sets of the same kind (Sec. 4)."""
     I_t = lagrange_matrix(tt_coarse.tau, tt_fine.tau)    # M_f x M_c
     P_t = lagrange_matrix(tt_fine.tau, tt_coarse.tau)    # M_c x M_f
     return I_t, P_t, I_t.T.copy()

@@ -1081,8 +1081,18 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   gll(P, L.xg, L.wg);
   if ((int)L.xg.size() != L.n1) fail(SISDC_EDEVICE, "GLL node construction failed");
   L.D = derivative_matrix(L.xg);
-  L.tau = radau_right(M);
-  if ((int)L.tau.size() != M) fail(SISDC_EDEVICE, "Radau node construction failed");
+  if (h->meth.nodes == SISDC_NODES_LOBATTO) {  // the M Gauss-Lobatto points mapped to [0, 1]
+    std::vector<double> x, w;
+    gll(M - 1, x, w);
+    L.tau.assign(M, 0.0);
+    for (int m = 0; m < M && m < (int)x.size(); ++m) L.tau[m] = 0.5 * (x[m] + 1.0);
+    L.tau[0] = 0.0;
+    L.tau[M - 1] = 1.0;
+    if ((int)x.size() != M) fail(SISDC_EDEVICE, "Lobatto node construction failed");
+  } else {
+    L.tau = radau_right(M);
+  }
+  if ((int)L.tau.size() != M) fail(SISDC_EDEVICE, "collocation node construction failed");
   L.dtau.resize(M);
   for (int m = 0; m < M; ++m) L.dtau[m] = L.tau[m] - (m ? L.tau[m - 1] : 0.0);
   L.wnn = nn_weights(L.tau);
@@ -1267,6 +1277,10 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
     fail(SISDC_EINVAL, "integrator");
   if (m->projection != SISDC_PROJ_INTERP && m->projection != SISDC_PROJ_L2) fail(SISDC_EINVAL, "projection");
   if (m->formulation != SISDC_INCREMENTAL && m->formulation != SISDC_NONINCREMENTAL) fail(SISDC_EINVAL, "formulation");
+  if (m->nodes != SISDC_NODES_RADAU_RIGHT && m->nodes != SISDC_NODES_LOBATTO) fail(SISDC_EINVAL, "nodes");
+  if (m->nodes == SISDC_NODES_LOBATTO)
+    for (int l = 0; l < m->n_levels; ++l)
+      if (m->M[l] < 2) fail(SISDC_EINVAL, "Lobatto nodes need M >= 2 on every level");
   if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");

@@ -20,6 +20,7 @@ EQ_CONVDIFF, EQ_BURGERS, EQ_EULER, EQ_NS = 0, 1, 2, 3
 SI2, SI1, IMEX_EULER = 0, 1, 2
 PROJ_INTERP, PROJ_L2 = 0, 1
 INCREMENTAL, NONINCREMENTAL = 0, 1
+NODES_RADAU_RIGHT, NODES_LOBATTO = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2
@@ -55,7 +56,8 @@ class Method(ctypes.Structure):
                 ("n_iter", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
-                ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int)]
+                ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int),
+                ("nodes", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -196,7 +198,7 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, 
 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
                 n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
-                inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL):
+                inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -215,6 +217,7 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.inner_rtol = inner_rtol
     m.projection = projection
     m.formulation = formulation
+    m.nodes = nodes
     return m
 
 

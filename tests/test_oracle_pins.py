@@ -563,3 +563,32 @@ def test_nonincremental_mlsdc_is_incremental_with_cumulated_restriction():
         c = complex(plain.step(np.complex128(1.0), 1.0))
         assert abs(a - b) < 1e-14, start
         assert abs(b - c) > 1e-10, start  # not equivalent to the incremental form
+
+
+# ---------------------------------------------------------------- Lobatto nodes (Sec. 3)
+def test_lobatto_tables_are_lobatto_iiia():
+    """M = 3 Lobatto nodes: tau = (0, 1/2, 1) and w^0n equal to the Butcher
+    matrix of the 3-stage Lobatto IIIA method (first row zero: u_1 = u_0)."""
+    tt = TimeTable(3, "lobatto")
+    np.testing.assert_allclose(tt.tau, [0.0, 0.5, 1.0], atol=1e-15)
+    A = [[0.0, 0.0, 0.0], [5 / 24, 1 / 3, -1 / 24], [1 / 6, 2 / 3, 1 / 6]]
+    np.testing.assert_allclose(tt.w0n, A, atol=1e-15)
+    np.testing.assert_allclose(TimeTable(4, "lobatto").tau, [0.0, (5 - sqrt(5)) / 10, (5 + sqrt(5)) / 10, 1.0],
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 5])
+@pytest.mark.parametrize("scheme", ["si2", "si1"])
+def test_lobatto_sdc_converges_to_diagonal_pade(M, scheme):
+    """Lobatto IIIA with M stages has the (M-1, M-1) Pade approximant of e^z
+    as stability function (order 2M - 2)."""
+    for z in (-0.5 + 0.3j, -2.0 + 1.0j, -0.1 - 0.8j):
+        R = dahlquist.amplification_sdc(z, M, 60, scheme, nodes="lobatto")
+        assert abs(R - pade(z, M - 1, M - 1)) < 1e-12
+
+
+def test_lobatto_mlsdc_converges_to_diagonal_pade():
+    for start in ("predictor", "cascade", "fmg"):
+        for z in (-0.5 + 0.3j, -1.0 - 0.5j):
+            ml = dahlquist.mlsdc(z.real, z.imag, [3, 4, 5], nodes="lobatto", cycles=40, start=start)
+            assert abs(complex(ml.step(np.complex128(1.0), 1.0)) - pade(z, 4, 4)) < 1e-12
