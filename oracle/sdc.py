@@ -148,6 +148,88 @@ class SpaceTransfer:
         return self._apply(rf, self.I1.T)
 
 
+class SpaceTransferH:
+    """2:1 h-coarsening in space (Sec. 6, "MLSDC transfer operators"), with
+    p-coarsening on top: every coarse element fuses 2 fine elements along
+    each axis.  Each operator is a 1-D matrix on an axis' "pair" of fine
+    elements (2 (Pf+1) nodes, left child first) applied along every axis:
+
+    * I (coarse -> fine): each child evaluates the coarse polynomial at its
+      nodes, xi_c = (xi_f - 1)/2 (left child) or (xi_f + 1)/2 (right);
+    * R = I^T (each coarse element sums its children's contributions);
+    * P (fine -> coarse), embedded interpolation: each coarse node takes the
+      value of the child containing it.  Before that the jump between the
+      two children is removed by linear blending (reading of the paper's
+      default adjustment): with J the right child's value at the shared
+      face minus the left child's, the left child gets + J/2 (xi_c + 1) and
+      the right child - J/2 (1 - xi_c), so both meet at the mean there (the
+      paper's averaged centre contribution) and the outer faces keep their
+      values;
+    * P, L^2 projection: both children contribute to the whole coarse
+      element, P = (I^T W I)^-1 I^T W with W = diag(w_f / 2, w_f / 2)."""
+
+    def __init__(self, fine, coarse, projection="interp"):
+        self.fine, self.coarse = fine, coarse
+        xf, xc = np.asarray(fine.ref.x), np.asarray(coarse.ref.x)
+        nf, nc = len(xf), len(xc)
+        self.I1 = np.vstack([lagrange_matrix(xc, (xf - 1.0) / 2.0),
+                             lagrange_matrix(xc, (xf + 1.0) / 2.0)])       # (2 nf, nc)
+        if projection == "interp":
+            B = np.zeros((nc, 2 * nf))
+            for j, x in enumerate(xc):
+                if x < 0.0:
+                    B[j, :nf] = lagrange_matrix(xf, np.array([2.0 * x + 1.0]))[0]
+                    phi = 0.5 * (x + 1.0)                 # blending weight J/2 * (x + 1)
+                elif x > 0.0:
+                    B[j, nf:] = lagrange_matrix(xf, np.array([2.0 * x - 1.0]))[0]
+                    phi = -0.5 * (1.0 - x)
+                else:                                     # the shared centre: the mean of both children
+                    B[j, nf - 1] += 0.5
+                    B[j, nf] += 0.5
+                    continue
+                # + phi * J, J = u_right(first node) - u_left(last node)
+                B[j, nf] += phi
+                B[j, nf - 1] -= phi
+            self.P1 = B
+        elif projection == "l2":
+            W = np.diag(np.concatenate([fine.ref.w, fine.ref.w]) / 2.0)
+            self.P1 = np.linalg.solve(self.I1.T @ W @ self.I1, self.I1.T @ W)
+        else:
+            raise ValueError(projection)
+
+    def _f2c(self, X, A):
+        """A (nc x 2 nf) along every axis: fine-level array -> coarse."""
+        mesh = self.fine.mesh
+        for d in range(mesh.dim):
+            ea, na = mesh.elem_axis(d), mesh.node_axis(d)
+            X = np.moveaxis(X, (ea, na), (-2, -1))
+            sh = X.shape
+            X = X.reshape(sh[:-2] + (sh[-2] // 2, 2 * sh[-1])) @ A.T
+            X = np.moveaxis(X, (-2, -1), (ea, na))
+        return X
+
+    def _c2f(self, X, A):
+        """A (2 nf x nc) along every axis: coarse-level array -> fine."""
+        mesh = self.fine.mesh
+        for d in range(mesh.dim):
+            ea, na = mesh.elem_axis(d), mesh.node_axis(d)
+            X = np.moveaxis(X, (ea, na), (-2, -1))
+            Y = X @ A.T                                   # (..., nc_elem, 2 nf)
+            sh = Y.shape
+            X = Y.reshape(sh[:-2] + (sh[-2] * 2, sh[-1] // 2))
+            X = np.moveaxis(X, (-2, -1), (ea, na))
+        return X
+
+    def I(self, xc):
+        return self._c2f(xc, self.I1)
+
+    def P(self, xf):
+        return self._f2c(xf, self.P1)
+
+    def R(self, rf):
+        return self._f2c(rf, self.I1.T)
+
+
 # --------------------------------------------------------------------------
 # single-level building blocks
 # --------------------------------------------------------------------------
@@ -306,7 +388,10 @@ class Transfer:
     def __init__(self, fine, coarse, space=None, projection="interp"):
         self.fine, self.coarse = fine, coarse
         self.It, self.Pt, self.Rt = time_transfer(fine.tt, coarse.tt)
-        self.space = space if space is not None else SpaceTransfer(fine, coarse, projection)
+        if space is None:
+            same = tuple(fine.mesh.n) == tuple(coarse.mesh.n)
+            space = SpaceTransfer(fine, coarse, projection) if same else SpaceTransferH(fine, coarse, projection)
+        self.space = space
 
     def interp(self, Uc):
         """(I_t (x) I_x) on nodes 1..M_c -> nodes 1..M_f (index 0: None)."""

@@ -592,3 +592,68 @@ def test_lobatto_mlsdc_converges_to_diagonal_pade():
         for z in (-0.5 + 0.3j, -1.0 - 0.5j):
             ml = dahlquist.mlsdc(z.real, z.imag, [3, 4, 5], nodes="lobatto", cycles=40, start=start)
             assert abs(complex(ml.step(np.complex128(1.0), 1.0)) - pade(z, 4, 4)) < 1e-12
+
+
+# ---------------------------------------------------------------- 2:1 h-coarsening (Sec. 6 transfers)
+def _h_pair(dim, Pf, Pc, projection="interp"):
+    phys = ConvDiff([1.0] * dim, 0.01)
+    nf = (4, 6) if dim == 2 else (2, 4, 2)
+    nc = tuple(v // 2 for v in nf)
+    lf = sdc.DGLevel(phys, nf, [0.0] * dim, [1.0] * dim, Pf, 2)
+    lc = sdc.DGLevel(phys, nc, [0.0] * dim, [1.0] * dim, Pc, 2)
+    return lf, lc, sdc.SpaceTransferH(lf, lc, projection)
+
+
+@pytest.mark.parametrize("dim,Pf,Pc", [(2, 4, 2), (2, 6, 6), (3, 3, 2)])
+def test_h_transfer_reproduces_polynomials(dim, Pf, Pc):
+    """I maps a coarse element's polynomial onto its children exactly, and P
+    recovers a polynomial of coarse degree that is continuous across the
+    fused children; R is the transpose of I."""
+    lf, lc, tr = _h_pair(dim, Pf, Pc)
+    xf, xc = lf.coords(), lc.coords()
+    f = lambda x: (x[0] ** min(Pc, 2) + 0.5 * x[1] - (0.3 * x[2] if dim == 3 else 0.0))[None]
+    assert np.max(np.abs(tr.I(f(xc)) - f(xf))) < 1e-13
+    assert np.max(np.abs(tr.P(f(xf)) - f(xc))) < 1e-13
+    rng = np.random.default_rng(3)
+    r, v = rng.standard_normal(lf.shape()), rng.standard_normal(lc.shape())
+    assert abs(np.sum(tr.R(r) * v) - np.sum(r * tr.I(v))) < 1e-12 * np.sqrt(r.size)
+
+
+def test_h_projection_blends_the_jump_linearly():
+    """Children constant c_L = 1 and c_R = 3 along x: the blended pair is
+    linear from c_L at the outer left face through the mean at the shared
+    face to c_R, so the P_c = 2 coarse nodes (-1, 0, 1) along x get 1, 2, 3."""
+    lf, lc, tr = _h_pair(2, 3, 2)
+    u = np.ones(lf.shape())
+    ex = np.arange(lf.mesh.n[0]).reshape(1, 1, -1, 1, 1)          # x element index on axis elem_axis(0) = 2
+    u = np.where(ex % 2 == 0, 1.0, 3.0) * u
+    uc = tr.P(u)
+    expect = np.broadcast_to(np.array([1.0, 2.0, 3.0]).reshape(1, 1, 1, 1, 3), uc.shape)  # x nodes: last axis
+    np.testing.assert_allclose(uc, expect, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim,Pf,Pc", [(2, 4, 2), (2, 5, 5), (3, 3, 2)])
+def test_h_l2_projection_properties(dim, Pf, Pc):
+    lf, lc, tr = _h_pair(dim, Pf, Pc, "l2")
+    rng = np.random.default_rng(5)
+    vc = rng.standard_normal(lc.shape())
+    np.testing.assert_allclose(tr.P(tr.I(vc)), vc, atol=1e-12)
+    uf = rng.standard_normal(lf.shape())
+    assert abs(lc.dg.integral(tr.P(uf))[0] - lf.dg.integral(uf)[0]) < 1e-12 * np.abs(uf).sum()
+    mom = tr.R(lf.dg.Wm * (uf - tr.I(tr.P(uf))))
+    assert np.max(np.abs(mom)) < 1e-12
+
+
+def test_h_mlsdc_fixed_point_is_the_fine_collocation_solution():
+    """FAS with h- and p-coarsening keeps the fine collocation solution: many
+    V-cycles land on what many single-level sweeps give."""
+    phys = ConvDiff([1.0, 0.5], 0.02)
+    lf = sdc.DGLevel(phys, (4, 4), [0, 0], [1, 1], 4, 3, rtol=1e-14)
+    lc = sdc.DGLevel(phys, (2, 2), [0, 0], [1, 1], 3, 2, rtol=1e-14)
+    x = lf.coords()
+    u0 = (np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1]))[None]
+    dt = 0.02
+    ref = sdc.sdc_step(lf, u0, dt, 40)
+    ml = sdc.MLSDC([lc, lf], n_coarse=2, start="cascade", cycles=25, post_sweep=True)
+    got = ml.step(u0, dt)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
