@@ -148,6 +148,11 @@ typedef struct {
                           RADAU_RIGHT (default; Radau IIA, order 2M - 1) or
                           SISDC_NODES_LOBATTO (both end points, tau_1 = 0 so
                           u_1 = u_0; Lobatto IIIA, order 2M - 2; M >= 2)    */
+  int h_coarsen[3];    /* 1: level l has half the elements of level l - 1
+                          along every axis (2:1 h-coarsening, Sec. 6
+                          "MLSDC transfer operators"; the counts must be
+                          even; in 3-D the finer degree must be <= 6);
+                          h_coarsen[0] = 0                                   */
 } sisdc_method;
 
 typedef struct {

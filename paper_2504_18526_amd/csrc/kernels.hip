@@ -1230,6 +1230,89 @@ __global__ void k_lincomb(double* __restrict__ out, LinComb lc, long n, const do
   }
 }
 
+// One axis of a tensor-product transfer on an LDS grid: dst = A along axis
+// `ax` of src (n0 x n1 x n2, axis 0 fastest), A an (m x n_ax) row-major
+// matrix; dst is the same grid with n_ax replaced by m.
+__device__ void contract_axis(const double* src, double* dst, const double* A, int ax, int n0, int n1, int n2,
+                              int m) {
+  const int na = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int o0 = ax == 0 ? m : n0, o1 = ax == 1 ? m : n1, o2 = ax == 2 ? m : n2;
+  const int tot = o0 * o1 * o2;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int i0 = idx % o0, i1 = (idx / o0) % o1, i2 = idx / (o0 * o1);
+    const int r = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
+    double acc = 0.0;
+    for (int a = 0; a < na; ++a) {
+      const int j0 = ax == 0 ? a : i0, j1 = ax == 1 ? a : i1, j2 = ax == 2 ? a : i2;
+      acc += A[r * na + a] * src[(j2 * n1 + j1) * n0 + j0];
+    }
+    dst[idx] = acc;
+  }
+}
+
+// 2:1 h-coarsening transfer (p-coarsening on top): one block per (variable,
+// coarse element).  A is the 1-D matrix on an axis' pair of fine elements
+// (2 n1f nodes, left child first), applied along every axis:
+//   mode 0, fine -> coarse: A is (n1c x 2 n1f); the input is the 2^dim children
+//   mode 1, coarse -> fine: A is (2 n1f x n1c); the output is the 2^dim children
+// Fine element (2 cx + kx, 2 cy + ky, 2 cz + kz) is child (kx, ky, kz) of
+// coarse element (cx, cy, cz); its node i along an axis is node k n1f + i of
+// the pair.  The grid of a pair fits kHGrid doubles: (2 n1f)^dim <= kHGrid.
+constexpr int kHGrid = 2744;
+__global__ void k_space_transfer_h(const double* __restrict__ in, double* __restrict__ out, int dim, int n1f, int n1c,
+                                   int ncx, int ncy, int ncz, const double* __restrict__ A, int mode) {
+  __shared__ double sa[kHGrid], sb[kHGrid];
+  __shared__ double sA[2 * (kMaxP + 1) * (kMaxP + 1)];
+  const int Ec = ncx * ncy * ncz;
+  const int nfx = 2 * ncx, nfy = 2 * ncy;
+  const long Ef = (long)Ec << dim;
+  const int var = (int)(blockIdx.x / Ec), ec = (int)(blockIdx.x % Ec);
+  const int cx = ec % ncx, cy = (ec / ncx) % ncy, cz = ec / (ncx * ncy);
+  const int S = 2 * n1f;
+  const int ni = mode == 0 ? S : n1c, no = mode == 0 ? n1c : S;
+  const int npf = dim == 2 ? n1f * n1f : n1f * n1f * n1f;
+  const int npc = dim == 2 ? n1c * n1c : n1c * n1c * n1c;
+  for (int k = threadIdx.x; k < no * ni; k += blockDim.x) sA[k] = A[k];
+  const int nin = dim == 2 ? ni * ni : ni * ni * ni;
+  for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) {
+    if (mode == 0) {
+      const int X = idx % ni, Y = (idx / ni) % ni, Z = dim == 3 ? idx / (ni * ni) : 0;
+      const int kx = X / n1f, ky = Y / n1f, kz = Z / n1f;
+      const int ix = X - kx * n1f, iy = Y - ky * n1f, iz = Z - kz * n1f;
+      const long fe = (2 * cx + kx) + (long)nfx * ((2 * cy + ky) + (long)nfy * (2 * cz + kz));
+      const int node = ix + n1f * (iy + n1f * iz);
+      sa[idx] = in[((long)var * Ef + fe) * npf + node];
+    } else {
+      sa[idx] = in[((long)var * Ec + ec) * npc + idx];
+    }
+  }
+  __syncthreads();
+  const int n2 = dim == 3 ? ni : 1;
+  contract_axis(sa, sb, sA, 0, ni, ni, n2, no);
+  __syncthreads();
+  contract_axis(sb, sa, sA, 1, no, ni, n2, no);
+  __syncthreads();
+  const double* res = sa;
+  if (dim == 3) {
+    contract_axis(sa, sb, sA, 2, no, no, ni, no);
+    __syncthreads();
+    res = sb;
+  }
+  const int nout = dim == 2 ? no * no : no * no * no;
+  for (int idx = threadIdx.x; idx < nout; idx += blockDim.x) {
+    if (mode == 0) {
+      out[((long)var * Ec + ec) * npc + idx] = res[idx];
+    } else {
+      const int X = idx % no, Y = (idx / no) % no, Z = dim == 3 ? idx / (no * no) : 0;
+      const int kx = X / n1f, ky = Y / n1f, kz = Z / n1f;
+      const int ix = X - kx * n1f, iy = Y - ky * n1f, iz = Z - kz * n1f;
+      const long fe = (2 * cx + kx) + (long)nfx * ((2 * cy + ky) + (long)nfy * (2 * cz + kz));
+      const int node = ix + n1f * (iy + n1f * iz);
+      out[((long)var * Ef + fe) * npf + node] = res[idx];
+    }
+  }
+}
+
 // out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
 __global__ void k_space_transfer(const double* __restrict__ in, double* __restrict__ out, int dim,
                                  int n1i, int n1o, int E, const double* __restrict__ A) {
@@ -1722,6 +1805,19 @@ hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim,
                                  const double* A, hipStream_t s) {
   hipLaunchKernelGGL(k_space_transfer, dim3((unsigned)((long)nv * E)), dim3(256), 0, s, in, out, dim, n1i, n1o,
                      E, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_space_transfer_h(const double* in, double* out, int nv, int dim, int n1f, int n1c, const int* nc,
+                                   const double* A, int mode, hipStream_t s) {
+  const int S = 2 * n1f;
+  const long grid = dim == 2 ? (long)S * S : (long)S * S * S;
+  if (grid > kHGrid || n1f > kMaxP + 1 || n1c > kMaxP + 1 || n1c > S || (dim != 2 && dim != 3))
+    return hipErrorInvalidValue;
+  const int ncz = dim == 3 ? nc[2] : 1;
+  const long blocks = (long)nv * nc[0] * nc[1] * ncz;
+  hipLaunchKernelGGL(k_space_transfer_h, dim3((unsigned)blocks), dim3(256), 0, s, in, out, dim, n1f, n1c, nc[0],
+                     nc[1], ncz, A, mode);
   return hipGetLastError();
 }
 

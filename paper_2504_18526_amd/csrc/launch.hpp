@@ -56,6 +56,12 @@ SISDC_DECLARE_PRECISION_LAUNCHERS(float)
 hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
                        hipStream_t s);
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s);
+// 2:1 h-coarsening transfer between a fine level and the coarse level of
+// nc[0] x nc[1] (x nc[2]) elements; mode 0: fine -> coarse with A (n1c x 2 n1f),
+// mode 1: coarse -> fine with A (2 n1f x n1c).  hipErrorInvalidValue when a
+// pair of fine elements does not fit the kernel's grid ((2 n1f)^dim > 2744).
+hipError_t launch_space_transfer_h(const double* in, double* out, int nv, int dim, int n1f, int n1c, const int* nc,
+                                   const double* A, int mode, hipStream_t s);
 hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
                                  const double* A, hipStream_t s);
 // mixed precision: FP64 -> FP32 copy; r32 = b - Ax with (r,r), (b,b) summed

@@ -114,6 +114,8 @@ struct Level {
 };
 
 struct Transfer {  // between level i (fine) and i+1 (coarse)
+  bool h = false;        // 2:1 h-coarsened: Ix is (2 n1f x n1c), Px and Rx (n1c x 2 n1f) on a pair of
+                         // fine elements per axis (left child first)
   double* Ix = nullptr;  // (n1f x n1c) coarse -> fine
   double* Px = nullptr;  // (n1c x n1f) fine -> coarse
   double* Rx = nullptr;  // (n1c x n1f) = Ix^T
@@ -876,7 +878,18 @@ void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const do
 
 void space_transfer(sisdc_handle* h, const Level& from, const Level& to, const double* in, double* out,
                     const double* A) {
-  HIPCHECK(launch_space_transfer(in, out, from.nv, from.g.dim, from.n1, to.n1, from.E, A, h->stream));
+  if (from.E == to.E) {
+    HIPCHECK(launch_space_transfer(in, out, from.nv, from.g.dim, from.n1, to.n1, from.E, A, h->stream));
+    return;
+  }
+  const int dim = from.g.dim;
+  if (from.E == (to.E << dim)) {  // fine -> coarse over 2:1 h-coarsening
+    HIPCHECK(launch_space_transfer_h(in, out, from.nv, dim, from.n1, to.n1, to.g.ne, A, 0, h->stream));
+  } else if (to.E == (from.E << dim)) {  // coarse -> fine
+    HIPCHECK(launch_space_transfer_h(in, out, from.nv, dim, to.n1, from.n1, from.g.ne, A, 1, h->stream));
+  } else {
+    fail(SISDC_EINVAL, "internal: levels are not related by 2:1 h-coarsening");
+  }
 }
 
 // FAS restriction from fine level i to coarse level i+1 (Alg. 2, residual
@@ -1053,14 +1066,14 @@ void do_step(sisdc_handle* h, double dt) {
 }
 
 // ------------------------------------------------------------------ setup
-void build_level(sisdc_handle* h, Level& L, int P, int M) {
+void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
   const sisdc_problem& pr = h->prob;
   L.P = P;
   L.M = M;
   L.n1 = P + 1;
   L.np = pr.dim == 2 ? L.n1 * L.n1 : L.n1 * L.n1 * L.n1;
   L.E = 1;
-  for (int d = 0; d < pr.dim; ++d) L.E *= pr.n_elem[d];
+  for (int d = 0; d < pr.dim; ++d) L.E *= ne[d];
   L.nv = h->eq.nv;
   L.vs = (long)L.E * L.np;
   L.vlen = L.vs * L.nv;
@@ -1073,8 +1086,8 @@ void build_level(sisdc_handle* h, Level& L, int P, int M) {
   g.E = L.E;
   g.J = 1.0;
   for (int d = 0; d < 3; ++d) {
-    g.ne[d] = d < pr.dim ? pr.n_elem[d] : 1;
-    g.h[d] = d < pr.dim ? (pr.hi[d] - pr.lo[d]) / pr.n_elem[d] : 1.0;
+    g.ne[d] = d < pr.dim ? ne[d] : 1;
+    g.h[d] = d < pr.dim ? (pr.hi[d] - pr.lo[d]) / ne[d] : 1.0;
     g.rh2[d] = 2.0 / g.h[d];
     if (d < pr.dim) g.J *= 0.5 * g.h[d];
   }
@@ -1219,13 +1232,69 @@ std::vector<double> l2_projection(const std::vector<double>& I, const std::vecto
   return B;
 }
 
+// 2:1 h-coarsening, one axis, on the pair of fine elements that a coarse
+// element fuses (2 n1f nodes, left child first; reference coordinates
+// xi_c = (xi_f - 1)/2 on the left child, (xi_f + 1)/2 on the right):
+//   I (2 n1f x n1c): each child evaluates the coarse polynomial at its nodes;
+//   P (n1c x 2 n1f), embedded interpolation: a coarse node takes the value of
+//     the child that holds it, after the jump J between the children (right
+//     child's shared-face value minus the left's) is blended away linearly:
+//     + J/2 (xi_c + 1) on the left child, - J/2 (1 - xi_c) on the right, so
+//     the shared centre gets the mean of both;
+//   P, L^2: (I^T W I)^-1 I^T W, W = diag(w_f / 2, w_f / 2).
+void h_transfer_tables(const Level& F, const Level& Cc, int projection, std::vector<double>& I,
+                       std::vector<double>& P) {
+  const int nf = F.n1, nc = Cc.n1;
+  std::vector<double> tl(nf), tr(nf);
+  for (int i = 0; i < nf; ++i) {
+    tl[i] = 0.5 * (F.xg[i] - 1.0);
+    tr[i] = 0.5 * (F.xg[i] + 1.0);
+  }
+  const std::vector<double> Il = lagrange(Cc.xg, tl), Ir = lagrange(Cc.xg, tr);  // (nf x nc) each
+  I.assign(2 * nf * nc, 0.0);
+  for (int i = 0; i < nf; ++i)
+    for (int j = 0; j < nc; ++j) {
+      I[i * nc + j] = Il[i * nc + j];
+      I[(nf + i) * nc + j] = Ir[i * nc + j];
+    }
+  if (projection == SISDC_PROJ_L2) {
+    std::vector<double> w2(2 * nf);
+    for (int i = 0; i < nf; ++i) w2[i] = w2[nf + i] = 0.5 * F.wg[i];
+    P = l2_projection(I, w2, 2 * nf, nc);
+    return;
+  }
+  P.assign(nc * 2 * nf, 0.0);
+  for (int j = 0; j < nc; ++j) {
+    const double x = Cc.xg[j];
+    double* row = &P[j * 2 * nf];
+    if (x == 0.0) {  // the shared centre
+      row[nf - 1] += 0.5;
+      row[nf] += 0.5;
+      continue;
+    }
+    const std::vector<double> t{x < 0.0 ? 2.0 * x + 1.0 : 2.0 * x - 1.0};
+    const std::vector<double> l = lagrange(F.xg, t);  // (1 x nf)
+    const int off = x < 0.0 ? 0 : nf;
+    for (int i = 0; i < nf; ++i) row[off + i] = l[i];
+    const double phi = x < 0.0 ? 0.5 * (x + 1.0) : -0.5 * (1.0 - x);  // weight of J
+    row[nf] += phi;
+    row[nf - 1] -= phi;
+  }
+}
+
 void build_transfer(Transfer& T, const Level& F, const Level& Cc, int projection, int formulation) {
-  std::vector<double> I = lagrange(Cc.xg, F.xg);   // (n1f x n1c)
-  std::vector<double> P = projection == SISDC_PROJ_L2 ? l2_projection(I, F.wg, F.n1, Cc.n1)
-                                                      : lagrange(F.xg, Cc.xg);  // (n1c x n1f)
-  std::vector<double> R(Cc.n1 * F.n1);
-  for (int i = 0; i < F.n1; ++i)
-    for (int j = 0; j < Cc.n1; ++j) R[j * F.n1 + i] = I[i * Cc.n1 + j];
+  T.h = Cc.E != F.E;
+  const int nfi = T.h ? 2 * F.n1 : F.n1;  // fine-side length of the 1-D operators
+  std::vector<double> I, P;
+  if (T.h) {
+    h_transfer_tables(F, Cc, projection, I, P);
+  } else {
+    I = lagrange(Cc.xg, F.xg);  // (n1f x n1c)
+    P = projection == SISDC_PROJ_L2 ? l2_projection(I, F.wg, F.n1, Cc.n1) : lagrange(F.xg, Cc.xg);  // (n1c x n1f)
+  }
+  std::vector<double> R(Cc.n1 * nfi);
+  for (int i = 0; i < nfi; ++i)
+    for (int j = 0; j < Cc.n1; ++j) R[j * nfi + i] = I[i * Cc.n1 + j];
   T.Ix = dalloc(I.size());
   T.Px = dalloc(P.size());
   T.Rx = dalloc(R.size());
@@ -1278,6 +1347,19 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->projection != SISDC_PROJ_INTERP && m->projection != SISDC_PROJ_L2) fail(SISDC_EINVAL, "projection");
   if (m->formulation != SISDC_INCREMENTAL && m->formulation != SISDC_NONINCREMENTAL) fail(SISDC_EINVAL, "formulation");
   if (m->nodes != SISDC_NODES_RADAU_RIGHT && m->nodes != SISDC_NODES_LOBATTO) fail(SISDC_EINVAL, "nodes");
+  if (m->h_coarsen[0] != 0) fail(SISDC_EINVAL, "h_coarsen[0] must be 0 (the finest level is not coarsened)");
+  {
+    int ne[3] = {p->n_elem[0], p->n_elem[1], p->dim == 3 ? p->n_elem[2] : 1};
+    for (int l = 1; l < m->n_levels; ++l) {
+      if (m->h_coarsen[l] != 0 && m->h_coarsen[l] != 1) fail(SISDC_EINVAL, "h_coarsen must be 0 or 1");
+      if (!m->h_coarsen[l]) continue;
+      for (int d = 0; d < p->dim; ++d) {
+        if (ne[d] % 2 != 0) fail(SISDC_EINVAL, "h-coarsening needs an even number of elements along every axis");
+        ne[d] /= 2;
+      }
+      if (p->dim == 3 && m->P[l - 1] > 6) fail(SISDC_EINVAL, "3-D h-coarsening supports fine degrees up to 6");
+    }
+  }
   if (m->nodes == SISDC_NODES_LOBATTO)
     for (int l = 0; l < m->n_levels; ++l)
       if (m->M[l] < 2) fail(SISDC_EINVAL, "Lobatto nodes need M >= 2 on every level");
@@ -1403,7 +1485,12 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->eq.mu = prob->eq == SISDC_EQ_NS ? prob->mu : 0.0;
     h->eq.lam_T = prob->eq == SISDC_EQ_NS ? prob->mu * (prob->gamma * h->eq.R / (prob->gamma - 1.0)) / prob->Pr : 0.0;
     h->lv.resize(meth->n_levels);
-    for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l]);
+    // elements per axis of each level: halved where the level is 2:1 h-coarsened
+    int ne[3][3];
+    for (int d = 0; d < 3; ++d) ne[0][d] = d < prob->dim ? prob->n_elem[d] : 1;
+    for (int l = 1; l < meth->n_levels; ++l)
+      for (int d = 0; d < 3; ++d) ne[l][d] = (meth->h_coarsen[l] && d < prob->dim) ? ne[l - 1][d] / 2 : ne[l - 1][d];
+    for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l], ne[l]);
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
     for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1], meth->projection, meth->formulation);
     h->partials = dalloc((size_t)7 * kElemCap);

@@ -57,7 +57,7 @@ class Method(ctypes.Structure):
                 ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int),
-                ("nodes", ctypes.c_int)]
+                ("nodes", ctypes.c_int), ("h_coarsen", ctypes.c_int * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -198,7 +198,8 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, 
 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
                 n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
-                inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT):
+                inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT,
+                h_coarsen=None):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -218,6 +219,8 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.projection = projection
     m.formulation = formulation
     m.nodes = nodes
+    for i, v in enumerate(h_coarsen or []):
+        m.h_coarsen[i] = int(v)
     return m
 
 

@@ -12,7 +12,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import sdc as osdc
-from oracle.sdc import DGLevel, SpaceTransfer, MLSDC
+from oracle.sdc import DGLevel, SpaceTransfer, SpaceTransferH, MLSDC
 from oracle import solve as osolve
 from helpers import rel_l2, oracle_phys, lib_problem, random_state, smooth_state
 
@@ -530,6 +530,97 @@ def test_lobatto_needs_two_nodes(S):
     prob = lib_problem(S, "convdiff", 2, (2, 2), [0.0, 0.0], [1.0, 1.0], nu=0.01)
     with pytest.raises(S.SisdcError, match="Lobatto"):
         S.Solver(prob, S.make_method([4, 2], [3, 1], nodes=S.NODES_LOBATTO))
+
+
+# ---------------------------------------------------------------- 2:1 h-coarsening
+def make_pair_h(S, eq, dim, n, Ps, Ms, hc, lo=None, hi=None, nu=0.01, **meth):
+    """Levels whose element counts halve where hc[l] = 1 (h_coarsen)."""
+    lo = lo if lo is not None else [0.0] * dim
+    hi = hi if hi is not None else [1.0 + 0.25 * d for d in range(dim)]
+    phys = oracle_phys(eq, dim, nu=nu)
+    ns, cur = [], list(n)
+    for l in range(len(Ps)):
+        if hc[l]:
+            cur = [v // 2 for v in cur]
+        ns.append(tuple(cur))
+    levels = [DGLevel(phys, nl, lo, hi, P, M, rtol=1e-14) for nl, P, M in zip(ns, Ps, Ms)]
+    prob = lib_problem(S, eq, dim, n, lo, hi, nu=nu)
+    m = S.make_method(list(Ps), list(Ms), cg_rtol=1e-14, cg_maxit=5000, h_coarsen=list(hc), **meth)
+    return phys, levels, S.Solver(prob, m)
+
+
+@pytest.mark.parametrize("dim,n,Pf,Pc,proj", [(2, (4, 6), 8, 4, "interp"), (2, (4, 2), 5, 5, "interp"),
+                                              (2, (6, 4), 6, 3, "l2"), (3, (2, 4, 2), 4, 2, "interp"),
+                                              (3, (2, 2, 4), 6, 6, "l2")])
+def test_h_transfers(S, dim, n, Pf, Pc, proj):
+    phys, (lf, lc), sv = make_pair_h(S, "convdiff", dim, n, [Pf, Pc], [3, 2], [0, 1],
+                                     projection=S.PROJ_L2 if proj == "l2" else S.PROJ_INTERP)
+    E, Np, nv, M = sv.level_info(1)
+    assert E == lc.mesh.E
+    tr = SpaceTransferH(lf, lc, proj)
+    rng = np.random.default_rng(41)
+    Xf = rng.standard_normal(lf.shape())
+    Xc = rng.standard_normal(lc.shape())
+    oc = torch.empty(Xc.size, dtype=torch.float64, device="cuda")
+    of = torch.empty(Xf.size, dtype=torch.float64, device="cuda")
+    sv.apply(S.OP_PROJECT, 0, dev(Xf.ravel()), oc)
+    assert rel_l2(host(oc), tr.P(Xf)) < TOL
+    sv.apply(S.OP_RESTRICT, 0, dev(Xf.ravel()), oc)
+    assert rel_l2(host(oc), tr.R(Xf)) < TOL
+    sv.apply(S.OP_INTERP, 0, dev(Xc.ravel()), of)
+    assert rel_l2(host(of), tr.I(Xc)) < TOL
+
+
+@pytest.mark.parametrize("case", ["burgers_2l", "convdiff_2l_h_only", "euler_3l_fmg", "ns_3d_2l"])
+def test_h_coarsened_steps(S, case):
+    """Multilevel steps with 2:1 h-coarsening (and p-coarsening on top)."""
+    if case == "burgers_2l":
+        args = dict(eq="burgers", dim=2, n=(4, 4), Ps=[8, 4], Ms=[5, 3], hc=[0, 1], n_iter=3, nu=5e-3,
+                    start=S.START_CASCADE)
+        dt = 5e-3
+    elif case == "convdiff_2l_h_only":
+        args = dict(eq="convdiff", dim=2, n=(4, 6), Ps=[4, 4], Ms=[3, 3], hc=[0, 1], n_iter=3, start=S.START_CASCADE)
+        dt = 1e-2
+    elif case == "euler_3l_fmg":
+        args = dict(eq="euler", dim=2, n=(8, 8), Ps=[4, 4, 2], Ms=[5, 3, 2], hc=[0, 1, 0], n_iter=2,
+                    start=S.START_FMG, lo=[0, 0], hi=[10, 10])
+        dt = 0.05
+    else:
+        args = dict(eq="ns", dim=3, n=(2, 4, 2), Ps=[4, 2], Ms=[3, 2], hc=[0, 1], n_iter=2, start=S.START_CASCADE,
+                    lo=[0, 0, 0], hi=[2 * np.pi] * 3)
+        dt = 4e-3
+    eq, dim = args["eq"], args["dim"]
+    phys, levels, sv = make_pair_h(S, eq, dim, args["n"], args["Ps"], args["Ms"], args["hc"], lo=args.get("lo"),
+                                   hi=args.get("hi"), nu=args.get("nu", 0.01), n_iter=args["n_iter"],
+                                   start=args["start"])
+    fine = levels[0]
+    if eq == "euler":
+        from paper_2504_18526_amd.inputs import isentropic_vortex
+        u = isentropic_vortex(fine.coords())
+    elif eq == "ns":
+        from paper_2504_18526_amd.inputs import taylor_green
+        u = taylor_green(fine.coords(), mach=0.1)
+    else:
+        u = smooth_state(phys, fine, np.random.default_rng(75))
+    name = {S.START_CASCADE: "cascade", S.START_FMG: "fmg"}[args["start"]]
+    ml = MLSDC(list(reversed(levels)), n_coarse=2, start=name, cycles=args["n_iter"], post_sweep=True)
+    sv.set_state(dev(u.ravel()))
+    out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    for k in range(2):
+        st = sv.step(dt)
+        u = ml.step(u, dt)
+        sv.get_state(out)
+        assert rel_l2(host(out), u) < TOL, (case, k)
+        assert st["not_converged"] == 0
+
+
+def test_h_coarsening_validation(S):
+    prob = lib_problem(S, "convdiff", 2, (3, 4), [0.0, 0.0], [1.0, 1.0], nu=0.01)
+    with pytest.raises(S.SisdcError, match="even"):
+        S.Solver(prob, S.make_method([4, 2], [3, 2], h_coarsen=[0, 1]))
+    prob = lib_problem(S, "convdiff", 3, (2, 2, 2), [0.0] * 3, [1.0] * 3, nu=0.01)
+    with pytest.raises(S.SisdcError, match="degrees up to 6"):
+        S.Solver(prob, S.make_method([7, 3], [3, 2], h_coarsen=[0, 1]))
 
 
 # ---------------------------------------------------------------- persistent PCG
