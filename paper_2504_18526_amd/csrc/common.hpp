@@ -80,6 +80,14 @@ struct LinComb {
   int n;
 };
 
+// Up to 8 outputs from the same up to 8 vectors, node-wise:
+// out[o] = sum_j c[o][j] x_j, each output vlen apart from the previous.
+struct LinCombMulti {
+  const double* x[8];
+  double c[8][8];
+  int nin, nout;
+};
+
 struct PCGArgs {
   const double* b;  // right-hand side, or null: then b = bl at every node
   LinComb bl;       // the right-hand side as a combination of vectors (used when b is null)

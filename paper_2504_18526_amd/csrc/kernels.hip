@@ -846,7 +846,7 @@ template <typename T, int P>
 __global__ void __launch_bounds__((ISO2<P>::NT))
 k_sipg_apply_iso2(const T* __restrict__ x, const T* __restrict__ isc, T* __restrict__ out, int nv, long vs, T nu,
                   T alpha, T beta, T ctau, Geo g, const T* __restrict__ tab, T* part,
-                  const int* __restrict__ done_gen, int id) {
+                  const int* __restrict__ done_gen, int id, const T* __restrict__ addv) {
   using I = ISO2<P>;
   constexpr int N1 = I::N1, LG = I::LG, SY = I::SY, REG = I::REG;
   if (done_gen != nullptr && *done_gen == id) return;
@@ -892,8 +892,10 @@ k_sipg_apply_iso2(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
     const T ja = J * wa;
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const T val = alpha * ja * w[k] * xl[k] + beta * (r[k] + R[a + SY * k]);
-      out[c * vs + (long)e * I::NP + line_node2<1, N1>(k, a)] = val;
+      const long oi = c * vs + (long)e * I::NP + line_node2<1, N1>(k, a);
+      T val = alpha * ja * w[k] * xl[k] + beta * (r[k] + R[a + SY * k]);
+      if (addv != nullptr) val = addv[oi] + val;
+      out[oi] = val;
       dacc += val * xl[k];
     }
     wave_lds_fence();
@@ -1313,6 +1315,23 @@ __global__ void k_space_transfer_h(const double* __restrict__ in, double* __rest
   }
 }
 
+// Several combinations of the same vectors in one pass: each input is read
+// once (the node quadrature q_m = sum_i S_{m,i} f_i for all m at once).
+__global__ void k_lincomb_multi(double* __restrict__ out, LinCombMulti lc, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double xv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xv[j] = j < lc.nin ? lc.x[j][i] : 0.0;
+    for (int o = 0; o < lc.nout; ++o) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < lc.nin) s += lc.c[o][j] * xv[j];
+      out[(long)o * n + i] = s;
+    }
+  }
+}
+
 // out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
 __global__ void k_space_transfer(const double* __restrict__ in, double* __restrict__ out, int dim,
                                  int n1i, int n1o, int E, const double* __restrict__ A) {
@@ -1564,7 +1583,7 @@ static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, co
                            vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
       else
         hipLaunchKernelGGL((k_sipg_apply_iso2<T, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const T*)nullptr, out, nv,
-                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id, (const T*)nullptr);
       return hipGetLastError();
     }
   }
@@ -1701,7 +1720,7 @@ static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const Co
                        alpha, beta, ctau, g, tab, part, done_gen, id);
   else
     hipLaunchKernelGGL((k_sipg_apply_iso2<T, P>), dim3(nb), dim3(ISO2<P>::NT), 0, s, x, isc, out, nv, vs, cf.nu,
-                       alpha, beta, ctau, g, tab, part, done_gen, id);
+                       alpha, beta, ctau, g, tab, part, done_gen, id, (const T*)nullptr);
   return hipGetLastError();
 }
 
@@ -1805,6 +1824,32 @@ hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim,
                                  const double* A, hipStream_t s) {
   hipLaunchKernelGGL(k_space_transfer, dim3((unsigned)((long)nv * E)), dim3(256), 0, s, in, out, dim, n1i, n1o,
                      E, A);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t iso2_add_p(const double* x, const double* add, double* out, int nv, const CoefT<double>& cf,
+                             double alpha, double beta, double ctau, const Geo& g, const double* tab, hipStream_t s) {
+  using K = IsoKernel<double, 2, P>;
+  const long vs = (long)g.E * (P + 1) * (P + 1);
+  const long groups = ((long)nv * g.E + K::GPB - 1) / K::GPB;
+  const int nbi = (int)std::min<long>(std::max<long>(groups, 1), 8192);
+  hipLaunchKernelGGL((k_sipg_apply_iso2<double, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const double*)nullptr, out,
+                     nv, vs, cf.nu, alpha, beta, ctau, g, tab, (double*)nullptr, (const int*)nullptr, 0, add);
+  return hipGetLastError();
+}
+
+hipError_t launch_sipg_iso2_add(const double* x, const double* add, double* out, int nv, const CoefT<double>& cf,
+                                double alpha, double beta, double ctau, const Geo& g, const double* tab,
+                                hipStream_t s) {
+  if (g.dim != 2 || !iso_path_t<double>(g, cf)) return hipErrorInvalidValue;
+  SISDC_DISPATCH_P(g.P, return (iso2_add_p<PP>(x, add, out, nv, cf, alpha, beta, ctau, g, tab, s)));
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lincomb_multi(double* out, const LinCombMulti& lc, long n, hipStream_t s) {
+  if (lc.nin < 1 || lc.nin > 8 || lc.nout < 1 || lc.nout > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lincomb_multi, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n);
   return hipGetLastError();
 }
 

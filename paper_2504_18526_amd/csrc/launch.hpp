@@ -56,6 +56,14 @@ SISDC_DECLARE_PRECISION_LAUNCHERS(float)
 hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
                        hipStream_t s);
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s);
+// out = add + alpha M x + beta K_{nu I} x on quadrilaterals with isotropic
+// constant D (the 2-D isotropic matvec with an added vector; add must not
+// overlap out); hipErrorInvalidValue where that kernel does not apply.
+hipError_t launch_sipg_iso2_add(const double* x, const double* add, double* out, int nv, const CoefT<double>& cf,
+                                double alpha, double beta, double ctau, const Geo& g, const double* tab,
+                                hipStream_t s);
+// out[o * n + i] = sum_j lc.c[o][j] lc.x[j][i], o < lc.nout, j < lc.nin (<= 8 each).
+hipError_t launch_lincomb_multi(double* out, const LinCombMulti& lc, long n, hipStream_t s);
 // 2:1 h-coarsening transfer between a fine level and the coarse level of
 // nc[0] x nc[1] (x nc[2]) elements; mode 0: fine -> coarse with A (n1c x 2 n1f),
 // mode 1: coarse -> fine with A (2 n1f x n1c).  hipErrorInvalidValue when a

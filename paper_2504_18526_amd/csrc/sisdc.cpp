@@ -294,6 +294,11 @@ bool has_physical_diffusion(sisdc_handle* h) { return !is_system(h) && h->eq.nu 
 // Cu = C(u) precomputed
 void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double* Cu, double* f) {
   if (has_physical_diffusion(h)) {
+    // quadrilaterals: f = C - K_nu u in one pass of the isotropic kernel
+    if (L.g.dim == 2 && f != Cu && launch_sipg_iso2_add(u, Cu, f, L.nv, coef_nu(h), 0.0, -1.0, h->ctau, L.g, L.tab, h->stream) ==
+                            hipSuccess)
+      return;
+    (void)hipGetLastError();
     sipg(h, L, coef_nu(h), u, L.t3, 0.0, 1.0);
     lincomb(h, L, f, {{1.0, Cu}, {-1.0, L.t3}});
     return;
@@ -787,8 +792,18 @@ void ensure_stored(sisdc_handle* h, Level& L, double dt) {
   L.stored_dt = dt;
 }
 
-// q_m = sum_i S_{m,i} f_i, S = dt w^nn, for m = 1..M
+// q_m = sum_i S_{m,i} f_i, S = dt w^nn, for m = 1..M (one pass over the f_i)
 void quadrature(sisdc_handle* h, Level& L, double dt) {
+  if (L.M <= 8) {
+    LinCombMulti lc{};
+    lc.nin = L.M;
+    lc.nout = L.M;
+    for (int i = 0; i < L.M; ++i) lc.x[i] = L.f + (long)i * L.vlen;
+    for (int m = 0; m < L.M; ++m)
+      for (int i = 0; i < L.M; ++i) lc.c[m][i] = dt * L.wnn[m * L.M + i];
+    HIPCHECK(launch_lincomb_multi(L.q, lc, L.vlen, h->stream));
+    return;
+  }
   for (int m = 0; m < L.M; ++m) {
     std::vector<double> c;
     std::vector<const double*> x;
