@@ -382,7 +382,9 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
         }
       }
       loc[c] = act ? jw * xo + a.dtm * r : 0.0;
-      __syncthreads();
+      // sQ is rewritten next by apply_faces, after the barrier's own
+      // __syncthreads; only a second component reuses it at once
+      if (NV > 1) __syncthreads();
     }
   };
   auto apply_faces = [&](double (&out)[NV], const double (&loc)[NV]) __attribute__((always_inline)) {
@@ -422,7 +424,10 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
         }
       }
       out[c] = act ? loc[c] + a.dtm * r : 0.0;
-      __syncthreads();
+      // sQ is rewritten next by apply_local, after the __syncthreads of the
+      // publish that precedes it (sx is read here at this thread's own node
+      // only); only a second component reuses it at once
+      if (NV > 1) __syncthreads();
     }
   };
 
