@@ -85,8 +85,13 @@ template <int K, typename F>
 __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned long long* rec, long cap,
                             unsigned* abort_w, unsigned tag, long spin_limit, int* s_ok, F&& overlap) {
   static_assert(K >= 1 && K <= 8, "a record holds up to 8 values");
-  __shared__ double sred[K][16];
-  __shared__ double stot[K][16];
+  // LDS sums by barrier parity (tag & 1): a barrier rewrites the ones of the
+  // barrier two before it, which every thread has left by the first
+  // __syncthreads of the barrier in between, so none is needed at the end
+  __shared__ double sred2[2][K][16];
+  __shared__ double stot2[2][K][16];
+  double (&sred)[K][16] = sred2[tag & 1u];
+  double (&stot)[K][16] = stot2[tag & 1u];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   for (int k = 0; k < K; ++k) {
     const double x = wave_sum63(v[k]);
@@ -148,9 +153,7 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
     for (int w = 0; w < nw; ++w) sb += stot[k][w];
     tot[k] = sb;
   }
-  const bool res = *s_ok != 0;
-  __syncthreads();
-  return res;
+  return *s_ok != 0;
 }
 
 __device__ __forceinline__ int nbr(const Geo& g, int e, int d, int s) {
@@ -181,7 +184,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   __shared__ double sx[NV * EPB * NP];
   __shared__ double sQ[EPB * DIM * NP];
   __shared__ double sc[EPB * NP];
-  __shared__ int s_ok;
+  __shared__ int s_ok[2];  // barrier outcome, by barrier parity (see sync_reduce)
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
@@ -464,7 +467,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
   // published vector into `loc` while it waits; advances the tag and the
   // face-buffer parity
   auto barrier1 = [&](const double (&v)[1], double (&tt)[1], double (&loc)[NV]) -> bool {
-    const bool r = sync_reduce<1>(v, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+    const bool r = sync_reduce<1>(v, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok[(a.tag0 + gen) & 1u],
                                   [&]() __attribute__((always_inline)) {
                                     apply_local(loc);
                                     prefetch_faces();
@@ -519,7 +522,7 @@ k_pcg_persistent(PCGArgs a, CoefP cf, Geo g, const double* __restrict__ tab) {
     const double v3[3] = {g_l, d_l, r_l};
     double tt[3];
     double nloc[NV];
-    ok = sync_reduce<3>(v3, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok,
+    ok = sync_reduce<3>(v3, tt, rec(), a.cap, abort_w, a.tag0 + gen, a.spin_limit, &s_ok[(a.tag0 + gen) & 1u],
                         [&]() __attribute__((always_inline)) {
                           apply_local(nloc);
                           prefetch_faces();
