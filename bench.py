@@ -39,7 +39,7 @@ COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 MEASURED_TRAFFIC = {
     # profiles/hbm_traffic_pcg_persistent_burgers2d_32x32_P8-4.md (timed-region dispatches)
     ("burgers2d_mlsdc_32x32_P8-4_M5-3", "k_pcg_persistent<2,8,1>"):
-        {"fetch_kib": 17016.58, "write_kib": 54680.72, "src": "f32c1805114272cf"},
+        {"fetch_kib": 16682.61, "write_kib": 53996.72, "src": "7e44882243c3472f"},
 }
 TRAFFIC_SOURCES = {
     "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],
