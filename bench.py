@@ -333,7 +333,7 @@ def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates, start):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (the sharded design is described, not run)"}))
         sys.exit(2)
     import numpy as np
     import torch
