@@ -623,6 +623,38 @@ def test_h_coarsening_validation(S):
         S.Solver(prob, S.make_method([7, 3], [3, 2], h_coarsen=[0, 1]))
 
 
+# ---------------------------------------------------------------- options together
+@pytest.mark.parametrize("scheme", ["si2", "eu"])
+def test_all_method_options_together(S, scheme):
+    """Lobatto nodes, the zero-to-node form, the L^2 projection and 2:1
+    h-coarsening on top of p-coarsening, all in one three-level FMG run."""
+    dim, n, Ps, Ms, hc = 2, (8, 4), [5, 4, 2], [4, 3, 2], [0, 1, 0]
+    lo, hi, nu, dt = [0.0, 0.0], [1.0, 1.25], 0.01, 1e-2
+    phys = oracle_phys("burgers", dim, nu=nu)
+    ns, cur = [], list(n)
+    for l in range(3):
+        if hc[l]:
+            cur = [v // 2 for v in cur]
+        ns.append(tuple(cur))
+    levels = [DGLevel(phys, nl, lo, hi, P, M, rtol=1e-14, nodes="lobatto") for nl, P, M in zip(ns, Ps, Ms)]
+    prob = lib_problem(S, "burgers", dim, n, lo, hi, nu=nu)
+    m = S.make_method(Ps, Ms, start=S.START_FMG, n_iter=2, cg_rtol=1e-14, cg_maxit=5000, h_coarsen=hc,
+                      nodes=S.NODES_LOBATTO, formulation=S.NONINCREMENTAL, projection=S.PROJ_L2,
+                      integrator=S.IMEX_EULER if scheme == "eu" else S.SI2)
+    sv = S.Solver(prob, m)
+    u = smooth_state(phys, levels[0], np.random.default_rng(76))
+    ml = MLSDC(list(reversed(levels)), scheme=scheme, n_coarse=2, start="fmg", cycles=2, post_sweep=True,
+               projection="l2", formulation="nonincremental")
+    sv.set_state(dev(u.ravel()))
+    out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    for k in range(2):
+        st = sv.step(dt)
+        u = ml.step(u, dt)
+        sv.get_state(out)
+        assert rel_l2(host(out), u) < TOL, (scheme, k)
+        assert st["not_converged"] == 0
+
+
 # ---------------------------------------------------------------- persistent PCG
 # The one-launch pipelined PCG runs at production tolerances (rtol >= 1e-11).
 # Its iterates differ from the oracle's exact solve by at most about
