@@ -99,7 +99,7 @@ typedef struct {
 typedef struct {
   int n_levels;        /* 1..3                                              */
   int P[3];            /* polynomial degree per level (index 0 finest), 1..8 */
-  int M[3];            /* Radau-right nodes per level, 1..8                 */
+  int M[3];            /* collocation nodes per level, 1..8 (see nodes)    */
   int integrator;      /* SISDC_SI2 (default), SISDC_SI1, or SISDC_IMEX_EULER
                           (eq. H_IMEX: the one-stage form with the physical
                           diffusion alone implicit, nu I for the scalar
