@@ -258,10 +258,13 @@ int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_
  *   SISDC_OP_PROJECT out(level+1) = P_x in(level)       (space, fine->coarse)
  *   SISDC_OP_INTERP  out(level)   = I_x in(level+1)     (space, coarse->fine)
  *   SISDC_OP_RESTRICT out(level+1) = I_x^T in(level)    (space, fine->coarse)
- * All vectors are single nodal vectors of the named level. */
+ *   SISDC_OP_QUAD    out[m] = sum_i S_{m,i} in[i], S = dt_m w^nn (eq.
+ *                    nn_weights; dt_m here is the step dt): in and out hold
+ *                    M nodal vectors each ([m][var][elem][node], nodes 1..M)
+ * All other vectors are single nodal vectors of the named level. */
 enum { SISDC_OP_MASS = 0, SISDC_OP_CONV = 1, SISDC_OP_FRHS = 2, SISDC_OP_SIPG = 3,
        SISDC_OP_HELM = 4, SISDC_OP_PROJECT = 5, SISDC_OP_INTERP = 6,
-       SISDC_OP_RESTRICT = 7 };
+       SISDC_OP_RESTRICT = 7, SISDC_OP_QUAD = 8 };
 int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* in,
                 const double* aux, double* out, int mem);
 

@@ -1808,6 +1808,20 @@ int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* i
   return guard([&] {
     Level& L = level_at(h, level);
     if (!in || !out) fail(SISDC_EINVAL, "null in or out");
+    if (op == SISDC_OP_QUAD) {  // the node quadrature over M vectors (L.q is scratch between sweeps)
+      const long n = (long)L.M * L.vlen;
+      const double* din = dev_in(h, in, n, mem, h->io);
+      double* dout = mem == SISDC_MEM_DEVICE ? out : L.q;
+      LinCombMulti lc{};
+      lc.nin = L.M;
+      lc.nout = L.M;
+      for (int i = 0; i < L.M; ++i) lc.x[i] = din + (long)i * L.vlen;
+      for (int m = 0; m < L.M; ++m)
+        for (int i = 0; i < L.M; ++i) lc.c[m][i] = dt_m * L.wnn[m * L.M + i];
+      HIPCHECK(launch_lincomb_multi(dout, lc, L.vlen, h->stream));
+      dev_out(h, out, dout, n, mem);
+      return;
+    }
     const bool down = op == SISDC_OP_PROJECT || op == SISDC_OP_RESTRICT;
     const bool up = op == SISDC_OP_INTERP;
     if ((down || up) && level + 1 >= (int)h->lv.size()) fail(SISDC_EINVAL, "transfer needs level+1");

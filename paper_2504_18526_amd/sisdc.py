@@ -24,7 +24,7 @@ NODES_RADAU_RIGHT, NODES_LOBATTO = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
 FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2
-OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT = range(8)
+OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT, OP_QUAD = range(9)
 
 EXPORTS = [
     "sisdc_last_error", "sisdc_create", "sisdc_destroy", "sisdc_level_info",

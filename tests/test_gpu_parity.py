@@ -532,6 +532,26 @@ def test_lobatto_needs_two_nodes(S):
         S.Solver(prob, S.make_method([4, 2], [3, 1], nodes=S.NODES_LOBATTO))
 
 
+@pytest.mark.parametrize("nodes", ["radau", "lobatto"])
+@pytest.mark.parametrize("M", [2, 3, 5, 8])
+def test_node_quadrature(S, M, nodes):
+    """q_m = dt sum_i w^nn_{m,i} f_i for all m (eq. nn_weights), host and device buffers."""
+    nd = S.NODES_LOBATTO if nodes == "lobatto" else S.NODES_RADAU_RIGHT
+    phys, (lv,), sv = make_pair(S, "burgers", 2, (3, 2), [4], [M], nodes=nd)
+    rng = np.random.default_rng(60 + M)
+    F = [None] + [rng.standard_normal(lv.shape()) for _ in range(M)]
+    dt = 0.037
+    ref = osdc.quadrature(lv, F, dt)
+    f = np.concatenate([F[i].ravel() for i in range(1, M + 1)])
+    got_d = torch.empty(f.size, dtype=torch.float64, device="cuda")
+    sv.apply(S.OP_QUAD, 0, dev(f), got_d, dt_m=dt)
+    got_h = np.empty(f.size)
+    sv.apply(S.OP_QUAD, 0, f, got_h, dt_m=dt)
+    want = np.concatenate([ref[m].ravel() for m in range(1, M + 1)])
+    assert rel_l2(host(got_d), want) < TOL
+    assert np.array_equal(host(got_d), got_h)
+
+
 # ---------------------------------------------------------------- 2:1 h-coarsening
 def make_pair_h(S, eq, dim, n, Ps, Ms, hc, lo=None, hi=None, nu=0.01, **meth):
     """Levels whose element counts halve where hc[l] = 1 (h_coarsen)."""
