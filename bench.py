@@ -39,7 +39,7 @@ COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 MEASURED_TRAFFIC = {
     # profiles/hbm_traffic_pcg_persistent_burgers2d_32x32_P8-4.md (timed-region dispatches)
     ("burgers2d_mlsdc_32x32_P8-4_M5-3", "k_pcg_persistent<2,8,1>"):
-        {"fetch_kib": 16682.61, "write_kib": 53996.72, "src": "7e44882243c3472f"},
+        {"fetch_kib": 16682.61, "write_kib": 53996.72, "src": "28d11f9c758d9d1a"},
 }
 TRAFFIC_SOURCES = {
     "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],
@@ -51,13 +51,22 @@ TRAFFIC_SOURCES = {
 }
 
 
+def strip_comments(src):
+    """C++ source without its comments and blank-line differences: the digest
+    follows the code the counters measured, not its wording."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def kernel_source_digest(kernel):
     import hashlib
     h = hashlib.sha256()
     base = kernel.split("<")[0]
     for f in TRAFFIC_SOURCES[base]:
-        with open(os.path.join(ROOT, "paper_2504_18526_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2504_18526_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -11,7 +11,12 @@
 // barrier.  The only data that leave a workgroup are the face values and
 // face traces (D grad m) of its elements and three partial sums; they are
 // written with device-scope stores and read with device-scope loads (both go
-// through to the point of coherence; no L2 write-back is needed).  When the
+// through to the point of coherence; no L2 write-back is needed), each
+// 64-bit word carrying 32 bits of a value and the 32-bit tag of its barrier,
+// so a reader validates what it loads and no flag or store ordering is
+// needed.  The volume part of the next matvec and the loads of the
+// neighbours' face words run while a barrier waits.  The right-hand side is
+// given, or formed at every node from up to eight vectors.  When the
 // recurred residual meets the tolerance the true residual b - A x is
 // computed; if it misses the tolerance (the recurrences drifted), r, u and w
 // are replaced by their true values and the iteration continues.  The
