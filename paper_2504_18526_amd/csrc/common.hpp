@@ -88,6 +88,18 @@ struct LinCombMulti {
   int nin, nout;
 };
 
+// A space-time transfer in one launch: for output node o < nout,
+// y[o] = [y[o] +] X(sum_j c[o][j] x[j]), X the tensor-product space map of
+// one element; y2[o], when set, receives the same values.
+constexpr int kTransferIn = 16, kTransferOut = 8;
+struct TransferMulti {
+  const double* x[kTransferIn];
+  double c[kTransferOut][kTransferIn];
+  double* y[kTransferOut];
+  double* y2[kTransferOut];
+  int nin, nout, accumulate;
+};
+
 struct PCGArgs {
   const double* b;  // right-hand side, or null: then b = bl at every node
   LinComb bl;       // the right-hand side as a combination of vectors (used when b is null)

@@ -1333,6 +1333,31 @@ __global__ void k_lincomb_multi(double* __restrict__ out, LinCombMulti lc, long 
 }
 
 // out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
+// Output node o of the tensor-product map (A x A [x A]) applied to one
+// element's nodal values sin_ (n1i per direction, x fastest).
+__device__ __forceinline__ double tp_map(const double* sA, const double* sin_, int o, int dim, int n1i, int n1o) {
+  const int ox = o % n1o, oy = (o / n1o) % n1o, oz = dim == 3 ? o / (n1o * n1o) : 0;
+  double s = 0.0;
+  if (dim == 2) {
+    for (int b = 0; b < n1i; ++b) {
+      double t = 0.0;
+      for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[b * n1i + a];
+      s += sA[oy * n1i + b] * t;
+    }
+  } else {
+    for (int c = 0; c < n1i; ++c) {
+      double tc = 0.0;
+      for (int b = 0; b < n1i; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[(c * n1i + b) * n1i + a];
+        tc += sA[oy * n1i + b] * t;
+      }
+      s += sA[oz * n1i + c] * tc;
+    }
+  }
+  return s;
+}
+
 __global__ void k_space_transfer(const double* __restrict__ in, double* __restrict__ out, int dim,
                                  int n1i, int n1o, int E, const double* __restrict__ A) {
   __shared__ double sA[(kMaxP + 1) * (kMaxP + 1)];
@@ -1343,27 +1368,33 @@ __global__ void k_space_transfer(const double* __restrict__ in, double* __restri
   for (int k = threadIdx.x; k < n1i * n1o; k += blockDim.x) sA[k] = A[k];
   for (int k = threadIdx.x; k < npi; k += blockDim.x) sin_[k] = in[blk * npi + k];
   __syncthreads();
+  for (int o = threadIdx.x; o < npo; o += blockDim.x) out[blk * npo + o] = tp_map(sA, sin_, o, dim, n1i, n1o);
+}
+
+// Space-time transfer, one block per (component, element) and output node:
+// the node's time combination of the inputs is formed in LDS, then mapped in
+// space. Inputs and outputs belong to levels with the same elements.
+__global__ void k_space_time_transfer(TransferMulti t, int dim, int n1i, int n1o, const double* __restrict__ A) {
+  __shared__ double sA[(kMaxP + 1) * (kMaxP + 1)];
+  __shared__ double sin_[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
+  const int npi = dim == 2 ? n1i * n1i : n1i * n1i * n1i;
+  const int npo = dim == 2 ? n1o * n1o : n1o * n1o * n1o;
+  const long blk = blockIdx.x;  // (var, e)
+  const int mo = blockIdx.y;
+  for (int k = threadIdx.x; k < n1i * n1o; k += blockDim.x) sA[k] = A[k];
+  for (int k = threadIdx.x; k < npi; k += blockDim.x) {
+    double v = 0.0;
+    for (int j = 0; j < t.nin; ++j) v += t.c[mo][j] * t.x[j][blk * npi + k];
+    sin_[k] = v;
+  }
+  __syncthreads();
+  double* const y = t.y[mo];
+  double* const y2 = t.y2[mo];
   for (int o = threadIdx.x; o < npo; o += blockDim.x) {
-    const int ox = o % n1o, oy = (o / n1o) % n1o, oz = dim == 3 ? o / (n1o * n1o) : 0;
-    double s = 0.0;
-    if (dim == 2) {
-      for (int b = 0; b < n1i; ++b) {
-        double t = 0.0;
-        for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[b * n1i + a];
-        s += sA[oy * n1i + b] * t;
-      }
-    } else {
-      for (int c = 0; c < n1i; ++c) {
-        double tc = 0.0;
-        for (int b = 0; b < n1i; ++b) {
-          double t = 0.0;
-          for (int a = 0; a < n1i; ++a) t += sA[ox * n1i + a] * sin_[(c * n1i + b) * n1i + a];
-          tc += sA[oy * n1i + b] * t;
-        }
-        s += sA[oz * n1i + c] * tc;
-      }
-    }
-    out[blk * npo + o] = s;
+    double v = tp_map(sA, sin_, o, dim, n1i, n1o);
+    if (t.accumulate) v += y[blk * npo + o];
+    y[blk * npo + o] = v;
+    if (y2) y2[blk * npo + o] = v;
   }
 }
 
@@ -1817,6 +1848,16 @@ hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g
 
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_space_time_transfer(const TransferMulti& t, int nv, int dim, int n1i, int n1o, int E,
+                                      const double* A, hipStream_t s) {
+  if (t.nin < 1 || t.nin > kTransferIn || t.nout < 1 || t.nout > kTransferOut || n1i > kMaxP + 1 ||
+      n1o > kMaxP + 1 || (dim != 2 && dim != 3))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_space_time_transfer, dim3((unsigned)((long)nv * E), (unsigned)t.nout), dim3(256), 0, s, t,
+                     dim, n1i, n1o, A);
   return hipGetLastError();
 }
 

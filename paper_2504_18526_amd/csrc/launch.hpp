@@ -72,6 +72,11 @@ hipError_t launch_space_transfer_h(const double* in, double* out, int nv, int di
                                    const double* A, int mode, hipStream_t s);
 hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
                                  const double* A, hipStream_t s);
+// y[o] = [y[o] +] X(sum_j c[o][j] x[j]) for o < t.nout, X the map A per
+// direction; the two levels have the same E elements. Invalid counts return
+// hipErrorInvalidValue before any launch.
+hipError_t launch_space_time_transfer(const TransferMulti& t, int nv, int dim, int n1i, int n1o, int E,
+                                      const double* A, hipStream_t s);
 // mixed precision: FP64 -> FP32 copy; r32 = b - Ax with (r,r), (b,b) summed
 // into tot[0..1] (FP64); x += e
 hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);

@@ -876,8 +876,10 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
   L.stored_dt = dt;
 }
 
-// F_m(u) = M (u_m - u_{m-1}) - q_m(u) into out[m-1]
-void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const double* g_minus) {
+// F_m(u) = M (u_m - u_{m-1}) - q_m(u) into out[m-1]; with g_minus, g_m - F_m(u);
+// with negate (and no g_minus), -F_m(u)
+void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const double* g_minus,
+                     bool negate = false) {
   ensure_stored(h, L, dt);
   quadrature(h, L, dt);
   for (int m = 1; m <= L.M; ++m) {
@@ -886,6 +888,8 @@ void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const do
     if (g_minus)  // r = g - F
       lincomb(h, L, o, {{1.0, g_minus + (long)(m - 1) * L.vlen}, {-1.0, L.um(m)}, {1.0, L.um(m - 1)}, {1.0, qm}},
               {0, 1, 1, 0});
+    else if (negate)
+      lincomb(h, L, o, {{-1.0, L.um(m)}, {1.0, L.um(m - 1)}, {1.0, qm}}, {1, 1, 0});
     else
       lincomb(h, L, o, {{1.0, L.um(m)}, {-1.0, L.um(m - 1)}, {-1.0, qm}}, {1, 1, 0});
   }
@@ -907,19 +911,40 @@ void space_transfer(sisdc_handle* h, const Level& from, const Level& to, const d
   }
 }
 
+// Space-time transfer in one launch when both levels have the same elements
+// and the node counts fit; false otherwise (the caller then transfers node by
+// node).
+bool st_transfer(sisdc_handle* h, const Level& from, const Level& to, const TransferMulti& t, const double* A) {
+  if (from.E != to.E) return false;
+  HIPCHECK(launch_space_time_transfer(t, from.nv, from.g.dim, from.n1, to.n1, from.E, A, h->stream));
+  return true;
+}
+
+bool st_fits(int nin, int nout) { return nin <= kTransferIn && nout <= kTransferOut; }
+
 // FAS restriction from fine level i to coarse level i+1 (Alg. 2, residual
 // evaluation, solution restriction and RHS composition).
 void restrict_fas(sisdc_handle* h, int i, double dt) {
   Level& F = h->lv[i];
   Level& Cc = h->lv[i + 1];
   Transfer& T = h->tr[i];
-  colloc_residual(h, F, dt, F.r, F.has_g ? F.gf : nullptr);
-  if (!F.has_g) {  // r = 0 - F(u)
-    for (int m = 0; m < F.M; ++m) lincomb(h, F, F.r + (long)m * F.vlen, {{-1.0, F.r + (long)m * F.vlen}});
-  }
-  // v_c = (P_t x P_x) u_f, v_c[0] = coarse u_0
+  colloc_residual(h, F, dt, F.r, F.has_g ? F.gf : nullptr, true);  // r = g - F(u), g = 0 on the top level
+  // v_c = (P_t x P_x) u_f, v_c[0] = coarse u_0; u_c <- v_c
   copy_d2d(h, Cc.v, Cc.um(0), Cc.vlen);
-  for (int mc = 0; mc < Cc.M; ++mc) {
+  const bool one_launch = F.E == Cc.E && st_fits(F.M, Cc.M);
+  if (one_launch) {
+    TransferMulti t{};
+    t.nin = F.M;
+    t.nout = Cc.M;
+    for (int j = 0; j < F.M; ++j) t.x[j] = F.um(j + 1);
+    for (int mc = 0; mc < Cc.M; ++mc) {
+      for (int j = 0; j < F.M; ++j) t.c[mc][j] = T.Pt[mc * F.M + j];
+      t.y[mc] = Cc.v + (long)(mc + 1) * Cc.vlen;
+      t.y2[mc] = Cc.um(mc + 1);
+    }
+    st_transfer(h, F, Cc, t, T.Px);
+  }
+  for (int mc = 0; mc < Cc.M && !one_launch; ++mc) {
     std::vector<double> c;
     std::vector<const double*> x;
     for (int j = 0; j < F.M; ++j) {
@@ -929,12 +954,24 @@ void restrict_fas(sisdc_handle* h, int i, double dt) {
     lincomb_v(h, F, F.t1, c, x, {});
     space_transfer(h, F, Cc, F.t1, Cc.v + (long)(mc + 1) * Cc.vlen, T.Px);
   }
-  // u_c <- v_c, then g_c = F_c(v_c) + R r_f
-  copy_d2d(h, Cc.u, Cc.v, (long)(Cc.M + 1) * Cc.vlen);
+  // g_c = F_c(v_c) + R r_f
+  if (!one_launch) copy_d2d(h, Cc.u, Cc.v, (long)(Cc.M + 1) * Cc.vlen);
   Cc.stale = true;
   Cc.has_g = false;
   colloc_residual(h, Cc, dt, Cc.gf, nullptr);
-  for (int mc = 0; mc < Cc.M; ++mc) {
+  if (one_launch) {
+    TransferMulti t{};
+    t.nin = F.M;
+    t.nout = Cc.M;
+    t.accumulate = 1;
+    for (int i2 = 0; i2 < F.M; ++i2) t.x[i2] = F.r + (long)i2 * F.vlen;
+    for (int mc = 0; mc < Cc.M; ++mc) {
+      for (int i2 = 0; i2 < F.M; ++i2) t.c[mc][i2] = T.Rt[mc * F.M + i2];
+      t.y[mc] = Cc.gf + (long)mc * Cc.vlen;
+    }
+    st_transfer(h, F, Cc, t, T.Rx);
+  }
+  for (int mc = 0; mc < Cc.M && !one_launch; ++mc) {
     std::vector<double> c;
     std::vector<const double*> x;
     for (int i2 = 0; i2 < F.M; ++i2) {
@@ -954,6 +991,26 @@ void prolong_correction(sisdc_handle* h, int i) {
   Level& F = h->lv[i];
   Level& Cc = h->lv[i + 1];
   Transfer& T = h->tr[i];
+  if (F.E == Cc.E && st_fits(2 * Cc.M, F.M)) {
+    TransferMulti t{};
+    t.nin = 2 * Cc.M;
+    t.nout = F.M;
+    t.accumulate = 1;
+    for (int j = 0; j < Cc.M; ++j) {
+      t.x[2 * j] = Cc.um(j + 1);
+      t.x[2 * j + 1] = Cc.v + (long)(j + 1) * Cc.vlen;
+    }
+    for (int mf = 0; mf < F.M; ++mf) {
+      for (int j = 0; j < Cc.M; ++j) {
+        t.c[mf][2 * j] = T.It[mf * Cc.M + j];
+        t.c[mf][2 * j + 1] = -T.It[mf * Cc.M + j];
+      }
+      t.y[mf] = F.um(mf + 1);
+    }
+    st_transfer(h, Cc, F, t, T.Ix);
+    F.stale = true;
+    return;
+  }
   for (int mf = 0; mf < F.M; ++mf) {
     std::vector<double> c;
     std::vector<const double*> x;
@@ -975,6 +1032,19 @@ void interpolate_up(sisdc_handle* h, int i) {
   Level& F = h->lv[i];
   Level& Cc = h->lv[i + 1];
   Transfer& T = h->tr[i];
+  if (F.E == Cc.E && st_fits(Cc.M, F.M)) {
+    TransferMulti t{};
+    t.nin = Cc.M;
+    t.nout = F.M;
+    for (int j = 0; j < Cc.M; ++j) t.x[j] = Cc.um(j + 1);
+    for (int mf = 0; mf < F.M; ++mf) {
+      for (int j = 0; j < Cc.M; ++j) t.c[mf][j] = T.It[mf * Cc.M + j];
+      t.y[mf] = F.um(mf + 1);
+    }
+    st_transfer(h, Cc, F, t, T.Ix);
+    F.stale = true;
+    return;
+  }
   for (int mf = 0; mf < F.M; ++mf) {
     std::vector<double> c;
     std::vector<const double*> x;
