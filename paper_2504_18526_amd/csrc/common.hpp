@@ -88,6 +88,19 @@ struct LinCombMulti {
   int nin, nout;
 };
 
+// The collocation residual of a level in one launch, for m = 1..M:
+// out[m-1] = [g[m-1] +] sign (mw (u_m - u_{m-1}) - sum_i S[m-1][i] f[i]),
+// u holding M+1 node vectors, f, g and out M, each vlen apart.
+struct CollocResid {
+  const double* u;
+  const double* f;
+  const double* g;  // or null
+  double* out;
+  double S[8][8];
+  int M;
+  double sign;
+};
+
 // A space-time transfer in one launch: for output node o < nout,
 // y[o] = [y[o] +] X(sum_j c[o][j] x[j]), X the tensor-product space map of
 // one element; y2[o], when set, receives the same values.

@@ -1332,6 +1332,28 @@ __global__ void k_lincomb_multi(double* __restrict__ out, LinCombMulti lc, long 
   }
 }
 
+// Collocation residual of all nodes in one pass over u, f (and g).
+__global__ void k_colloc_residual(CollocResid c, long n, const double* __restrict__ mw, int np) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double w = mw[i % np];
+    double fv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fv[j] = j < c.M ? c.f[(long)j * n + i] : 0.0;
+    double prev = c.u[i];
+    for (int m = 1; m <= c.M; ++m) {
+      const double cur = c.u[(long)m * n + i];
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < c.M) q += c.S[m - 1][j] * fv[j];
+      double r = c.sign * (w * (cur - prev) - q);
+      if (c.g) r += c.g[(long)(m - 1) * n + i];
+      c.out[(long)(m - 1) * n + i] = r;
+      prev = cur;
+    }
+  }
+}
+
 // out[var][e][o] = sum_{a,b,c} A[ox][a] A[oy][b] A[oz][c] in[var][e][(a,b,c)]
 // Output node o of the tensor-product map (A x A [x A]) applied to one
 // element's nodal values sin_ (n1i per direction, x fastest).
@@ -1848,6 +1870,12 @@ hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g
 
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
   hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, out, lc, n, mw, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_colloc_residual(const CollocResid& c, long n, const double* mw, int np, hipStream_t s) {
+  if (c.M < 1 || c.M > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_colloc_residual, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, c, n, mw, np);
   return hipGetLastError();
 }
 

@@ -72,6 +72,10 @@ hipError_t launch_space_transfer_h(const double* in, double* out, int nv, int di
                                    const double* A, int mode, hipStream_t s);
 hipError_t launch_space_transfer(const double* in, double* out, int nv, int dim, int n1i, int n1o, int E,
                                  const double* A, hipStream_t s);
+// The collocation residual of a level (all M nodes) in one pass; mw holds the
+// np diagonal mass weights of one element. M outside 1..8 returns
+// hipErrorInvalidValue before any launch.
+hipError_t launch_colloc_residual(const CollocResid& c, long n, const double* mw, int np, hipStream_t s);
 // y[o] = [y[o] +] X(sum_j c[o][j] x[j]) for o < t.nout, X the map A per
 // direction; the two levels have the same E elements. Invalid counts return
 // hipErrorInvalidValue before any launch.

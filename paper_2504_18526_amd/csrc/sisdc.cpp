@@ -881,6 +881,19 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
 void colloc_residual(sisdc_handle* h, Level& L, double dt, double* out, const double* g_minus,
                      bool negate = false) {
   ensure_stored(h, L, dt);
+  if (L.M <= 8) {
+    CollocResid c{};
+    c.u = L.u;
+    c.f = L.f;
+    c.g = g_minus;
+    c.out = out;
+    c.M = L.M;
+    c.sign = (g_minus || negate) ? -1.0 : 1.0;
+    for (int m = 0; m < L.M; ++m)
+      for (int i = 0; i < L.M; ++i) c.S[m][i] = dt * L.wnn[m * L.M + i];
+    HIPCHECK(launch_colloc_residual(c, L.vlen, L.mw, L.np, h->stream));
+    return;
+  }
   quadrature(h, L, dt);
   for (int m = 1; m <= L.M; ++m) {
     double* o = out + (long)(m - 1) * L.vlen;
