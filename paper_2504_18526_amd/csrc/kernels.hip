@@ -150,6 +150,8 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
   constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sf[EPB * NV * NP];
+  u += (long)blockIdx.y * NV * vs;  // node blockIdx.y of a batch of node vectors
+  out += (long)blockIdx.y * NV * vs;
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
   const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = (le < EPB) && (e < g.E);
@@ -1575,22 +1577,24 @@ int reduce_grid(const Geo& g) { return std::min(elem_tile_count(g), kElemCap); }
 
 template <int DIM, int P>
 static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
-                             hipStream_t s) {
+                             int nodes, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  if (q.nv == 1)
-    hipLaunchKernelGGL((k_conv<DIM, P, 1>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+  const dim3 grid(elem_tiles<DIM, P>(g), nodes);
+  if (nodes < 1)
+    return hipErrorInvalidValue;
+  else if (q.nv == 1)
+    hipLaunchKernelGGL((k_conv<DIM, P, 1>), grid, dim3(L::NT), 0, s, u, out, g, q, tab, vs);
   else if (q.nv == DIM + 2)
-    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, g, q,
-                       tab, vs);
+    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), grid, dim3(L::NT), 0, s, u, out, g, q, tab, vs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
-                       hipStream_t s) {
-  SISDC_DISPATCH(g, conv_dim_p, u, out, g, q, tab, s);
+                       hipStream_t s, int nodes) {
+  SISDC_DISPATCH(g, conv_dim_p, u, out, g, q, tab, nodes, s);
 }
 
 template <typename T, int DIM, int P>

@@ -13,8 +13,10 @@ namespace sisdc {
 // sum all partials in every block)
 constexpr int kElemCap = 512;
 
+// out = C(u) for `nodes` consecutive node vectors of u (each nv * E * np
+// values) into the same number of consecutive vectors of out
 hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q, const double* tab,
-                       hipStream_t s);
+                       hipStream_t s, int nodes = 1);
 // The SIPG and PCG launchers exist for double (FP64 path) and float (the
 // inner solves of the mixed-precision path).
 #define SISDC_DECLARE_PRECISION_LAUNCHERS(T)                                                                    \

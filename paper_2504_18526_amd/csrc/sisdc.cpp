@@ -278,8 +278,8 @@ CoefP coef_nu(sisdc_handle* h) {
   return c;
 }
 
-void conv(sisdc_handle* h, const Level& L, const double* in, double* out) {
-  HIPCHECK(launch_conv(in, out, L.g, h->eq, L.tab, h->stream));
+void conv(sisdc_handle* h, const Level& L, const double* in, double* out, int nodes = 1) {
+  HIPCHECK(launch_conv(in, out, L.g, h->eq, L.tab, h->stream, nodes));
 }
 
 void sipg(sisdc_handle* h, const Level& L, const CoefP& cf, const double* x, double* out, double alpha,
@@ -782,10 +782,16 @@ sisdc_solve_stats solve_lc(sisdc_handle* h, Level& L, const CoefP& cf, double dt
 // the f of sweep k-1 are kept).
 void ensure_stored(sisdc_handle* h, Level& L, double dt) {
   if (!L.stale && L.stored_dt == dt) return;
-  for (int m = 0; m <= L.M; ++m) conv(h, L, L.um(m), L.C + (long)m * L.vlen);
+  conv(h, L, L.um(0), L.C, L.M + 1);  // all nodes in one launch (node vectors are consecutive)
+  // f_m = C_m - K_nu u_m of all nodes in one launch where the isotropic kernel
+  // applies: the M node vectors act as M nv independent components
+  const bool f_batched = has_physical_diffusion(h) && L.g.dim == 2 &&
+                         launch_sipg_iso2_add(L.um(1), L.C + L.vlen, L.f, L.nv * L.M, coef_nu(h), 0.0, -1.0, h->ctau,
+                                              L.g, L.tab, h->stream) == hipSuccess;
+  if (!f_batched) (void)hipGetLastError();
   for (int m = 1; m <= L.M; ++m) {
     const double dtm = dt * L.dtau[m - 1];
-    frhs_from_c(h, L, L.um(m), L.C + (long)m * L.vlen, L.f + (long)(m - 1) * L.vlen);
+    if (!f_batched) frhs_from_c(h, L, L.um(m), L.C + (long)m * L.vlen, L.f + (long)(m - 1) * L.vlen);
     sipg(h, L, coef_for(h, L, dtm, L.um(m - 1)), L.um(m), L.X + (long)(m - 1) * L.vlen, 0.0, 1.0);
   }
   L.stale = false;
