@@ -930,13 +930,12 @@ void space_transfer(sisdc_handle* h, const Level& from, const Level& to, const d
   }
 }
 
-// Space-time transfer in one launch when both levels have the same elements
-// and the node counts fit; false otherwise (the caller then transfers node by
-// node).
-bool st_transfer(sisdc_handle* h, const Level& from, const Level& to, const TransferMulti& t, const double* A) {
-  if (from.E != to.E) return false;
+// Space-time transfer in one launch between levels with the same elements
+// (the callers check st_fits and the element counts first, and otherwise
+// transfer node by node).
+void st_transfer(sisdc_handle* h, const Level& from, const Level& to, const TransferMulti& t, const double* A) {
+  if (from.E != to.E) fail(SISDC_EINVAL, "internal: one-launch transfer between different meshes");
   HIPCHECK(launch_space_time_transfer(t, from.nv, from.g.dim, from.n1, to.n1, from.E, A, h->stream));
-  return true;
 }
 
 bool st_fits(int nin, int nout) { return nin <= kTransferIn && nout <= kTransferOut; }
