@@ -39,7 +39,7 @@ COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 MEASURED_TRAFFIC = {
     # profiles/hbm_traffic_pcg_persistent_burgers2d_32x32_P8-4.md (timed-region dispatches)
     ("burgers2d_mlsdc_32x32_P8-4_M5-3", "k_pcg_persistent<2,8,1>"):
-        {"fetch_kib": 16691.24, "write_kib": 53996.72, "src": "dd0416aef38a10a3"},
+        {"fetch_kib": 16690.32, "write_kib": 53996.72, "src": "4118bc0ba6c77eb1"},
 }
 TRAFFIC_SOURCES = {
     "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],

@@ -40,12 +40,15 @@ namespace sisdc {
 
 namespace {
 
+// Tile of one workgroup: EPB whole elements, one node per thread, up to 512
+// threads; elements of at most 32 nodes take 256-thread tiles, since the grid
+// barrier's latency, not the workgroup count, bounds those small levels.
 template <int DIM, int P>
 struct PT {
   static constexpr int N1 = P + 1;
   static constexpr int NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
   static constexpr int NF = DIM == 2 ? N1 : N1 * N1;
-  static constexpr int EPB = NP >= 512 ? 1 : 512 / NP;
+  static constexpr int EPB = NP >= 512 ? 1 : (NP <= 32 ? 256 : 512) / NP;
   static constexpr int NT = ((EPB * NP + 63) / 64) * 64;
   static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
 };
