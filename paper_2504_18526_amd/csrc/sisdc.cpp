@@ -961,19 +961,20 @@ void restrict_fas(sisdc_handle* h, int i, double dt) {
       t.y2[mc] = Cc.um(mc + 1);
     }
     st_transfer(h, F, Cc, t, T.Px);
-  }
-  for (int mc = 0; mc < Cc.M && !one_launch; ++mc) {
-    std::vector<double> c;
-    std::vector<const double*> x;
-    for (int j = 0; j < F.M; ++j) {
-      c.push_back(T.Pt[mc * F.M + j]);
-      x.push_back(F.um(j + 1));
+  } else {
+    for (int mc = 0; mc < Cc.M; ++mc) {
+      std::vector<double> c;
+      std::vector<const double*> x;
+      for (int j = 0; j < F.M; ++j) {
+        c.push_back(T.Pt[mc * F.M + j]);
+        x.push_back(F.um(j + 1));
+      }
+      lincomb_v(h, F, F.t1, c, x, {});
+      space_transfer(h, F, Cc, F.t1, Cc.v + (long)(mc + 1) * Cc.vlen, T.Px);
     }
-    lincomb_v(h, F, F.t1, c, x, {});
-    space_transfer(h, F, Cc, F.t1, Cc.v + (long)(mc + 1) * Cc.vlen, T.Px);
+    copy_d2d(h, Cc.u, Cc.v, (long)(Cc.M + 1) * Cc.vlen);
   }
   // g_c = F_c(v_c) + R r_f
-  if (!one_launch) copy_d2d(h, Cc.u, Cc.v, (long)(Cc.M + 1) * Cc.vlen);
   Cc.stale = true;
   Cc.has_g = false;
   colloc_residual(h, Cc, dt, Cc.gf, nullptr);
@@ -988,18 +989,19 @@ void restrict_fas(sisdc_handle* h, int i, double dt) {
       t.y[mc] = Cc.gf + (long)mc * Cc.vlen;
     }
     st_transfer(h, F, Cc, t, T.Rx);
-  }
-  for (int mc = 0; mc < Cc.M && !one_launch; ++mc) {
-    std::vector<double> c;
-    std::vector<const double*> x;
-    for (int i2 = 0; i2 < F.M; ++i2) {
-      c.push_back(T.Rt[mc * F.M + i2]);
-      x.push_back(F.r + (long)i2 * F.vlen);
+  } else {
+    for (int mc = 0; mc < Cc.M; ++mc) {
+      std::vector<double> c;
+      std::vector<const double*> x;
+      for (int i2 = 0; i2 < F.M; ++i2) {
+        c.push_back(T.Rt[mc * F.M + i2]);
+        x.push_back(F.r + (long)i2 * F.vlen);
+      }
+      lincomb_v(h, F, F.t1, c, x, {});
+      space_transfer(h, F, Cc, F.t1, Cc.t1, T.Rx);
+      double* gm = Cc.gf + (long)mc * Cc.vlen;
+      lincomb(h, Cc, gm, {{1.0, gm}, {1.0, Cc.t1}});
     }
-    lincomb_v(h, F, F.t1, c, x, {});
-    space_transfer(h, F, Cc, F.t1, Cc.t1, T.Rx);
-    double* gm = Cc.gf + (long)mc * Cc.vlen;
-    lincomb(h, Cc, gm, {{1.0, gm}, {1.0, Cc.t1}});
   }
   Cc.has_g = true;
 }
