@@ -42,7 +42,10 @@ MLSDC:incremental:residual):
 Transfers (Sec. 4 "MLSDC transfer operators", Sec. 6 "MLSDC transfer
 operators"): space-time products of 1-D Lagrange interpolation matrices,
 I = I_t (x) I_x, P = P_t (x) P_x (embedded interpolation), R = I^T.
-V-cycle: Alg. 2; cascade start: Alg. 3; FMG start: Alg. 4.
+V-cycle: Alg. 2; cascade start: Alg. 3; FMG start: Alg. 4 with C_fmg V-cycles
+per added level; the constant start spreads u_0 to every node of every level
+and the predictor start runs the SI predictor on every level (Sec. 4,
+"Multilevel algorithm").
 """
 import numpy as np
 
@@ -512,6 +515,10 @@ class MLSDC:
         if self.start == "predictor":
             for i in range(L):
                 self.U[i] = predictor(self.levels[i], self.u0[i], dt, self.params, self.scheme)
+            return
+        if self.start == "constant":                                  # u_0 spread to every node
+            for i in range(L):
+                self.U[i] = [self.u0[i]] * (self.levels[i].tt.M + 1)
             return
         self.U[0] = predictor(self.levels[0], self.u0[0], dt, self.params, self.scheme)
         if L == 1:

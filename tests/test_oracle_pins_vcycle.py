@@ -112,3 +112,51 @@ def test_hand_steps_converge_to_radau_iia_m2():
         R = hand_two_level(z, "si2", 60, True)
         pade = (1 + z / 3) / (1 - 2 * z / 3 + z * z / 6)
         assert abs(R - pade) < 1e-12
+
+
+def pade(z, m, n):
+    """(m, n) Pade approximant of e^z (closed form)."""
+    from math import factorial
+    N = sum(factorial(m + n - j) * factorial(m) / (factorial(m + n) * factorial(j) * factorial(m - j)) * z ** j
+            for j in range(m + 1))
+    D = sum(factorial(m + n - j) * factorial(n) / (factorial(m + n) * factorial(j) * factorial(n - j)) * (-z) ** j
+            for j in range(n + 1))
+    return N / D
+
+
+@pytest.mark.parametrize("z", ZS[:2])
+def test_fmg_start_with_many_cycles_solves_the_middle_level(z):
+    """Alg. 4 with C_fmg V-cycles on the two coarsest levels of three: as
+    C_fmg grows, the middle level reaches its own collocation solution (a
+    two-level V-cycle with g = 0 on its top level has it as fixed point): at
+    its last node the (M-1, M) Pade approximant of e^z for M = 3 Radau nodes.
+    One cycle per level is not yet there, so the pin sees C_fmg."""
+    ml = dahlquist.mlsdc(z.real, z.imag, [2, 3, 5], start="fmg", cycles=0, post_sweep=False, c_fmg=40,
+                         scheme="si2", n_coarse=2)
+    ml.set_initial(np.complex128(1.0), None)
+    ml.start_levels(1.0)
+    assert abs(ml.U[1][-1] - pade(z, 2, 3)) < 1e-12
+    one = dahlquist.mlsdc(z.real, z.imag, [2, 3, 5], start="fmg", cycles=0, post_sweep=False, c_fmg=1,
+                          scheme="si2", n_coarse=2)
+    one.set_initial(np.complex128(1.0), None)
+    one.start_levels(1.0)
+    assert abs(one.U[1][-1] - pade(z, 2, 3)) > 1e-6   # one cycle per level is not yet converged
+
+
+def test_constant_start_spreads_u0_and_converges():
+    """The constant start puts u_0 on every node of every level; V-cycles from
+    it converge to the fine collocation solution (Radau IIA, the (M-1, M) Pade
+    approximant), and it needs at least as many cycles as the predictor start
+    for a given accuracy (Sec. 7, test 4 observes one more)."""
+    z = -1.0 + 0.8j
+    ml = dahlquist.mlsdc(z.real, z.imag, [2, 3], start="constant", cycles=0, post_sweep=False)
+    ml.set_initial(np.complex128(1.0), None)
+    ml.start_levels(1.0)
+    for i in range(2):
+        assert all(u == 1.0 for u in ml.U[i])
+    assert abs(dahlquist.amplification_mlsdc(z, [2, 3], 40, start="constant") - pade(z, 2, 3)) < 1e-12
+    errs = {}
+    for start in ("constant", "predictor"):
+        errs[start] = [abs(dahlquist.amplification_mlsdc(z, [2, 3], c, start=start) - pade(z, 2, 3))
+                       for c in range(1, 6)]
+    assert sum(errs["constant"]) > sum(errs["predictor"])
