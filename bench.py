@@ -1,19 +1,21 @@
 """Throughput of the SI-MLSDC / DG-SEM hot path on one MI355X.
 
-Workload: two-level SI-MLSDC for 2-D viscous Burgers, 32 x 32 elements,
-fine P = 8 / M = 5, coarse P = 4 / M = 3 (see paper_2504_18526_amd/workloads.py).
-One step = one time step of the method: cascade start, 3 V-cycles, fine
-post-sweep, every implicit system solved by PCG to a relative residual of
-1e-10.  Metric: fine-level DOF-updates/s =
-nodes_fine * n_var * M_fine * fine_sweeps_per_step / (s / step).
+Default workload: two-level SI-MLSDC for the 3-D compressible Navier-Stokes
+Taylor-Green vortex on [0, 2 pi]^3, 16^3 hexahedra, fine P = 7 / M = 4,
+coarse P = 3 / M = 2 (2.1 M nodes x 5 conserved variables on the fine
+level; see paper_2504_18526_amd/workloads.py).  One step = one time step of
+the method: cascade start, 3 V-cycles, fine post-sweep, every implicit
+system solved by PCG to a relative residual of 1e-10.  Metric: fine-level
+DOF-updates/s = nodes_fine * n_var * M_fine * fine_sweeps_per_step / (s / step).
+`--workload burgers|convdiff|euler|batch` selects the other workloads.
 
 Prints one JSON line with the contract fields plus `roofline` and
 `cpu_baseline` (the CPU oracle on a bounded sample, rank 0, N = 1).  The
-roofline kernel is the persistent fine-level PCG (one launch per Helmholtz
-solve), timed with HIP events on the solver's stream around each of its
-launches in the timed steps; where the fine level runs the multi-kernel PCG
-it is the longer of that PCG's two kernels (matvec, vector update), timed
-over back-to-back launches.
+roofline kernel is the dominant kernel of the fine level's implicit solves,
+timed with HIP events on the solver's stream around each of its launches in
+the timed steps: the persistent PCG (one launch per Helmholtz solve) where
+the fine level uses it, else the multi-kernel PCG's vector update (its
+full-work launches; the matvec is reported beside it).
 """
 import argparse
 import json
@@ -83,7 +85,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 200; the batch workload: its 20 steps)")
+                    help="timed steps (default: the workload's own count; 20 for the default workload)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -92,15 +94,17 @@ def parse():
                     help="steps timed for each of the mixed / learned variants (0: skip them)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="burgers",
-                    help="burgers (default: the two-level Burgers workload), convdiff, euler, ns, "
+    ap.add_argument("--workload", default="ns",
+                    help="ns (default: the two-level 3-D Navier-Stokes workload), burgers, convdiff, euler, "
                          "batch (64 independent instances)")
     return ap.parse_args()
 
 
 def cpu_baseline(w, u0_path, gpu_step1_path, nsteps):
-    """Time the CPU oracle on `nsteps` steps in a child process with one
-    BLAS/OpenMP thread (the paper's runs were single-threaded)."""
+    """Time the CPU oracle on `nsteps` steps of workload `w` from the state in
+    `u0_path`, in a child process with one BLAS/OpenMP thread (the paper's
+    runs were single-threaded); the oracle's first step is compared with the
+    GPU's in `gpu_step1_path`."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = "1"
@@ -136,6 +140,50 @@ print(json.dumps({{"seconds": el, "steps": {nsteps}, "rel_l2_step1": err}}))
     if out.returncode != 0:
         raise RuntimeError("cpu baseline failed: " + out.stderr[-2000:])
     return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def ns_cpu_baseline(S, w, prob, meth, stream, dev, ne=4, nsteps=2):
+    """The oracle on a bounded sample of the Navier-Stokes workload: `nsteps`
+    time steps of the same two-level method (same degrees, nodes, start,
+    cycles, CFL rule, initial data) on an ne^3-element mesh of the same
+    domain, timed in a child process with one thread; the GPU steps the same
+    sample from the same u0 and the first steps of both are compared."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2504_18526_amd.inputs import taylor_green
+    from paper_2504_18526_amd.workloads import fine_sweeps_per_step, systems_dt
+    ws = dict(w)
+    ws["n_elem"] = (ne,) * w["dim"]
+    ps = S.Problem()
+    ctypes.memmove(ctypes.addressof(ps), ctypes.addressof(prob), ctypes.sizeof(S.Problem))
+    for d in range(w["dim"]):
+        ps.n_elem[d] = ne
+    sv = S.Solver(ps, meth, stream=stream.cuda_stream)
+    E, Np, nv, M = sv.level_info(0)
+    x = sv.coords(0)
+    u0 = np.ascontiguousarray(taylor_green([x[d] for d in range(w["dim"])], mach=w["mach"]).reshape(nv, E, Np))
+    ws["dt"] = systems_dt(ws, u0)
+    ud = torch.from_numpy(u0).to(dev)
+    sv.set_state(ud)
+    sv.step(ws["dt"])
+    out = torch.empty_like(ud)
+    sv.get_state(out)
+    torch.cuda.synchronize()
+    sv.close()
+    with tempfile.TemporaryDirectory() as td:
+        p0 = os.path.join(td, "u0.npy")
+        p1 = os.path.join(td, "g1.npy")
+        np.save(p0, u0)
+        np.save(p1, out.cpu().numpy())
+        r = cpu_baseline(ws, p0, p1, nsteps)
+    dofu = E * Np * nv * M * fine_sweeps_per_step(ws) * r["steps"]
+    return {"value": dofu / r["seconds"], "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{r['steps']} time steps of the same two-level method (P {w['P']}, M {w['M']}, cascade, "
+                      f"{w['cycles']} V-cycles + post-sweep, CFL {w['cfl']}, Taylor-Green data, oracle CG to the same "
+                      f"1e-10 tolerance) on a {ne}^3-element mesh of the same domain ({E * Np * nv} DOF, 1/"
+                      f"{(w['n_elem'][0] // ne) ** w['dim']} of the workload), {r['seconds']:.1f} s",
+            "gpu_vs_oracle_rel_l2_step1": r["rel_l2_step1"]}
 
 
 def cpu_baseline_batch(inst, budget_s=15.0):
@@ -356,7 +404,7 @@ def main():
     if w["eq"] == "batch":
         return main_batch(a, w)
     if a.steps is None:
-        a.steps = 200
+        a.steps = w.get("steps", 200)
     dev = torch.device("cuda:0")
     if a.copy_probe_mb > 0:
         src = torch.empty(a.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -401,7 +449,11 @@ def main():
             sv.get_state(out)
             step1 = out.cpu().numpy()
 
-    sv.pcg_timing(True)  # events around every persistent PCG launch of the timed steps
+    # events around every persistent PCG launch of the timed steps, and
+    # around the launches of every 8th multi-kernel solve (an event costs
+    # several microseconds of queue work; timing every solve would slow the
+    # timed steps by several per cent)
+    sv.pcg_timing(True, stride=8)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -423,22 +475,21 @@ def main():
     dof_updates = E * Np * nv * M * sweeps
     value = dof_updates / (ms_step / 1000.0)
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel, from the events recorded around its
+    # launches in the timed steps
     pcg_n, pcg_it, pcg_us = sv.pcg_timing_get(0)
+    up_n, up_us = sv.cg_kernel_timing_get(0, S.K_CG_UPDATE)
+    mv_n, mv_us = sv.cg_kernel_timing_get(0, S.K_SIPG_APPLY)
     sv.pcg_timing(False)
     fine_dof = E * Np * nv
-    # the multi-kernel PCG's two kernels on the fine level at a representative
-    # substep (separate back-to-back launches under HIP events): the matvec
-    # (M + dt_m K_D) z with its fused dot product, and the vector update
-    dtm = dt / M
     nf = (w["P"][0] + 1) ** (w["dim"] - 1)  # face nodes per element face
     traces = 2 * w["dim"] * nf / Np         # face-trace words per DOF
     iso = w["eq"] in ("euler", "ns") and (w["dim"] == 2 or w["P"][0] in (1, 3, 7))
     if iso:
         # isotropic kernels: the matvec reads r (scaled in-kernel to z) and
         # writes w; the update reads r, w, p, s and writes r, p, s, and on odd
-        # iterations also x (read + write).  The timed launches alternate odd
-        # and even iterations: 8 words on average.
+        # iterations also x (read + write): 8 words per DOF on average over
+        # the launches of a solve.
         mv_words, up_words = 2.0, 8.0
         mv_name = f"k_sipg_apply_iso{w['dim']}<{w['P'][0]}>"
         up_name = f"k_cg_iter_iso<{Np}>"
@@ -448,14 +499,15 @@ def main():
         up_words = 12.0 + reads_ub + traces                # z, w, p, s, x, r, diag in; p, s, x, r, z, traces out
         mv_name = f"k_sipg_apply<{w['dim']},{w['P'][0]}>"
         up_name = f"k_cg_iter<{w['dim']},{w['P'][0]}>"
-    kern = {}
-    for key, kid, name, words in (("matvec", S.K_SIPG_APPLY, mv_name, mv_words),
-                                  ("update", S.K_CG_UPDATE, up_name, up_words)):
-        us = sv.profile_kernel(kid, 0, dtm, reps=a.reps)
+
+    def kern_rec(name, words, n, us):
         nbytes = 8.0 * words * fine_dof
-        kern[key] = {"kernel": name, "avg_launch_us": round(us, 3), "algo_bytes_per_launch": int(nbytes),
-                     "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
-    matvec = kern["matvec"]
+        avg = us / n if n > 0 else float("nan")
+        return {"kernel": name, "launches": n, "avg_launch_us": round(avg, 3), "algo_bytes_per_launch": int(nbytes),
+                "achieved_GBs": round(nbytes / (avg * 1e-6) / 1e9, 1) if n > 0 else None}
+
+    matvec = kern_rec(mv_name, mv_words, mv_n, mv_us)
+    update = kern_rec(up_name, up_words, up_n, up_us)
     if pcg_n > 0:
         # the persistent PCG: one launch = one whole fine-level Helmholtz solve.
         # Algorithmic bytes of a streaming PCG: 5 FP64 words per DOF to set up
@@ -469,16 +521,18 @@ def main():
                     "kernel": name + " (whole fine-level PCG solve)",
                     "avg_launch_us": round(pcg_us / pcg_n, 3), "launches": pcg_n,
                     "iters_per_launch": round(pcg_it / pcg_n, 3),
-                    "algo_bytes_per_launch": int(algo / pcg_n), "matvec": matvec}
+                    "algo_bytes_per_launch": int(algo / pcg_n), "timing": "HIP events around every launch of the timed steps"}
     else:
-        # multi-kernel PCG: the kernel with the longer launch dominates (both run once per iteration)
-        dom = max(kern.values(), key=lambda k: k["avg_launch_us"])
-        other = kern["update"] if dom is kern["matvec"] else kern["matvec"]
+        # multi-kernel PCG: the kernel with the larger summed time dominates
+        # (both run once per iteration)
+        dom, other = (update, matvec) if up_us >= mv_us else (matvec, update)
         roofline = {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4) if dom["achieved_GBs"] else None,
                     "traffic": measured_traffic(w["name"], dom["kernel"]),
-                    "kernel": dom["kernel"], "avg_launch_us": dom["avg_launch_us"],
-                    "algo_bytes_per_launch": dom["algo_bytes_per_launch"], "other": other}
+                    "kernel": dom["kernel"], "avg_launch_us": dom["avg_launch_us"], "launches": dom["launches"],
+                    "algo_bytes_per_launch": dom["algo_bytes_per_launch"],
+                    "timing": "HIP events around every full-work launch of every 8th solve of the timed steps",
+                    "other": other}
 
     variants = None
     if a.variant_steps > 0:
@@ -486,17 +540,20 @@ def main():
 
     cpu = None
     if not a.no_cpu_baseline:
-        with tempfile.TemporaryDirectory() as td:
-            p0 = os.path.join(td, "u0.npy")
-            p1 = os.path.join(td, "g1.npy")
-            np.save(p0, u0)
-            np.save(p1, step1)
-            r = cpu_baseline(w, p0, p1, a.cpu_steps)
-        cpu_rate = dof_updates * r["steps"] / r["seconds"]
-        cpu = {"value": cpu_rate, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"{r['steps']} time steps of the same workload from the same u0 "
-                         f"(oracle CG to the same 1e-10 tolerance), {r['seconds']:.1f} s",
-               "gpu_vs_oracle_rel_l2_step1": r["rel_l2_step1"]}
+        if w["eq"] == "ns":
+            cpu = ns_cpu_baseline(S, w, prob, meth, stream, dev, nsteps=a.cpu_steps)
+        else:
+            with tempfile.TemporaryDirectory() as td:
+                p0 = os.path.join(td, "u0.npy")
+                p1 = os.path.join(td, "g1.npy")
+                np.save(p0, u0)
+                np.save(p1, step1)
+                r = cpu_baseline(w, p0, p1, a.cpu_steps)
+            cpu_rate = dof_updates * r["steps"] / r["seconds"]
+            cpu = {"value": cpu_rate, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{r['steps']} time steps of the same workload from the same u0 "
+                             f"(oracle CG to the same 1e-10 tolerance), {r['seconds']:.1f} s",
+                   "gpu_vs_oracle_rel_l2_step1": r["rel_l2_step1"]}
 
     rec = {
         "metric": "fine-level DOF-updates/s (s/step at fixed PCG tolerance 1e-10)",

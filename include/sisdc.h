@@ -74,7 +74,12 @@ enum { SISDC_PROJ_INTERP = 0, SISDC_PROJ_L2 = 1 };                /* Sec. 4 */
 enum { SISDC_INCREMENTAL = 0, SISDC_NONINCREMENTAL = 1 };        /* Sec. 3, 4 */
 enum { SISDC_NODES_RADAU_RIGHT = 0, SISDC_NODES_LOBATTO = 1 };  /* Sec. 3 */
 enum { SISDC_START_CASCADE = 0, SISDC_START_FMG = 1,   /* Alg. 3, Alg. 4    */
-       SISDC_START_PREDICTOR = 2 };                    /* Sec. 4            */
+       SISDC_START_PREDICTOR = 2,                      /* Sec. 4: the SI
+                                                          predictor on every
+                                                          level              */
+       SISDC_START_CONSTANT = 3 };                     /* Sec. 4: u_0 spread
+                                                          to every node of
+                                                          every level        */
 enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
        SISDC_MIXED = 1 }; /* FP32 Jacobi-PCG inside FP64 iterative refinement:
                              the outer residual b - A x, the solution update,
@@ -153,6 +158,17 @@ typedef struct {
                           "MLSDC transfer operators"; the counts must be
                           even; in 3-D the finer degree must be <= 6);
                           h_coarsen[0] = 0                                   */
+  int c_fmg;           /* SISDC_START_FMG: V-cycles per added level, C_fmg of
+                          Alg. 4 (FMG_1, FMG_2, ...); <= 0 means 1.  With two
+                          levels the FMG start equals the cascade start    */
+  int conserve;        /* 1: after every implicit solve each component of the
+                          solution is shifted by the constant that makes its
+                          total 1^T M x equal the right-hand side's total (the
+                          exact solution has it, since the SIPG operator is
+                          symmetric with the constants in its kernel), so the
+                          totals the method conserves hold to round-off at any
+                          PCG tolerance; 0: the iterate as the PCG leaves it
+                          (totals drift by up to the tolerance per solve)   */
 } sisdc_method;
 
 typedef struct {
@@ -165,6 +181,9 @@ typedef struct {
   int ir_rounds;          /* SISDC_MIXED: FP32 inner solves (refinement rounds) */
   int net_guesses;        /* learned initial guesses computed               */
   int net_rejected;       /* ... of which refused (no positive step)        */
+  int ir_fallbacks;       /* SISDC_MIXED: solves whose refinement stalled (a
+                             round that did not halve the FP64 residual, or
+                             20 rounds) and that FP64 PCG finished          */
 } sisdc_stats;
 
 typedef struct {
@@ -291,7 +310,7 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
 
 /* Measurement hook for the persistent PCG (one cooperative launch per
  * Helmholtz solve, used for levels whose tiles are co-resident and for
- * tolerances >= 1e-11).  With on = 1 the handle records a pair of HIP events
+ * tolerances >= 1e-11).  With on >= 1 the handle records a pair of HIP events
  * on its stream around every persistent launch and accumulates, per level,
  * the launches, the CG iterations they report and the event time between
  * each pair; switching on clears the sums.  on = 0 stops recording (the sums
@@ -302,6 +321,19 @@ int sisdc_pcg_timing(sisdc_handle* h, int on);
  * event time in microseconds (any output pointer may be NULL). */
 int sisdc_pcg_timing_get(sisdc_handle* h, int level, long long* launches, long long* iters,
                          double* total_us);
+/* The same switch also times the multi-kernel PCG (the Chronopoulos-Gear
+ * form of Sec. 8's implicit solves, used for systems, large levels and
+ * tolerances below 1e-11): while it is on, in every on-th multi-kernel solve
+ * of the handle (on = 1: every solve) a HIP event is recorded on the
+ * handle's stream before and after every vector-update launch and after
+ * every matvec launch, and the elapsed times of the launches that did a full
+ * iteration's work (not the one that only found convergence, nor those that
+ * exit at once behind it) are summed per level.  kernel: SISDC_K_CG_UPDATE
+ * (the vector update with its two dot products) or SISDC_K_SIPG_APPLY (the
+ * matvec with its dot product).  Launches of FP32 inner solves (SISDC_MIXED)
+ * count as well.  Each event costs several microseconds of queue work, so a
+ * stride above 1 keeps the timed run close to the untimed one. */
+int sisdc_cg_kernel_timing_get(sisdc_handle* h, int level, int kernel, long long* launches, double* total_us);
 
 /* Learned initial guess of a level's Helmholtz solves: an element-local MLP
  * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)

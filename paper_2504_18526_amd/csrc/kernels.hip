@@ -1455,6 +1455,47 @@ __global__ void k_sum2(const double* __restrict__ part, int n, double* tot) {
 }
 
 // block partials of (a, b) -> part[blk] and (a, c) -> part[kElemCap + blk]
+// Conservation correction of an implicit solve (A = M + dt_m K_D, K_D
+// symmetric with the constants in its kernel, so 1^T A x = 1^T M x): per
+// component c, x_c += (1^T b_c - 1^T M x_c) / 1^T M 1, which makes the
+// solution's total 1^T M x equal the right-hand side's total up to the
+// rounding of the sums.  b is a vector or, when b == NULL, the combination
+// lc (mass weights where lc.m[j]).  Pass 1: grid (nb, nv), block partials of
+// both sums per component into part[(2 c) nb + blk] and part[(2 c + 1) nb +
+// blk]; pass 2: grid (*, nv), every block sums its component's partials in
+// the same fixed order and adds the constant.
+__global__ void k_conserve_sums(const double* __restrict__ b, LinComb lc, const double* __restrict__ x, long vs,
+                                const double* __restrict__ mw, int np, double* part) {
+  const int c = blockIdx.y, nb = gridDim.x;
+  const long o = (long)c * vs;
+  double v[2] = {0.0, 0.0};
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vs; i += (long)nb * blockDim.x) {
+    const double m = mw[i % np];
+    double bi;
+    if (b) {
+      bi = b[o + i];
+    } else {
+      bi = 0.0;
+      for (int j = 0; j < lc.n; ++j) bi += lc.c[j] * (lc.m[j] ? m : 1.0) * lc.x[j][o + i];
+    }
+    v[0] += bi;
+    v[1] += m * x[o + i];
+  }
+  double* const pp[2] = {part + (long)(2 * c) * nb, part + (long)(2 * c + 1) * nb};
+  block_partials<double, 2>(v, pp);
+}
+
+__global__ void k_conserve_apply(double* __restrict__ x, long vs, const double* __restrict__ part, int nb,
+                                 double mass_total) {
+  const int c = blockIdx.y;
+  double tot[2];
+  const double* const pr[2] = {part + (long)(2 * c) * nb, part + (long)(2 * c + 1) * nb};
+  sum_partials<double, 2>(pr, nb, tot);
+  const double shift = (tot[0] - tot[1]) / mass_total;
+  double* const xc = x + (long)c * vs;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < vs; i += (long)gridDim.x * blockDim.x) xc[i] += shift;
+}
+
 __global__ void k_dot2(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
                        long n, double* part) {
   double v[2] = {0.0, 0.0};
@@ -1957,6 +1998,18 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, long n
   const int nb = blocks_for(n, 256, kElemCap);
   hipLaunchKernelGGL(k_dot2, dim3(nb), dim3(256), 0, s, a, b, c, n, part);
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, part, nb, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_conserve(const double* b, const LinComb* lc, double* x, int nv, long vs, const double* mw, int np,
+                           double mass_total, double* part, int part_cap, hipStream_t s) {
+  if (nv < 1 || part_cap < 2 * nv || !(mass_total > 0.0) || (!b && !lc)) return hipErrorInvalidValue;
+  const int nb = std::max(1, std::min(blocks_for(vs, 256, kElemCap), part_cap / (2 * nv)));
+  LinComb l{};
+  if (!b) l = *lc;
+  hipLaunchKernelGGL(k_conserve_sums, dim3(nb, nv), dim3(256), 0, s, b, l, (const double*)x, vs, mw, np, part);
+  hipLaunchKernelGGL(k_conserve_apply, dim3(blocks_for(vs, 256, 1024), nv), dim3(256), 0, s, x, vs,
+                     (const double*)part, nb, mass_total);
   return hipGetLastError();
 }
 

@@ -89,6 +89,12 @@ hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);
 hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
                              hipStream_t s);
 hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s);
+// Conservation correction after an implicit solve: x_c += (1^T b_c - 1^T M
+// x_c) / mass_total for every component c (b a vector, or the combination lc
+// when b is NULL); part holds at least 2 nv partials per block (part_cap
+// values in all).  Two launches, deterministic fixed-order sums.
+hipError_t launch_conserve(const double* b, const LinComb* lc, double* x, int nv, long vs, const double* mw, int np,
+                           double mass_total, double* part, int part_cap, hipStream_t s);
 // tot[0] = (a, b), tot[1] = (a, c) (deterministic partial sums in part)
 hipError_t launch_dot2(const double* a, const double* b, const double* c, long n, double* part, double* tot,
                        hipStream_t s);

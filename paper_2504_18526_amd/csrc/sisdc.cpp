@@ -105,6 +105,7 @@ struct Level {
     double* lossp = nullptr;                                     // loss partials, 64 per batch
     int loss_cap = 0;                                            // batches the loss buffer holds
   } net;
+  double mass_total = 0.0;  // 1^T M 1 of one component: E times the sum of the element's mass weights
   bool stale = true;
   double stored_dt = -1.0;
   bool has_g = false;
@@ -165,6 +166,14 @@ struct sisdc_handle {
   std::vector<char> ring_timed;  // per record: events recorded
   std::vector<double> pt_us;     // per level: summed event time (us) ...
   std::vector<long long> pt_n, pt_it;  // ... launches and iterations
+  // event timing of the multi-kernel PCG's launches (sisdc_cg_kernel_timing_get):
+  // per level and kernel (2 level + 0: vector update, 2 level + 1: matvec),
+  // the launches that did a full iteration's work and their summed event time
+  std::vector<hipEvent_t> mev;   // pool: 3 events per iteration of a chunk
+  std::vector<double> kt_us;
+  std::vector<long long> kt_n;
+  int kt_stride = 1;             // time every kt_stride-th multi-kernel solve
+  long long kt_solves = 0;       // multi-kernel solves since timing was switched on
   double* lam_dev = nullptr;
   double* hlam = nullptr;      // pinned
   double* state = nullptr;
@@ -317,15 +326,18 @@ struct CGBufs {
   T* partials;
   T* alpha;
   T* idg;
+  int* done_gen;  // id of the last converged solve
+  CGRes* res;     // result record
 };
 
 CGBufs<double> bufs64(sisdc_handle* h, Level& L) {
-  return CGBufs<double>{L.cr, L.cz, L.cp, L.cs, L.cw, L.diag, L.trace, L.tab, h->partials, h->alpha, L.idg};
+  return CGBufs<double>{L.cr,       L.cz,     L.cp,  L.cs,        L.cw,  L.diag, L.trace,
+                        L.tab,      h->partials, h->alpha, L.idg, h->done_gen, h->res};
 }
 
 CGBufs<float> bufs32(sisdc_handle* h, Level& L) {
-  return CGBufs<float>{L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32, L.tab32, h->partials32,
-                       h->alpha32, L.idg32};
+  return CGBufs<float>{L.cr32, L.cz32,        L.cp32,      L.cs32, L.cw32,      L.diag32, L.trace32,
+                       L.tab32, h->partials32, h->alpha32, L.idg32, h->done_gen, h->res};
 }
 
 template <typename T>
@@ -346,8 +358,8 @@ CGStateT<T> cg_state(sisdc_handle* h, const CGBufs<T>& B, const T* b, T* x, doub
   cg.del = B.partials + 5 * kElemCap;
   cg.bbp = B.partials + 6 * kElemCap;
   cg.alpha = B.alpha;
-  cg.done_gen = h->done_gen;
-  cg.res = h->res;
+  cg.done_gen = B.done_gen;
+  cg.res = B.res;
   cg.tol2 = (T)(rtol * rtol);
   return cg;
 }
@@ -365,6 +377,17 @@ void account(sisdc_handle* h, int iters, bool converged, double rel) {
   h->st.cg_iters_max = std::max(h->st.cg_iters_max, iters);
   h->st.max_rel_residual = std::max(h->st.max_rel_residual, rel);
   if (!converged) h->st.not_converged += 1;
+}
+
+// Conservation correction after a solve (method option `conserve`): shift
+// every component of x by a constant so that 1^T M x = 1^T b, which the
+// exact solution satisfies (the SIPG operator annihilates constants and is
+// symmetric); an iterative solve leaves 1^T (b - A x) of the order of its
+// tolerance, and the shift removes it, so the totals the method conserves
+// hold to round-off whatever the tolerance.
+void conserve_fix(sisdc_handle* h, Level& L, const double* b, const LinComb* bl, double* x) {
+  if (!h->meth.conserve) return;
+  HIPCHECK(launch_conserve(b, bl, x, L.nv, L.vs, L.mw, L.np, L.mass_total, h->partials, 7 * kElemCap, h->stream));
 }
 
 // Collect the result records of persistent solves enqueued since the last
@@ -387,7 +410,7 @@ void drain(sisdc_handle* h) {
     if (r.it_last < 0) aborted = true;
     const bool conv = (r.it_last & 2) != 0;
     const double rel = r.bb > 0.0 ? std::sqrt(r.rr / r.bb) : 0.0;
-    if (!std::isfinite(rel)) nonfinite = true;
+    if (!std::isfinite(rel) || !std::isfinite(r.rr) || !std::isfinite(r.bb)) nonfinite = true;
     account(h, r.it, conv, rel);
     const int li = h->ring_meta[i].first;
     Level& L = h->lv[li];
@@ -468,6 +491,15 @@ void porder_unregister(int dev, hipStream_t s) {
       break;
     }
   if (po.pending && po.last == s) po.pending = false;
+  // the last handle of the device is gone: release the ordering event, so no
+  // HIP object of the library outlives its handles
+  if (po.streams.empty()) {
+    if (po.done) (void)hipEventDestroy(po.done);
+    po.done = nullptr;
+    po.pending = false;
+    po.marked = false;
+    po.last = nullptr;
+  }
 }
 
 // b null: the kernel forms the right-hand side from `bl`.
@@ -538,6 +570,7 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   h->ring_timed.push_back(h->ptime ? 1 : 0);
   h->ring_meta.emplace_back((int)(&L - h->lv.data()), maxit);
   h->ring_n += 1;
+  conserve_fix(h, L, b, b ? nullptr : bl, x);
   return true;
 }
 
@@ -574,25 +607,57 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
   int chunk = std::max(2, L.last_iters + 1);
   int it = 0;
   bool converged = false;
+  const int li = (int)(&L - h->lv.data());
+  const bool timed = h->ptime && (size_t)(2 * li + 1) < h->kt_us.size() && (h->kt_solves++ % h->kt_stride) == 0;
   while (true) {
+    const int first = it;
     const int stop = std::min(maxit + 1, it + chunk);  // iteration kernel `it` checks the residual after it updates
+    if (timed)
+      while (h->mev.size() < (size_t)(3 * (stop - first))) {
+        hipEvent_t ev = nullptr;
+        HIPCHECK(hipEventCreate(&ev));
+        h->mev.push_back(ev);
+      }
     for (; it < stop; ++it) {
-      if (iso) {
+      hipEvent_t* ev = timed ? &h->mev[3 * (it - first)] : nullptr;
+      if (timed) HIPCHECK(hipEventRecord(ev[0], s));
+      if (iso)
         HIPCHECK(launch_cg_iter_iso(cg, B.idg, L.nv, L.g, it, id, s));
-        if (it < maxit)
-          HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
-                                         (const int*)h->done_gen, id, s));
-      } else {
+      else
         HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
-        if (it < maxit)
+      if (timed) HIPCHECK(hipEventRecord(ev[1], s));
+      if (it < maxit) {
+        if (iso)
+          HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
+                                         (const int*)B.done_gen, id, s));
+        else
           HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
-                                     (const int*)h->done_gen, id, s));
+                                     (const int*)B.done_gen, id, s));
+      }
+      if (timed) HIPCHECK(hipEventRecord(ev[2], s));
+    }
+    HIPCHECK(hipMemcpyAsync(h->hres, B.res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(h->hdone, B.done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const bool done = *h->hdone == id;
+    if (timed) {
+      // launches before the converged iteration did a full iteration's work;
+      // the converged one only tests, later ones exit at once
+      const int full_end = done ? std::min(stop, h->hres->it) : stop;
+      for (int k = first; k < full_end; ++k) {
+        const hipEvent_t* ev = &h->mev[3 * (k - first)];
+        float ms = 0.0f;
+        HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        h->kt_us[2 * li] += 1000.0 * ms;
+        h->kt_n[2 * li] += 1;
+        if (k < maxit) {
+          HIPCHECK(hipEventElapsedTime(&ms, ev[1], ev[2]));
+          h->kt_us[2 * li + 1] += 1000.0 * ms;
+          h->kt_n[2 * li + 1] += 1;
+        }
       }
     }
-    HIPCHECK(hipMemcpyAsync(h->hres, h->res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(h->hdone, h->done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    if (*h->hdone == id) {
+    if (done) {
       converged = true;
       break;
     }
@@ -605,7 +670,8 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
   const double rel = h->hres->bb > 0.0 ? std::sqrt(h->hres->rr / h->hres->bb) : 0.0;
   r.rel_residual = rel;
   r.converged = converged;
-  if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
+  if (!std::isfinite(rel) || !std::isfinite(h->hres->rr) || !std::isfinite(h->hres->bb))
+    fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
   L.last_iters = std::max(1, r.iters);
   return r;
 }
@@ -633,8 +699,8 @@ sisdc_solve_stats mixed_solve(sisdc_handle* h, Level& L, const CoefP& cf, double
   CGBufs<float> B = bufs32(h, L);
   sisdc_solve_stats out{};
   int total = 0, rounds = 0;
-  double rel = 0.0;
-  bool converged = false;
+  double rel = 0.0, rel_prev = 0.0;
+  bool converged = false, stalled = false;
   const double inner = h->meth.inner_rtol > 0.0 ? h->meth.inner_rtol : 1e-5;
   while (true) {
     HIPCHECK(launch_sipg(x, L.cw, L.nv, cf, L.trace, 1.0, dtm, h->ctau, L.g, L.tab, s));
@@ -643,17 +709,32 @@ sisdc_solve_stats mixed_solve(sisdc_handle* h, Level& L, const CoefP& cf, double
     HIPCHECK(hipStreamSynchronize(s));
     const double rr = h->hir_tot[0], bb = h->hir_tot[1];
     rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
-    if (!std::isfinite(rel)) fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
+    if (!std::isfinite(rel) || !std::isfinite(rr) || !std::isfinite(bb))
+      fail(SISDC_ENONFINITE, "non-finite residual in the Helmholtz solve");
     if (rr <= rtol * rtol * bb) {
       converged = true;
       break;
     }
-    if (total >= maxit || rounds >= 20) break;
+    if (total >= maxit) break;
+    // refinement that no longer halves the FP64 residual per round (or runs
+    // out of rounds) has stalled: FP64 PCG finishes the solve
+    if (rounds >= 20 || (rounds > 0 && rel > 0.5 * rel_prev)) {
+      stalled = true;
+      break;
+    }
+    rel_prev = rel;
     const double tol_in = std::max(inner, 0.5 * rtol * std::sqrt(bb / rr));
     sisdc_solve_stats ri = cg_multi<float>(h, L, B, cf32, (float)dtm, L.r32, L.e32, tol_in, maxit - total, true);
     total += ri.iters;
     rounds += 1;
     HIPCHECK(launch_add_f2d(x, L.e32, L.vlen, s));
+  }
+  if (stalled) {
+    sisdc_solve_stats r64 = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, rtol, maxit - total, false);
+    total += r64.iters;
+    converged = r64.converged != 0;
+    rel = r64.rel_residual;
+    h->st.ir_fallbacks += 1;
   }
   out.iters = total;
   out.converged = converged;
@@ -728,7 +809,11 @@ sisdc_solve_stats cg_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dt
 
 sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                                 double rtol, int maxit) {
-  if (h->meth.precision == SISDC_MIXED) return mixed_solve(h, L, cf, dtm, b, x, rtol, maxit);
+  if (h->meth.precision == SISDC_MIXED) {
+    sisdc_solve_stats r = mixed_solve(h, L, cf, dtm, b, x, rtol, maxit);
+    conserve_fix(h, L, b, nullptr, x);
+    return r;
+  }
   // the pipelined persistent form is used for production tolerances only
   if (L.persistent && rtol >= kPersistentMinRtol && persistent_solve(h, L, cf, dtm, b, x, rtol, maxit)) {
     sisdc_solve_stats r{};
@@ -738,6 +823,7 @@ sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, doub
   }
   sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, rtol, maxit, false);
   account(h, r.iters, r.converged, r.rel_residual);
+  conserve_fix(h, L, b, nullptr, x);
   return r;
 }
 
@@ -1142,6 +1228,11 @@ void do_step(sisdc_handle* h, double dt) {
     if (start == SISDC_START_PREDICTOR) {
       for (int i = 0; i < nl; ++i) predictor(h, h->lv[i], dt);
       h->st.fine_sweeps += 1;
+    } else if (start == SISDC_START_CONSTANT) {  // u_{l,m} = u_{l,0} on every node of every level
+      for (auto& L : h->lv) {
+        for (int m = 1; m <= L.M; ++m) copy_d2d(h, L.um(m), L.um(0), L.vlen);
+        L.stale = true;
+      }
     } else {
       predictor(h, h->lv[Lc], dt);
       if (start == SISDC_START_CASCADE) {  // Alg. 3
@@ -1149,11 +1240,12 @@ void do_step(sisdc_handle* h, double dt) {
           level_sweep(h, i, dt);
           interpolate_up(h, i - 1);
         }
-      } else {  // Alg. 4, C_fmg = 1
+      } else {  // Alg. 4: C_fmg V-cycles per added level
+        const int cfmg = std::max(1, h->meth.c_fmg);
         level_sweep(h, Lc, dt);
         interpolate_up(h, Lc - 1);
         for (int i = Lc - 1; i >= 1; --i) {
-          vcycle(h, i, dt);
+          for (int c = 0; c < cfmg; ++c) vcycle(h, i, dt);
           interpolate_up(h, i - 1);
         }
       }
@@ -1227,6 +1319,9 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
   }
   L.mw = dalloc(L.np);
   HIPCHECK(hipMemcpy(L.mw, mw.data(), L.np * sizeof(double), hipMemcpyHostToDevice));
+  L.mass_total = 0.0;
+  for (int n = 0; n < L.np; ++n) L.mass_total += mw[n];
+  L.mass_total *= L.E;
   const long n = L.vlen;
   L.u = dalloc((M + 1) * n);
   L.unew = dalloc((M + 1) * n);
@@ -1468,8 +1563,9 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->nodes == SISDC_NODES_LOBATTO)
     for (int l = 0; l < m->n_levels; ++l)
       if (m->M[l] < 2) fail(SISDC_EINVAL, "Lobatto nodes need M >= 2 on every level");
-  if (m->start < 0 || m->start > 2) fail(SISDC_EINVAL, "start");
+  if (m->start < SISDC_START_CASCADE || m->start > SISDC_START_CONSTANT) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
+  if (m->conserve != 0 && m->conserve != 1) fail(SISDC_EINVAL, "conserve must be 0 or 1");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
   if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL &&
@@ -1689,6 +1785,7 @@ int sisdc_destroy(sisdc_handle* h) {
   if (h->ring) (void)hipFree(h->ring);
   if (h->hring) (void)hipHostFree(h->hring);
   for (hipEvent_t ev : h->pev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : h->mev) (void)hipEventDestroy(ev);
   if (h->state) (void)hipFree(h->state);
   if (h->io) (void)hipFree(h->io);
   delete h;
@@ -1959,8 +2056,23 @@ int sisdc_pcg_timing(sisdc_handle* h, int on) {
       h->pt_us.assign(h->lv.size(), 0.0);
       h->pt_n.assign(h->lv.size(), 0);
       h->pt_it.assign(h->lv.size(), 0);
+      h->kt_us.assign(2 * h->lv.size(), 0.0);
+      h->kt_n.assign(2 * h->lv.size(), 0);
+      h->kt_stride = std::max(1, on);
+      h->kt_solves = 0;
     }
     h->ptime = on != 0;
+  });
+}
+
+int sisdc_cg_kernel_timing_get(sisdc_handle* h, int level, int kernel, long long* launches, double* total_us) {
+  return guard([&] {
+    level_at(h, level);
+    if (kernel != SISDC_K_CG_UPDATE && kernel != SISDC_K_SIPG_APPLY) fail(SISDC_EINVAL, "kernel must be SISDC_K_CG_UPDATE or SISDC_K_SIPG_APPLY");
+    const size_t k = 2 * (size_t)level + (kernel == SISDC_K_SIPG_APPLY ? 1 : 0);
+    const bool have = k < h->kt_us.size();
+    if (launches) *launches = have ? h->kt_n[k] : 0;
+    if (total_us) *total_us = have ? h->kt_us[k] : 0.0;
   });
 }
 

@@ -6,8 +6,11 @@ binding picks SISDC_MEM_DEVICE / SISDC_MEM_HOST accordingly.  If the shared
 library has not been built the import of this module raises: there is no
 fallback path.
 """
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -21,7 +24,7 @@ SI2, SI1, IMEX_EULER = 0, 1, 2
 PROJ_INTERP, PROJ_L2 = 0, 1
 INCREMENTAL, NONINCREMENTAL = 0, 1
 NODES_RADAU_RIGHT, NODES_LOBATTO = 0, 1
-START_CASCADE, START_FMG, START_PREDICTOR = 0, 1, 2
+START_CASCADE, START_FMG, START_PREDICTOR, START_CONSTANT = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2
 OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT, OP_QUAD = range(9)
@@ -32,7 +35,7 @@ EXPORTS = [
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
-    "sisdc_pcg_timing", "sisdc_pcg_timing_get",
+    "sisdc_pcg_timing", "sisdc_pcg_timing_get", "sisdc_cg_kernel_timing_get",
     "sisdc_batch_create", "sisdc_batch_destroy", "sisdc_batch_size", "sisdc_batch_handle",
     "sisdc_batch_set_threads", "sisdc_batch_step", "sisdc_batch_tune",
     "sisdc_net_init", "sisdc_net_get_params", "sisdc_net_set_params", "sisdc_net_forward",
@@ -57,14 +60,16 @@ class Method(ctypes.Structure):
                 ("cg_maxit", ctypes.c_int), ("c_tau", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int),
-                ("nodes", ctypes.c_int), ("h_coarsen", ctypes.c_int * 3)]
+                ("nodes", ctypes.c_int), ("h_coarsen", ctypes.c_int * 3), ("c_fmg", ctypes.c_int),
+                ("conserve", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("fine_sweeps", ctypes.c_int), ("solves", ctypes.c_int),
                 ("cg_iters", ctypes.c_longlong), ("cg_iters_max", ctypes.c_int),
                 ("not_converged", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
-                ("ir_rounds", ctypes.c_int), ("net_guesses", ctypes.c_int), ("net_rejected", ctypes.c_int)]
+                ("ir_rounds", ctypes.c_int), ("net_guesses", ctypes.c_int), ("net_rejected", ctypes.c_int),
+                ("ir_fallbacks", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,6 +115,7 @@ def load():
         "sisdc_batch_set_threads": ([P, I], I),
         "sisdc_batch_step": ([P, P, P], I),
         "sisdc_batch_tune": ([P, P, ctypes.POINTER(I), P], I),
+        "sisdc_cg_kernel_timing_get": ([P, I, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)], I),
         "sisdc_pcg_timing_get": ([P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(D)], I),
         "sisdc_net_init": ([P, I, I, ctypes.c_ulonglong, I, I], I),
@@ -199,7 +205,7 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
                 n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
                 inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT,
-                h_coarsen=None):
+                h_coarsen=None, c_fmg=1, conserve=1):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -221,7 +227,26 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.nodes = nodes
     for i, v in enumerate(h_coarsen or []):
         m.h_coarsen[i] = int(v)
+    m.c_fmg = c_fmg
+    m.conserve = conserve
     return m
+
+
+# Handles still open when the interpreter exits are closed by an exit handler,
+# while the HIP runtime (and torch's use of it) is still fully alive; finalizers
+# that run during interpreter teardown make no library call.
+_LIVE = weakref.WeakSet()
+
+
+def _close_all():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
 
 
 class Solver:
@@ -236,6 +261,7 @@ class Solver:
         self.problem = problem
         self.method = method
         self.dim = problem.dim
+        _LIVE.add(self)
 
     def close(self):
         if self.h:
@@ -243,6 +269,8 @@ class Solver:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -336,9 +364,11 @@ class Solver:
         _check(self._lib.sisdc_profile_kernel(self.h, kernel, level, dt_m, reps, ctypes.byref(us)))
         return us.value
 
-    def pcg_timing(self, on):
-        """Start (clearing the sums) or stop event timing of the persistent PCG launches."""
-        _check(self._lib.sisdc_pcg_timing(self.h, 1 if on else 0))
+    def pcg_timing(self, on, stride=1):
+        """Start (clearing the sums) or stop event timing of the persistent PCG
+        launches and, in every stride-th multi-kernel solve, of the
+        multi-kernel PCG's launches."""
+        _check(self._lib.sisdc_pcg_timing(self.h, max(1, int(stride)) if on else 0))
 
     def pcg_timing_get(self, level):
         """(launches, CG iterations, total event time in us) of the persistent
@@ -346,6 +376,14 @@ class Solver:
         n, it, us = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_double()
         _check(self._lib.sisdc_pcg_timing_get(self.h, level, ctypes.byref(n), ctypes.byref(it), ctypes.byref(us)))
         return n.value, it.value, us.value
+
+    def cg_kernel_timing_get(self, level, kernel):
+        """(launches, total event time in us) of the full-work launches of the
+        multi-kernel PCG's vector update (K_CG_UPDATE) or matvec
+        (K_SIPG_APPLY) on a level since timing was switched on."""
+        n, us = ctypes.c_longlong(), ctypes.c_double()
+        _check(self._lib.sisdc_cg_kernel_timing_get(self.h, level, kernel, ctypes.byref(n), ctypes.byref(us)))
+        return n.value, us.value
 
     # ---- learned initial guess (element-local MLP) ----
     def net_init(self, level, hidden, seed=0, max_batch=4096, max_rows=65536):
@@ -438,6 +476,7 @@ class Batch:
             h = ctypes.c_void_p()
             _check(self._lib.sisdc_batch_handle(self.b, i, ctypes.byref(h)))
             self.members.append(_Member(self, h, problems[i], methods[i]))
+        _LIVE.add(self)
 
     def close(self):
         if self.b:
@@ -447,6 +486,8 @@ class Batch:
             self.b = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
