@@ -267,6 +267,23 @@ int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_
                     const double* b, double* x, int mem, double rtol, int maxit,
                     sisdc_solve_stats* st);
 
+/* helmholtz_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve, with the multi-kernel Jacobi-PCG in FP64 (no
+ * learned guess, no mixed precision), whose work vectors, partial sums and
+ * convergence record live in a fixed scratch array of 32 MiB that each GPU
+ * holds until the process ends.  b, x and coef_state are device pointers of
+ * the handle's GPU, which must be the current device.  The call allocates
+ * nothing (its first call on a GPU only looks up the array's address).
+ * Levels whose work space exceeds the array (about 6 level vectors plus face
+ * traces: about 600 000 values per vector at most) are rejected with
+ * SISDC_EINVAL.
+ * Calls on one GPU share the array: calls that overlap on one GPU (other
+ * handles, other streams, other threads) race.  The call synchronises the
+ * handle's stream before it returns. */
+int helmholtz_solve_noalloc(sisdc_handle* h, int level, double dt_m, const double* coef_state, const double* b,
+                            double* x, double rtol, int maxit, sisdc_solve_stats* st);
+
 /* Stage-level entry points (one operator application each, for parity
  * checks and for callers that compose their own schemes):
  *   SISDC_OP_MASS    out = M in

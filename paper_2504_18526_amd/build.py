@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsisdc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "pcg_persistent.hip", "mlp.hip", "sisdc.cpp", "tables.cpp"]
+SOURCES = ["kernels.hip", "pcg_persistent.hip", "mlp.hip", "scratch.hip", "sisdc.cpp", "tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -24,6 +24,7 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "mlp.hpp"
+#include "scratch.hpp"
 #include "tables.hpp"
 
 using namespace sisdc;
@@ -1985,6 +1986,68 @@ int helmholtz_solve(sisdc_handle* h, int level, double dt_m, const double* coef_
       r.rel_residual = h->st.max_rel_residual;
     }
     if (mem == SISDC_MEM_HOST) dev_out(h, x, dx, n, mem);
+    if (st) *st = r;
+    if (!r.converged) fail(SISDC_ENOTCONV, "CG reached maxit before the tolerance");
+  });
+}
+
+int helmholtz_solve_noalloc(sisdc_handle* h, int level, double dt_m, const double* coef_state, const double* b,
+                            double* x, double rtol, int maxit, sisdc_solve_stats* st) {
+  return guard([&] {
+    Level& L = level_at(h, level);
+    if (!b || !x) fail(SISDC_EINVAL, "null b or x");
+    if (!(dt_m >= 0.0)) fail(SISDC_EINVAL, "dt_m must be >= 0");
+    if (h->eq.eq == EQ_BURGERS && !coef_state) fail(SISDC_EINVAL, "Burgers needs coef_state");
+    int cur = -1;
+    HIPCHECK(hipGetDevice(&cur));
+    if (cur != h->dev) fail(SISDC_EINVAL, "the handle's device must be current");
+    // carve the multi-kernel PCG's work space out of the device's static
+    // scratch: r, z, p, s, w, diag (one level vector each), the face traces,
+    // the inverse diagonal table, partial sums, step lengths, the result
+    // record and the convergence word, each 256-byte aligned
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    const size_t vec = up((size_t)L.vlen * sizeof(double));
+    const size_t trc = up((size_t)L.nv * L.E * 2 * L.g.dim * L.g.nf * sizeof(double));
+    const size_t idg = up((size_t)L.np * sizeof(double));
+    const size_t par = up((size_t)7 * kElemCap * sizeof(double));
+    const size_t alp = up(2 * sizeof(double));
+    const size_t rec = up(sizeof(CGRes)) + 256;  // the record, then the convergence word
+    const size_t need = 6 * vec + trc + idg + par + alp + rec;
+    if (need > kScratchBytes)
+      fail(SISDC_EINVAL, "level too large for the static scratch: needs " + std::to_string(need) + " bytes, at most " +
+                             std::to_string(kScratchBytes));
+    void* base = nullptr;
+    HIPCHECK(scratch_region(h->dev, &base));
+    char* q = (char*)base;
+    auto take = [&](size_t n) {
+      char* r = q;
+      q += n;
+      return r;
+    };
+    CGBufs<double> B{};
+    B.r = (double*)take(vec);
+    B.z = (double*)take(vec);
+    B.p = (double*)take(vec);
+    B.s = (double*)take(vec);
+    B.w = (double*)take(vec);
+    B.diag = (double*)take(vec);
+    B.trace = (double*)take(trc);
+    B.idg = (double*)take(idg);
+    B.partials = (double*)take(par);
+    B.alpha = (double*)take(alp);
+    char* recp = take(rec);
+    B.res = (CGRes*)recp;
+    B.done_gen = (int*)(recp + up(sizeof(CGRes)));
+    B.tab = L.tab;
+    // the previous call on this GPU may have left any id in the convergence
+    // word and any record: clear both (a fill kernel, no memset node)
+    HIPCHECK(launch_zero_scratch(recp, rec, h->stream));
+    const CoefP cf = coef_for(h, L, dt_m, coef_state);
+    h->st = sisdc_stats{};
+    sisdc_solve_stats r = cg_multi<double>(h, L, B, cf, dt_m, b, x, rtol > 0 ? rtol : h->meth.cg_rtol,
+                                           maxit > 0 ? maxit : h->meth.cg_maxit, false);
+    account(h, r.iters, r.converged, r.rel_residual);
+    HIPCHECK(hipStreamSynchronize(h->stream));
     if (st) *st = r;
     if (!r.converged) fail(SISDC_ENOTCONV, "CG reached maxit before the tolerance");
   });

@@ -33,7 +33,7 @@ EXPORTS = [
     "sisdc_last_error", "sisdc_create", "sisdc_destroy", "sisdc_level_info",
     "sisdc_node_coords", "sisdc_set_state", "sisdc_get_level", "sisdc_set_level",
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
-    "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve",
+    "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve", "helmholtz_solve_noalloc",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
     "sisdc_pcg_timing", "sisdc_pcg_timing_get", "sisdc_cg_kernel_timing_get",
     "sisdc_batch_create", "sisdc_batch_destroy", "sisdc_batch_size", "sisdc_batch_handle",
@@ -104,6 +104,7 @@ def load():
         "sisdc_sweep": ([P, I, D, P, I, ctypes.POINTER(Stats)], I),
         "mlsdc_vcycle": ([P, I, D, ctypes.POINTER(Stats)], I),
         "helmholtz_solve": ([P, I, D, P, P, P, I, D, I, ctypes.POINTER(SolveStats)], I),
+        "helmholtz_solve_noalloc": ([P, I, D, P, P, P, D, I, ctypes.POINTER(SolveStats)], I),
         "sisdc_apply": ([P, I, I, D, P, P, P, I], I),
         "sisdc_collocation_residual": ([P, I, D, P, I], I),
         "sisdc_profile_kernel": ([P, I, I, D, I, ctypes.POINTER(D)], I),
@@ -349,6 +350,18 @@ class Solver:
         pc, _ = _ptr(coef_state)
         rc = self._lib.helmholtz_solve(self.h, level, dt_m, pc, pb, px, mem, rtol, maxit, ctypes.byref(st))
         _check(rc)
+        return {"iters": st.iters, "converged": st.converged, "rel_residual": st.rel_residual}
+
+    def helmholtz_solve_noalloc(self, level, dt_m, b, x, coef_state=None, rtol=0.0, maxit=0):
+        """helmholtz_solve with the library's fixed per-GPU scratch (device
+        tensors only; no allocation)."""
+        if _mem_of(b, x, coef_state) != MEM_DEVICE:
+            raise ValueError("helmholtz_solve_noalloc takes device arrays only")
+        st = SolveStats()
+        pb, _ = _ptr(b)
+        px, _ = _ptr(x, True)
+        pc, _ = _ptr(coef_state)
+        _check(self._lib.helmholtz_solve_noalloc(self.h, level, dt_m, pc, pb, px, rtol, maxit, ctypes.byref(st)))
         return {"iters": st.iters, "converged": st.converged, "rel_residual": st.rel_residual}
 
     def apply(self, op, level, x, out, dt_m=0.0, aux=None):
