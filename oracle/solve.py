@@ -32,15 +32,18 @@ def dense_solve(apply, b):
 
 def cg(apply, b, x0, precond_diag, rtol=1e-14, maxit=10000):
     """Preconditioned CG; returns (x, iterations, final relative residual).
+    precond_diag: the diagonal preconditioner's entries (z = r / diag), or a
+    function r -> z (another symmetric positive definite preconditioner).
 
     Stops at the tolerance, or when the residual has not decreased for 50
     iterations (FP64 stagnation), keeping the best iterate."""
+    pre = precond_diag if callable(precond_diag) else (lambda v: v / precond_diag)
     x = x0.copy()
     r = b - apply(x)
     bn = np.sqrt(np.sum(b * b))
     if bn == 0.0:
         return np.zeros_like(b), 0, 0.0
-    z = r / precond_diag
+    z = pre(r)
     p = z.copy()
     rz = np.sum(r * z)
     best = (np.sqrt(np.sum(r * r)) / bn, x.copy())
@@ -59,7 +62,7 @@ def cg(apply, b, x0, precond_diag, rtol=1e-14, maxit=10000):
         alpha = rz / np.sum(p * Ap)
         x = x + alpha * p
         r = r - alpha * Ap
-        z = r / precond_diag
+        z = pre(r)
         rz_new = np.sum(r * z)
         p = z + (rz_new / rz) * p
         rz = rz_new
