@@ -332,18 +332,24 @@ def main_batch(a, w):
 
 def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates, start):
     """Plain FP64 vs mixed precision vs the learned initial guess (and both),
-    each from the same state after the same warm-up, same PCG tolerance.
+    and, on the systems' isotropic levels, vs the element-block Jacobi
+    preconditioner by fast diagonalisation, each from the same state after
+    the same warm-up, same PCG tolerance.
     The network of each level is trained on rows harvested from the plain
     solves of the warm-up steps (its training time is reported, not timed)."""
     import time
     import torch
     out = {}
     ref = None
-    for name, prec, learned in (("plain_fp64", S.FP64, False), ("mixed", S.MIXED, False),
-                                ("learned_fp64", S.FP64, True), ("learned_mixed", S.MIXED, True)):
+    iso = w["eq"] in ("euler", "ns")  # the block-Jacobi (fast-diagonalisation) preconditioner applies there
+    cases = [("plain_fp64", S.FP64, False, S.PRECOND_JACOBI), ("mixed", S.MIXED, False, S.PRECOND_JACOBI),
+             ("learned_fp64", S.FP64, True, S.PRECOND_JACOBI), ("learned_mixed", S.MIXED, True, S.PRECOND_JACOBI)]
+    if iso:
+        cases.append(("fds_fp64", S.FP64, False, S.PRECOND_FDS))
+    for name, prec, learned, pc in cases:
         meth = S.make_method(w["P"], w["M"], start=start, n_coarse_sweeps=w["n_coarse"],
                              post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
-                             cg_maxit=1000, precision=prec)
+                             cg_maxit=1000, precision=prec, precond=pc)
         sv = S.Solver(prob, meth, stream=stream.cuda_stream)
         sv.set_state(u0)
         train_s = 0.0

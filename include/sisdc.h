@@ -87,6 +87,10 @@ enum { SISDC_FP64 = 0,   /* every solve in FP64                             */
                              FP64; operators and CG vectors of the inner
                              solves are FP32 with FP32 accumulation        */
 enum { SISDC_CG_AUTO = 0, SISDC_CG_MULTI_KERNEL = 1, SISDC_CG_PERSISTENT_COOPERATIVE = 2 };
+enum { SISDC_PRECOND_JACOBI = 0,  /* point Jacobi (the diagonal of A)               */
+       SISDC_PRECOND_FDS = 1 };   /* element-block Jacobi by fast diagonalisation
+                                     (Sec. 8, "Runtime analysis": the paper's
+                                     alternative to PCG, here as a preconditioner) */
 
 typedef struct {
   int dim;             /* 2 or 3                                            */
@@ -169,6 +173,15 @@ typedef struct {
                           totals the method conserves hold to round-off at any
                           PCG tolerance; 0: the iterate as the PCG leaves it
                           (totals drift by up to the tolerance per solve)   */
+  int precond;         /* PCG preconditioner: SISDC_PRECOND_JACOBI (default)
+                          or SISDC_PRECOND_FDS: on levels whose implicit
+                          coefficient is isotropic and constant (the systems'
+                          kappa_m I; the scalar equations under IMEX Euler),
+                          z = A_ee^-1 r per element, A_ee the element's
+                          diagonal block of M + dt_m K, applied exactly by
+                          fast diagonalisation (one small eigenproblem per
+                          axis at set-up); FP64 solves of those levels only,
+                          other levels and the FP32 inner solves keep Jacobi */
 } sisdc_method;
 
 typedef struct {
@@ -297,10 +310,13 @@ int helmholtz_solve_noalloc(sisdc_handle* h, int level, double dt_m, const doubl
  *   SISDC_OP_QUAD    out[m] = sum_i S_{m,i} in[i], S = dt_m w^nn (eq.
  *                    nn_weights; dt_m here is the step dt): in and out hold
  *                    M nodal vectors each ([m][var][elem][node], nodes 1..M)
+ *   SISDC_OP_PRECOND out = A_ee^-1 in per element: the element-block Jacobi
+ *                    preconditioner of M + dt_m K_D (isotropic constant D
+ *                    only, else SISDC_EINVAL), by fast diagonalisation
  * All other vectors are single nodal vectors of the named level. */
 enum { SISDC_OP_MASS = 0, SISDC_OP_CONV = 1, SISDC_OP_FRHS = 2, SISDC_OP_SIPG = 3,
        SISDC_OP_HELM = 4, SISDC_OP_PROJECT = 5, SISDC_OP_INTERP = 6,
-       SISDC_OP_RESTRICT = 7, SISDC_OP_QUAD = 8 };
+       SISDC_OP_RESTRICT = 7, SISDC_OP_QUAD = 8, SISDC_OP_PRECOND = 9 };
 int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* in,
                 const double* aux, double* out, int mem);
 

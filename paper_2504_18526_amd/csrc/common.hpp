@@ -5,6 +5,7 @@
 namespace sisdc {
 
 constexpr int kMaxP = 8;
+constexpr int kMaxComp = 5;  // conserved components (Navier-Stokes in 3-D)
 
 // Periodic uniform Cartesian mesh of one level.
 struct Geo {
@@ -54,6 +55,10 @@ struct CGRes {
 template <typename T>
 struct CGStateT {
   T *x, *r, *z, *p, *s, *w;
+  const T* zs;     // streaming isotropic path with the block-Jacobi preconditioner: the stored z
+                   // (its kernel writes z and the (r, z), (r, r) partials after every update); NULL: z = r idg
+  const T* x0;     // streaming isotropic path: the initial guess when x does not hold it (else NULL);
+                   // the first update of x reads it, so no copy x0 -> x precedes the solve
   T* trace;        // face traces of (D grad z)
   const T* b;
   const T* diag;
@@ -66,6 +71,18 @@ struct CGStateT {
   CGRes* res;
   T tol2;
   int cap;         // partial slots per array (>= grid of the element kernels)
+  // Conservation correction fused into the streaming isotropic PCG (NULL:
+  // off).  Block partial sums by component c < kMaxComp, cap slots each:
+  // cons[c cap, ...) sum b, cons[(5 + c) cap, ...) sum A x0 (= sum M x0),
+  // cons[(10 + c) cap, ...) each update block's running sum over the
+  // iterations k of alpha_k sum s_k (s_k = A p_k, so sum s_k = sum M p_k).
+  // The last kernel shifts every component of x by (sum b - sum M x) /
+  // mass_total, sum M x = sum M x0 + sum_k alpha_k sum M p_k.
+  T* cons;
+  long vs;         // values per component
+  int nv;          // components (at most kMaxComp)
+  int nparts;      // grid of the start and update kernels
+  T mass_total;    // 1^T M 1 of one component
 };
 using CGState = CGStateT<double>;
 

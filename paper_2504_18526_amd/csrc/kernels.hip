@@ -84,6 +84,27 @@ __device__ void block_partials(const T (&v)[K], T* const (&part)[K]) {
   }
 }
 
+// Block-wide sums of K per-thread values, returned to thread 0 (tot is
+// undefined in the other threads).  Every thread of the block must call it.
+template <typename T, int K>
+__device__ void block_sum(const T (&v)[K], T (&tot)[K]) {
+  __shared__ T sred[K][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    const T x = wave_sum63(v[k]);
+    if (lane == 63) sred[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) {
+      T s = T(0);
+      for (int w = 0; w < nw; ++w) s += sred[k][w];
+      tot[k] = s;
+    }
+}
+
 // Fixed-order sums of the first n partials of each of K arrays, returned to
 // every thread of the block (the same bits in every block).  Every thread of
 // the block must call it.
@@ -317,11 +338,12 @@ k_visc_trace(const double* __restrict__ u, double* __restrict__ trace, Geo g, Eq
 }
 
 // Pass 2: out += V(u) = J w sum_d (2/h_d) D_d f_v,d + sum_faces J_f w_f
-// ({f_v} - f_v^-).n  (accumulated onto out, which holds C(u)).
+// ({f_v} - f_v^-).n  (accumulated onto out, which holds C(u)); with add
+// != NULL, out = add + V(u) instead (add holds C(u), out is not read).
 template <int DIM, int P>
 __global__ void __launch_bounds__((EL<DIM, P>::NT))
 k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ trace, Geo g, EqP q,
-             const double* __restrict__ tab, long vs) {
+             const double* __restrict__ tab, long vs, const double* __restrict__ add) {
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2;
   __shared__ double sD[N1 * N1], sw[N1];
@@ -380,7 +402,13 @@ k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const doubl
         acc[v] += jfwf * 0.5 * sgn * (fnb - f[v]);
       }
     }
-  for (int v = 1; v < NV; ++v) out[v * vs + (long)e * NP + n] += acc[v];
+  const long i0 = (long)e * NP + n;
+  if (add) {
+    out[i0] = add[i0];  // the mass row has no viscous term
+    for (int v = 1; v < NV; ++v) out[v * vs + i0] = add[v * vs + i0] + acc[v];
+  } else {
+    for (int v = 1; v < NV; ++v) out[v * vs + i0] += acc[v];
+  }
 }
 
 // ---------------------------------------------------------------- SIPG
@@ -661,10 +689,11 @@ __device__ __forceinline__ constexpr T gll_w() {
   return v;
 }
 
+// Axis D of the isotropic apply on one grid line, the neighbours' lines
+// across the two faces given (nlm: minus side, nlp: plus side).
 template <typename T, int P, int D>
-__device__ __forceinline__ void iso_axis(const T* __restrict__ xc, const T* sc, bool scaled,
-                                         const T (&xl)[P + 1], T (&r)[P + 1], int nbm, int nbp, int a, int b,
-                                         const Geo& g, T nu, T pen, T wab) {
+__device__ __forceinline__ void iso_axis_nl(const T (&xl)[P + 1], const T (&nlm)[P + 1], const T (&nlp)[P + 1],
+                                            T (&r)[P + 1], const Geo& g, T nu, T pen, T wab) {
   constexpr int N1 = P + 1;
   const T rh = (T)g.rh2[D], J = (T)g.J;
   T q[N1], Q[N1];
@@ -682,8 +711,7 @@ __device__ __forceinline__ void iso_axis(const T* __restrict__ xc, const T* sc, 
     constexpr int ke = side ? P : 0;   // this element's node on the face
     constexpr int kn = side ? 0 : P;   // the neighbour's node on the face
     const T sgn = side ? T(1.0) : -T(1.0);
-    T nl[N1];
-    load_line<T, P, D>(xc, side ? nbp : nbm, a, b, sc, scaled, nl);
+    const T(&nl)[N1] = side ? nlp : nlm;
     T sn = T(0.0);
     static_for<N1>([&](auto jc) { sn += gll_d<T, P, kn, decltype(jc)::value>() * nl[decltype(jc)::value]; });
     const T qn = T(0.5) * sgn * (q[ke] + nu * rh * sn);
@@ -697,6 +725,17 @@ __device__ __forceinline__ void iso_axis(const T* __restrict__ xc, const T* sc, 
     static_for<N1>([&](auto jc) { s += gll_d<T, P, decltype(jc)::value, k>() * Q[decltype(jc)::value]; });
     r[k] += rh * s;
   });
+}
+
+// Axis D with the neighbours' lines loaded from global memory.
+template <typename T, int P, int D>
+__device__ __forceinline__ void iso_axis(const T* __restrict__ xc, const T* sc, bool scaled,
+                                         const T (&xl)[P + 1], T (&r)[P + 1], int nbm, int nbp, int a, int b,
+                                         const Geo& g, T nu, T pen, T wab) {
+  T nlm[P + 1], nlp[P + 1];
+  load_line<T, P, D>(xc, nbm, a, b, sc, scaled, nlm);
+  load_line<T, P, D>(xc, nbp, a, b, sc, scaled, nlp);
+  iso_axis_nl<T, P, D>(xl, nlm, nlp, r, g, nu, pen, wab);
 }
 
 template <typename T, int P>
@@ -769,6 +808,136 @@ k_sipg_apply_iso3(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
       dacc += val * xl[k];
     }
     wave_lds_fence();  // the next pair's stores follow these loads
+  }
+  if (part != nullptr) {
+    const T v1[1] = {dacc};
+    T* const pp[1] = {part};
+    block_partials<T, 1>(v1, pp);
+  }
+}
+
+// The isotropic apply on hexahedra with P = 7 (one wave per element, a lane
+// per grid line) for meshes with an even number of elements along every
+// axis, by 2 x 2 x 2 bricks: a workgroup of 8 waves takes one brick of one
+// component at a time, loads the brick's 8 elements once into LDS (padded
+// rows, so that lines along any axis are read with at most 3-way bank
+// conflicts), and reads every line of an element and of the neighbour inside
+// the brick from there; only the neighbour outside the brick, one per axis,
+// comes from global memory (the first axis's lines are requested before the
+// brick is staged).  Per element that is 4 element-sized reads through the
+// cache hierarchy instead of 9 (own element once per axis, both neighbours
+// per axis).  Same operator, operand scaling, output and partials as
+// k_sipg_apply_iso3; bricks are numbered x fastest and every XCD takes a
+// contiguous range of (component, brick) tasks.
+template <int P>
+struct ISOB {
+  static constexpr int N1 = P + 1, NP = N1 * N1 * N1;
+  static constexpr int SY = N1 + 1, SZ = N1 * SY, REG = N1 * SZ;  // padded element layout in LDS
+  static constexpr int NT = 8 * 64;
+  static_assert(N1 * N1 == 64, "one lane per grid line of a wave");
+};
+
+template <typename T, int P, int D>
+__device__ __forceinline__ void lds_line(const T* el, int a, int b, T (&v)[P + 1]) {
+  using I = ISOB<P>;
+#pragma unroll
+  for (int k = 0; k < P + 1; ++k)
+    v[k] = el[D == 0 ? k + I::SY * a + I::SZ * b : (D == 1 ? a + I::SY * k + I::SZ * b : a + I::SY * b + I::SZ * k)];
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__((ISOB<P>::NT), 4)
+k_sipg_apply_iso3_brick(const T* __restrict__ x, const T* __restrict__ isc, T* __restrict__ out, int nv, long vs,
+                        T nu, T alpha, T beta, T ctau, Geo g, const T* __restrict__ tab, T* part,
+                        const int* __restrict__ done_gen, int id) {
+  using I = ISOB<P>;
+  constexpr int N1 = I::N1, NP = I::NP, SY = I::SY, SZ = I::SZ, REG = I::REG;
+  if (done_gen != nullptr && *done_gen == id) return;
+  __shared__ T sX[8 * REG];  // the brick's operand, element w at sX + w REG
+  __shared__ T sR[8 * REG];  // per wave: the axis contributions of its element
+  __shared__ T sc[NP];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int a = lane % N1, b = lane / N1;
+  const int bx = wave & 1, by = (wave >> 1) & 1, bz = wave >> 2;
+  T* const R = &sR[wave * REG];
+  T* const X = &sX[wave * REG];
+  const T* const w = tab + N1 * N1;
+  const T pen = ctau * (T)(N1 * N1), J = (T)g.J;
+  const T wab[3] = {w[b] * w[a], w[a] * w[b], w[a] * w[b]};
+  const bool scaled = isc != nullptr;
+  for (int k = threadIdx.x; k < NP; k += blockDim.x) sc[k] = scaled ? isc[k] : T(1.0);
+  __syncthreads();
+  const int nbx = g.ne[0] / 2, nby = g.ne[1] / 2, nbz = g.ne[2] / 2;
+  const long nbr = (long)nbx * nby * nbz, ntask = (long)nv * nbr;
+  const int G = gridDim.x, xcd = blockIdx.x % kXcd, per = G / kXcd, rem = G % kXcd;
+  const long kx = per + (xcd < rem ? 1 : 0);
+  const long lb0 = (long)xcd * per + (xcd < rem ? xcd : rem);
+  const long ts = lb0 * ntask / G, te = (lb0 + kx) * ntask / G;
+  T dacc = T(0.0);
+  for (long t = ts + blockIdx.x / kXcd; t < te; t += kx) {
+    const int c = (int)(t / nbr);
+    const long br = t - (long)c * nbr;
+    const int Bx = (int)(br % nbx), By = (int)((br / nbx) % nby), Bz = (int)(br / ((long)nbx * nby));
+    const int ex = 2 * Bx + bx, ey = 2 * By + by, ez = 2 * Bz + bz;
+    const int e = ex + g.ne[0] * (ey + g.ne[1] * ez);
+    // the neighbour outside the brick along each axis (periodic)
+    const int ox = bx ? (ex + 1 == g.ne[0] ? 0 : ex + 1) : (ex == 0 ? g.ne[0] - 1 : ex - 1);
+    const int oy = by ? (ey + 1 == g.ne[1] ? 0 : ey + 1) : (ey == 0 ? g.ne[1] - 1 : ey - 1);
+    const int oz = bz ? (ez + 1 == g.ne[2] ? 0 : ez + 1) : (ez == 0 ? g.ne[2] - 1 : ez - 1);
+    const int nx = ox + g.ne[0] * (ey + g.ne[1] * ez);
+    const int ny = ex + g.ne[0] * (oy + g.ne[1] * ez);
+    const int nz = ex + g.ne[0] * (ey + g.ne[1] * oz);
+    const T* const xc = x + c * vs;
+    T ext[N1];
+    load_line<T, P, 0>(xc, nx, a, b, sc, scaled, ext);
+    // stage the element (scaled) into the brick: lane holds node q 64 + lane
+    {
+      const T* const xe = xc + (long)e * NP;
+#pragma unroll
+      for (int q = 0; q < N1; ++q) {
+        const int n = q * 64 + lane;
+        X[(n % N1) + SY * ((n / N1) % N1) + SZ * q] = xe[n] * sc[n];
+      }
+    }
+    __syncthreads();  // the brick is staged
+    T xl[N1], nl[N1], r[N1];
+    // axis 0: the neighbour inside the brick is wave ^ 1
+    lds_line<T, P, 0>(X, a, b, xl);
+    lds_line<T, P, 0>(&sX[(wave ^ 1) * REG], a, b, nl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    if (bx) iso_axis_nl<T, P, 0>(xl, nl, ext, r, g, nu, pen, wab[0]);
+    else    iso_axis_nl<T, P, 0>(xl, ext, nl, r, g, nu, pen, wab[0]);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) R[k + SY * a + SZ * b] = r[k];
+    wave_lds_fence();
+    // axis 1: wave ^ 2
+    load_line<T, P, 1>(xc, ny, a, b, sc, scaled, ext);
+    lds_line<T, P, 1>(X, a, b, xl);
+    lds_line<T, P, 1>(&sX[(wave ^ 2) * REG], a, b, nl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    if (by) iso_axis_nl<T, P, 1>(xl, nl, ext, r, g, nu, pen, wab[1]);
+    else    iso_axis_nl<T, P, 1>(xl, ext, nl, r, g, nu, pen, wab[1]);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) R[a + SY * k + SZ * b] += r[k];
+    wave_lds_fence();
+    // axis 2: wave ^ 4, then the mass term and the output along z-lines
+    load_line<T, P, 2>(xc, nz, a, b, sc, scaled, ext);
+    lds_line<T, P, 2>(X, a, b, xl);
+    lds_line<T, P, 2>(&sX[(wave ^ 4) * REG], a, b, nl);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = T(0.0);
+    if (bz) iso_axis_nl<T, P, 2>(xl, nl, ext, r, g, nu, pen, wab[2]);
+    else    iso_axis_nl<T, P, 2>(xl, ext, nl, r, g, nu, pen, wab[2]);
+    const T jab = J * w[a] * w[b];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const T val = alpha * jab * w[k] * xl[k] + beta * (r[k] + R[a + SY * b + SZ * k]);
+      out[c * vs + (long)e * NP + line_node<2, N1>(k, a, b)] = val;
+      dacc += val * xl[k];
+    }
+    __syncthreads();  // every wave is done with the brick and its R region
   }
   if (part != nullptr) {
     const T v1[1] = {dacc};
@@ -929,30 +1098,97 @@ __global__ void k_inv_table(const T* __restrict__ diag, T* __restrict__ idg, int
   for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < np; n += gridDim.x * blockDim.x) idg[n] = T(1.0) / diag[n];
 }
 
+// Per-thread sums by component over a flat vector in components of vs
+// values, for a thread striding upwards through its range: the running sum
+// of the current component is folded into acc[c] only when the index passes
+// into the next component (at most a few times per thread).
+template <typename T>
+struct CompSum {
+  T acc[kMaxComp];
+  T cur;
+  int c;
+  long next;
+  __device__ __forceinline__ void init(long vs) {
+#pragma unroll
+    for (int k = 0; k < kMaxComp; ++k) acc[k] = T(0.0);
+    cur = T(0.0);
+    c = 0;
+    next = vs;
+  }
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int k = 0; k < kMaxComp; ++k) acc[k] += k == c ? cur : T(0.0);
+    cur = T(0.0);
+  }
+  __device__ __forceinline__ void add(long i, long vs, T v) {
+    if (i >= next) {
+      fold();
+      while (i >= next) {
+        ++c;
+        next += vs;
+      }
+    }
+    cur += v;
+  }
+};
+
 // Jacobi-PCG (Chronopoulos-Gear) for the isotropic operator, streaming form:
 // z = r idg is never stored (the matvec scales r itself), so an iteration
 // moves r, w, p, s, x in and r, p, s, x out, with no face traces.  Same
 // partial-sum protocol and stopping test as k_cg_start / k_cg_iter; blocks
 // take contiguous ranges of the flattened vectors.
+// With cg.b == NULL the right-hand side is the combination bl, formed node
+// by node here (mw: the element's NP mass weights), so no assembly pass
+// writes it first.
 template <typename T, int NP>
-__global__ void __launch_bounds__(1024) k_cg_start_iso(CGStateT<T> cg, const T* __restrict__ idg, long n) {
+__global__ void __launch_bounds__(1024)
+k_cg_start_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, LinComb bl, const double* __restrict__ mw) {
   T a[3] = {T(0.0), T(0.0), T(0.0)};
+  CompSum<T> sb, sw;  // conservation: sum b and sum A x0 by component
+  sb.init(cg.vs);
+  sw.init(cg.vs);
   const long lb = xcd_block(blockIdx.x, gridDim.x);
   const long i0 = lb * n / gridDim.x, i1 = (lb + 1) * n / gridDim.x;
+  if (cg.cons && threadIdx.x < kMaxComp) cg.cons[(10 + threadIdx.x) * cg.cap + blockIdx.x] = T(0.0);
   for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const T bi = cg.b[i];
-    const T ri = bi - cg.w[i];
+    T bi;
+    if (cg.b) {
+      bi = cg.b[i];
+    } else {
+      const double m = mw[i % NP];
+      double v = 0.0;
+      for (int j = 0; j < bl.n; ++j) v += bl.c[j] * (bl.m[j] ? m : 1.0) * bl.x[j][i];
+      bi = (T)v;
+    }
+    const T wi = cg.w[i];
+    const T ri = bi - wi;
     const T zi = ri * idg[i % NP];
     cg.r[i] = ri;
     a[0] += ri * zi;
     a[1] += ri * ri;
     a[2] += bi * bi;
+    if (cg.cons) {
+      sb.add(i, cg.vs, bi);
+      sw.add(i, cg.vs, wi);
+    }
   }
   T* const pp[3] = {cg.gam, cg.rr, cg.bbp};
   block_partials<T, 3>(a, pp);
+  if (cg.cons) {  // uniform over the grid
+    sb.fold();
+    sw.fold();
+    T* const pb[kMaxComp] = {cg.cons, cg.cons + cg.cap, cg.cons + 2 * cg.cap, cg.cons + 3 * cg.cap,
+                             cg.cons + 4 * cg.cap};
+    block_partials<T, kMaxComp>(sb.acc, pb);
+    T* const pw[kMaxComp] = {cg.cons + 5 * cg.cap, cg.cons + 6 * cg.cap, cg.cons + 7 * cg.cap, cg.cons + 8 * cg.cap,
+                             cg.cons + 9 * cg.cap};
+    block_partials<T, kMaxComp>(sw.acc, pw);
+  }
 }
 
-template <typename T, int NP>
+// ZS: z is stored (block-Jacobi preconditioner); CONS: conservation sums.
+// Both are template flags, so the plain form's loop carries no test of them.
+template <typename T, int NP, bool ZS, bool CONS>
 __global__ void __launch_bounds__(1024)
 k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id, int nparts, int ndel) {
   if (*cg.done_gen == id) return;
@@ -997,37 +1233,191 @@ k_cg_iter_iso(CGStateT<T> cg, const T* __restrict__ idg, long n, int it, int id,
   // k_cg_fix_iso adds a last pending step after the loop.
   const bool odd = (it & 1) != 0;
   const T aprev = odd ? cg.alpha[(it + 1) % 2] : T(0.0);
+  // conservation: sum M p by component, as sum s (s = A p, and the SIPG part
+  // of A sums to zero)
+  CompSum<T> cs;
+  cs.init(cg.vs);
   for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const T ig = idg[i % NP];
     const T r0 = cg.r[i], wi = cg.w[i];
-    const T z0 = r0 * ig;
+    const T z0 = ZS ? cg.zs[i] : r0 * ig;  // stored z of the block-Jacobi preconditioner
     const T pold = it == 0 ? T(0.0) : cg.p[i];
     const T pi = z0 + beta * pold;
     const T si = it == 0 ? wi : wi + beta * cg.s[i];
     cg.p[i] = pi;
     cg.s[i] = si;
-    if (odd) cg.x[i] += aprev * pold + alpha * pi;
+    if (odd) cg.x[i] = (it == 1 && cg.x0 ? cg.x0[i] : cg.x[i]) + aprev * pold + alpha * pi;
     const T ri = r0 - alpha * si;
     cg.r[i] = ri;
     const T zi = ri * ig;
     a[0] += ri * zi;
     a[1] += ri * ri;
+    if (CONS) cs.add(i, cg.vs, si);
   }
   T* const pp[2] = {cg.gam + ((it + 1) % 3) * cap, cg.rr + ((it + 1) % 2) * cap};
   block_partials<T, 2>(a, pp);
+  if (CONS) {
+    // this block's share of alpha_it sum M p_it joins its running total (the
+    // block owns its slots, so no other block reads or writes them)
+    cs.fold();
+    T tot[kMaxComp];
+    block_sum<T, kMaxComp>(cs.acc, tot);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < kMaxComp; ++c) cg.cons[(10 + c) * cap + blockIdx.x] += alpha * tot[c];
+  }
+}
+
+// Element-block Jacobi preconditioner of the isotropic operator by fast
+// diagonalisation: z_e = A_ee^-1 r_e, A_ee the element's diagonal block of
+// M + dt_m K_{nu I}, which on an affine hexahedron (quadrilateral) with
+// constant nu is the Kronecker sum J (W x W x W + dtk sum_d K_d x W x W),
+// each K_d the one-axis matrix of the host's fds_axis.  With S_d^T W S_d =
+// I and S_d^T K_d S_d = diag(lam_d):
+//   A_ee^-1 = (1/J) (S_z x S_y x S_x) diag(1 / (1 + dtk (lam_x + lam_y +
+//   lam_z))) (S_z x S_y x S_x)^T,
+// applied as one contraction per axis forward (S^T), the diagonal, and one
+// per axis back (S), through two LDS buffers.  fds: S_0, S_1, S_2 (n1^2
+// each, row-major S[i n1 + k]) then lam_0, lam_1, lam_2 (n1 each).  A
+// workgroup holds EPB elements of one component (a tile, one thread per
+// node) and loops over the (component, tile) pairs of its contiguous range.
+// part_rz / part_rr != NULL: block partials of (r, z) and (r, r);
+// done_gen != NULL: exit when *done_gen == id.
+template <typename T, int DIM, int P>
+__global__ void __launch_bounds__((EL<DIM, P>::NT))
+k_fds_apply(const T* __restrict__ r, T* __restrict__ z, int nv, Geo g, const T* __restrict__ fds, T dtk,
+            T* part_rz, T* part_rr, const int* __restrict__ done_gen, int id) {
+  using L = EL<DIM, P>;
+  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  if (done_gen != nullptr && *done_gen == id) return;
+  __shared__ T sS[3 * N1 * N1], sl[3 * N1];
+  __shared__ T b0[EPB * NP], b1[EPB * NP];
+  for (int k = threadIdx.x; k < 3 * N1 * N1; k += blockDim.x) sS[k] = fds[k];
+  for (int k = threadIdx.x; k < 3 * N1; k += blockDim.x) sl[k] = fds[3 * N1 * N1 + k];
+  const int t = threadIdx.x, le = t / NP, n = t - le * NP;
+  int ii[3];
+  decomp<DIM, N1>(n, ii);
+  const int tiles = (g.E + EPB - 1) / EPB, ntot = nv * tiles;
+  int t0, t1;
+  tile_range(ntot, t0, t1);
+  const long vs = (long)g.E * NP;
+  const T invJ = T(1.0) / (T)g.J;
+  T arz = T(0.0), arr = T(0.0);
+  __syncthreads();
+  for (int tt = t0; tt < t1; ++tt) {
+    const int c = tt / tiles, tile = tt - c * tiles;
+    const int e = tile * EPB + le;
+    const bool act = le < EPB && e < g.E;
+    const long gi = c * vs + (long)e * NP + n;
+    const T rv = act ? r[gi] : T(0.0);
+    T* const B0 = &b0[le * NP];
+    T* const B1 = &b1[le * NP];
+    if (le < EPB) B0[n] = rv;
+    __syncthreads();
+    // forward: u <- S_d^T u along each axis d (B0 -> B1 -> B0 -> B1)
+    T* src = B0;
+    T* dst = B1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (le < EPB) {
+        const int st = L::stride(d);
+        const T* row = &src[n - ii[d] * st];
+        const T* Sd = &sS[d * N1 * N1];
+        T v = T(0.0);
+#pragma unroll
+        for (int a = 0; a < N1; ++a) v += Sd[a * N1 + ii[d]] * row[a * st];
+        dst[n] = v;
+      }
+      __syncthreads();
+      T* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+    if (le < EPB) {
+      T lsum = T(0.0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) lsum += sl[d * N1 + ii[d]];
+      src[n] *= invJ / (T(1.0) + dtk * lsum);
+    }
+    __syncthreads();
+    // back: u <- S_d u along each axis
+#pragma unroll
+    for (int d = DIM - 1; d >= 0; --d) {
+      if (le < EPB) {
+        const int st = L::stride(d);
+        const T* row = &src[n - ii[d] * st];
+        const T* Sd = &sS[d * N1 * N1];
+        T v = T(0.0);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) v += Sd[ii[d] * N1 + k] * row[k * st];
+        dst[n] = v;
+      }
+      __syncthreads();
+      T* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+    if (act) {
+      const T zv = src[n];
+      z[gi] = zv;
+      arz += rv * zv;
+      arr += rv * rv;
+    }
+    __syncthreads();  // the next tile overwrites both buffers
+  }
+  if (part_rz != nullptr) {
+    const T v2[2] = {arz, arr};
+    T* const pp[2] = {part_rz, part_rr};
+    block_partials<T, 2>(v2, pp);
+  }
 }
 
 // After the loop of k_cg_iter_iso: if the last iteration that updated the
 // vectors (L) was even, x still lacks alpha_L p_L; add it.  L is read from
 // the result record (the converged iteration - 1, else the last launched).
+// With cg.x0 set, x has not been written before iteration 1: L = 0 adds the
+// step to x0, and L < 0 (no update at all) copies x0.
+// With cg.cons set, every component is also shifted by the constant that
+// makes its total sum M x equal sum b: sum M x = sum M x0 + sum_k alpha_k
+// sum M p_k, sum M x0 = sum A x0 (the SIPG part sums to zero), all from the
+// partial sums of the start and update kernels, so x is read and written
+// once more and nothing else.
 template <typename T>
 __global__ void k_cg_fix_iso(CGStateT<T> cg, long n, int id) {
   const bool done = *cg.done_gen == id;
   const int L = done ? cg.res->it - 1 : cg.res->it_last;
-  if (L < 0 || (L & 1)) return;
-  const T al = cg.alpha[L % 2];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    cg.x[i] += al * cg.p[i];
+  T shift[kMaxComp];
+#pragma unroll
+  for (int c = 0; c < kMaxComp; ++c) shift[c] = T(0.0);
+  if (cg.cons) {  // uniform over the grid
+    const int cap = cg.cap;
+    T sb[kMaxComp], sw[kMaxComp], sp[kMaxComp];
+    const T* const pb[kMaxComp] = {cg.cons, cg.cons + cap, cg.cons + 2 * cap, cg.cons + 3 * cap, cg.cons + 4 * cap};
+    sum_partials<T, kMaxComp>(pb, cg.nparts, sb);
+    const T* const pw[kMaxComp] = {cg.cons + 5 * cap, cg.cons + 6 * cap, cg.cons + 7 * cap, cg.cons + 8 * cap,
+                                   cg.cons + 9 * cap};
+    sum_partials<T, kMaxComp>(pw, cg.nparts, sw);
+    const T* const pr[kMaxComp] = {cg.cons + 10 * cap, cg.cons + 11 * cap, cg.cons + 12 * cap, cg.cons + 13 * cap,
+                                   cg.cons + 14 * cap};
+    sum_partials<T, kMaxComp>(pr, cg.nparts, sp);
+    for (int c = 0; c < cg.nv && c < kMaxComp; ++c) shift[c] = (sb[c] - (sw[c] + sp[c])) / cg.mass_total;
+  } else {
+    if (L >= 0 && (L & 1)) return;  // x already holds every step (the test is on L >= 0: -1 & 1 is 1)
+    if (L < 0 && !cg.x0) return;
+  }
+  const bool pend = L >= 0 && (L & 1) == 0;  // alpha_L p_L not yet in x
+  const T al = pend ? cg.alpha[L % 2] : T(0.0);
+  const T* const xs = cg.x0 && L <= 0 ? cg.x0 : cg.x;  // x0 when x was never written (no odd update)
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    T v = xs[i];
+    if (pend) v += al * cg.p[i];
+    if (cg.cons) {
+      const int c = (int)(i / cg.vs);
+#pragma unroll
+      for (int k = 0; k < kMaxComp; ++k)
+        if (k == c) v += shift[k];
+    }
+    cg.x[i] = v;
+  }
 }
 
 // Jacobi diagonal of M + dt_m K_D (volume terms with d = d' and the face
@@ -1395,34 +1785,89 @@ __global__ void k_space_transfer(const double* __restrict__ in, double* __restri
   for (int o = threadIdx.x; o < npo; o += blockDim.x) out[blk * npo + o] = tp_map(sA, sin_, o, dim, n1i, n1o);
 }
 
-// Space-time transfer, one block per (component, element) and output node:
-// the node's time combination of the inputs is formed in LDS, then mapped in
-// space. Inputs and outputs belong to levels with the same elements.
-__global__ void k_space_time_transfer(TransferMulti t, int dim, int n1i, int n1o, const double* __restrict__ A) {
-  __shared__ double sA[(kMaxP + 1) * (kMaxP + 1)];
-  __shared__ double sin_[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
+// Space-time transfer, one block per (component, element): every source
+// vector of the element is read once, the time combinations of all output
+// nodes are formed in LDS, then each output node is mapped in space by sum
+// factorisation (one 1-D contraction per axis, through two LDS buffers).
+// Inputs and outputs belong to levels with the same elements.  Dynamic LDS:
+// A (n1o x n1i), nout * npi time combinations, two buffers of n1max^dim.
+__global__ void __launch_bounds__(256)
+k_space_time_transfer(TransferMulti t, int dim, int n1i, int n1o, const double* __restrict__ A) {
+  extern __shared__ double smem[];
   const int npi = dim == 2 ? n1i * n1i : n1i * n1i * n1i;
   const int npo = dim == 2 ? n1o * n1o : n1o * n1o * n1o;
-  const long blk = blockIdx.x;  // (var, e)
-  const int mo = blockIdx.y;
+  const int n1m = n1i > n1o ? n1i : n1o;
+  const int nbuf = dim == 2 ? n1m * n1m : n1m * n1m * n1m;
+  double* const sA = smem;                 // A[o * n1i + i]
+  double* const sT = sA + n1o * n1i;       // time combinations, nout x npi
+  double* const sB0 = sT + t.nout * npi;
+  double* const sB1 = sB0 + nbuf;
+  const long blk = blockIdx.x;  // (component, element)
   for (int k = threadIdx.x; k < n1i * n1o; k += blockDim.x) sA[k] = A[k];
   for (int k = threadIdx.x; k < npi; k += blockDim.x) {
-    double v = 0.0;
-    for (int j = 0; j < t.nin; ++j) v += t.c[mo][j] * t.x[j][blk * npi + k];
-    sin_[k] = v;
+    double xv[kTransferIn];
+#pragma unroll
+    for (int j = 0; j < kTransferIn; ++j) xv[j] = j < t.nin ? t.x[j][blk * npi + k] : 0.0;
+    for (int mo = 0; mo < t.nout; ++mo) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < kTransferIn; ++j) v += t.c[mo][j] * xv[j];
+      sT[mo * npi + k] = v;
+    }
   }
   __syncthreads();
-  double* const y = t.y[mo];
-  double* const y2 = t.y2[mo];
-  for (int o = threadIdx.x; o < npo; o += blockDim.x) {
-    double v = tp_map(sA, sin_, o, dim, n1i, n1o);
-    if (t.accumulate) v += y[blk * npo + o];
-    y[blk * npo + o] = v;
-    if (y2) y2[blk * npo + o] = v;
+  for (int mo = 0; mo < t.nout; ++mo) {
+    const double* const src = sT + mo * npi;
+    double* const y = t.y[mo];
+    double* const y2 = t.y2[mo];
+    if (dim == 3) {
+      // x: B0[(c n1i + b) n1o + ox] = sum_a A[ox][a] src[(c n1i + b) n1i + a]
+      for (int k = threadIdx.x; k < n1i * n1i * n1o; k += blockDim.x) {
+        const int ox = k % n1o, cb = k / n1o;
+        double v = 0.0;
+        for (int a = 0; a < n1i; ++a) v += sA[ox * n1i + a] * src[cb * n1i + a];
+        sB0[k] = v;
+      }
+      __syncthreads();
+      // y: B1[(c n1o + oy) n1o + ox] = sum_b A[oy][b] B0[(c n1i + b) n1o + ox]
+      for (int k = threadIdx.x; k < n1i * n1o * n1o; k += blockDim.x) {
+        const int ox = k % n1o, oy = (k / n1o) % n1o, c = k / (n1o * n1o);
+        double v = 0.0;
+        for (int b = 0; b < n1i; ++b) v += sA[oy * n1i + b] * sB0[(c * n1i + b) * n1o + ox];
+        sB1[k] = v;
+      }
+      __syncthreads();
+      // z: out[(oz n1o + oy) n1o + ox] = sum_c A[oz][c] B1[(c n1o + oy) n1o + ox]
+      for (int o = threadIdx.x; o < npo; o += blockDim.x) {
+        const int oxy = o % (n1o * n1o), oz = o / (n1o * n1o);
+        double v = 0.0;
+        for (int c = 0; c < n1i; ++c) v += sA[oz * n1i + c] * sB1[c * n1o * n1o + oxy];
+        if (t.accumulate) v += y[blk * npo + o];
+        y[blk * npo + o] = v;
+        if (y2) y2[blk * npo + o] = v;
+      }
+    } else {
+      // x: B0[b n1o + ox] = sum_a A[ox][a] src[b n1i + a]
+      for (int k = threadIdx.x; k < n1i * n1o; k += blockDim.x) {
+        const int ox = k % n1o, b = k / n1o;
+        double v = 0.0;
+        for (int a = 0; a < n1i; ++a) v += sA[ox * n1i + a] * src[b * n1i + a];
+        sB0[k] = v;
+      }
+      __syncthreads();
+      for (int o = threadIdx.x; o < npo; o += blockDim.x) {
+        const int ox = o % n1o, oy = o / n1o;
+        double v = 0.0;
+        for (int b = 0; b < n1i; ++b) v += sA[oy * n1i + b] * sB0[b * n1o + ox];
+        if (t.accumulate) v += y[blk * npo + o];
+        y[blk * npo + o] = v;
+        if (y2) y2[blk * npo + o] = v;
+      }
+    }
+    __syncthreads();  // the next output node overwrites the buffers
   }
 }
 
-// ---------------------------------------------------------------- mixed precision
 __global__ void k_cast_f(const double* __restrict__ in, float* __restrict__ out, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
@@ -1664,6 +2109,11 @@ static bool iso_coef(const CoefT<T>& cf) {
 }
 
 template <typename T, int DIM, int P>
+static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha, T beta,
+                              T ctau, const Geo& g, const T* tab, T* part, const int* done_gen, int id,
+                              hipStream_t s);
+
+template <typename T, int DIM, int P>
 static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, const T* trace, T alpha, T beta,
                               T ctau, const Geo& g, const T* tab, const T* dotv, T* part, const int* done_gen,
                               int id, hipStream_t s) {
@@ -1672,18 +2122,10 @@ static hipError_t apply_dim_p(const T* x, T* out, int nv, const CoefT<T>& cf, co
   // the partial count must equal the grid of the CG kernels that sum them
   const int nb = part ? std::min(elem_tiles<DIM, P>(g), kElemCap) : elem_tiles<DIM, P>(g);
   if constexpr (DIM == 2 || P == 1 || P == 3 || P == 7) {
-    if (iso_coef(cf) && part == nullptr) {  // the isotropic CG calls launch_sipg_apply_iso
-      using K = IsoKernel<T, DIM, P>;
-      const long groups = ((long)nv * g.E + K::GPB - 1) / K::GPB;
-      const int nbi = (int)std::min<long>(std::max<long>(groups, 1), 8192);
-      if constexpr (DIM == 3)
-        hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const T*)nullptr, out, nv,
-                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
-      else
-        hipLaunchKernelGGL((k_sipg_apply_iso2<T, P>), dim3(nbi), dim3(K::NT), 0, s, x, (const T*)nullptr, out, nv,
-                           vs, cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id, (const T*)nullptr);
-      return hipGetLastError();
-    }
+    // the isotropic kernel in the launch configuration of the isotropic CG
+    // (launch_sipg_apply_iso), so a stage application runs the same grid
+    if (iso_coef(cf) && part == nullptr)
+      return apply_iso_p<T, DIM, P>(x, nullptr, out, nv, cf, alpha, beta, ctau, g, tab, nullptr, done_gen, id, s);
   }
   hipLaunchKernelGGL((k_sipg_apply<T, DIM, P>), dim3(nb), dim3(L::NT), 0, s, x, out, nv, vs, cf, trace, alpha,
                      beta, ctau, g, tab, dotv, part, done_gen, id);
@@ -1792,9 +2234,31 @@ static int iso_grid(const Geo& g) {
 // Grid of the isotropic matvec: the workgroups that are resident at once
 // (so that each XCD's interleaved window of pairs is the one in flight),
 // at most kElemCap (partial sums) and at most one per lane group needed.
+// The brick form of the hexahedral P = 7 matvec needs an even number of
+// elements along every axis.
+template <int DIM, int P>
+static bool iso_brick(const Geo& g) {
+  return DIM == 3 && P == 7 && g.ne[0] % 2 == 0 && g.ne[1] % 2 == 0 && g.ne[2] % 2 == 0;
+}
+
 template <typename T, int DIM, int P>
 static int iso_apply_grid(const Geo& g, int nv) {
   using K = IsoKernel<T, DIM, P>;
+  if constexpr (DIM == 3 && P == 7) {
+    if (iso_brick<DIM, P>(g)) {
+      static const int resident_b = [] {
+        int dev = 0, ncu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sipg_apply_iso3_brick<T, P>,
+                                                         ISOB<P>::NT, 0) != hipSuccess)
+          return kElemCap;
+        return std::max(1, per_cu * ncu);
+      }();
+      const long tasks = (long)nv * (g.E / 8);
+      return (int)std::max<long>(1, std::min<long>({(long)resident_b, (long)kElemCap, tasks}));
+    }
+  }
   static const int resident = [] {
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1813,6 +2277,13 @@ static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const Co
                               hipStream_t s) {
   const long vs = (long)g.E * EL<DIM, P>::NP;
   const int nb = iso_apply_grid<T, DIM, P>(g, nv);
+  if constexpr (DIM == 3 && P == 7) {
+    if (iso_brick<DIM, P>(g)) {
+      hipLaunchKernelGGL((k_sipg_apply_iso3_brick<T, P>), dim3(nb), dim3(ISOB<P>::NT), 0, s, x, isc, out, nv, vs,
+                         cf.nu, alpha, beta, ctau, g, tab, part, done_gen, id);
+      return hipGetLastError();
+    }
+  }
   if constexpr (DIM == 3)
     hipLaunchKernelGGL((k_sipg_apply_iso3<T, P>), dim3(nb), dim3(ISO<P>::NT), 0, s, x, isc, out, nv, vs, cf.nu,
                        alpha, beta, ctau, g, tab, part, done_gen, id);
@@ -1823,10 +2294,14 @@ static hipError_t apply_iso_p(const T* x, const T* isc, T* out, int nv, const Co
 }
 
 template <typename T, int DIM, int P>
-static hipError_t cg_start_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {
+static hipError_t cg_start_iso_p(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, const LinComb* bl,
+                                 const double* mw, hipStream_t s) {
   constexpr int NP = EL<DIM, P>::NP;
+  if (!cg.b && (!bl || !mw)) return hipErrorInvalidValue;
+  LinComb l{};
+  if (!cg.b) l = *bl;
   hipLaunchKernelGGL((k_cg_start_iso<T, NP>), dim3(iso_grid<DIM, P>(g)), dim3(1024), 0, s, cg, idg,
-                     (long)nv * g.E * NP);
+                     (long)nv * g.E * NP, l, mw);
   return hipGetLastError();
 }
 
@@ -1835,9 +2310,61 @@ static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, con
                                 hipStream_t s) {
   constexpr int NP = EL<DIM, P>::NP;
   const int nb = iso_grid<DIM, P>(g);
-  hipLaunchKernelGGL((k_cg_iter_iso<T, NP>), dim3(nb), dim3(1024), 0, s, cg, idg, (long)nv * g.E * NP, it, id, nb,
-                     iso_apply_grid<T, DIM, P>(g, nv));
+  const long n = (long)nv * g.E * NP;
+  const int nd = iso_apply_grid<T, DIM, P>(g, nv);
+  if (cg.zs && cg.cons)
+    hipLaunchKernelGGL((k_cg_iter_iso<T, NP, true, true>), dim3(nb), dim3(1024), 0, s, cg, idg, n, it, id, nb, nd);
+  else if (cg.zs)
+    hipLaunchKernelGGL((k_cg_iter_iso<T, NP, true, false>), dim3(nb), dim3(1024), 0, s, cg, idg, n, it, id, nb, nd);
+  else if (cg.cons)
+    hipLaunchKernelGGL((k_cg_iter_iso<T, NP, false, true>), dim3(nb), dim3(1024), 0, s, cg, idg, n, it, id, nb, nd);
+  else
+    hipLaunchKernelGGL((k_cg_iter_iso<T, NP, false, false>), dim3(nb), dim3(1024), 0, s, cg, idg, n, it, id, nb, nd);
   return hipGetLastError();
+}
+
+template <int DIM, int P>
+static hipError_t fds_dim_p(const double* r, double* z, int nv, const Geo& g, const double* fds, double dtk,
+                            double* part_rz, double* part_rr, const int* done_gen, int id, hipStream_t s) {
+  using L = EL<DIM, P>;
+  const int tiles = elem_tiles<DIM, P>(g);
+  // with partials: the grid of the streaming CG kernels, whose partial counts they replace
+  const int nb = part_rz ? iso_grid<DIM, P>(g) : std::max(1, std::min(nv * tiles, 4096));
+  hipLaunchKernelGGL((k_fds_apply<double, DIM, P>), dim3(nb), dim3(L::NT), 0, s, r, z, nv, g, fds, dtk, part_rz,
+                     part_rr, done_gen, id);
+  return hipGetLastError();
+}
+
+hipError_t launch_fds(const double* r, double* z, int nv, const Geo& g, const double* fds, double dtk,
+                      double* part_rz, double* part_rr, const int* done_gen, int id, hipStream_t s) {
+  SISDC_DISPATCH(g, fds_dim_p, r, z, nv, g, fds, dtk, part_rz, part_rr, done_gen, id, s);
+}
+
+// Grid of the streaming isotropic CG's start and update kernels on a level
+// (the count of their block partials); 0 where that path does not apply.
+int iso_cg_grid(const Geo& g) {
+  if (g.dim == 3) {
+    switch (g.P) {
+      case 1: return iso_grid<3, 1>(g);
+      case 3: return iso_grid<3, 3>(g);
+      case 7: return iso_grid<3, 7>(g);
+      default: return 0;
+    }
+  }
+  if (g.dim == 2) {
+    switch (g.P) {
+      case 1: return iso_grid<2, 1>(g);
+      case 2: return iso_grid<2, 2>(g);
+      case 3: return iso_grid<2, 3>(g);
+      case 4: return iso_grid<2, 4>(g);
+      case 5: return iso_grid<2, 5>(g);
+      case 6: return iso_grid<2, 6>(g);
+      case 7: return iso_grid<2, 7>(g);
+      case 8: return iso_grid<2, 8>(g);
+      default: return 0;
+    }
+  }
+  return 0;
 }
 
 #define SISDC_PRECISION_LAUNCHERS(T)                                                                            \
@@ -1882,8 +2409,9 @@ static hipError_t cg_iter_iso_p(const CGStateT<T>& cg, const T* idg, int nv, con
     SISDC_DISPATCH_ISO_DIM(g, return (apply_iso_p<T, DD, PP>(x, isc, out, nv, cf, alpha, beta, ctau, g, tab,    \
                                                              part, done_gen, id, s)));                          \
   }                                                                                                             \
-  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s) {    \
-    SISDC_DISPATCH_ISO_DIM(g, return (cg_start_iso_p<T, DD, PP>(cg, idg, nv, g, s)));                           \
+  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, const LinComb* bl,   \
+                                 const double* mw, hipStream_t s) {                                             \
+    SISDC_DISPATCH_ISO_DIM(g, return (cg_start_iso_p<T, DD, PP>(cg, idg, nv, g, bl, mw, s)));                   \
   }                                                                                                             \
   hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
                                 hipStream_t s) {                                                                \
@@ -1898,19 +2426,20 @@ SISDC_PRECISION_LAUNCHERS(double)
 SISDC_PRECISION_LAUNCHERS(float)
 
 template <int DIM, int P>
-static hipError_t visc_dim_p(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
-                             hipStream_t s) {
+static hipError_t visc_dim_p(const double* u, const double* add, double* out, double* trace, const Geo& g,
+                             const EqP& q, const double* tab, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
   hipLaunchKernelGGL((k_visc_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, trace, g, q, tab, vs);
   hipLaunchKernelGGL((k_visc_apply<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, trace, g, q, tab,
-                     vs);
+                     vs, add);
   return hipGetLastError();
 }
 
-hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
-                       hipStream_t s) {
-  SISDC_DISPATCH(g, visc_dim_p, u, out, trace, g, q, tab, s);
+hipError_t launch_visc(const double* u, const double* add, double* out, double* trace, const Geo& g, const EqP& q,
+                       const double* tab, hipStream_t s) {
+  if (add == out) add = nullptr;  // in place: out += V(u)
+  SISDC_DISPATCH(g, visc_dim_p, u, add, out, trace, g, q, tab, s);
 }
 
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s) {
@@ -1929,8 +2458,12 @@ hipError_t launch_space_time_transfer(const TransferMulti& t, int nv, int dim, i
   if (t.nin < 1 || t.nin > kTransferIn || t.nout < 1 || t.nout > kTransferOut || n1i > kMaxP + 1 ||
       n1o > kMaxP + 1 || (dim != 2 && dim != 3))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_space_time_transfer, dim3((unsigned)((long)nv * E), (unsigned)t.nout), dim3(256), 0, s, t,
-                     dim, n1i, n1o, A);
+  const int npi = dim == 2 ? n1i * n1i : n1i * n1i * n1i;
+  const int n1m = std::max(n1i, n1o);
+  const int nbuf = dim == 2 ? n1m * n1m : n1m * n1m * n1m;
+  const size_t lds = sizeof(double) * ((size_t)n1i * n1o + (size_t)t.nout * npi + 2 * (size_t)nbuf);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_space_time_transfer, dim3((unsigned)((long)nv * E)), dim3(256), lds, s, t, dim, n1i, n1o, A);
   return hipGetLastError();
 }
 

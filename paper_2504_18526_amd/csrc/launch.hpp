@@ -45,18 +45,32 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
   hipError_t launch_sipg_apply_iso(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha,       \
                                    T beta, T ctau, const Geo& g, const T* tab, T* part, const int* done_gen,    \
                                    int id, hipStream_t s);                                                      \
-  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, hipStream_t s);     \
+  /* cg.b == NULL: the right-hand side is the combination bl (FP64 only; mw the element's mass weights) */     \
+  hipError_t launch_cg_start_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, const LinComb* bl,   \
+                                 const double* mw, hipStream_t s);                                              \
   hipError_t launch_cg_iter_iso(const CGStateT<T>& cg, const T* idg, int nv, const Geo& g, int it, int id,      \
                                 hipStream_t s);                                                                 \
   /* the streaming CG updates x every second iteration; this adds the step still pending after its loop */     \
   hipError_t launch_cg_fix_iso(const CGStateT<T>& cg, long n, int id, hipStream_t s);
 
+// z = A_ee^-1 r per element: the element-block Jacobi preconditioner of the
+// isotropic operator M + dtk K_{I} by fast diagonalisation (fds: the S and
+// lam tables of the three axes, fds_axis); with part_rz != NULL also the
+// block partials of (r, z) and (r, r) in the streaming CG's grid.
+hipError_t launch_fds(const double* r, double* z, int nv, const Geo& g, const double* fds, double dtk,
+                      double* part_rz, double* part_rr, const int* done_gen, int id, hipStream_t s);
+
+// grid of the streaming isotropic CG's start and update kernels (their
+// partial-sum count) on a level; 0 where that path does not apply
+int iso_cg_grid(const Geo& g);
+
 SISDC_DECLARE_PRECISION_LAUNCHERS(double)
 SISDC_DECLARE_PRECISION_LAUNCHERS(float)
 
-// out += V(u), the BR1 viscous term of Navier-Stokes (trace pass + apply pass)
-hipError_t launch_visc(const double* u, double* out, double* trace, const Geo& g, const EqP& q, const double* tab,
-                       hipStream_t s);
+// out = add + V(u), the BR1 viscous term of Navier-Stokes (trace pass + apply
+// pass); add == out (or NULL) accumulates onto out in place
+hipError_t launch_visc(const double* u, const double* add, double* out, double* trace, const Geo& g, const EqP& q,
+                       const double* tab, hipStream_t s);
 hipError_t launch_lincomb(double* out, const LinComb& lc, long n, const double* mw, int np, hipStream_t s);
 // out = add + alpha M x + beta K_{nu I} x on quadrilaterals with isotropic
 // constant D (the 2-D isotropic matvec with an added vector; add must not

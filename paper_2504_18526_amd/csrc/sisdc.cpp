@@ -17,6 +17,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -107,6 +108,7 @@ struct Level {
     int loss_cap = 0;                                            // batches the loss buffer holds
   } net;
   double mass_total = 0.0;  // 1^T M 1 of one component: E times the sum of the element's mass weights
+  double* fds = nullptr;    // fast-diagonalisation tables of the element block (S_d, lam_d per axis)
   bool stale = true;
   double stored_dt = -1.0;
   bool has_g = false;
@@ -138,6 +140,7 @@ struct sisdc_handle {
   std::vector<Level> lv;
   std::vector<Transfer> tr;
   double* partials = nullptr;  // CG partial sums: gam (3 cap), rr (2 cap), del, bbp (cap each)
+  double* cons = nullptr;      // partial sums of the conservation correction fused into the isotropic PCG
   double* alpha = nullptr;     // 2 CG step lengths
   float* partials32 = nullptr; // FP32 CG partial sums (7 cap)
   float* alpha32 = nullptr;
@@ -252,6 +255,11 @@ void copy_d2d(sisdc_handle* h, double* dst, const double* src, long n) {
   HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
 }
 
+template <typename T>
+void copy_any(sisdc_handle* h, T* dst, const T* src, long n) {
+  HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
+}
+
 CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
   CoefP c{};
   if (h->meth.integrator == SISDC_IMEX_EULER) {  // eq. H_IMEX: A_d alone
@@ -313,9 +321,11 @@ void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double*
     lincomb(h, L, f, {{1.0, Cu}, {-1.0, L.t3}});
     return;
   }
+  if (h->eq.eq == EQ_NS && h->eq.mu != 0.0) {
+    HIPCHECK(launch_visc(u, Cu, f, L.trace, L.g, h->eq, L.tab, h->stream));  // f = C(u) + V(u), no copy
+    return;
+  }
   if (f != Cu) copy_d2d(h, f, Cu, L.vlen);
-  if (h->eq.eq == EQ_NS && h->eq.mu != 0.0)
-    HIPCHECK(launch_visc(u, f, L.trace, L.g, h->eq, L.tab, h->stream));
 }
 
 // ------------------------------------------------------------------ PCG
@@ -329,16 +339,17 @@ struct CGBufs {
   T* idg;
   int* done_gen;  // id of the last converged solve
   CGRes* res;     // result record
+  T* cons;        // partial sums of the fused conservation correction (NULL: none)
 };
 
 CGBufs<double> bufs64(sisdc_handle* h, Level& L) {
   return CGBufs<double>{L.cr,       L.cz,     L.cp,  L.cs,        L.cw,  L.diag, L.trace,
-                        L.tab,      h->partials, h->alpha, L.idg, h->done_gen, h->res};
+                        L.tab,      h->partials, h->alpha, L.idg, h->done_gen, h->res, h->cons};
 }
 
 CGBufs<float> bufs32(sisdc_handle* h, Level& L) {
   return CGBufs<float>{L.cr32, L.cz32,        L.cp32,      L.cs32, L.cw32,      L.diag32, L.trace32,
-                       L.tab32, h->partials32, h->alpha32, L.idg32, h->done_gen, h->res};
+                       L.tab32, h->partials32, h->alpha32, L.idg32, h->done_gen, h->res, nullptr};
 }
 
 template <typename T>
@@ -352,6 +363,9 @@ CGStateT<T> cg_state(sisdc_handle* h, const CGBufs<T>& B, const T* b, T* x, doub
   cg.w = B.w;
   cg.trace = B.trace;
   cg.b = b;
+  cg.x0 = nullptr;
+  cg.zs = nullptr;
+  cg.cons = nullptr;
   cg.diag = B.diag;
   cg.cap = kElemCap;
   cg.gam = B.partials;
@@ -580,26 +594,58 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
 // reads the convergence record once per batch.  Returns the iterations, the
 // convergence flag and the final relative (recurred) residual.
 template <typename T>
+// b == NULL: the right-hand side is the combination bl (isotropic levels
+// only: the start kernel forms it node by node).  x0 != NULL: the initial
+// guess, when x does not hold it (on isotropic levels no copy to x is made;
+// the first update of x reads x0).
 sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const CoefT<T>& cf, T dtm, const T* b, T* x,
-                           double rtol, int maxit, bool x_is_zero) {
+                           double rtol, int maxit, bool x_is_zero, const LinComb* bl = nullptr,
+                           const T* x0 = nullptr) {
   hipStream_t s = h->stream;
   const int id = ++h->solve_id;
   const T ctau = (T)h->ctau, one = (T)1;
-  CGStateT<T> cg = cg_state<T>(h, B, b, x, rtol);
-  HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
   // isotropic hexahedral levels: streaming CG, z = r / diag formed inside the matvec
   const bool iso = sipg_iso_path(L.g, cf);
+  if (x0 == x || x_is_zero) x0 = nullptr;
+  if (x0 && !iso) {
+    copy_any(h, x, x0, L.vlen);
+    x0 = nullptr;
+  }
+  if (!b && !(iso && bl)) fail(SISDC_EINVAL, "internal: no right-hand side for the multi-kernel PCG");
+  CGStateT<T> cg = cg_state<T>(h, B, b, x, rtol);
+  cg.x0 = x0;
+  if (iso && B.cons && h->meth.conserve && !x_is_zero) {  // the shift is fused into the PCG's kernels
+    cg.cons = B.cons;
+    cg.vs = L.vs;
+    cg.nv = L.nv;
+    cg.nparts = iso_cg_grid(L.g);
+    cg.mass_total = (T)L.mass_total;
+    if (L.nv > kMaxComp) fail(SISDC_EINVAL, "internal: more components than the conservation sums hold");
+  }
+  HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
   if (iso) HIPCHECK(launch_inv_table(B.diag, B.idg, L.np, s));
   if (x_is_zero) {  // start from x = 0, so A x0 = 0
     HIPCHECK(hipMemsetAsync(x, 0, L.vlen * sizeof(T), s));
     HIPCHECK(hipMemsetAsync(B.w, 0, L.vlen * sizeof(T), s));
   } else {
-    HIPCHECK(launch_sipg(x, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, s));  // A x0
+    HIPCHECK(launch_sipg(x0 ? x0 : x, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, s));  // A x0
   }
+  // element-block Jacobi by fast diagonalisation (FP64 isotropic levels): z
+  // is stored; its kernel follows every update and replaces the update's
+  // (r, z) and (r, r) partials, and the matvec reads z
+  T* const zfds = (iso && h->meth.precond == SISDC_PRECOND_FDS && std::is_same<T, double>::value && L.fds)
+                      ? B.z : nullptr;
+  const double dtk = (double)dtm * (double)cf.nu;
+  auto fds_step = [&](int k, const int* dg, int sid) {  // z = A_ee^-1 r, partials of iteration k
+    HIPCHECK(launch_fds((const double*)B.r, (double*)zfds, L.nv, L.g, L.fds, dtk,
+                        (double*)(cg.gam + (k % 3) * cg.cap), (double*)(cg.rr + (k % 2) * cg.cap), dg, sid, s));
+  };
+  cg.zs = zfds;
   if (iso) {
-    HIPCHECK(launch_cg_start_iso(cg, B.idg, L.nv, L.g, s));
-    HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
-                                   (const int*)nullptr, 0, s));
+    HIPCHECK(launch_cg_start_iso(cg, B.idg, L.nv, L.g, b ? nullptr : bl, L.mw, s));
+    if (zfds) fds_step(0, nullptr, 0);
+    HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g,
+                                   B.tab, cg.del, (const int*)nullptr, 0, s));
   } else {
     HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, B.tab, s));
     HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
@@ -628,9 +674,10 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
         HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
       if (timed) HIPCHECK(hipEventRecord(ev[1], s));
       if (it < maxit) {
+        if (zfds) fds_step(it + 1, (const int*)B.done_gen, id);
         if (iso)
-          HIPCHECK(launch_sipg_apply_iso(B.r, B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g, B.tab, cg.del,
-                                         (const int*)B.done_gen, id, s));
+          HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : B.idg, B.w, L.nv, cf, one, dtm, ctau,
+                                         L.g, B.tab, cg.del, (const int*)B.done_gen, id, s));
         else
           HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
                                      (const int*)B.done_gen, id, s));
@@ -824,7 +871,24 @@ sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, doub
   }
   sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, rtol, maxit, false);
   account(h, r.iters, r.converged, r.rel_residual);
-  conserve_fix(h, L, b, nullptr, x);
+  if (!sipg_iso_path(L.g, cf)) conserve_fix(h, L, b, nullptr, x);  // fused into the isotropic PCG
+  return r;
+}
+
+// Plain FP64 solves on isotropic levels (the systems' kappa_m I) run the
+// streaming multi-kernel PCG straight from the right-hand side's combination
+// (formed node by node in its start kernel) and from x0 (read by its first
+// update of x): no assembly pass and no copy of x0.
+bool stream_iso(sisdc_handle* h, const Level& L, const CoefP& cf) {
+  return h->meth.precision == SISDC_FP64 && sipg_iso_path(L.g, cf);
+}
+
+sisdc_solve_stats solve_iso(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b,
+                            const LinComb* bl, double* x, const double* x0) {
+  // the conservation shift is fused into the PCG's kernels here
+  sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, h->meth.cg_rtol, h->meth.cg_maxit, false,
+                                         bl, x0);
+  account(h, r.iters, r.converged, r.rel_residual);
   return r;
 }
 
@@ -841,6 +905,7 @@ sisdc_solve_stats solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, 
     r.converged = 1;
     return r;
   }
+  if (x0 != x && plain && stream_iso(h, L, cf)) return solve_iso(h, L, cf, dtm, b, nullptr, x, x0);
   if (x0 != x) copy_d2d(h, x, x0, L.vlen);
   return cg_solve(h, L, cf, dtm, b, x, rtol, h->meth.cg_maxit);
 }
@@ -859,6 +924,7 @@ sisdc_solve_stats solve_lc(sisdc_handle* h, Level& L, const CoefP& cf, double dt
     r.converged = 1;
     return r;
   }
+  if (plain && stream_iso(h, L, cf)) return solve_iso(h, L, cf, dtm, nullptr, &lc, x, x0);
   HIPCHECK(launch_lincomb(L.b, lc, L.vlen, L.mw, L.np, h->stream));
   return solve(h, L, cf, dtm, L.b, x, x0);
 }
@@ -1323,6 +1389,23 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
   L.mass_total = 0.0;
   for (int n = 0; n < L.np; ++n) L.mass_total += mw[n];
   L.mass_total *= L.E;
+  {  // fast diagonalisation of the isotropic element block, per axis (unit diffusivity)
+    std::vector<double> ft((size_t)3 * L.n1 * L.n1 + 3 * L.n1, 0.0);
+    for (int d = 0; d < 3; ++d) {
+      std::vector<double> S, lam;
+      if (d < pr.dim) {
+        fds_axis(L.wg, L.D, g.rh2[d], h->ctau * (double)(L.n1 * L.n1), S, lam);
+      } else {
+        S.assign((size_t)L.n1 * L.n1, 0.0);
+        for (int i = 0; i < L.n1; ++i) S[i * L.n1 + i] = 1.0;
+        lam.assign(L.n1, 0.0);
+      }
+      std::copy(S.begin(), S.end(), ft.begin() + (size_t)d * L.n1 * L.n1);
+      std::copy(lam.begin(), lam.end(), ft.begin() + (size_t)3 * L.n1 * L.n1 + d * L.n1);
+    }
+    L.fds = dalloc(ft.size());
+    HIPCHECK(hipMemcpy(L.fds, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   const long n = L.vlen;
   L.u = dalloc((M + 1) * n);
   L.unew = dalloc((M + 1) * n);
@@ -1383,7 +1466,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
 
 void free_level(Level& L) {
   double* ptrs[] = {L.tab, L.mw, L.u, L.unew, L.f, L.C, L.Cnew, L.X, L.gf, L.v, L.r, L.q, L.b, L.y,
-                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.idg};
+                    L.t1, L.t2, L.t3, L.diag, L.cr, L.cz, L.cp, L.cs, L.cw, L.trace, L.idg, L.fds};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (L.fz) (void)hipFree(L.fz);
@@ -1567,6 +1650,7 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->start < SISDC_START_CASCADE || m->start > SISDC_START_CONSTANT) fail(SISDC_EINVAL, "start");
   if (m->n_iter < 0 || m->n_coarse_sweeps < 0) fail(SISDC_EINVAL, "negative sweep count");
   if (m->conserve != 0 && m->conserve != 1) fail(SISDC_EINVAL, "conserve must be 0 or 1");
+  if (m->precond != SISDC_PRECOND_JACOBI && m->precond != SISDC_PRECOND_FDS) fail(SISDC_EINVAL, "precond");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
   if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL &&
@@ -1696,6 +1780,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->tr.resize(meth->n_levels > 1 ? meth->n_levels - 1 : 0);
     for (int l = 0; l + 1 < meth->n_levels; ++l) build_transfer(h->tr[l], h->lv[l], h->lv[l + 1], meth->projection, meth->formulation);
     h->partials = dalloc((size_t)7 * kElemCap);
+    h->cons = dalloc((size_t)15 * kElemCap + 64);
     h->ir_tot = dalloc(2);
     h->gtot = dalloc(4);
     void* pn = nullptr;
@@ -1772,6 +1857,7 @@ int sisdc_destroy(sisdc_handle* h) {
     if (T.Rx) (void)hipFree(T.Rx);
   }
   if (h->partials) (void)hipFree(h->partials);
+  if (h->cons) (void)hipFree(h->cons);
   if (h->alpha) (void)hipFree(h->alpha);
   if (h->partials32) (void)hipFree(h->partials32);
   if (h->ir_tot) (void)hipFree(h->ir_tot);
@@ -2092,6 +2178,13 @@ int sisdc_apply(sisdc_handle* h, int op, int level, double dt_m, const double* i
       case SISDC_OP_PROJECT: space_transfer(h, L, Lout, din, dout, h->tr[level].Px); break;
       case SISDC_OP_RESTRICT: space_transfer(h, L, Lout, din, dout, h->tr[level].Rx); break;
       case SISDC_OP_INTERP: space_transfer(h, Lin, L, din, dout, h->tr[level].Ix); break;
+      case SISDC_OP_PRECOND: {
+        const CoefP cf = coef_for(h, L, dt_m, daux);
+        if (!sipg_iso_path(L.g, cf))
+          fail(SISDC_EINVAL, "the block-Jacobi preconditioner needs an isotropic constant coefficient");
+        HIPCHECK(launch_fds(din, dout, L.nv, L.g, L.fds, dt_m * cf.nu, nullptr, nullptr, nullptr, 0, h->stream));
+        break;
+      }
       default: fail(SISDC_EINVAL, "unknown op");
     }
     dev_out(h, out, dout, Lout.vlen, mem);
@@ -2171,7 +2264,7 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     if (iso) HIPCHECK(launch_inv_table(L.diag, L.idg, L.np, s));
     HIPCHECK(launch_sipg(L.t2, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, s));
     if (iso) {
-      HIPCHECK(launch_cg_start_iso(cg, L.idg, L.nv, L.g, s));
+      HIPCHECK(launch_cg_start_iso(cg, L.idg, L.nv, L.g, nullptr, L.mw, s));
       HIPCHECK(launch_sipg_apply_iso(L.cr, L.idg, L.cw, L.nv, cf, 1.0, dt_m, h->ctau, L.g, L.tab, cg.del,
                                      (const int*)nullptr, 0, s));
     } else {

@@ -149,4 +149,73 @@ std::vector<double> nn_weights(const std::vector<double>& tau) {
   return W;
 }
 
+
+void fds_axis(const std::vector<double>& w, const std::vector<double>& D, double rh, double pen,
+              std::vector<double>& S, std::vector<double>& lam) {
+  const int n = (int)w.size();
+  std::vector<double> K((size_t)n * n, 0.0);
+  // volume: D^T W D
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) v += D[k * n + i] * w[k] * D[k * n + j];
+      K[i * n + j] = v;
+    }
+  // the element's own face terms at its two end nodes
+  for (int side = 0; side < 2; ++side) {
+    const int e = side ? n - 1 : 0;
+    const double sgn = side ? 1.0 : -1.0;
+    for (int j = 0; j < n; ++j) {
+      K[j * n + e] -= 0.5 * sgn * D[e * n + j];  // D^T e e^T: row j, column e
+      K[e * n + j] -= 0.5 * sgn * D[e * n + j];  // e e^T D: row e, column j
+    }
+    K[e * n + e] += 0.5 * pen;
+  }
+  for (double& v : K) v *= rh * rh;
+  // B = W^-1/2 K W^-1/2, symmetric; cyclic Jacobi rotations B -> Q^T B Q
+  std::vector<double> B((size_t)n * n), Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    Q[i * n + i] = 1.0;
+    for (int j = 0; j < n; ++j) B[i * n + j] = K[i * n + j] / std::sqrt(w[i] * w[j]);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) B[i * n + j] = B[j * n + i] = 0.5 * (B[i * n + j] + B[j * n + i]);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) (i == j ? diag : off) += B[i * n + j] * B[i * n + j];
+    if (off <= 1e-32 * diag) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double bpq = B[p * n + q];
+        if (bpq == 0.0) continue;
+        const double theta = 0.5 * (B[q * n + q] - B[p * n + p]) / bpq;
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double bkp = B[k * n + p], bkq = B[k * n + q];
+          B[k * n + p] = c * bkp - sn * bkq;
+          B[k * n + q] = sn * bkp + c * bkq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double bpk = B[p * n + k], bqk = B[q * n + k];
+          B[p * n + k] = c * bpk - sn * bqk;
+          B[q * n + k] = sn * bpk + c * bqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double qkp = Q[k * n + p], qkq = Q[k * n + q];
+          Q[k * n + p] = c * qkp - sn * qkq;
+          Q[k * n + q] = sn * qkp + c * qkq;
+        }
+      }
+  }
+  S.assign((size_t)n * n, 0.0);
+  lam.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    lam[k] = B[k * n + k];
+    for (int i = 0; i < n; ++i) S[i * n + k] = Q[i * n + k] / std::sqrt(w[i]);
+  }
+}
+
 }  // namespace sisdc
+

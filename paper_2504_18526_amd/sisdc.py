@@ -27,7 +27,8 @@ NODES_RADAU_RIGHT, NODES_LOBATTO = 0, 1
 START_CASCADE, START_FMG, START_PREDICTOR, START_CONSTANT = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 CG_AUTO, CG_MULTI_KERNEL, CG_PERSISTENT_COOPERATIVE = 0, 1, 2
-OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT, OP_QUAD = range(9)
+OP_MASS, OP_CONV, OP_FRHS, OP_SIPG, OP_HELM, OP_PROJECT, OP_INTERP, OP_RESTRICT, OP_QUAD, OP_PRECOND = range(10)
+PRECOND_JACOBI, PRECOND_FDS = 0, 1
 
 EXPORTS = [
     "sisdc_last_error", "sisdc_create", "sisdc_destroy", "sisdc_level_info",
@@ -61,7 +62,7 @@ class Method(ctypes.Structure):
                 ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int),
                 ("nodes", ctypes.c_int), ("h_coarsen", ctypes.c_int * 3), ("c_fmg", ctypes.c_int),
-                ("conserve", ctypes.c_int)]
+                ("conserve", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -206,7 +207,7 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
                 n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
                 inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT,
-                h_coarsen=None, c_fmg=1, conserve=1):
+                h_coarsen=None, c_fmg=1, conserve=1, precond=PRECOND_JACOBI):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -230,6 +231,7 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
         m.h_coarsen[i] = int(v)
     m.c_fmg = c_fmg
     m.conserve = conserve
+    m.precond = precond
     return m
 
 

@@ -138,3 +138,64 @@ def test_learned_guess_gain(S):
           f"(rejected guesses {its[True][1]}), train loss {loss0:.3e} -> {loss:.3e}")
     assert rel_l2(out_b.cpu().numpy(), out_a.cpu().numpy()) < 1e-8
     assert its[True][0] <= its[False][0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["convdiff_1l", "burgers_2l", "ns_3d_2l"])
+def test_learned_forms_match_oracle(S, case, precision):
+    """The learned initial guess (and the learned guess with mixed-precision
+    refinement) changes only the starting point of each PCG solve: every step
+    matches the FP64 oracle's step from the same state to the 1e-10 bar
+    (GPU PCG tolerance 1e-12, oracle 1e-14).  The network of every level is
+    first trained on rows harvested from the GPU's own plain solves."""
+    from oracle.sdc import DGLevel, MLSDC, sdc_step
+    if case == "convdiff_1l":
+        eq, dim, n, Ps, Ms, dt, lo, hi = "convdiff", 2, (6, 5), [4], [3], 1.686e-2, [0, 0], [1, 1]
+    elif case == "burgers_2l":
+        eq, dim, n, Ps, Ms, dt, lo, hi = "burgers", 2, (4, 3), [8, 4], [5, 3], 5e-3, [0, 0], [1, 1]
+    else:
+        eq, dim, n, Ps, Ms, dt, lo, hi = "ns", 3, (2, 3, 2), [4, 2], [3, 2], 4e-3, [0] * 3, [2 * np.pi] * 3
+    prob = lib_problem(S, eq, dim, n, lo, hi, nu=5e-3 if eq == "burgers" else 0.01)
+    prec = S.MIXED if precision == "mixed" else S.FP64
+    meth = S.make_method(Ps, Ms, n_iter=3 if len(Ps) == 1 else 2, cg_rtol=1e-12, cg_maxit=4000, precision=prec)
+    sv = S.Solver(prob, meth)
+    phys = oracle_phys(eq, dim, nu=5e-3 if eq == "burgers" else 0.01)
+    levels = [DGLevel(phys, n, lo, hi, P, M, rtol=1e-14) for P, M in zip(Ps, Ms)]
+    fine = levels[0]
+    if eq == "ns":
+        from paper_2504_18526_amd.inputs import taylor_green
+        u = taylor_green(fine.coords(), mach=0.1)
+    else:
+        u = smooth_state(phys, fine, np.random.default_rng(4))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for lvl in range(len(Ps)):
+        sv.net_init(lvl, 32, seed=2 + lvl, max_batch=512, max_rows=20000)
+        sv.net_harvest(lvl, 1)
+    sv.set_state(dev(u.ravel()))
+    for _ in range(2):
+        sv.step(dt)
+    for lvl in range(len(Ps)):
+        sv.net_harvest(lvl, 0)
+        sv.net_train(lvl, 30, 256, 1e-3)
+        sv.net_use(lvl, 1)
+    if len(Ps) == 1:
+        stepper = lambda v: sdc_step(fine, v, dt, 3)
+    else:
+        ml = MLSDC(list(reversed(levels)), n_coarse=2, start="cascade", cycles=2, post_sweep=True)
+        stepper = lambda v: ml.step(v, dt)
+    state = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    sv.get_state(state)
+    cur = state.cpu().numpy().reshape(u.shape)
+    guesses = 0
+    for k in range(3):
+        sv.set_state(dev(cur.ravel()))
+        st = sv.step(dt)
+        guesses += st["net_guesses"]
+        sv.get_state(state)
+        got = state.cpu().numpy().reshape(u.shape)
+        ref = stepper(cur)
+        assert rel_l2(got, ref) < 1e-10, (case, precision, k)
+        assert st["not_converged"] == 0
+        cur = got
+    assert guesses > 0
+    sv.close()
