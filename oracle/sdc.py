@@ -54,6 +54,7 @@ from .temporal import TimeTable, time_transfer
 from .mesh import Mesh
 from .dg import DG
 from . import solve as _solve
+from . import av as _av
 
 
 # --------------------------------------------------------------------------
@@ -75,6 +76,7 @@ class DGLevel:
         self.solver = solver
         self.nv = phys.nv
         self.solve_log = []
+        self.av = None   # artificial viscosity eps_e at the nodes (av.py), set per step
 
     def shape(self):
         return self.mesh.shape(self.nv)
@@ -86,13 +88,37 @@ class DGLevel:
         return self.dg.conv(u)
 
     def frhs(self, u):
-        return self.dg.frhs(u)
+        if self.av is None:
+            return self.dg.frhs(u)
+        # with artificial viscosity the diffusive flux is (nu + eps_e) grad u
+        # (scalar equations) or eps_e grad u of every component (systems)
+        out = self.dg.conv(u)
+        nu = 0.0 if self.phys.system else self.phys.nu
+        out = out - self.dg.sipg(self._iso(nu + self.av), u)
+        if getattr(self.phys, "mu", 0.0) != 0.0:
+            out = out + self.dg.visc(u)
+        return out
+
+    def _iso(self, field):
+        dim = self.mesh.dim
+        Dc = np.zeros((dim, dim) + np.shape(field))
+        for d in range(dim):
+            Dc[d, d] = field
+        return Dc
+
+    def _with_av(self, Dc):
+        if self.av is None:
+            return Dc
+        Dc = Dc.copy()
+        for d in range(self.mesh.dim):
+            Dc[d, d] = Dc[d, d] + self.av
+        return Dc
 
     def coef(self, ub, dtm, params):
-        return self.phys.coef(ub, dtm, params)
+        return self._with_av(self.phys.coef(ub, dtm, params))
 
     def coef_d(self, ub, dtm, params):
-        return self.phys.coef_d(ub, dtm, params)
+        return self._with_av(self.phys.coef_d(ub, dtm, params))
 
     def K(self, Dc, x):
         return self.dg.sipg(Dc, x)
@@ -439,8 +465,9 @@ class MLSDC:
 
     def __init__(self, levels, transfers=None, scheme="si2", n_coarse=2,
                  start="cascade", cycles=3, post_sweep=True, c_fmg=1, projection="interp",
-                 formulation="incremental"):
+                 formulation="incremental", av=None):
         self.levels = levels
+        self.av = av  # (kappa_s, c_s) of the artificial viscosity (av.py), or None
         if formulation not in ("incremental", "nonincremental"):
             raise ValueError(formulation)
         self.nonincremental = formulation == "nonincremental"
@@ -541,6 +568,13 @@ class MLSDC:
         """One time step; returns u at t + dt (u_{L,M}, Radau right)."""
         params = self.levels[-1].phys.step_params(u0_fine) \
             if hasattr(self.levels[-1], "phys") else None
+        if self.av is not None:  # eps_e from u_0 on the finest level, used on every level
+            fine = self.levels[-1]
+            eps = _av.element_eps(fine.mesh, fine.phys, u0_fine, *self.av)
+            for lv in self.levels:
+                if lv.mesh.n != fine.mesh.n:
+                    raise ValueError("artificial viscosity needs the same elements on every level")
+                lv.av = _av.nodal(lv.mesh, eps)
         self.set_initial(u0_fine, params)
         self.start_levels(dt)
         if self.L == 1:
