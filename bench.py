@@ -261,7 +261,7 @@ def main_batch(a, w):
         fine_dof += E * Np * nv
     dts = [wi["dt"] for wi in inst]
     t0 = time.perf_counter()
-    threads, variants = batch.tune(dts)
+    threads, variants, precs, graph = batch.tune(dts, full=True)
     tune_s = time.perf_counter() - t0
     step1 = None
     for k in range(max(1, a.warmup)):
@@ -317,10 +317,12 @@ def main_batch(a, w):
         "metric": "fine-level DOF-updates/s (s/step at fixed PCG tolerance 1e-10)",
         "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (FP32 inner PCG)", "data": "synthetic (seeded Fourier initial data)",
+        "dtype": "f64" if all(p == S.FP64 for p in precs) else "f64 (FP32 inner PCG where tuned)",
+        "data": "synthetic (seeded Fourier initial data)",
         "config": {"workload": w["name"], "instances": len(inst), "fine_dof": fine_dof, "global_batch": len(inst),
                    "seq_len": None, "parallelism": "none", "host_threads": threads,
-                   "persistent_instances": int(sum(1 for v in variants if v == S.CG_AUTO)) if threads == 1 else 0,
+                   "persistent_pcg_instances": int(sum(1 for v in variants if v == S.CG_AUTO)),
+                   "fp64_instances": int(sum(1 for p in precs if p == S.FP64)), "step_graphs": bool(graph),
                    "tune_s": round(tune_s, 2), "cg_iters_per_step": tot["cg_iters"] / steps,
                    "ir_rounds_per_step": tot["ir_rounds"] / steps, "not_converged": tot["not_converged"]},
         "roofline": roofline,

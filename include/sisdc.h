@@ -182,6 +182,27 @@ typedef struct {
                           fast diagonalisation (one small eigenproblem per
                           axis at set-up); FP64 solves of those levels only,
                           other levels and the FP32 inner solves keep Jacobi */
+  double av_kappa;     /* kappa_s and c_s of the Persson-Peraire artificial */
+  double av_c;         /* viscosity (Sec. 6: the diffusion matrix supplemented
+                          for shocks; Sec. 8 gives kappa_s, c_s per test).
+                          av_c > 0 switches it
+                          on: at the start of every step, from u_0 on the
+                          finest level, per element e the share S_e of the
+                          L2 energy of u (the density of a system) in the
+                          Legendre modes of degree P, s_e = log10 S_e,
+                          s_0 = -4 log10 P, and
+                            eps_e = eps_0 sw((s_e - s_0) / kappa_s),
+                            sw(r) = 0 (r < -1), 1 (r > 1),
+                                    (1 + sin(pi r / 2)) / 2 between,
+                            eps_0 = c_s (min_d h_d / P) lam_e,
+                          lam_e the largest wave speed over the element's
+                          nodes; eps_e grad u joins the diffusive flux of
+                          every component (in F and in the implicit
+                          coefficient D_m) for the whole step, on every
+                          level.  Requires the same elements on every level
+                          (no h_coarsen) and FP64 solves (precision
+                          SISDC_FP64) and av_kappa > 0; the levels take the
+                          multi-kernel PCG                                  */
 } sisdc_method;
 
 typedef struct {
@@ -368,6 +389,33 @@ int sisdc_pcg_timing_get(sisdc_handle* h, int level, long long* launches, long l
  * stride above 1 keeps the timed run close to the untimed one. */
 int sisdc_cg_kernel_timing_get(sisdc_handle* h, int level, int kernel, long long* launches, double* total_us);
 
+/* Artificial viscosity (method av_c > 0): sisdc_av_update evaluates eps_e
+ * from the current state (sisdc_set_state) as a step does from u_0, for
+ * the operator hooks (sisdc_apply), which use the eps last evaluated (by a
+ * step or by this call); sisdc_av_get copies eps_e (E_fine doubles, element
+ * order x fastest) to host or device memory.  Both fail with SISDC_EINVAL on
+ * a handle without it. */
+int sisdc_av_update(sisdc_handle* h);
+int sisdc_av_get(sisdc_handle* h, double* eps, int mem);
+
+/* Step graphs (the launch side of the time step, Sec. 4's sweeps as one unit
+ * of device work).  With on = 1, sisdc_step captures the whole step into a
+ * HIP graph the first time and replays it afterwards: one graph launch per
+ * step instead of one launch per kernel, and the host waits once, at the end
+ * of the step, to collect the solves' result records.  A step can be
+ * captured when every Helmholtz solve of it is a persistent PCG launch (a
+ * scalar equation, FP64 solves, every level within the persistent kernel's
+ * limits, tolerance >= 1e-11, no learned guess, PCG timing off); every solve
+ * still stops on its own convergence test on the device, so a replayed step
+ * gives the same result as the uncaptured step, bit for bit.  The graph
+ * holds the step size and the solver form: a step with another dt, or after
+ * the form changed, captures again.  A step that cannot be captured runs as
+ * usual (uncaptured).  on = 0 releases the graph. */
+int sisdc_set_graph(sisdc_handle* h, int on);
+/* Graph counters: whether the last sisdc_step ran through the graph, and the
+ * captures and graph launches so far (any output pointer may be NULL). */
+int sisdc_graph_info(sisdc_handle* h, int* last_step_graphed, long long* captures, long long* replays);
+
 /* Learned initial guess of a level's Helmholtz solves: an element-local MLP
  * n -> H -> H -> n (n = (P+1)^d, ReLU) applied to every (element, component)
  * row of the mass-scaled initial residual z0 = M^-1 (b - A x0), normalised to
@@ -411,12 +459,13 @@ int sisdc_net_use(sisdc_handle* h, int level, int on);
  * HIP stream created by the batch, so the kernels of different instances
  * overlap on the device.  The host work of a batch step is spread over a
  * number of host threads (instance i on thread i mod threads; default
- * min(n, 8)).  With more than one thread every instance runs the
- * multi-kernel PCG (persistent launches of different streams are not known
- * to be co-resident); with one thread the instances run one after the other,
- * each with the PCG form of its method (or the tuner's choice).  Instances
+ * min(n, 8)); each thread steps one instance at a time.  A persistent PCG
+ * launch needs all its workgroups resident at once: with T > 1 threads, a
+ * launch whose grid is at most 1/(T + 1) of the workgroups the device holds
+ * overlaps the launches of the other threads, a larger one waits for them
+ * and they for it, so the overlapping grids always fit together.  Instances
  * are independent: a batch step gives every instance the result of
- * sisdc_step on its own, up to the PCG tolerance.
+ * sisdc_step on its own with the same solver form, up to the PCG tolerance.
  *
  * sisdc_batch_handle gives the handle of instance i for the per-instance
  * calls (sisdc_set_state, sisdc_get_state, sisdc_level_info, ...); the batch
@@ -424,13 +473,17 @@ int sisdc_net_use(sisdc_handle* h, int level, int on);
  * its dt[i] and fills st[i] (st may be NULL); on failure the message names
  * the first failing instance, and the other instances have still been
  * stepped.  sisdc_batch_tune is the batch's autotuner: from the current
- * states (which it restores) it times one step of every instance with the
- * persistent and with the multi-kernel PCG and keeps the faster for
- * one-thread stepping, then times whole batch steps with 1, 2, 4, 8 and 16
- * host threads and keeps the fastest; threads_out and variants_out[n]
- * (SISDC_CG_*, the one-thread choices) receive the choices (either may be
- * NULL).  It needs a state on every instance and allocates
- * one fine-level state copy per instance while it runs. */
+ * states (which it restores) it times one step of every instance with each
+ * solver form (persistent PCG where it fits, or multi-kernel PCG; for an
+ * instance whose method asks for mixed precision also plain FP64 PCG, which
+ * meets the same FP64 residual tolerance) and keeps the fastest, then times
+ * whole batch steps with 1, 2, 4, 8 and 16 host threads and keeps the
+ * fastest, then whole batch steps with and without step graphs
+ * (sisdc_set_graph) and keeps the faster; threads_out, variants_out[n]
+ * (SISDC_CG_*), precisions_out[n] (SISDC_FP64 / SISDC_MIXED) and graph_out
+ * (0 / 1) receive the choices (any may be NULL).  It
+ * needs a state on every instance and allocates one fine-level state copy
+ * per instance while it runs. */
 typedef struct sisdc_batch sisdc_batch;
 int sisdc_batch_create(int n, const sisdc_problem* probs, const sisdc_method* meths, sisdc_batch** out);
 int sisdc_batch_destroy(sisdc_batch* b);
@@ -438,7 +491,10 @@ int sisdc_batch_size(const sisdc_batch* b, int* n);
 int sisdc_batch_handle(sisdc_batch* b, int i, sisdc_handle** h);
 int sisdc_batch_set_threads(sisdc_batch* b, int threads);
 int sisdc_batch_step(sisdc_batch* b, const double* dt, sisdc_stats* st);
-int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out);
+int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out,
+                     int* precisions_out, int* graph_out);
+/* sisdc_set_graph on every instance of the batch. */
+int sisdc_batch_set_graph(sisdc_batch* b, int on);
 
 #ifdef __cplusplus
 }

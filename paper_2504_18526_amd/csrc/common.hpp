@@ -29,14 +29,16 @@ struct EqP {
   double R;      // gas constant
 };
 
-// Implicit coefficient D_ij = c w^2 v_i v_j + nu delta_ij, w = ub[node] or 1,
-// in the arithmetic type T of the operator.
+// Implicit coefficient D_ij = c w^2 v_i v_j + (nu + eps_e) delta_ij,
+// w = ub[node] or 1, eps_e the artificial viscosity of the node's element
+// (0 without), in the arithmetic type T of the operator.
 template <typename T>
 struct CoefT {
   T c;
   T v[3];
   T nu;
-  const T* ub;  // state the coefficient is evaluated at (nullable)
+  const T* ub;   // state the coefficient is evaluated at (nullable)
+  const T* eps;  // artificial viscosity per element (nullable)
 };
 using CoefP = CoefT<double>;
 

@@ -419,6 +419,12 @@ __device__ __forceinline__ T coef_w2(const CoefT<T>& cf, long idx) {
   return cf.c * w * w;
 }
 
+// nu + eps_e of element e (the isotropic part of D there)
+template <typename T>
+__device__ __forceinline__ T coef_nu(const CoefT<T>& cf, int e) {
+  return cf.eps != nullptr ? cf.nu + cf.eps[e] : cf.nu;
+}
+
 // (D grad x)_d at the face nodes of one element from its LDS tile sx,
 // stored in trace[c][e][d][side][f].
 template <typename T, int DIM, int P>
@@ -445,7 +451,7 @@ __device__ __forceinline__ void store_trace(const T* sx, const T* sD, int n, con
   for (int d = 0; d < DIM; ++d) {
     const bool lo = ii[d] == 0, hi = ii[d] == P;
     if (!lo && !hi) continue;
-    const T qd = cw * cf.v[d] * vg + cf.nu * gr[d];
+    const T qd = cw * cf.v[d] * vg + coef_nu(cf, e) * gr[d];
     const long base = (((long)c * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
     if (lo) trace[base] = qd;
     if (hi) trace[base + NF] = qd;
@@ -514,6 +520,7 @@ k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, Coef
     const bool act = (le < EPB) && (e < g.E);
     const long own = (long)e * NP + n;
     const T cw = act ? coef_w2(cf, own) : T(0.0);
+    const T nue = act ? coef_nu(cf, e) : T(0.0);
     for (int c = 0; c < nv; ++c) {
       __syncthreads();
       if (act) sx[le * NP + n] = x[c * vs + own];
@@ -534,7 +541,7 @@ k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, Coef
         for (int j = 0; j < DIM; ++j) vg += cf.v[j] * gr[j];
         T qv[DIM], Qd[DIM];
         for (int d = 0; d < DIM; ++d) {
-          qv[d] = cw * cf.v[d] * vg + cf.nu * gr[d];
+          qv[d] = cw * cf.v[d] * vg + nue * gr[d];
           Qd[d] = jw * qv[d];
         }
         for (int d = 0; d < DIM; ++d) {
@@ -547,15 +554,15 @@ k_sipg_apply(const T* __restrict__ x, T* __restrict__ out, int nv, long vs, Coef
             const T xnb = x[c * vs + nbi];
             const T qnb = trace[(((long)c * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) +
                                      face_index<DIM, N1>(d, ii)];
-            const T dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + cf.nu;
-            const T dow = cw * cf.v[d] * cf.v[d] + cf.nu;
+            const T dnb = coef_w2(cf, nbi) * cf.v[d] * cf.v[d] + coef_nu(cf, nb);
+            const T dow = cw * cf.v[d] * cf.v[d] + nue;
             const T qn = T(0.5) * sgn * (qv[d] + qnb);
             const T tau = pen * fmax(dow, dnb) * T(0.5) * rh2[d];
             const T jump = xo - xnb;
             const T jfwf = gJ * rh2[d] * wn / sw[ii[d]];
             r += jfwf * (-qn + tau * jump);
             for (int d2 = 0; d2 < DIM; ++d2)
-              Qd[d2] -= T(0.5) * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? cf.nu : T(0.0)));
+              Qd[d2] -= T(0.5) * jfwf * jump * sgn * (cw * cf.v[d2] * cf.v[d] + (d2 == d ? nue : T(0.0)));
           }
         }
         for (int d = 0; d < DIM; ++d) sQ[(le * DIM + d) * NP + n] = Qd[d];
@@ -1445,13 +1452,14 @@ k_helm_diag(T* __restrict__ diag, int nv, long vs, CoefT<T> cf, T dtm, T ctau, G
   if (!act) return;
   T wn = T(1.0);
   for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
+  const T nue = coef_nu(cf, e);
   T kd = T(0.0);
   for (int d = 0; d < DIM; ++d) {
     const int st = L::stride(d);
     T s = T(0.0);
     for (int k = 0; k < N1; ++k) {
       const int nk = n + (k - ii[d]) * st;
-      const T dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + cf.nu;
+      const T dd = sc[le * NP + nk] * cf.v[d] * cf.v[d] + nue;
       const T wk = wn / sw[ii[d]] * sw[k];
       s += sD[k * N1 + ii[d]] * sD[k * N1 + ii[d]] * wk * dd;
     }
@@ -1464,8 +1472,8 @@ k_helm_diag(T* __restrict__ diag, int nv, long vs, CoefT<T> cf, T dtm, T ctau, G
       const T sgn = side ? T(1.0) : -T(1.0);
       const int nb = neighbour(g, e, d, side ? 1 : -1);
       const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
-      const T dnb = coef_w2(cf, (long)nb * NP + nn) * cf.v[d] * cf.v[d] + cf.nu;
-      const T dow = dow_c * cf.v[d] * cf.v[d] + cf.nu;
+      const T dnb = coef_w2(cf, (long)nb * NP + nn) * cf.v[d] * cf.v[d] + coef_nu(cf, nb);
+      const T dow = dow_c * cf.v[d] * cf.v[d] + nue;
       const T tau = ctau * (T)(N1 * N1) * fmax(dow, dnb) * T(0.5) * rh2[d];
       const T jfwf = gJ * rh2[d] * wn / sw[ii[d]];
       kd += jfwf * (tau - sgn * rh2[d] * dow * sD[ii[d] * N1 + ii[d]]);
@@ -1868,6 +1876,12 @@ k_space_time_transfer(TransferMulti t, int dim, int n1i, int n1o, const double* 
   }
 }
 
+// out = in, word by word (device copies of a step under graph capture are
+// kernels, not copy nodes)
+__global__ void k_copy(const double* __restrict__ in, double* __restrict__ out, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) out[i] = in[i];
+}
+
 __global__ void k_cast_f(const double* __restrict__ in, float* __restrict__ out, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
@@ -2105,7 +2119,7 @@ static hipError_t sipg_trace_t(const T* x, int nv, const CoefT<T>& cf, T* trace,
 // coefficient state) for the degrees whose line groups tile a wave.
 template <typename T>
 static bool iso_coef(const CoefT<T>& cf) {
-  return cf.ub == nullptr && cf.v[0] == T(0.0) && cf.v[1] == T(0.0) && cf.v[2] == T(0.0);
+  return cf.ub == nullptr && cf.eps == nullptr && cf.v[0] == T(0.0) && cf.v[1] == T(0.0) && cf.v[2] == T(0.0);
 }
 
 template <typename T, int DIM, int P>
@@ -2513,6 +2527,12 @@ hipError_t launch_space_transfer_h(const double* in, double* out, int nv, int di
   return hipGetLastError();
 }
 
+hipError_t launch_copy(const double* in, double* out, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_f, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
@@ -2549,6 +2569,126 @@ hipError_t launch_conserve(const double* b, const LinComb* lc, double* x, int nv
 hipError_t launch_add_f2d(double* x, const float* e, long n, hipStream_t s) {
   hipLaunchKernelGGL(k_add_f2d, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, x, e, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- artificial viscosity
+// Persson-Peraire viscosity of one element per workgroup (Sec. 6 supplements
+// the diffusion matrix with it): the coefficients of component 0 in the
+// orthonormal Legendre tensor basis (the discrete transform A, applied along
+// each axis in LDS), the share S of their energy in the modes with some index
+// equal to P, and the largest wave speed over the element's nodes and the
+// axes; then eps_e = ceps lam_e sw(log10 S) with the sine switch of
+// half-width kappa around s0 (eps_e = 0 for S = 0).  The sums run in a fixed
+// order (per thread, then the waves in turn), so eps is deterministic.
+template <int DIM, int P>
+struct AVS {
+  static constexpr int N1 = P + 1, NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+  static constexpr int NT = ((NP + 63) / 64) * 64 > 512 ? 512 : ((NP + 63) / 64) * 64;
+  static constexpr int NW = NT / 64;
+};
+
+template <int DIM, int P, int NV>
+__global__ void __launch_bounds__((AVS<DIM, P>::NT))
+k_av_sensor(const double* __restrict__ u, long vs, EqP q, int E, const double* __restrict__ A, double s0, double kappa,
+            double ceps, double* __restrict__ eps) {
+  using K = AVS<DIM, P>;
+  constexpr int N1 = K::N1, NP = K::NP, NT = K::NT, NW = K::NW;
+  __shared__ double sa[NP], sb[NP], sA[N1 * N1];
+  __shared__ double red[3][NW];
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (e >= E) return;
+  for (int k = t; k < N1 * N1; k += NT) sA[k] = A[k];
+  double lam = 0.0;
+  for (int n = t; n < NP; n += NT) {
+    const long i = (long)e * NP + n;
+    double uv[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) uv[c] = u[c * vs + i];
+    sa[n] = uv[0];
+    for (int d = 0; d < DIM; ++d) lam = fmax(lam, wave_speed<NV>(q, d, uv));
+  }
+  __syncthreads();
+  // transform along x (fastest), then y (then z); each pass reads one buffer
+  // and writes the other
+  double* src = sa;
+  double* dst = sb;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    const int st = ax == 0 ? 1 : (ax == 1 ? N1 : N1 * N1);
+    for (int n = t; n < NP; n += NT) {
+      const int k = (n / st) % N1;
+      const int base = n - k * st;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) acc += sA[k * N1 + i] * src[base + i * st];
+      dst[n] = acc;
+    }
+    __syncthreads();
+    double* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  double tot = 0.0, top = 0.0;
+  for (int n = t; n < NP; n += NT) {
+    const double c = src[n];
+    const int k0 = n % N1, k1 = (n / N1) % N1, k2 = DIM == 3 ? n / (N1 * N1) : 0;
+    tot += c * c;
+    if (k0 == P || k1 == P || (DIM == 3 && k2 == P)) top += c * c;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    tot += __shfl_down(tot, off, 64);
+    top += __shfl_down(top, off, 64);
+    lam = fmax(lam, __shfl_down(lam, off, 64));
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = tot;
+    red[1][t >> 6] = top;
+    red[2][t >> 6] = lam;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double T0 = 0.0, T1 = 0.0, L = 0.0;
+  for (int w = 0; w < NW; ++w) {
+    T0 += red[0][w];
+    T1 += red[1][w];
+    L = fmax(L, red[2][w]);
+  }
+  double sw = 0.0;
+  if (T0 > 0.0 && T1 > 0.0) {
+    const double sl = log10(T1 / T0);
+    if (sl > s0 + kappa)
+      sw = 1.0;
+    else if (sl >= s0 - kappa)
+      sw = 0.5 * (1.0 + sin(M_PI * (sl - s0) / (2.0 * kappa)));
+  }
+  eps[e] = ceps * L * sw;
+}
+
+template <int DIM, int P>
+static hipError_t av_dim_p(const double* u, int nv, const Geo& g, const EqP& q, const double* A, double s0,
+                           double kappa, double ceps, double* eps, hipStream_t s) {
+  using K = AVS<DIM, P>;
+  const long vs = (long)g.E * K::NP;
+  if (nv == 1)
+    hipLaunchKernelGGL((k_av_sensor<DIM, P, 1>), dim3(g.E), dim3(K::NT), 0, s, u, vs, q, g.E, A, s0, kappa, ceps, eps);
+  else if (nv == DIM + 2)
+    hipLaunchKernelGGL((k_av_sensor<DIM, P, DIM + 2>), dim3(g.E), dim3(K::NT), 0, s, u, vs, q, g.E, A, s0, kappa,
+                       ceps, eps);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_av_sensor(const double* u, int nv, const Geo& g, const EqP& q, const double* A, double kappa,
+                            double c_s, double* eps, hipStream_t s) {
+  if (g.E < 1 || !(kappa > 0.0)) return hipErrorInvalidValue;
+  const double s0 = -4.0 * std::log10((double)g.P);
+  double hmin = g.h[0];
+  for (int d = 1; d < g.dim; ++d) hmin = std::min(hmin, g.h[d]);
+  const double ceps = c_s * hmin / g.P;
+  if (g.dim == 2) { SISDC_DISPATCH_P(g.P, return (av_dim_p<2, PP>(u, nv, g, q, A, s0, kappa, ceps, eps, s))); }
+  if (g.dim == 3) { SISDC_DISPATCH_P(g.P, return (av_dim_p<3, PP>(u, nv, g, q, A, s0, kappa, ceps, eps, s))); }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, double* part, double* result,

@@ -99,6 +99,13 @@ hipError_t launch_space_time_transfer(const TransferMulti& t, int nv, int dim, i
                                       const double* A, hipStream_t s);
 // mixed precision: FP64 -> FP32 copy; r32 = b - Ax with (r,r), (b,b) summed
 // into tot[0..1] (FP64); x += e
+// Persson-Peraire artificial viscosity per element from the state u (nv
+// components, component 0 sensed): A the (P+1)^2 discrete Legendre
+// transform, kappa the switch half-width kappa_s, c_s the scale of
+// eps_0 = c_s (min_d h_d / P) lam_e.
+hipError_t launch_av_sensor(const double* u, int nv, const Geo& g, const EqP& q, const double* A, double kappa,
+                            double c_s, double* eps, hipStream_t s);
+hipError_t launch_copy(const double* in, double* out, long n, hipStream_t s);
 hipError_t launch_cast_f(const double* in, float* out, long n, hipStream_t s);
 hipError_t launch_resid_cast(const double* b, const double* Ax, float* r32, long n, double* part, double* tot,
                              hipStream_t s);
@@ -125,6 +132,7 @@ hipError_t launch_euler_lam(const double* u, long vs, const EqP& q, int dim, dou
 hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, const Geo& g, const double* tab,
                                  int max_blocks, bool cooperative, hipStream_t s);
 int pcg_persistent_blocks_per_cu(const Geo& g, int nv);
+int pcg_persistent_grid(const Geo& g);
 int elem_tile_count(const Geo& g);
 int reduce_grid(const Geo& g);
 

@@ -647,6 +647,13 @@ hipError_t launch_pcg_persistent(const PCGArgs& a, int nv, const CoefP& cf, cons
   return hipErrorInvalidValue;
 }
 
+// Workgroups of one persistent launch on this geometry (one per tile).
+int pcg_persistent_grid(const Geo& g) {
+  if (g.dim == 2) { SISDC_PDISPATCH(g.P, return ((g.E + PT<2, PP>::EPB - 1) / PT<2, PP>::EPB)); }
+  if (g.dim == 3) { SISDC_PDISPATCH(g.P, return ((g.E + PT<3, PP>::EPB - 1) / PT<3, PP>::EPB)); }
+  return 0;
+}
+
 int pcg_persistent_blocks_per_cu(const Geo& g, int nv) {
   if (g.dim == 2) { SISDC_PDISPATCH(g.P, return (occ_dim_p<2, PP>(nv))); }
   if (g.dim == 3) { SISDC_PDISPATCH(g.P, return (occ_dim_p<3, PP>(nv))); }

@@ -32,6 +32,10 @@ using namespace sisdc;
 
 namespace {
 
+// Thrown where a step under capture would need the host (a wait for the GPU);
+// the capture is dropped and the step runs without a graph.
+struct CaptureNeedsHost {};
+
 thread_local std::string g_last_error;
 
 struct Err {
@@ -84,6 +88,7 @@ struct Level {
   double* trace = nullptr;
   unsigned long long* fz = nullptr;  // tagged face values of the persistent PCG (2 buffers, 2 words each)
   unsigned long long* ft = nullptr;  // tagged face traces of the persistent PCG (2 buffers, 2 words each)
+  size_t fwords = 0;                 // words of fz and of ft
   bool persistent = false;     // solves run as one persistent launch
   // FP32 copies and work vectors of the mixed-precision inner solves
   float* tab32 = nullptr;
@@ -136,6 +141,21 @@ struct sisdc_handle {
   hipStream_t stream = nullptr;
   int dev = 0;              // device current at creation
   bool registered = false;  // stream entered in the persistent-solve order
+  int lane = -1;            // host thread of the batch step running this handle (-1: none)
+  int lanes = 0;            // host threads of that batch step
+  // step graph (sisdc_set_graph): the whole step captured once and replayed
+  bool graph_on = false;
+  bool capturing = false;           // a step is being captured on `stream`
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr; // stream the step is captured on (the handle's own may be the null stream)
+  double g_dt = 0.0;                // step size and solver form the graph was captured with
+  int g_form = -1;
+  int g_refused_form = -1;          // form whose capture needed the host (not tried again)
+  double g_refused_dt = 0.0;
+  std::vector<std::pair<int, int>> g_ring_meta;  // result records the graph writes
+  sisdc_stats g_st{};               // host-side counts of one captured step
+  long long g_captures = 0, g_replays = 0;
+  bool g_last = false;              // the last step ran through the graph
   EqP eq{};
   std::vector<Level> lv;
   std::vector<Transfer> tr;
@@ -182,6 +202,11 @@ struct sisdc_handle {
   double* hlam = nullptr;      // pinned
   double* state = nullptr;
   double* io = nullptr;      // staging for host pointers, (Mmax+1) x vlen_max
+  // artificial viscosity (method av_c > 0): eps per element, the same on
+  // every level; the fine level's discrete Legendre transform
+  bool av = false;
+  double* eps = nullptr;
+  double* av_tab = nullptr;
   size_t io_len = 0;
   double lam = 0.0;
   double visc = 0.0;           // viscous bound added to kappa_m (NS)
@@ -252,16 +277,22 @@ void lincomb_v(sisdc_handle* h, const Level& L, double* out, const std::vector<d
 }
 
 void copy_d2d(sisdc_handle* h, double* dst, const double* src, long n) {
+  if (h->capturing) {
+    HIPCHECK(launch_copy(src, dst, n, h->stream));
+    return;
+  }
   HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
 }
 
 template <typename T>
 void copy_any(sisdc_handle* h, T* dst, const T* src, long n) {
+  if (h->capturing) throw CaptureNeedsHost{};
   HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
 }
 
 CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
   CoefP c{};
+  c.eps = h->av ? h->eps : nullptr;  // the artificial viscosity joins the diffusion
   if (h->meth.integrator == SISDC_IMEX_EULER) {  // eq. H_IMEX: A_d alone
     c.nu = (h->eq.eq == EQ_EULER || h->eq.eq == EQ_NS) ? 0.0 : h->eq.nu;
     (void)L;
@@ -290,9 +321,11 @@ CoefP coef_for(sisdc_handle* h, const Level& L, double dtm, const double* ub) {
   return c;
 }
 
+// The physical diffusion nu I (+ eps_e I) of F's diffusive term.
 CoefP coef_nu(sisdc_handle* h) {
   CoefP c{};
   c.nu = h->eq.nu;
+  c.eps = h->av ? h->eps : nullptr;
   return c;
 }
 
@@ -305,12 +338,24 @@ void sipg(sisdc_handle* h, const Level& L, const CoefP& cf, const double* x, dou
   HIPCHECK(launch_sipg(x, out, L.nv, cf, L.trace, alpha, beta, h->ctau, L.g, L.tab, h->stream));
 }
 
-bool is_system(sisdc_handle* h) { return h->eq.eq == EQ_EULER || h->eq.eq == EQ_NS; }
-bool has_physical_diffusion(sisdc_handle* h) { return !is_system(h) && h->eq.nu != 0.0; }
+bool is_system(const sisdc_handle* h) { return h->eq.eq == EQ_EULER || h->eq.eq == EQ_NS; }
+bool has_physical_diffusion(sisdc_handle* h) { return !is_system(h) && (h->eq.nu != 0.0 || h->av); }
 
-// f = F(u) = C(u) - K_nu u (scalars), C(u) (Euler), C(u) + V(u) (NS);
-// Cu = C(u) precomputed
+// f = F(u) = C(u) - K_nu u (scalars), C(u) (Euler), C(u) + V(u) (NS); with
+// artificial viscosity nu + eps_e in the scalars' term and - K_eps u added
+// for systems; Cu = C(u) precomputed
 void frhs_from_c(sisdc_handle* h, const Level& L, const double* u, const double* Cu, double* f) {
+  if (h->av && is_system(h)) {
+    if (h->eq.eq == EQ_NS && h->eq.mu != 0.0)
+      HIPCHECK(launch_visc(u, Cu, f, L.trace, L.g, h->eq, L.tab, h->stream));
+    else if (f != Cu)
+      copy_d2d(h, f, Cu, L.vlen);
+    CoefP ce{};
+    ce.eps = h->eps;
+    sipg(h, L, ce, u, L.t3, 0.0, 1.0);
+    lincomb(h, L, f, {{1.0, f}, {-1.0, L.t3}});
+    return;
+  }
   if (has_physical_diffusion(h)) {
     // quadrilaterals: f = C - K_nu u in one pass of the isotropic kernel
     if (L.g.dim == 2 && f != Cu && launch_sipg_iso2_add(u, Cu, f, L.nv, coef_nu(h), 0.0, -1.0, h->ctau, L.g, L.tab, h->stream) ==
@@ -408,6 +453,7 @@ void conserve_fix(sisdc_handle* h, Level& L, const double* b, const LinComb* bl,
 // Collect the result records of persistent solves enqueued since the last
 // collection (one stream synchronisation).
 void drain_rejections(sisdc_handle* h) {
+  if (h->capturing) throw CaptureNeedsHost{};
   HIPCHECK(hipMemcpyAsync(h->hnrej, h->nrej, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   h->st.net_rejected += *h->hnrej - h->nrej_seen;
@@ -415,6 +461,7 @@ void drain_rejections(sisdc_handle* h) {
 }
 
 void drain(sisdc_handle* h) {
+  if (h->capturing) throw CaptureNeedsHost{};
   if (h->st.net_guesses > 0) drain_rejections(h);
   if (h->ring_n == 0) return;
   HIPCHECK(hipMemcpyAsync(h->hring, h->ring, h->ring_n * sizeof(CGRes), hipMemcpyDeviceToHost, h->stream));
@@ -456,7 +503,7 @@ void drain(sisdc_handle* h) {
 // multi-kernel form is faster (three-level Euler workload: 54 against 84 ms
 // per step).
 bool persistent_fits(const sisdc_handle* h, const Level& L, int variant) {
-  return (variant == SISDC_CG_AUTO || variant == SISDC_CG_PERSISTENT_COOPERATIVE) && L.nv == 1 &&
+  return (variant == SISDC_CG_AUTO || variant == SISDC_CG_PERSISTENT_COOPERATIVE) && L.nv == 1 && !h->av &&
          elem_tile_count(L.g) <= h->pcap;
 }
 
@@ -468,6 +515,13 @@ bool persistent_fits(const sisdc_handle* h, const Level& L, int variant) {
 // this and no event is recorded; with several, an event recorded after
 // each launch marks it (a launch made before the second stream appeared is
 // marked when first needed, by an event recorded on its stream then).
+//
+// Lanes: the host threads of a batch step (lane = thread).  A lane's solve
+// whose grid is at most 1/(lanes + 1) of the workgroups the device holds at
+// once may overlap the solves of the other lanes (at most `lanes` of them
+// run at a time, each thread stepping one instance at a time, and together
+// they fit on the device); it still waits for the latest ordinary launch,
+// and an ordinary launch waits for the latest solve of every lane.
 struct PersistentOrder {
   std::mutex m;
   std::vector<std::pair<hipStream_t, int>> streams;  // streams of live handles, with handle counts
@@ -475,6 +529,8 @@ struct PersistentOrder {
   hipStream_t last = nullptr;  // stream of the latest persistent launch
   bool pending = false;        // that launch may still be running
   bool marked = false;         // `done` was recorded after it
+  std::vector<hipEvent_t> lane_ev;      // recorded after the latest overlapping solve of each lane
+  std::vector<hipStream_t> lane_last;   // its stream; null once an ordinary launch has waited for it
 };
 constexpr int kMaxDevices = 64;
 PersistentOrder g_porder[kMaxDevices];
@@ -506,15 +562,83 @@ void porder_unregister(int dev, hipStream_t s) {
       break;
     }
   if (po.pending && po.last == s) po.pending = false;
-  // the last handle of the device is gone: release the ordering event, so no
+  for (auto& ls : po.lane_last)
+    if (ls == s) ls = nullptr;
+  // the last handle of the device is gone: release the ordering events, so no
   // HIP object of the library outlives its handles
   if (po.streams.empty()) {
     if (po.done) (void)hipEventDestroy(po.done);
+    for (hipEvent_t e : po.lane_ev)
+      if (e) (void)hipEventDestroy(e);
+    po.lane_ev.clear();
+    po.lane_last.clear();
     po.done = nullptr;
     po.pending = false;
     po.marked = false;
     po.last = nullptr;
   }
+}
+
+// Whether a lane's persistent launch on level L may overlap those of the
+// other lanes: its grid is at most 1/(lanes + 1) of the workgroups the
+// device holds at once.
+bool lane_may_overlap(const sisdc_handle* h, const Level& L) {
+  if (h->lane < 0) return false;
+  int ncu = 0;
+  HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->dev));
+  const long max_blocks = (long)pcg_persistent_blocks_per_cu(L.g, L.nv) * ncu;
+  return (long)pcg_persistent_grid(L.g) * (h->lanes + 1) <= max_blocks;
+}
+
+// Ordering of one persistent launch (or of a captured step holding them) on
+// h's stream against the persistent launches of other streams; po.m held.
+void porder_before(PersistentOrder& po, sisdc_handle* h, bool overlap) {
+  if (po.streams.size() <= 1) return;
+  if (!po.done) HIPCHECK(hipEventCreateWithFlags(&po.done, hipEventDisableTiming));
+  if (po.pending && po.last != h->stream) {
+    if (!po.marked) HIPCHECK(hipEventRecord(po.done, po.last));
+    po.marked = true;
+    HIPCHECK(hipStreamWaitEvent(h->stream, po.done, 0));
+  }
+  if (!overlap)
+    for (size_t l = 0; l < po.lane_last.size(); ++l)
+      if (po.lane_last[l] && po.lane_last[l] != h->stream) {
+        HIPCHECK(hipStreamWaitEvent(h->stream, po.lane_ev[l], 0));
+        po.lane_last[l] = nullptr;
+      }
+}
+
+void porder_after(PersistentOrder& po, sisdc_handle* h, bool overlap) {
+  const bool several = po.streams.size() > 1;
+  if (overlap && several) {
+    if (po.lane_ev.size() <= (size_t)h->lane) {
+      po.lane_ev.resize(h->lane + 1, nullptr);
+      po.lane_last.resize(h->lane + 1, nullptr);
+    }
+    if (!po.lane_ev[h->lane]) HIPCHECK(hipEventCreateWithFlags(&po.lane_ev[h->lane], hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(po.lane_ev[h->lane], h->stream));
+    po.lane_last[h->lane] = h->stream;
+    return;
+  }
+  po.last = h->stream;
+  po.pending = true;
+  po.marked = false;
+  if (several) {
+    HIPCHECK(hipEventRecord(po.done, h->stream));
+    po.marked = true;
+  }
+}
+
+// Zero every tagged word of the persistent PCG (barrier records, and the face
+// records of every level), so that no tag handed out afterwards from 1 on
+// can match a word written before.
+void clear_tagged_records(sisdc_handle* h) {
+  HIPCHECK(launch_zero_scratch(h->ppart, (size_t)2 * 16 * h->pcap * sizeof(unsigned long long), h->stream));
+  for (auto& L : h->lv)
+    if (L.fz) {
+      HIPCHECK(launch_zero_scratch(L.fz, L.fwords * sizeof(unsigned long long), h->stream));
+      HIPCHECK(launch_zero_scratch(L.ft, L.fwords * sizeof(unsigned long long), h->stream));
+    }
 }
 
 // b null: the kernel forms the right-hand side from `bl`.
@@ -546,7 +670,8 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   const unsigned long long need = 2ull * (unsigned long long)maxit + 64ull;
   if (need > 0x40000000ull) return false;  // such an iteration cap takes the multi-kernel form
   if ((unsigned long long)h->tag + need >= 0xffffffffull) {
-    HIPCHECK(hipMemsetAsync(h->ppart, 0, (size_t)2 * 16 * h->pcap * sizeof(unsigned long long), h->stream));
+    if (h->capturing) throw CaptureNeedsHost{};
+    clear_tagged_records(h);
     h->tag = 0;
   }
   a.tag0 = h->tag + 1u;
@@ -557,15 +682,13 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
   const int max_blocks = pcg_persistent_blocks_per_cu(L.g, L.nv) * ncu;
   const int slot = h->ring_n;
   const bool cooperative = h->meth.cg_variant == SISDC_CG_PERSISTENT_COOPERATIVE;
+  // a lane's solve small enough to share the device with the other lanes
+  const bool overlap = !cooperative && lane_may_overlap(h, L);
   PersistentOrder& po = porder(h->dev);
-  std::lock_guard<std::mutex> lock(po.m);
-  const bool several = po.streams.size() > 1;
-  if (several) {
-    if (!po.done) HIPCHECK(hipEventCreateWithFlags(&po.done, hipEventDisableTiming));
-    if (po.pending && po.last != h->stream) {
-      if (!po.marked) HIPCHECK(hipEventRecord(po.done, po.last));
-      HIPCHECK(hipStreamWaitEvent(h->stream, po.done, 0));
-    }
+  std::unique_lock<std::mutex> lock(po.m, std::defer_lock);
+  if (!h->capturing) {  // a captured step is ordered as a whole when it is launched
+    lock.lock();
+    porder_before(po, h, overlap);
   }
   if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot], h->stream));
   hipError_t e = launch_pcg_persistent(a, L.nv, cf, L.g, L.tab, max_blocks, cooperative, h->stream);
@@ -574,13 +697,7 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
     L.persistent = false;
     return false;
   }
-  po.last = h->stream;
-  po.pending = true;
-  po.marked = false;
-  if (several) {
-    HIPCHECK(hipEventRecord(po.done, h->stream));
-    po.marked = true;
-  }
+  if (!h->capturing) porder_after(po, h, overlap);
   if (h->ptime) HIPCHECK(hipEventRecord(h->pev[2 * slot + 1], h->stream));
   h->ring_timed.push_back(h->ptime ? 1 : 0);
   h->ring_meta.emplace_back((int)(&L - h->lv.data()), maxit);
@@ -601,6 +718,7 @@ template <typename T>
 sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const CoefT<T>& cf, T dtm, const T* b, T* x,
                            double rtol, int maxit, bool x_is_zero, const LinComb* bl = nullptr,
                            const T* x0 = nullptr) {
+  if (h->capturing) throw CaptureNeedsHost{};  // the host reads the convergence record
   hipStream_t s = h->stream;
   const int id = ++h->solve_id;
   const T ctau = (T)h->ctau, one = (T)1;
@@ -742,6 +860,7 @@ CoefT<float> coef32(sisdc_handle* h, Level& L, const CoefP& cf) {
 //   to a relative tolerance max(inner_rtol, rtol ||b|| / (2 ||r||)); x += e.
 sisdc_solve_stats mixed_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b, double* x,
                               double rtol, int maxit) {
+  if (h->capturing) throw CaptureNeedsHost{};  // the host decides every refinement round
   hipStream_t s = h->stream;
   const CoefT<float> cf32 = coef32(h, L, cf);
   CGBufs<float> B = bufs32(h, L);
@@ -1262,12 +1381,19 @@ void set_level_initial(sisdc_handle* h) {
   }
 }
 
+// eps_e of the artificial viscosity from the fine-level state u.
+void av_update(sisdc_handle* h, const double* u) {
+  const Level& F = h->lv[0];
+  HIPCHECK(launch_av_sensor(u, F.nv, F.g, h->eq, h->av_tab, h->meth.av_kappa, h->meth.av_c, h->eps, h->stream));
+}
+
 void update_lam(sisdc_handle* h) {
   if (!is_system(h)) {
     h->lam = 0.0;
     h->visc = 0.0;
     return;
   }
+  if (h->capturing) throw CaptureNeedsHost{};  // the bound is read on the host
   Level& L = h->lv[0];
   HIPCHECK(launch_euler_lam(L.um(0), L.vs, h->eq, L.g.dim, h->partials, h->lam_dev, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hlam, h->lam_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1281,8 +1407,11 @@ void update_lam(sisdc_handle* h) {
   }
 }
 
-void do_step(sisdc_handle* h, double dt) {
+// One time step up to the copy of the new state (everything but collecting
+// the solves' records): the work a step graph captures.
+void step_body(sisdc_handle* h, double dt) {
   set_level_initial(h);
+  if (h->av) av_update(h, h->lv[0].um(0));
   update_lam(h);
   const int nl = (int)h->lv.size();
   const int Lc = nl - 1;
@@ -1325,8 +1454,144 @@ void do_step(sisdc_handle* h, double dt) {
   }
   Level& F = h->lv[0];
   copy_d2d(h, h->state, F.um(F.M), F.vlen);
+}
+
+void do_step(sisdc_handle* h, double dt) {
+  step_body(h, dt);
   drain(h);
   HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+// ------------------------------------------------------------------ step graphs
+// A step whose every Helmholtz solve is a persistent PCG launch needs the host
+// only at its end (to collect the solves' result records), so it can be
+// captured once into a HIP graph and replayed: one launch per step instead of
+// one per kernel.  Each solve still ends on its own convergence test on the
+// device.  The graph bakes in the step size, the device buffers and the
+// solver form; another dt or form captures again.  The persistent PCG's
+// tagged records (barrier and face words) are cleared by the graph's first
+// kernels and its tags restart from the captured values, so replays never
+// meet stale tags.
+
+// Why this handle's step cannot be captured (nullptr: it may be).
+const char* graph_refusal(const sisdc_handle* h) {
+  if (is_system(h)) return "the step's wave-speed bound is read on the host";
+  if (h->meth.precision != SISDC_FP64) return "mixed-precision refinement is decided on the host";
+  if (h->meth.cg_variant == SISDC_CG_PERSISTENT_COOPERATIVE) return "cooperative launches are not captured";
+  if (h->meth.cg_rtol < kPersistentMinRtol) return "the tolerance takes the multi-kernel PCG";
+  if (h->ptime) return "PCG event timing is on";
+  for (const auto& L : h->lv) {
+    if (!L.persistent) return "a level takes the multi-kernel PCG";
+    if (L.net.on) return "a learned initial guess is in use";
+  }
+  return nullptr;
+}
+
+int graph_form(const sisdc_handle* h) { return h->meth.cg_variant * 8 + h->meth.precision; }
+
+void graph_drop(sisdc_handle* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+}
+
+// Capture one step (nothing runs).  False when the step needed the host.
+bool capture_step(sisdc_handle* h, double dt) {
+  graph_drop(h);
+  drain(h);
+  const unsigned tag_before = h->tag;
+  const sisdc_stats saved = h->st;
+  if (!h->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t const own = h->stream;
+  auto reset = [&]() {
+    h->stream = own;
+    h->capturing = false;
+    h->ring_n = 0;
+    h->ring_meta.clear();
+    h->ring_timed.clear();
+    h->st = saved;
+  };
+  h->st = sisdc_stats{};
+  h->tag = 0;
+  // captured on a stream of its own (nothing runs there); the graph is
+  // launched on the handle's stream
+  HIPCHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+  h->stream = h->cap_stream;
+  h->capturing = true;
+  bool needs_host = false;
+  try {
+    clear_tagged_records(h);
+    step_body(h, dt);
+  } catch (const CaptureNeedsHost&) {
+    needs_host = true;
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    reset();
+    h->tag = tag_before;
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  const std::vector<std::pair<int, int>> meta = h->ring_meta;
+  const sisdc_stats counted = h->st;
+  reset();
+  if (needs_host || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    h->tag = tag_before;  // nothing ran: the records still hold the earlier tags
+    if (!needs_host) HIPCHECK(e);
+    return false;
+  }
+  const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->gexec = nullptr;
+    h->tag = tag_before;
+    HIPCHECK(ei);
+  }
+  h->g_ring_meta = meta;
+  h->g_st = counted;
+  h->g_captures += 1;
+  return true;
+}
+
+// Run one step through the handle's graph (capturing it first when needed).
+// False, with nothing run, when the step cannot be captured.
+bool graph_step(sisdc_handle* h, double dt) {
+  if (graph_refusal(h)) {
+    graph_drop(h);
+    return false;
+  }
+  const int form = graph_form(h);
+  if (h->g_refused_form == form && h->g_refused_dt == dt) return false;
+  if (!h->gexec || h->g_dt != dt || h->g_form != form) {
+    if (!capture_step(h, dt)) {
+      h->g_refused_form = form;
+      h->g_refused_dt = dt;
+      return false;
+    }
+    h->g_dt = dt;
+    h->g_form = form;
+  }
+  // the graph is ordered against other streams' persistent launches as one
+  // launch: it may overlap other lanes when every level's grid may
+  bool overlap = h->lane >= 0;
+  for (const auto& L : h->lv) overlap = overlap && lane_may_overlap(h, L);
+  PersistentOrder& po = porder(h->dev);
+  {
+    std::lock_guard<std::mutex> lock(po.m);
+    porder_before(po, h, overlap);
+    HIPCHECK(hipGraphLaunch(h->gexec, h->stream));
+    porder_after(po, h, overlap);
+  }
+  h->g_replays += 1;
+  h->st = h->g_st;
+  h->ring_n = (int)h->g_ring_meta.size();
+  h->ring_meta = h->g_ring_meta;
+  h->ring_timed.assign(h->ring_n, 0);
+  drain(h);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return true;
 }
 
 // ------------------------------------------------------------------ setup
@@ -1441,6 +1706,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
     }
     L.fz = (unsigned long long*)pz;
     L.ft = (unsigned long long*)pt;
+    L.fwords = words;
     HIPCHECK(hipMemset(L.fz, 0, words * sizeof(unsigned long long)));
     HIPCHECK(hipMemset(L.ft, 0, words * sizeof(unsigned long long)));
   }
@@ -1653,6 +1919,13 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->precond != SISDC_PRECOND_JACOBI && m->precond != SISDC_PRECOND_FDS) fail(SISDC_EINVAL, "precond");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
+  if (!(m->av_c >= 0.0)) fail(SISDC_EINVAL, "av_c must be >= 0");
+  if (m->av_c > 0.0) {
+    if (!(m->av_kappa > 0.0)) fail(SISDC_EINVAL, "artificial viscosity needs av_kappa > 0");
+    if (m->precision != SISDC_FP64) fail(SISDC_EINVAL, "artificial viscosity runs with FP64 solves");
+    for (int l = 1; l < m->n_levels; ++l)
+      if (m->h_coarsen[l]) fail(SISDC_EINVAL, "artificial viscosity needs the same elements on every level");
+  }
   if (m->cg_variant != SISDC_CG_AUTO && m->cg_variant != SISDC_CG_MULTI_KERNEL &&
       m->cg_variant != SISDC_CG_PERSISTENT_COOPERATIVE)
     fail(SISDC_EINVAL, "cg_variant");
@@ -1824,6 +2097,15 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     void* hrr = nullptr;
     if (hipHostMalloc(&hrr, kRing * sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
     h->hring = (CGRes*)hrr;
+    h->av = meth->av_c > 0.0;
+    if (h->av) {
+      Level& F = h->lv[0];
+      h->eps = dalloc(F.E);
+      HIPCHECK(hipMemset(h->eps, 0, F.E * sizeof(double)));
+      const std::vector<double> A = legendre_analysis(F.P, F.xg, F.wg);
+      h->av_tab = dalloc(A.size());
+      HIPCHECK(hipMemcpy(h->av_tab, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     for (auto& L : h->lv)
       L.persistent = persistent_fits(h, L, meth->cg_variant);
     h->state = dalloc(h->lv[0].vlen);
@@ -1847,6 +2129,8 @@ int sisdc_destroy(sisdc_handle* h) {
   if (!h) return SISDC_OK;
   (void)hipDeviceSynchronize();
   if (h->registered) porder_unregister(h->dev, h->stream);
+  graph_drop(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& L : h->lv) {
     net_free(L);
     free_level(L);
@@ -1874,6 +2158,8 @@ int sisdc_destroy(sisdc_handle* h) {
   for (hipEvent_t ev : h->pev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : h->mev) (void)hipEventDestroy(ev);
   if (h->state) (void)hipFree(h->state);
+  if (h->eps) (void)hipFree(h->eps);
+  if (h->av_tab) (void)hipFree(h->av_tab);
   if (h->io) (void)hipFree(h->io);
   delete h;
   return SISDC_OK;
@@ -1994,7 +2280,8 @@ int sisdc_step(sisdc_handle* h, double t, double dt, sisdc_stats* st) {
     if (!h->have_state) fail(SISDC_ESTATE, "sisdc_set_state must precede sisdc_step");
     if (!(dt > 0.0)) fail(SISDC_EINVAL, "dt must be positive");
     h->st = sisdc_stats{};
-    do_step(h, dt);
+    h->g_last = h->graph_on && graph_step(h, dt);
+    if (!h->g_last) do_step(h, dt);
     if (st) *st = h->st;
     if (h->st.not_converged) fail(SISDC_ENOTCONV, "a Helmholtz solve reached cg_maxit");
   });
@@ -2197,6 +2484,44 @@ int sisdc_collocation_residual(sisdc_handle* h, int level, double dt, double* ou
     if (!out) fail(SISDC_EINVAL, "null output");
     colloc_residual(h, L, dt, L.r, nullptr);
     dev_out(h, out, L.r, (long)L.M * L.vlen, mem);
+  });
+}
+
+int sisdc_av_update(sisdc_handle* h) {
+  return guard([&] {
+    if (!h) fail(SISDC_EINVAL, "null handle");
+    if (!h->av) fail(SISDC_EINVAL, "the method has no artificial viscosity (av_c = 0)");
+    if (!h->have_state) fail(SISDC_ESTATE, "sisdc_set_state must precede sisdc_av_update");
+    av_update(h, h->state);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  });
+}
+
+int sisdc_av_get(sisdc_handle* h, double* eps, int mem) {
+  return guard([&] {
+    if (!h) fail(SISDC_EINVAL, "null handle");
+    if (!h->av) fail(SISDC_EINVAL, "the method has no artificial viscosity (av_c = 0)");
+    if (!eps) fail(SISDC_EINVAL, "null output");
+    dev_out(h, eps, h->eps, h->lv[0].E, mem);
+  });
+}
+
+int sisdc_set_graph(sisdc_handle* h, int on) {
+  return guard([&] {
+    if (!h) fail(SISDC_EINVAL, "null handle");
+    if (on != 0 && on != 1) fail(SISDC_EINVAL, "on must be 0 or 1");
+    h->graph_on = on != 0;
+    if (!on) graph_drop(h);
+    h->g_refused_form = -1;
+  });
+}
+
+int sisdc_graph_info(sisdc_handle* h, int* last_step_graphed, long long* captures, long long* replays) {
+  return guard([&] {
+    if (!h) fail(SISDC_EINVAL, "null handle");
+    if (last_step_graphed) *last_step_graphed = h->g_last ? 1 : 0;
+    if (captures) *captures = h->g_captures;
+    if (replays) *replays = h->g_replays;
   });
 }
 
@@ -2501,16 +2826,16 @@ int sisdc_net_use(sisdc_handle* h, int level, int on) {
 // thread i mod threads.
 }  // extern "C"
 
-// Persistent PCG solves of one device run one after another, whatever their
-// stream, so with more than one host thread every instance runs the
-// multi-kernel PCG (the instances' solves then overlap on the device); with
-// one thread the instances run one after the other and each uses its own
-// PCG choice (`variant`).
+// With more than one host thread, each thread is a lane of the persistent-
+// solve order: persistent solves small enough to share the device overlap
+// those of the other threads, larger ones run alone.
 struct sisdc_batch {
   std::vector<sisdc_handle*> h;
   std::vector<hipStream_t> streams;
-  std::vector<int> variant;  // PCG form of each instance when stepped by one thread
+  std::vector<int> variant;    // PCG form of each instance
+  std::vector<int> precision;  // arithmetic of each instance's Helmholtz solves
   int threads = 1;
+  int graph = 0;               // step graphs on every instance
 };
 
 namespace {
@@ -2553,6 +2878,11 @@ void set_cg_variant(sisdc_handle* h, int variant) {
   for (auto& L : h->lv) L.persistent = persistent_fits(h, L, variant);
 }
 
+void set_form(sisdc_handle* h, int variant, int precision) {
+  h->meth.precision = precision;
+  set_cg_variant(h, variant);
+}
+
 }  // namespace
 
 extern "C" {
@@ -2590,6 +2920,7 @@ int sisdc_batch_create(int n, const sisdc_problem* probs, const sisdc_method* me
     }
     b->h.push_back(h);
     b->variant.push_back(meths[i].cg_variant);
+    b->precision.push_back(meths[i].precision);
   }
   b->threads = std::min(n, 8);
   *out = b;
@@ -2631,22 +2962,43 @@ int sisdc_batch_set_threads(sisdc_batch* b, int threads) {
   return SISDC_OK;
 }
 
+int sisdc_batch_set_graph(sisdc_batch* b, int on) {
+  if (!b || (on != 0 && on != 1)) {
+    g_last_error = "null batch or on not 0 / 1";
+    return SISDC_EINVAL;
+  }
+  for (sisdc_handle* h : b->h) {
+    const int rc = sisdc_set_graph(h, on);
+    if (rc != SISDC_OK) return rc;
+  }
+  b->graph = on;
+  return SISDC_OK;
+}
+
 int sisdc_batch_step(sisdc_batch* b, const double* dt, sisdc_stats* st) {
   if (!b || !dt) {
     g_last_error = "null batch or dt";
     return SISDC_EINVAL;
   }
-  const bool concurrent = std::min(b->threads, (int)b->h.size()) > 1;
-  for (size_t i = 0; i < b->h.size(); ++i) set_cg_variant(b->h[i], concurrent ? SISDC_CG_MULTI_KERNEL : b->variant[i]);
-  return batch_run(b, [&](int i) { return sisdc_step(b->h[i], 0.0, dt[i], st ? &st[i] : nullptr); });
+  const int n = (int)b->h.size();
+  const int T = std::max(1, std::min(b->threads, n));  // as in batch_run: instance i on thread i mod T
+  for (int i = 0; i < n; ++i) {
+    set_form(b->h[i], b->variant[i], b->precision[i]);
+    b->h[i]->lane = T > 1 ? i % T : -1;
+    b->h[i]->lanes = T;
+  }
+  const int rc = batch_run(b, [&](int i) { return sisdc_step(b->h[i], 0.0, dt[i], st ? &st[i] : nullptr); });
+  for (sisdc_handle* h : b->h) h->lane = -1;
+  return rc;
 }
 
-// Autotuner: per instance, the PCG form for one-thread stepping (persistent
-// where it fits, or multi-kernel), then the number of host threads for the
-// whole batch (more than one thread runs every instance with the
-// multi-kernel PCG), each by the wall time of one step from the same state,
-// which is restored afterwards.
-int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out) {
+// Autotuner: per instance, the form of its Helmholtz solves (persistent PCG
+// where it fits, or multi-kernel; for an instance configured for mixed
+// precision also plain FP64, which meets the same FP64 residual tolerance),
+// then the number of host threads for the whole batch, each by the wall
+// time of one step from the same state, which is restored afterwards.
+int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* variants_out, int* precisions_out,
+                     int* graph_out) {
   if (!b || !dt) {
     g_last_error = "null batch or dt";
     return SISDC_EINVAL;
@@ -2678,16 +3030,23 @@ int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* va
     }
   }
   auto restore = [&](int i) { return sisdc_set_state(b->h[i], saved[i], SISDC_MEM_DEVICE); };
+  for (sisdc_handle* h : b->h) h->graph_on = false;  // instances are timed uncaptured first
   auto now = []() { return std::chrono::steady_clock::now(); };
   auto secs = [](auto a, auto c) { return std::chrono::duration<double>(c - a).count(); };
   int rc = SISDC_OK;
   for (int i = 0; i < n && rc == SISDC_OK; ++i) {
     sisdc_handle* h = b->h[i];
-    const int original = h->meth.cg_variant;
+    h->lane = -1;
+    const int configured = b->precision[i];
+    std::vector<std::pair<int, int>> forms = {{SISDC_CG_AUTO, configured}, {SISDC_CG_MULTI_KERNEL, configured}};
+    if (configured == SISDC_MIXED) {
+      forms.emplace_back(SISDC_CG_AUTO, SISDC_FP64);
+      forms.emplace_back(SISDC_CG_MULTI_KERNEL, SISDC_FP64);
+    }
     double best = 1e300;
-    int pick = original;
-    for (int v : {SISDC_CG_AUTO, SISDC_CG_MULTI_KERNEL}) {
-      set_cg_variant(h, v);
+    std::pair<int, int> pick = forms[0];
+    for (const auto& f : forms) {
+      set_form(h, f.first, f.second);
       if ((rc = sisdc_step(h, 0.0, dt[i], nullptr)) != SISDC_OK) break;  // warm-up of this form
       if ((rc = restore(i)) != SISDC_OK) break;
       const auto t0 = now();
@@ -2696,15 +3055,19 @@ int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* va
       if ((rc = restore(i)) != SISDC_OK) break;
       if (tv < best) {
         best = tv;
-        pick = v;
+        pick = f;
       }
     }
-    set_cg_variant(h, pick);
-    b->variant[i] = pick;
-    if (variants_out) variants_out[i] = pick;
+    set_form(h, pick.first, pick.second);
+    b->variant[i] = pick.first;
+    b->precision[i] = pick.second;
+    if (variants_out) variants_out[i] = pick.first;
+    if (precisions_out) precisions_out[i] = pick.second;
   }
+  const int graph_before = b->graph;
+  double best_steps = 1e300;
+  if (rc == SISDC_OK) rc = sisdc_batch_set_graph(b, 0);
   if (rc == SISDC_OK) {
-    double best = 1e300;
     int pick = b->threads;
     for (int T : {1, 2, 4, 8, 16}) {
       if (T > n && T != 1) continue;
@@ -2714,13 +3077,29 @@ int sisdc_batch_tune(sisdc_batch* b, const double* dt, int* threads_out, int* va
       const double tv = secs(t0, now());
       for (int i = 0; i < n && rc == SISDC_OK; ++i) rc = restore(i);
       if (rc != SISDC_OK) break;
-      if (tv < best) {
-        best = tv;
+      if (tv < best_steps) {
+        best_steps = tv;
         pick = T;
       }
     }
     b->threads = pick;
     if (threads_out) *threads_out = pick;
+  }
+  if (rc == SISDC_OK) {  // step graphs: one step captures, the next is timed
+    int pick = 0;
+    if ((rc = sisdc_batch_set_graph(b, 1)) == SISDC_OK && (rc = sisdc_batch_step(b, dt, nullptr)) == SISDC_OK) {
+      for (int i = 0; i < n && rc == SISDC_OK; ++i) rc = restore(i);
+      const auto t0 = now();
+      if (rc == SISDC_OK && (rc = sisdc_batch_step(b, dt, nullptr)) == SISDC_OK) {
+        const double tv = secs(t0, now());
+        for (int i = 0; i < n && rc == SISDC_OK; ++i) rc = restore(i);
+        if (tv < best_steps) pick = 1;
+      }
+    }
+    if (rc == SISDC_OK) rc = sisdc_batch_set_graph(b, pick);
+    if (graph_out) *graph_out = pick;
+  } else {
+    (void)sisdc_batch_set_graph(b, graph_before);
   }
   const std::string m = g_last_error;
   release();

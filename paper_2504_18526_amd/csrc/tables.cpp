@@ -150,6 +150,35 @@ std::vector<double> nn_weights(const std::vector<double>& tau) {
 }
 
 
+std::vector<double> legendre_analysis(int P, const std::vector<double>& x, const std::vector<double>& w) {
+  const int n = P + 1;
+  std::vector<double> phi((size_t)n * n);  // phi[k*n + i] = phi_k(x_i)
+  for (int i = 0; i < n; ++i) {
+    double pm = 1.0, pk = x[i];
+    for (int k = 0; k < n; ++k) {
+      double val;
+      if (k == 0) {
+        val = 1.0;
+      } else if (k == 1) {
+        val = x[i];
+      } else {
+        const double next = ((2.0 * k - 1.0) * x[i] * pk - (k - 1.0) * pm) / k;
+        pm = pk;
+        pk = next;
+        val = next;
+      }
+      phi[(size_t)k * n + i] = std::sqrt(0.5 * (2.0 * k + 1.0)) * val;
+    }
+  }
+  std::vector<double> A((size_t)n * n);
+  for (int k = 0; k < n; ++k) {
+    double g = 0.0;
+    for (int j = 0; j < n; ++j) g += w[j] * phi[(size_t)k * n + j] * phi[(size_t)k * n + j];
+    for (int i = 0; i < n; ++i) A[(size_t)k * n + i] = w[i] * phi[(size_t)k * n + i] / g;
+  }
+  return A;
+}
+
 void fds_axis(const std::vector<double>& w, const std::vector<double>& D, double rh, double pen,
               std::vector<double>& S, std::vector<double>& lam) {
   const int n = (int)w.size();

@@ -15,6 +15,15 @@ std::vector<double> radau_right(int M);
 // Incremental weights w^nn[m*M+i] = int_{tau_{m-1}}^{tau_m} l_i (tau_0 = 0).
 std::vector<double> nn_weights(const std::vector<double>& tau);
 
+// Discrete Legendre transform on the GLL nodes x (weights w) of degree P:
+// A[k*n + i] = w_i phi_k(x_i) / sum_j w_j phi_k(x_j)^2, phi_k the Legendre
+// polynomial of degree k scaled to unit L2 norm on [-1, 1].  Applied along an
+// axis, A maps nodal values to the coefficients in the phi_k basis (the
+// quadrature is exact for every product phi_j phi_k with j != k, so the
+// basis is orthogonal in it and the transform inverts the nodal
+// evaluation).
+std::vector<double> legendre_analysis(int P, const std::vector<double>& x, const std::vector<double>& w);
+
 // Fast diagonalisation of one axis of an element's diagonal block of the
 // isotropic Helmholtz operator.  Per unit of J w_a w_b nu (the weights of the
 // other axes, the Jacobian and the diffusivity), the axis contributes the

@@ -36,9 +36,10 @@ EXPORTS = [
     "sisdc_get_fas", "sisdc_set_fas", "sisdc_get_state", "sisdc_update_step_params",
     "sisdc_step", "sisdc_predict", "sisdc_sweep", "mlsdc_vcycle", "helmholtz_solve", "helmholtz_solve_noalloc",
     "sisdc_apply", "sisdc_collocation_residual", "sisdc_profile_kernel",
-    "sisdc_pcg_timing", "sisdc_pcg_timing_get", "sisdc_cg_kernel_timing_get",
+    "sisdc_pcg_timing", "sisdc_pcg_timing_get", "sisdc_cg_kernel_timing_get", "sisdc_set_graph", "sisdc_graph_info",
+    "sisdc_av_update", "sisdc_av_get",
     "sisdc_batch_create", "sisdc_batch_destroy", "sisdc_batch_size", "sisdc_batch_handle",
-    "sisdc_batch_set_threads", "sisdc_batch_step", "sisdc_batch_tune",
+    "sisdc_batch_set_threads", "sisdc_batch_step", "sisdc_batch_tune", "sisdc_batch_set_graph",
     "sisdc_net_init", "sisdc_net_get_params", "sisdc_net_set_params", "sisdc_net_forward",
     "sisdc_net_train_step", "sisdc_net_grad", "sisdc_net_harvest", "sisdc_net_train", "sisdc_net_use",
 ]
@@ -62,7 +63,8 @@ class Method(ctypes.Structure):
                 ("precision", ctypes.c_int), ("cg_variant", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("projection", ctypes.c_int), ("formulation", ctypes.c_int),
                 ("nodes", ctypes.c_int), ("h_coarsen", ctypes.c_int * 3), ("c_fmg", ctypes.c_int),
-                ("conserve", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("conserve", ctypes.c_int), ("precond", ctypes.c_int),
+                ("av_kappa", ctypes.c_double), ("av_c", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -116,7 +118,13 @@ def load():
         "sisdc_batch_handle": ([P, I, ctypes.POINTER(P)], I),
         "sisdc_batch_set_threads": ([P, I], I),
         "sisdc_batch_step": ([P, P, P], I),
-        "sisdc_batch_tune": ([P, P, ctypes.POINTER(I), P], I),
+        "sisdc_batch_tune": ([P, P, ctypes.POINTER(I), P, P, ctypes.POINTER(I)], I),
+        "sisdc_batch_set_graph": ([P, I], I),
+        "sisdc_set_graph": ([P, I], I),
+        "sisdc_av_update": ([P], I),
+        "sisdc_av_get": ([P, P, I], I),
+        "sisdc_graph_info": ([P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong),
+                              ctypes.POINTER(ctypes.c_longlong)], I),
         "sisdc_cg_kernel_timing_get": ([P, I, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)], I),
         "sisdc_pcg_timing_get": ([P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(D)], I),
@@ -207,7 +215,7 @@ def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, 
 def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, post_sweep=1,
                 n_iter=1, cg_rtol=1e-13, cg_maxit=2000, c_tau=2.0, precision=FP64, cg_variant=CG_AUTO,
                 inner_rtol=0.0, projection=PROJ_INTERP, formulation=INCREMENTAL, nodes=NODES_RADAU_RIGHT,
-                h_coarsen=None, c_fmg=1, conserve=1, precond=PRECOND_JACOBI):
+                h_coarsen=None, c_fmg=1, conserve=1, precond=PRECOND_JACOBI, av=None):
     m = Method()
     m.n_levels = len(P)
     for i in range(3):
@@ -232,6 +240,8 @@ def make_method(P, M, integrator=SI2, start=START_CASCADE, n_coarse_sweeps=2, po
     m.c_fmg = c_fmg
     m.conserve = conserve
     m.precond = precond
+    if av is not None:  # (kappa_s, c_s) of the artificial viscosity
+        m.av_kappa, m.av_c = float(av[0]), float(av[1])
     return m
 
 
@@ -385,6 +395,27 @@ class Solver:
         multi-kernel PCG's launches."""
         _check(self._lib.sisdc_pcg_timing(self.h, max(1, int(stride)) if on else 0))
 
+    def av_update(self):
+        """Evaluate the artificial viscosity from the current state."""
+        _check(self._lib.sisdc_av_update(self.h))
+
+    def av_get(self, out):
+        """eps per fine element into `out` (E_fine float64 values)."""
+        p, mem = _ptr(out, True)
+        _check(self._lib.sisdc_av_get(self.h, p, mem))
+        return out
+
+    def set_graph(self, on):
+        """Capture the step into a HIP graph and replay it (where the step
+        allows it; otherwise steps run uncaptured)."""
+        _check(self._lib.sisdc_set_graph(self.h, 1 if on else 0))
+
+    def graph_info(self):
+        """(last step ran through the graph, captures, graph launches)."""
+        last, cap, rep = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_longlong()
+        _check(self._lib.sisdc_graph_info(self.h, ctypes.byref(last), ctypes.byref(cap), ctypes.byref(rep)))
+        return bool(last.value), cap.value, rep.value
+
     def pcg_timing_get(self, level):
         """(launches, CG iterations, total event time in us) of the persistent
         PCG launches on a level since timing was switched on."""
@@ -523,12 +554,21 @@ class Batch:
         _check(self._lib.sisdc_batch_step(self.b, ctypes.cast(dt, ctypes.c_void_p), ctypes.cast(st, ctypes.c_void_p)))
         return [s.as_dict() for s in st]
 
-    def tune(self, dts):
-        """Autotune the PCG form of every instance and the host thread count;
-        returns (threads, [variant per instance])."""
+    def set_graph(self, on):
+        _check(self._lib.sisdc_batch_set_graph(self.b, 1 if on else 0))
+
+    def tune(self, dts, full=False):
+        """Autotune the solver form of every instance, the host thread count
+        and step graphs; returns (threads, [variant per instance]), or with
+        `full` (threads, [variant], [precision per instance], graph)."""
         dt = (ctypes.c_double * self.n)(*[float(d) for d in dts])
         th = ctypes.c_int()
         var = (ctypes.c_int * self.n)()
+        prec = (ctypes.c_int * self.n)()
+        gr = ctypes.c_int()
         _check(self._lib.sisdc_batch_tune(self.b, ctypes.cast(dt, ctypes.c_void_p), ctypes.byref(th),
-                                          ctypes.cast(var, ctypes.c_void_p)))
+                                          ctypes.cast(var, ctypes.c_void_p), ctypes.cast(prec, ctypes.c_void_p),
+                                          ctypes.byref(gr)))
+        if full:
+            return th.value, list(var), list(prec), bool(gr.value)
         return th.value, list(var)

@@ -126,3 +126,45 @@ def test_batch_errors_name_the_instance(S):
     with pytest.raises(S.SisdcError, match="instance 2"):
         batch.step(dts)
     batch.close()
+
+
+def test_overlapping_persistent_solves_match_single_handles(S):
+    """Four host threads, production tolerance: the instances' persistent PCG
+    launches (small grids) overlap on the device and give the results of the
+    same instances stepped alone, bit for bit; mixed-precision instances
+    tuned to FP64 stay within the mixed bar of the oracle."""
+    probs, meths, orc, dts = build(S, S.FP64, 1e-10)
+    probs2, meths2, orc2, dts2 = build(S, S.MIXED, 1e-10)
+    probs, meths, orc, dts = probs + probs2, meths + meths2, orc + orc2, dts + dts2
+    u0 = initial_states(orc)
+    batch = S.Batch(probs, meths)
+    for i, u in enumerate(u0):
+        batch[i].set_state(torch.from_numpy(u.ravel().copy()).cuda())
+    threads, variants, precs, graph = batch.tune(dts, full=True)
+    assert all(p in (S.FP64, S.MIXED) for p in precs)
+    assert all(p == S.FP64 for p in precs[:len(INSTANCES)])
+    batch.set_threads(4)
+    singles = []
+    for i, (p, m) in enumerate(zip(probs, meths)):
+        m2 = S.make_method(list(m.P[:m.n_levels]), list(m.M[:m.n_levels]), start=S.START_CASCADE, n_iter=2,
+                           cg_rtol=1e-10, cg_maxit=5000, precision=precs[i], cg_variant=variants[i])
+        singles.append(S.Solver(p, m2))
+        singles[i].set_state(torch.from_numpy(u0[i].ravel().copy()).cuda())
+    ref = [u.copy() for u in u0]
+    for k in range(2):
+        stats = batch.step(dts)
+        for i, (phys, levels) in enumerate(orc):
+            assert stats[i]["not_converged"] == 0
+            singles[i].step(dts[i])
+            ml = MLSDC(list(reversed(levels)), n_coarse=2, start="cascade", cycles=2, post_sweep=True)
+            ref[i] = ml.step(ref[i], dts[i])
+            out = torch.empty(u0[i].size, dtype=torch.float64, device="cuda")
+            batch[i].get_state(out)
+            one = torch.empty_like(out)
+            singles[i].get_state(one)
+            got = out.cpu().numpy()
+            assert np.array_equal(got, one.cpu().numpy()), (k, i)
+            assert rel_l2(got, ref[i]) < 1e-8, (k, i)
+    for s in singles:
+        s.close()
+    batch.close()
