@@ -108,3 +108,21 @@ def taylor_green(coords, mach=0.1, gamma=1.4, rho0=1.0, V0=1.0):
     rho = p / T0
     E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
     return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def sod_pair(coords, h, gamma=1.4, width=0.2):
+    """Periodic pair of Sod shock tubes on [0, 2] (x only): the left state of
+    Sod's problem (rho = 1, p = 1, v = 0) on [0, 1), the right state (rho =
+    0.125, p = 0.1) on [1, 2), each jump smoothed by a tanh of width `width`
+    h (h the element size).  Until the two wave systems meet, [0.5, 1.5]
+    holds Sod's tube with its diaphragm at x = 1.  Returns the conserved
+    state (4, ...)."""
+    import numpy as np
+    x = np.asarray(coords[0], dtype=np.float64)
+    w = 0.5 * (np.tanh(x / (width * h)) - np.tanh((x - 1.0) / (width * h))
+               + np.tanh((x - 2.0) / (width * h)) + 1.0)
+    w = np.clip(w, 0.0, 1.0)
+    rho = 0.125 + 0.875 * w
+    p = 0.1 + 0.9 * w
+    zero = np.zeros_like(rho)
+    return np.stack([rho, zero, zero, p / (gamma - 1.0)])

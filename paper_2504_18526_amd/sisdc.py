@@ -281,8 +281,8 @@ class Solver:
             self._lib.sisdc_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -531,8 +531,8 @@ class Batch:
             self._lib.sisdc_batch_destroy(self.b)
             self.b = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

@@ -134,10 +134,26 @@ def batch_64():
     return dict(name="batch2d_64_instances_mlsdc_mixed", eq="batch", dim=2, instances=inst, steps=20)
 
 
+def sod_2level():
+    """Shock workload shaped like the paper's Sod test (Sec. 8: 80 elements of
+    degree 5 on [0, 1], levels P 5/3, M 7/5, 32 steps to t = 0.2, cascade
+    start, artificial viscosity kappa_s = 2, c_s = 0.4): 2-D Euler on the
+    periodic strip [0, 2] x [0, 1/80] with a pair of Sod tubes
+    (inputs.sod_pair, jumps smoothed over 0.2 h), 160 x 1 elements of size
+    1/80, 2 V-cycles + post-sweep, N_c = 2."""
+    return dict(
+        name="euler2d_sod_pair_av_160x1_P5-3_M7-5",
+        eq="euler", dim=2, n_elem=(160, 1), lo=(0.0, 0.0), hi=(2.0, 1.0 / 80), gamma=1.4,
+        P=[5, 3], M=[7, 5], start="cascade", cycles=2, n_coarse=2, post_sweep=1,
+        dt=0.2 / 32, steps=32, cg_rtol=1e-10, av=(2.0, 0.4), init="sod",
+    )
+
+
 WORKLOADS = {
     "convdiff": convdiff_1level,
     "burgers": burgers_2level,
     "euler": euler_3level,
     "ns": ns_2level,
     "batch": batch_64,
+    "sod": sod_2level,
 }
