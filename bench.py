@@ -97,6 +97,9 @@ def parse():
                     help="steps timed for each of the mixed / learned variants (0: skip them)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
+                    help="only launch the fine level's CG matvec and vector update REPS times each, back to back "
+                         "(for profiler counter runs), print their average times and exit")
     ap.add_argument("--workload", default="ns",
                     help="ns (default: the two-level 3-D Navier-Stokes workload), burgers, convdiff, euler, "
                          "batch (64 independent instances)")
@@ -332,6 +335,33 @@ def main_batch(a, w):
     batch.close()
 
 
+def single_instance_rate(S, w, prob, meth, u0, dt, steps, warmup, dof_updates, stream):
+    """One instance of a stacked ensemble stepped through its own handle:
+    ms per step and fine-level DOF-updates/s, timed as the ensemble is."""
+    import ctypes
+    import torch
+    p1 = S.Problem()
+    ctypes.memmove(ctypes.byref(p1), ctypes.byref(prob), ctypes.sizeof(prob))
+    p1.stack = 1
+    sv = S.Solver(p1, meth, stream=stream.cuda_stream)
+    ud = torch.from_numpy(u0.copy()).cuda()
+    sv.set_state(ud)
+    for _ in range(max(1, warmup)):
+        sv.step(dt)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+    for _ in range(steps):
+        sv.step(dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sv.close()
+    return {"ms_per_step": ms, "value": dof_updates / (ms / 1000.0), "unit": "DOF-updates/s"}
+
+
 def run_variants(S, w, prob, stream, u0, dt, nsteps, dof_updates, start):
     """Plain FP64 vs mixed precision vs the learned initial guess (and both),
     and, on the systems' isotropic levels, vs the element-block Jacobi
@@ -425,18 +455,24 @@ def main():
         del src, dst
     stream = torch.cuda.Stream(device=dev)
     eqc = {"convdiff": S.EQ_CONVDIFF, "burgers": S.EQ_BURGERS, "euler": S.EQ_EULER, "ns": S.EQ_NS}[w["eq"]]
+    B = w.get("stack", 1)
     prob = S.make_problem(w["dim"], w["n_elem"], w["lo"], w["hi"], eqc, a=w.get("a", (0.0, 0.0, 0.0)),
                           nu=w.get("nu", 0.0), gamma=w.get("gamma", 1.4), mu=w.get("mu", 0.0),
-                          Pr=w.get("Pr", 0.71))
+                          Pr=w.get("Pr", 0.71), stack=B)
     start = {"cascade": S.START_CASCADE, "fmg": S.START_FMG}[w["start"]]
     meth = S.make_method(w["P"], w["M"], start=start, n_coarse_sweeps=w["n_coarse"],
                          post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"],
-                         cg_maxit=w.get("cg_maxit", 1000), av=w.get("av"))
+                         cg_maxit=w.get("cg_maxit", 1000), av=w.get("av"), conserve=w.get("conserve", 1))
     sv = S.Solver(prob, meth, stream=stream.cuda_stream)
     E, Np, nv, M = sv.level_info(0)
     x = sv.coords(0)
     xs = [x[d] for d in range(w["dim"])]
-    if w["eq"] == "burgers":
+    if w["eq"] == "burgers" and B > 1:  # instance k: seed + k, on its own box
+        Ei = E // B
+        xi = [c.reshape(B, Ei * Np) for c in xs]
+        u0 = np.concatenate([burgers_field([c[k] for c in xi], seed=w["seed"] + k, kmax=w["kmax"])
+                             for k in range(B)])[None]
+    elif w["eq"] == "burgers":
         u0 = burgers_field(xs, seed=w["seed"], kmax=w["kmax"])[None]
     elif w["eq"] == "convdiff":
         u0 = convdiff_field(xs, seed=w["seed"], kmax=w["kmax"])[None]
@@ -452,6 +488,14 @@ def main():
     ud = torch.from_numpy(u0).to(dev)
     sv.set_state(ud)
     dt = w["dt"]
+    if a.kernels_only > 0:
+        sv.update_step_params()
+        rec = {"workload": w["name"], "dt_m": dt / M}
+        for key, kid in (("matvec_us", S.K_SIPG_APPLY), ("update_us", S.K_CG_UPDATE)):
+            rec[key] = sv.profile_kernel(kid, 0, dt / M, reps=a.kernels_only)
+        print(json.dumps(rec), flush=True)
+        sv.close()
+        return
 
     # warm-up (the first warm-up step is kept for the parity check against the oracle)
     step1 = None
@@ -556,24 +600,31 @@ def main():
         if w["eq"] == "ns":
             cpu = ns_cpu_baseline(S, w, prob, meth, stream, dev, nsteps=a.cpu_steps)
         else:
+            Ei = E // B  # a stacked ensemble: the oracle steps its first instance
             with tempfile.TemporaryDirectory() as td:
                 p0 = os.path.join(td, "u0.npy")
                 p1 = os.path.join(td, "g1.npy")
-                np.save(p0, u0)
-                np.save(p1, step1)
+                np.save(p0, u0[:, :Ei])
+                np.save(p1, step1.reshape(nv, E, Np)[:, :Ei])
                 r = cpu_baseline(w, p0, p1, a.cpu_steps)
-            cpu_rate = dof_updates * r["steps"] / r["seconds"]
+            cpu_rate = dof_updates / B * r["steps"] / r["seconds"]
             cpu = {"value": cpu_rate, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
                    "sample": f"{r['steps']} time steps of the same workload from the same u0 "
-                             f"(oracle CG to the same 1e-10 tolerance), {r['seconds']:.1f} s",
+                             + (f"(its first instance) " if B > 1 else "")
+                             + f"(oracle CG to the same 1e-10 tolerance), {r['seconds']:.1f} s",
                    "gpu_vs_oracle_rel_l2_step1": r["rel_l2_step1"]}
 
+    single = None
+    if B > 1:  # the ensemble's first instance stepped alone, for comparison
+        single = single_instance_rate(S, w, prob, meth, u0[:, :E // B], dt, a.steps, a.warmup,
+                                      dof_updates / B, stream)
     rec = {
         "metric": "fine-level DOF-updates/s (s/step at fixed PCG tolerance 1e-10)",
         "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded Fourier initial data)",
-        "config": {"workload": w["name"], "levels_P": w["P"], "levels_M": w["M"], "global_batch": 1, "seq_len": None, "parallelism": "none",
+        "config": {"workload": w["name"], "levels_P": w["P"], "levels_M": w["M"], "global_batch": B, "seq_len": None, "parallelism": "none",
+                   "single_instance": single,
                    "dt": dt, "fine_dof": E * Np * nv, "fine_sweeps_per_step": sweeps,
                    "cg_iters_per_step": tot["cg_iters"] / a.steps, "solves_per_step": tot["solves"] / a.steps,
                    "not_converged": tot["not_converged"], "max_rel_residual": tot["max_rel_residual"],
