@@ -103,6 +103,20 @@ typedef struct {
   double mu;           /* dynamic viscosity (NS)                            */
   double Pr;           /* Prandtl number (NS)                               */
   double R;            /* gas constant (EULER, NS; <= 0 means 1)            */
+  int stack;           /* 0 or 1: one instance.  B > 1: an ensemble of B
+                          independent instances of this problem stacked
+                          along the last axis, each on its own periodic box
+                          of n_elem elements: the handle's state holds B
+                          consecutive element blocks (instance k: elements
+                          k E .. (k+1) E - 1 of every component, E the
+                          elements of one instance) and every kernel of a
+                          step runs once for all of them.  The instances
+                          share dt, the method and each Helmholtz solve:
+                          their systems are solved as one block-diagonal
+                          system, stopped on the joint relative residual.
+                          Scalar equations only (CONVDIFF, BURGERS), with
+                          conserve = 0 (the conservation shift is one
+                          constant per component) and no h_coarsen          */
 } sisdc_problem;
 
 typedef struct {

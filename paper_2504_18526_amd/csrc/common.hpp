@@ -15,6 +15,7 @@ struct Geo {
   double h[3];             // element size per axis
   double rh2[3];           // 2 / h
   double J;                // prod h / 2
+  int wl;                  // elements of one instance along the last axis (ensembles stack instances there)
 };
 
 // Equation parameters.

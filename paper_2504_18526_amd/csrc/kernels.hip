@@ -48,15 +48,20 @@ __device__ __forceinline__ int face_index(int d, const int (&i)[3]) {
   return d == 0 ? i[1] + N1 * i[2] : (d == 1 ? i[0] + N1 * i[2] : i[0] + N1 * i[1]);
 }
 
-// Element across the face of element e normal to d on side s (-1 / +1).
+// Element across the face of element e normal to d on side s (-1 / +1);
+// periodic, along the last axis within the instance's block of g.wl
+// elements.
 __device__ __forceinline__ int neighbour(const Geo& g, int e, int d, int s) {
   int c[3];
   c[0] = e % g.ne[0];
   c[1] = (e / g.ne[0]) % g.ne[1];
   c[2] = g.dim == 3 ? e / (g.ne[0] * g.ne[1]) : 0;
-  c[d] += s;
-  if (c[d] < 0) c[d] += g.ne[d];
-  if (c[d] >= g.ne[d]) c[d] -= g.ne[d];
+  const int span = d == g.dim - 1 ? g.wl : g.ne[d];
+  const int base = c[d] - c[d] % span;
+  int loc = c[d] - base + s;
+  if (loc < 0) loc += span;
+  if (loc >= span) loc -= span;
+  c[d] = base + loc;
   return c[0] + g.ne[0] * (c[1] + g.ne[1] * c[2]);
 }
 
@@ -786,7 +791,8 @@ k_sipg_apply_iso3(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
     // neighbours across the faces normal to each axis (periodic)
     const int nbm0 = e + (ex > 0 ? -sx : (g.ne[0] - 1) * sx), nbp0 = e + (ex < g.ne[0] - 1 ? sx : -(g.ne[0] - 1) * sx);
     const int nbm1 = e + (ey > 0 ? -sy : (g.ne[1] - 1) * sy), nbp1 = e + (ey < g.ne[1] - 1 ? sy : -(g.ne[1] - 1) * sy);
-    const int nbm2 = e + (ez > 0 ? -sz : (g.ne[2] - 1) * sz), nbp2 = e + (ez < g.ne[2] - 1 ? sz : -(g.ne[2] - 1) * sz);
+    const int ezl = ez % g.wl;  // position inside the instance along z
+    const int nbm2 = e + (ezl > 0 ? -sz : (g.wl - 1) * sz), nbp2 = e + (ezl < g.wl - 1 ? sz : -(g.wl - 1) * sz);
     const T* const xc = x + c * vs;
     T xl[N1], r[N1];
     load_line<T, P, 0>(xc, e, a, b, sc, scaled, xl);
@@ -890,7 +896,8 @@ k_sipg_apply_iso3_brick(const T* __restrict__ x, const T* __restrict__ isc, T* _
     // the neighbour outside the brick along each axis (periodic)
     const int ox = bx ? (ex + 1 == g.ne[0] ? 0 : ex + 1) : (ex == 0 ? g.ne[0] - 1 : ex - 1);
     const int oy = by ? (ey + 1 == g.ne[1] ? 0 : ey + 1) : (ey == 0 ? g.ne[1] - 1 : ey - 1);
-    const int oz = bz ? (ez + 1 == g.ne[2] ? 0 : ez + 1) : (ez == 0 ? g.ne[2] - 1 : ez - 1);
+    const int ezl = ez % g.wl, ez0 = ez - ezl;  // bricks do not straddle instances (g.wl even)
+    const int oz = ez0 + (bz ? (ezl + 1 == g.wl ? 0 : ezl + 1) : (ezl == 0 ? g.wl - 1 : ezl - 1));
     const int nx = ox + g.ne[0] * (ey + g.ne[1] * ez);
     const int ny = ex + g.ne[0] * (oy + g.ne[1] * ez);
     const int nz = ex + g.ne[0] * (ey + g.ne[1] * oz);
@@ -1053,7 +1060,8 @@ k_sipg_apply_iso2(const T* __restrict__ x, const T* __restrict__ isc, T* __restr
     const int ex = e % g.ne[0], ey = e / g.ne[0];
     const int sy = g.ne[0];
     const int nbm0 = e + (ex > 0 ? -1 : g.ne[0] - 1), nbp0 = e + (ex < g.ne[0] - 1 ? 1 : -(g.ne[0] - 1));
-    const int nbm1 = e + (ey > 0 ? -sy : (g.ne[1] - 1) * sy), nbp1 = e + (ey < g.ne[1] - 1 ? sy : -(g.ne[1] - 1) * sy);
+    const int eyl = ey % g.wl;  // position inside the instance along y
+    const int nbm1 = e + (eyl > 0 ? -sy : (g.wl - 1) * sy), nbp1 = e + (eyl < g.wl - 1 ? sy : -(g.wl - 1) * sy);
     const T* const xc = x + c * vs;
     T xl[N1], r[N1];
     load_line2<T, P, 0>(xc, e, a, sc, scaled, xl);
@@ -2252,7 +2260,7 @@ static int iso_grid(const Geo& g) {
 // elements along every axis.
 template <int DIM, int P>
 static bool iso_brick(const Geo& g) {
-  return DIM == 3 && P == 7 && g.ne[0] % 2 == 0 && g.ne[1] % 2 == 0 && g.ne[2] % 2 == 0;
+  return DIM == 3 && P == 7 && g.ne[0] % 2 == 0 && g.ne[1] % 2 == 0 && g.ne[2] % 2 == 0 && g.wl % 2 == 0;
 }
 
 template <typename T, int DIM, int P>

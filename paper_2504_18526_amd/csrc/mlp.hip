@@ -10,6 +10,8 @@
 // b3, row-major [out][in].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 #include "mlp.hpp"
@@ -17,7 +19,6 @@
 namespace sisdc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
 __device__ __forceinline__ short to_bf16(float f) {
@@ -28,56 +29,106 @@ __device__ __forceinline__ short to_bf16(float f) {
 
 // C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (relu).  op(A)(i,k) =
 // transA ? A[k*lda + i] : A[i*lda + k]; op(B)(k,j) = transB ? B[j*ldb + k] :
-// B[k*ldb + j].  One wave computes a 32 x 32 tile of C as 2 x 2 MFMA 16 x 16
-// blocks; out-of-range operands read as 0 and out-of-range results are not
-// stored.  BF16: operands rounded to bfloat16 on load, FP32 accumulation.
+// B[k*ldb + j].  A workgroup of four waves computes a 64 x 64 tile of C, each
+// wave a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16.  K advances in
+// slabs of 32: the workgroup stages op(A) (64 x 32) and op(B)^T (64 x 32) in
+// LDS, k contiguous, rounded to bfloat16 on the way in (BF16) or kept in
+// FP32, and the waves read their operands from there.  Out-of-range
+// operands are staged as 0 and out-of-range results are not stored.  BF16:
+// FP32 accumulation.
 //
-// MFMA operand layout (lane l of 64): 16x16x4 f32: A(row l%16, k l/16),
-// B(k l/16, col l%16); 16x16x16 bf16: A(row l%16, k 4(l/16)+i), B(k
-// 4(l/16)+i, col l%16), i = 0..3; result lane l, register j: row 4(l/16)+j,
-// col l%16.
+// MFMA operand layout (lane l of 64, r = l % 16, q = l / 16):
+//   16x16x32 bf16 (gfx950): A(row r, k 8q + t), B(k 8q + t, col r), t = 0..7;
+//   16x16x4 f32: A(row r, k q), B(k q, col r);
+//   result: lane l, register j holds row 4q + j, col r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+
 template <bool BF16>
-__global__ void __launch_bounds__(64)
+struct GemmTile {
+  static constexpr int TM = 64, TN = 64, TK = 32;
+  static constexpr int LD = BF16 ? TK + 8 : TK + 4;  // padded row (k) length; 16-byte aligned rows
+  using E = typename std::conditional<BF16, short, float>::type;
+};
+
+template <bool BF16>
+__global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
        int transB, float* __restrict__ C, int ldc, const float* __restrict__ bias, int relu) {
-  const int l = threadIdx.x;
-  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  using G = GemmTile<BF16>;
+  using E = typename G::E;
+  constexpr int TM = G::TM, TN = G::TN, TK = G::TK, LD = G::LD;
+  __shared__ __align__(16) E sA[TM * LD];  // sA[i*LD + k] = op(A)(i0 + i, k0 + k)
+  __shared__ __align__(16) E sB[TN * LD];  // sB[j*LD + k] = op(B)(k0 + k, j0 + j)
+  const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  const int wi = (wv >> 1) * 32, wj = (wv & 1) * 32;
+  const int r = l % 16, q = l / 16;
   floatx4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  auto ldA = [&](int i, int k) -> float {
-    if (i >= M || k >= K) return 0.f;
-    return transA ? A[(long)k * lda + i] : A[(long)i * lda + k];
+  auto put = [](float v) -> E {
+    if constexpr (BF16) return to_bf16(v);
+    else return v;
   };
-  auto ldB = [&](int k, int j) -> float {
-    if (k >= K || j >= N) return 0.f;
-    return transB ? B[(long)j * ldb + k] : B[(long)k * ldb + j];
-  };
-  const int r = l % 16, q = l / 16;
-  if constexpr (!BF16) {
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      float av[2], bv[2];
-      for (int a = 0; a < 2; ++a) av[a] = ldA(i0 + 16 * a + r, k0 + q);
-      for (int b = 0; b < 2; ++b) bv[b] = ldB(k0 + q, j0 + 16 * b + r);
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    // stage: 2048 values of each operand, 8 per thread, consecutive threads
+    // along the operand's contiguous global axis
+#pragma unroll
+    for (int st = 0; st < (TM * TK) / 256; ++st) {
+      const int idx = t + 256 * st;
+      int i, k;
+      if (transA) {
+        k = idx / TM;
+        i = idx % TM;
+      } else {
+        i = idx / TK;
+        k = idx % TK;
+      }
+      const int gi = i0 + i, gk = k0 + k;
+      float v = 0.f;
+      if (gi < M && gk < K) v = transA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+      sA[i * LD + k] = put(v);
+      int j, kb;
+      if (transB) {
+        j = idx / TK;
+        kb = idx % TK;
+      } else {
+        kb = idx / TN;
+        j = idx % TN;
+      }
+      const int gj = j0 + j, gkb = k0 + kb;
+      float u = 0.f;
+      if (gj < N && gkb < K) u = transB ? B[(long)gj * ldb + gkb] : B[(long)gkb * ldb + gj];
+      sB[j * LD + kb] = put(u);
     }
-  } else {
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      shortx4 av[2], bv[2];
+    __syncthreads();
+    if constexpr (BF16) {
+      bf16x8 av[2], bv[2];
       for (int a = 0; a < 2; ++a)
-        for (int t = 0; t < 4; ++t) av[a][t] = to_bf16(ldA(i0 + 16 * a + r, k0 + 4 * q + t));
+        av[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8*>(&sA[(wi + 16 * a + r) * LD + 8 * q]));
       for (int b = 0; b < 2; ++b)
-        for (int t = 0; t < 4; ++t) bv[b][t] = to_bf16(ldB(k0 + 4 * q + t, j0 + 16 * b + r));
+        bv[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8*>(&sB[(wj + 16 * b + r) * LD + 8 * q]));
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        float av[2], bv[2];
+        for (int a = 0; a < 2; ++a) av[a] = sA[(wi + 16 * a + r) * LD + kk + q];
+        for (int b = 0; b < 2; ++b) bv[b] = sB[(wj + 16 * b + r) * LD + kk + q];
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     }
+    __syncthreads();  // the next slab overwrites the tiles
   }
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int jj = 0; jj < 4; ++jj) {
-        const int i = i0 + 16 * a + 4 * q + jj, j = j0 + 16 * b + r;
+        const int i = i0 + wi + 16 * a + 4 * q + jj, j = j0 + wj + 16 * b + r;
         if (i < M && j < N) {
           float v = acc[a][b][jj];
           if (bias) v += bias[j];
@@ -203,11 +254,12 @@ static inline int gblocks(long n) {
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int transA, const float* B, int ldb, int transB,
                        float* C, int ldc, const float* bias, int relu, int bf16, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid((N + 31) / 32, (M + 31) / 32);
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
   if (bf16)
-    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(64), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias, relu);
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
+                       relu);
   else
-    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(64), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
                        relu);
   return hipGetLastError();
 }

@@ -164,14 +164,18 @@ __device__ bool sync_reduce(const double (&v)[K], double (&tot)[K], unsigned lon
   return *s_ok != 0;
 }
 
+// periodic neighbour; along the last axis within the instance's g.wl elements
 __device__ __forceinline__ int nbr(const Geo& g, int e, int d, int s) {
   int c[3];
   c[0] = e % g.ne[0];
   c[1] = (e / g.ne[0]) % g.ne[1];
   c[2] = g.dim == 3 ? e / (g.ne[0] * g.ne[1]) : 0;
-  c[d] += s;
-  if (c[d] < 0) c[d] += g.ne[d];
-  if (c[d] >= g.ne[d]) c[d] -= g.ne[d];
+  const int span = d == g.dim - 1 ? g.wl : g.ne[d];
+  const int base = c[d] - c[d] % span;
+  int loc = c[d] - base + s;
+  if (loc < 0) loc += span;
+  if (loc >= span) loc -= span;
+  c[d] = base + loc;
   return c[0] + g.ne[0] * (c[1] + g.ne[1] * c[2]);
 }
 

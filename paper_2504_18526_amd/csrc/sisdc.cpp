@@ -445,6 +445,17 @@ void account(sisdc_handle* h, int iters, bool converged, double rel) {
 // symmetric); an iterative solve leaves 1^T (b - A x) of the order of its
 // tolerance, and the shift removes it, so the totals the method conserves
 // hold to round-off whatever the tolerance.
+// On the streaming isotropic PCG the shift can instead be fused into the
+// solve (running sums in every update kernel): that pays on large levels,
+// where the update is bandwidth-bound and the sums ride along, but on small
+// ones the sums' block reductions cost more per iteration than the two
+// passes after the solve (three-level Euler workload: 39.2 against 33.4 ms
+// per step with every level fused).
+constexpr long kFusedConserveMin = 1L << 21;  // values per vector
+bool fused_conserve(const sisdc_handle* h, const Level& L) {
+  return h->meth.conserve && L.vlen >= kFusedConserveMin;
+}
+
 void conserve_fix(sisdc_handle* h, Level& L, const double* b, const LinComb* bl, double* x) {
   if (!h->meth.conserve) return;
   HIPCHECK(launch_conserve(b, bl, x, L.nv, L.vs, L.mw, L.np, L.mass_total, h->partials, 7 * kElemCap, h->stream));
@@ -732,7 +743,7 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
   if (!b && !(iso && bl)) fail(SISDC_EINVAL, "internal: no right-hand side for the multi-kernel PCG");
   CGStateT<T> cg = cg_state<T>(h, B, b, x, rtol);
   cg.x0 = x0;
-  if (iso && B.cons && h->meth.conserve && !x_is_zero) {  // the shift is fused into the PCG's kernels
+  if (iso && B.cons && fused_conserve(h, L) && !x_is_zero) {  // the shift is fused into the PCG's kernels
     cg.cons = B.cons;
     cg.vs = L.vs;
     cg.nv = L.nv;
@@ -990,7 +1001,7 @@ sisdc_solve_stats cg_solve_core(sisdc_handle* h, Level& L, const CoefP& cf, doub
   }
   sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, rtol, maxit, false);
   account(h, r.iters, r.converged, r.rel_residual);
-  if (!sipg_iso_path(L.g, cf)) conserve_fix(h, L, b, nullptr, x);  // fused into the isotropic PCG
+  if (!(sipg_iso_path(L.g, cf) && fused_conserve(h, L))) conserve_fix(h, L, b, nullptr, x);
   return r;
 }
 
@@ -1004,10 +1015,10 @@ bool stream_iso(sisdc_handle* h, const Level& L, const CoefP& cf) {
 
 sisdc_solve_stats solve_iso(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, const double* b,
                             const LinComb* bl, double* x, const double* x0) {
-  // the conservation shift is fused into the PCG's kernels here
   sisdc_solve_stats r = cg_multi<double>(h, L, bufs64(h, L), cf, dtm, b, x, h->meth.cg_rtol, h->meth.cg_maxit, false,
                                          bl, x0);
   account(h, r.iters, r.converged, r.rel_residual);
+  if (!fused_conserve(h, L)) conserve_fix(h, L, b, b ? nullptr : bl, x);
   return r;
 }
 
@@ -1614,12 +1625,14 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
   g.nf = pr.dim == 2 ? L.n1 : L.n1 * L.n1;
   g.E = L.E;
   g.J = 1.0;
+  const int stack = pr.stack > 1 ? pr.stack : 1;  // instances stacked along the last axis
   for (int d = 0; d < 3; ++d) {
     g.ne[d] = d < pr.dim ? ne[d] : 1;
-    g.h[d] = d < pr.dim ? (pr.hi[d] - pr.lo[d]) / ne[d] : 1.0;
+    g.h[d] = d < pr.dim ? (pr.hi[d] - pr.lo[d]) / (d == pr.dim - 1 ? ne[d] / stack : ne[d]) : 1.0;
     g.rh2[d] = 2.0 / g.h[d];
     if (d < pr.dim) g.J *= 0.5 * g.h[d];
   }
+  g.wl = g.ne[pr.dim - 1] / stack;
   gll(P, L.xg, L.wg);
   if ((int)L.xg.size() != L.n1) fail(SISDC_EDEVICE, "GLL node construction failed");
   L.D = derivative_matrix(L.xg);
@@ -1919,6 +1932,14 @@ void validate(const sisdc_problem* p, const sisdc_method* m) {
   if (m->precond != SISDC_PRECOND_JACOBI && m->precond != SISDC_PRECOND_FDS) fail(SISDC_EINVAL, "precond");
   if (!(m->cg_rtol > 0.0) || m->cg_maxit < 1) fail(SISDC_EINVAL, "cg_rtol > 0 and cg_maxit >= 1 required");
   if (m->precision != SISDC_FP64 && m->precision != SISDC_MIXED) fail(SISDC_EINVAL, "precision");
+  if (p->stack < 0) fail(SISDC_EINVAL, "stack must be >= 0");
+  if (p->stack > 1) {
+    if (sys) fail(SISDC_EINVAL, "stacked ensembles take scalar equations (CONVDIFF, BURGERS)");
+    if (m->conserve) fail(SISDC_EINVAL, "stacked ensembles need conserve = 0 (the shift is one constant per component)");
+    for (int l = 1; l < m->n_levels; ++l)
+      if (m->h_coarsen[l]) fail(SISDC_EINVAL, "stacked ensembles take no h_coarsen");
+    if ((long)p->stack * p->n_elem[p->dim - 1] > (1L << 20)) fail(SISDC_EINVAL, "stack too large");
+  }
   if (!(m->av_c >= 0.0)) fail(SISDC_EINVAL, "av_c must be >= 0");
   if (m->av_c > 0.0) {
     if (!(m->av_kappa > 0.0)) fail(SISDC_EINVAL, "artificial viscosity needs av_kappa > 0");
@@ -2047,6 +2068,7 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     // elements per axis of each level: halved where the level is 2:1 h-coarsened
     int ne[3][3];
     for (int d = 0; d < 3; ++d) ne[0][d] = d < prob->dim ? prob->n_elem[d] : 1;
+    if (prob->stack > 1) ne[0][prob->dim - 1] *= prob->stack;  // the instances, one after another
     for (int l = 1; l < meth->n_levels; ++l)
       for (int d = 0; d < 3; ++d) ne[l][d] = (meth->h_coarsen[l] && d < prob->dim) ? ne[l - 1][d] / 2 : ne[l - 1][d];
     for (int l = 0; l < meth->n_levels; ++l) build_level(h, h->lv[l], meth->P[l], meth->M[l], ne[l]);
@@ -2188,7 +2210,8 @@ int sisdc_node_coords(sisdc_handle* h, int level, double* x, int mem) {
       for (int n = 0; n < L.np; ++n) {
         int ic[3] = {n % L.n1, (n / L.n1) % L.n1, n / (L.n1 * L.n1)};
         for (int d = 0; d < dim; ++d)
-          c[((size_t)d * L.E + e) * L.np + n] = h->prob.lo[d] + L.g.h[d] * (ec[d] + 0.5 * (L.xg[ic[d]] + 1.0));
+          c[((size_t)d * L.E + e) * L.np + n] =
+              h->prob.lo[d] + L.g.h[d] * ((d == dim - 1 ? ec[d] % L.g.wl : ec[d]) + 0.5 * (L.xg[ic[d]] + 1.0));
       }
     }
     if (mem == SISDC_MEM_HOST) {

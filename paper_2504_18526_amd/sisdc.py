@@ -51,7 +51,8 @@ class Problem(ctypes.Structure):
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("eq", ctypes.c_int), ("a", ctypes.c_double * 3),
                 ("nu", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("mu", ctypes.c_double), ("Pr", ctypes.c_double), ("R", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("Pr", ctypes.c_double), ("R", ctypes.c_double),
+                ("stack", ctypes.c_int)]
 
 
 class Method(ctypes.Structure):
@@ -195,8 +196,11 @@ def _mem_of(*arrays):
     return mems.pop() if mems else MEM_HOST
 
 
-def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, Pr=0.71, R=1.0):
+def make_problem(dim, n_elem, lo, hi, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, Pr=0.71, R=1.0, stack=1):
+    """stack = B > 1: an ensemble of B instances of this problem stacked along
+    the last axis (one handle, every kernel once for all instances)."""
     p = Problem()
+    p.stack = stack
     p.dim = dim
     for d in range(3):
         p.n_elem[d] = n_elem[d] if d < dim else 1

@@ -134,6 +134,22 @@ def batch_64():
     return dict(name="batch2d_64_instances_mlsdc_mixed", eq="batch", dim=2, instances=inst, steps=20)
 
 
+def burgers_ensemble():
+    """Ensemble: 64 independent instances of the two-level Burgers
+    configuration (P 8/4, M 5/3, nu = 5e-3, cascade, 3 V-cycles + post-sweep,
+    N_c = 2) on 16 x 16-element boxes [0,1]^2, instance k with u0 from
+    seeded Fourier modes (seed k, |k| <= 6, scaled to max |u0| = 1), one
+    shared dt (CFL 2 on h = 1/16), 20 steps; stacked in one handle (problem
+    `stack`), no conservation shift."""
+    return dict(
+        name="burgers2d_ensemble_64x16x16_P8-4_M5-3",
+        eq="burgers", dim=2, n_elem=(16, 16), lo=(0.0, 0.0), hi=(1.0, 1.0), nu=5e-3,
+        P=[8, 4], M=[5, 3], start="cascade", cycles=3, n_coarse=2, post_sweep=1,
+        dt=cfl_dt(2.0, 1.0 / 16, 8, 2.0), steps=20, seed=0, kmax=6, cg_rtol=1e-10,
+        stack=64, conserve=0,
+    )
+
+
 def sod_2level():
     """Shock workload shaped like the paper's Sod test (Sec. 8: 80 elements of
     degree 5 on [0, 1], levels P 5/3, M 7/5, 32 steps to t = 0.2, cascade
@@ -156,4 +172,5 @@ WORKLOADS = {
     "ns": ns_2level,
     "batch": batch_64,
     "sod": sod_2level,
+    "ensemble": burgers_ensemble,
 }
