@@ -439,7 +439,7 @@ def main():
     from paper_2504_18526_amd.inputs import burgers_field
     from paper_2504_18526_amd.workloads import fine_sweeps_per_step
 
-    from paper_2504_18526_amd.inputs import convdiff_field, isentropic_vortex, taylor_green, sod_pair
+    from paper_2504_18526_amd.inputs import convdiff_field, convdiff_exact, isentropic_vortex, taylor_green, sod_pair
     from paper_2504_18526_amd.workloads import WORKLOADS, systems_dt
     w = WORKLOADS[a.workload]()
     if w["eq"] == "batch":
@@ -518,15 +518,34 @@ def main():
         ev0.record(stream)
     t0 = time.perf_counter()
     tot = {"cg_iters": 0, "solves": 0, "fine_sweeps": 0, "not_converged": 0, "max_rel_residual": 0.0}
+    step_ev = []  # an event after every step, for the median step time
     for _ in range(a.steps):
         st = sv.step(dt)
         for k in ("cg_iters", "solves", "fine_sweeps", "not_converged"):
             tot[k] += st[k]
         tot["max_rel_residual"] = max(tot["max_rel_residual"], st["max_rel_residual"])
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        step_ev.append(e)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = ev0.elapsed_time(ev1) / a.steps
+    per_step = [ev0.elapsed_time(step_ev[0])] + [step_ev[k - 1].elapsed_time(step_ev[k]) for k in range(1, a.steps)]
+    ms_median = float(np.median(per_step))
+    # error against the exact solution where the problem has one
+    err_exact = None
+    if w["eq"] in ("euler", "convdiff") and w.get("init") != "sod" and B == 1:
+        t_end = (max(1, a.warmup) + a.steps) * dt
+        fin = torch.empty_like(ud)
+        sv.get_state(fin)
+        if w["eq"] == "euler":
+            ex = isentropic_vortex(xs, t=t_end)
+        else:
+            ex = convdiff_exact(xs, t_end, w["a"], w["nu"], seed=w["seed"], kmax=w["kmax"])
+        ex = np.ascontiguousarray(np.asarray(ex).reshape(nv, E, Np))
+        fv = fin.cpu().numpy()
+        err_exact = float(np.linalg.norm(fv - ex) / np.linalg.norm(ex))
 
     sweeps = fine_sweeps_per_step(w)
     dof_updates = E * Np * nv * M * sweeps
@@ -624,7 +643,8 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic (seeded Fourier initial data)",
         "config": {"workload": w["name"], "levels_P": w["P"], "levels_M": w["M"], "global_batch": B, "seq_len": None, "parallelism": "none",
-                   "single_instance": single,
+                   "single_instance": single, "ms_per_step_median": ms_median,
+                   "rel_l2_error_vs_exact_solution": err_exact,
                    "dt": dt, "fine_dof": E * Np * nv, "fine_sweeps_per_step": sweeps,
                    "cg_iters_per_step": tot["cg_iters"] / a.steps, "solves_per_step": tot["solves"] / a.steps,
                    "not_converged": tot["not_converged"], "max_rel_residual": tot["max_rel_residual"],

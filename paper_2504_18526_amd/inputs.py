@@ -61,6 +61,21 @@ def convdiff_field(coords, seed=0, kmax=4):
     return u
 
 
+def convdiff_exact(coords, t, a, nu, seed=0, kmax=4):
+    """The convection-diffusion field of convdiff_field after time t of
+    u_t + a.grad u = nu lap u on the periodic unit box: every Fourier mode k
+    moves with a and decays by exp(-nu (2 pi |k|)^2 t)."""
+    dim = len(coords)
+    xs = [coords[d] - a[d] * t for d in range(dim)]
+    decay = lambda n2: np.exp(-nu * 4.0 * np.pi * np.pi * n2 * t)
+    u = np.sin(2 * np.pi * xs[0]) * np.sin(2 * np.pi * xs[1]) * decay(2.0)
+    for k, ak, bk in fourier_modes(seed, dim, kmax, "normal"):
+        n2 = float(sum(v * v for v in k))
+        th = _phase(xs, k)
+        u = u + (ak * np.cos(th) + bk * np.sin(th)) / n2 * decay(n2)
+    return u
+
+
 def burgers_field(coords, seed=0, kmax=6):
     """Initial field of the Burgers case, max |u| = 1 over the points."""
     dim = len(coords)
