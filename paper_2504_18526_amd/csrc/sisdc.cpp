@@ -1144,7 +1144,15 @@ void sweep(sisdc_handle* h, Level& L, double dt, const double* g) {
         gm ? make_lc({{1.0, ua}, {1.0, qm}, {1.0, gm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0, 0})
            : make_lc({{1.0, ua}, {1.0, qm}, {dtm, Ca}, {-dtm, Cold_prev}, {dtm, Xm}}, {1, 0, 0, 0, 0});
     double* y = si1 ? L.unm(m) : L.y;
-    solve_lc(h, L, cf, dtm, b1, y, L.um(m));
+    // initial guess: u^{k-1}_m shifted by the change this sweep made at node
+    // m-1 (the corrections of neighbouring nodes are close); the guess moves
+    // the PCG iterates only, not the solution it converges to
+    const double* x0 = L.um(m);
+    if (m > 1) {
+      lincomb(h, L, L.t2, {{1.0, L.um(m)}, {1.0, L.unm(m - 1)}, {-1.0, L.um(m - 1)}});
+      x0 = L.t2;
+    }
+    solve_lc(h, L, cf, dtm, b1, y, x0);
     if (!si1) {
       // stage 2: M u^k_m = M u^k_{m-1} + q_m + g_m + H(y,u^k_{m-1},u^k_m) - H(u^{k-1}_m,u^{k-1}_{m-1},u^{k-1}_m)
       conv(h, L, y, L.t1);
