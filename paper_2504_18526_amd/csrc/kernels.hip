@@ -32,6 +32,10 @@ struct EL {
   static constexpr int NF = DIM == 2 ? N1 : N1 * N1;
   static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
   static constexpr int NT = ((EPB * NP + 63) / 64) * 64;
+  // threads of the kernels with face tasks (a thread per node and a thread
+  // per face node of the workgroup's elements, whichever needs more)
+  static constexpr int NFT = EPB * 2 * DIM * NF;
+  static constexpr int NTF = NT > NFT ? NT : ((NFT + 63) / 64) * 64;
   static constexpr int stride(int d) { return d == 0 ? 1 : (d == 1 ? N1 : N1 * N1); }
 };
 
@@ -134,6 +138,17 @@ __device__ void sum_partials(const T* const (&part)[K], int n, T (&tot)[K]) {
   __syncthreads();
 }
 
+// f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>):
+// loop indices that are constant expressions.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // ---------------------------------------------------------------- fluxes
 template <int NV>
 __device__ __forceinline__ void flux(const EqP& q, int d, const double (&u)[NV], double (&f)[NV]) {
@@ -167,30 +182,76 @@ __device__ __forceinline__ double wave_speed(const EqP& q, int d, const double (
 }
 
 // ---------------------------------------------------------------- C(u)
+// Node (i0, i1, i2) of face node fn on the face normal to d at index `at`
+// along d (the inverse of face_index).
+template <int DIM, int N1>
+__device__ __forceinline__ int face_node(int d, int fn, int at) {
+  if (DIM == 2) return d == 0 ? at + N1 * fn : fn + N1 * at;
+  const int f0 = fn % N1, f1 = fn / N1;
+  return d == 0 ? at + N1 * (f0 + N1 * f1) : (d == 1 ? f0 + N1 * (at + N1 * f1) : f0 + N1 * (f1 + N1 * at));
+}
+
+// The 2 DIM face neighbours of the workgroup's EPB elements e0 + l, in
+// snb[l][2 d + side] (side 0: minus, 1: plus); every thread calls it.
+template <int DIM, int EPB>
+__device__ __forceinline__ void face_neighbours(const Geo& g, int e0, int* snb) {
+  const int t = threadIdx.x;
+  if (t < EPB * 2 * DIM) {
+    const int l = t / (2 * DIM), f = t - l * 2 * DIM;
+    snb[t] = e0 + l < g.E ? neighbour(g, e0 + l, f >> 1, (f & 1) ? 1 : -1) : 0;
+  }
+}
+
 // out = C(u): -J w (sum_d 2/h_d D_d f_d(u)) - sum_faces J_f w_f (f* - f(u^-)).n
+// A thread per node forms the volume term.  The face term is formed by a
+// thread per face node (face and node are what every lane of a wave works
+// on, so no wave runs a face at a fraction of its lanes) into LDS, and the
+// node threads subtract it; the neighbours of the workgroup's elements are
+// found once.
 template <int DIM, int P, int NV>
-__global__ void __launch_bounds__((EL<DIM, P>::NT))
+__global__ void __launch_bounds__((EL<DIM, P>::NTF))
 k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
        const double* __restrict__ tab, long vs) {
   using L = EL<DIM, P>;
-  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NFC = 2 * DIM;
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sf[EPB * NV * NP];
+  __shared__ double su[EPB * NV * NP];
+  __shared__ double sF[EPB * NFC * NF * NV];
+  __shared__ int snb[EPB * NFC];
   u += (long)blockIdx.y * NV * vs;  // node blockIdx.y of a batch of node vectors
   out += (long)blockIdx.y * NV * vs;
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+  const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB, e = e0 + le;
   const bool act = (le < EPB) && (e < g.E);
-  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
-  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  static_assert(L::NT >= N1 * N1, "a thread per entry of the tables");
+  // every global load of the prologue is issued before the first wait
+  double uu[NV], acc[NV];
+  for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
+  const double dv = t < N1 * N1 ? tab[t] : 0.0, wv = t < N1 ? tab[N1 * N1 + t] : 0.0;
+  face_neighbours<DIM, EPB>(g, e0, snb);
+  if (t < N1 * N1) sD[t] = dv;
+  if (t < N1) sw[t] = wv;
   int ii[3];
   decomp<DIM, N1>(n, ii);
-  double uu[NV], acc[NV];
   for (int v = 0; v < NV; ++v) {
-    uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
     acc[v] = 0.0;
+    if (act) su[(le * NV + v) * NP + n] = uu[v];
   }
   __syncthreads();
+  // face tasks, a thread per (element, face, face node): the neighbour's
+  // state at the face node of task k
+  constexpr int NTASK = EPB * NFC * NF;
+  auto outside = [&](int k, double (&uo)[NV]) {
+    const int l = k / (NFC * NF), f = (k / NF) % NFC, fn = k % NF;
+    const int nn = face_node<DIM, N1>(f >> 1, fn, (f & 1) ? 0 : P);
+    const long nb = snb[l * NFC + f];
+    for (int v = 0; v < NV; ++v) uo[v] = u[v * vs + nb * NP + nn];
+  };
+  // the first task's values are requested before the volume term and used
+  // after it
+  double uo0[NV];
+  if (t < NTASK && e0 + t / (NFC * NF) < g.E) outside(t, uo0);
   for (int d = 0; d < DIM; ++d) {
     if (act) {
       double f[NV];
@@ -211,29 +272,48 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
     }
     __syncthreads();
   }
+  // the face terms into sF; the axis is made a constant, so the state's
+  // components stay in registers
+  for (int k = t; k < NTASK; k += L::NTF) {
+    const int l = k / (NFC * NF), f = (k / NF) % NFC, fn = k % NF;
+    if (e0 + l >= g.E) continue;
+    double uo[NV];
+    if (k == t)
+      for (int v = 0; v < NV; ++v) uo[v] = uo0[v];
+    else
+      outside(k, uo);
+    static_for<DIM>([&](auto dc) {
+      constexpr int d = decltype(dc)::value;
+      if ((f >> 1) != d) return;
+      const int side = f & 1;
+      const double sgn = side ? 1.0 : -1.0;
+      const int nown = face_node<DIM, N1>(d, fn, side ? P : 0);
+      double ui[NV], fi[NV], fo[NV];
+      for (int v = 0; v < NV; ++v) ui[v] = su[(l * NV + v) * NP + nown];
+      flux<NV>(q, d, ui, fi);
+      flux<NV>(q, d, uo, fo);
+      const double lam = fmax(wave_speed<NV>(q, d, ui), wave_speed<NV>(q, d, uo));
+      // the face weight: w over the axes other than d
+      const double wf = DIM == 2 ? sw[fn] : sw[fn % N1] * sw[fn / N1];
+      const double jfwf = g.J * g.rh2[d] * wf;
+      for (int v = 0; v < NV; ++v) {
+        const double fin = sgn * fi[v], fout = sgn * fo[v];
+        const double fstar = 0.5 * (fin + fout) - 0.5 * lam * (uo[v] - ui[v]);
+        sF[k * NV + v] = jfwf * (fstar - fin);
+      }
+    });
+  }
+  __syncthreads();
   if (!act) return;
   double wn = 1.0;
   for (int d = 0; d < DIM; ++d) wn *= sw[ii[d]];
   for (int v = 0; v < NV; ++v) acc[v] *= g.J * wn;
-  for (int d = 0; d < DIM; ++d) {
+  for (int d = 0; d < DIM; ++d)
     for (int side = 0; side < 2; ++side) {
       if (ii[d] != (side ? P : 0)) continue;
-      const double sgn = side ? 1.0 : -1.0;
-      const int nb = neighbour(g, e, d, side ? 1 : -1);
-      const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
-      double uo[NV], fi[NV], fo[NV];
-      for (int v = 0; v < NV; ++v) uo[v] = u[v * vs + (long)nb * NP + nn];
-      flux<NV>(q, d, uu, fi);
-      flux<NV>(q, d, uo, fo);
-      const double lam = fmax(wave_speed<NV>(q, d, uu), wave_speed<NV>(q, d, uo));
-      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
-      for (int v = 0; v < NV; ++v) {
-        const double fin = sgn * fi[v], fout = sgn * fo[v];
-        const double fstar = 0.5 * (fin + fout) - 0.5 * lam * (uo[v] - uu[v]);
-        acc[v] -= jfwf * (fstar - fin);
-      }
+      const double* c = &sF[((le * NFC + 2 * d + side) * NF + face_index<DIM, N1>(d, ii)) * NV];
+      for (int v = 0; v < NV; ++v) acc[v] -= c[v];
     }
-  }
   for (int v = 0; v < NV; ++v) out[v * vs + (long)e * NP + n] = acc[v];
 }
 
@@ -268,77 +348,136 @@ __device__ __forceinline__ void visc_flux(const EqP& q, int d, const double (&u)
   f[DIM + 1] = work + q.lam_T * G[d][DIM];
 }
 
-// BR1 lifted gradients at a node: grad q from the LDS tiles sq (component j
-// at sq[j * EPB * NP]) plus (2/h_d) / w_face * ({q} - q^-) n_d at face nodes.
+// The viscous term in two passes over u, both built the same way as C(u):
+// every global load of a pass is issued at its start (a face task's
+// neighbour values included), and work on faces runs as face tasks, a
+// thread per (element, face, face node), into LDS.
+//
+// BR1 lifted gradients at node n (indices ii) of element slot l: grad q from
+// the LDS tiles sq (component j at sq[j * EPB * NP]) plus, at face nodes,
+// (2/h_d) / w_face * ({q} - q^-) n_d = (2/h_d) / w_face * (q^+ - q^-) / 2 n_d
+// with the jumps q^+ - q^- of the faces in sdq[face task][j].
 template <int DIM, int P>
-__device__ __forceinline__ void lifted_grad(const double* sq, int le, int n, const int (&ii)[3], const double* sD,
-                                            const double* sw, const Geo& g, const EqP& q, const double* u, long vs,
-                                            int e, const double (&qo)[DIM + 1], double (&G)[DIM][DIM + 1]) {
+__device__ __forceinline__ void lifted_grad(const double* sq, const double* sdq, int l, int n, const int (&ii)[3],
+                                            const double* sD, const double* sw, const Geo& g,
+                                            double (&G)[DIM][DIM + 1]) {
   using L = EL<DIM, P>;
-  constexpr int N1 = L::N1, NP = L::NP, EPB = L::EPB;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NQ = DIM + 1, NFC = 2 * DIM;
+#pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int st = L::stride(d);
-    for (int j = 0; j <= DIM; ++j) {
-      const double* row = &sq[(j * EPB + le) * NP + n - ii[d] * st];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const double* row = &sq[(j * EPB + l) * NP + n - ii[d] * st];
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < N1; ++k) s += sD[ii[d] * N1 + k] * row[k * st];
       G[d][j] = g.rh2[d] * s;
     }
   }
+#pragma unroll
   for (int d = 0; d < DIM; ++d)
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       if (ii[d] != (side ? P : 0)) continue;
-      const double sgn = side ? 1.0 : -1.0;
-      const int nb = neighbour(g, e, d, side ? 1 : -1);
-      const int nn = n + ((side ? 0 : P) - ii[d]) * L::stride(d);
-      double uo[DIM + 2], qn[DIM + 1];
-      for (int v = 0; v < DIM + 2; ++v) uo[v] = u[v * vs + (long)nb * NP + nn];
-      prim_q<DIM>(q, uo, qn);
-      const double lift = g.rh2[d] / sw[ii[d]] * 0.5 * sgn;
-      for (int j = 0; j <= DIM; ++j) G[d][j] += lift * (qn[j] - qo[j]);
+      const double lift = g.rh2[d] / sw[ii[d]] * 0.5 * (side ? 1.0 : -1.0);
+      const double* dq = &sdq[((l * NFC + 2 * d + side) * NF + face_index<DIM, N1>(d, ii)) * NQ];
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) G[d][j] += lift * dq[j];
     }
+}
+
+// Face task k of a workgroup of EPB elements from e0: element slot l, face
+// f = 2 d + side, face node fn; the node on the face (nown), the matching
+// node of the neighbour (nn) and the neighbour (nb).
+template <int DIM, int P>
+struct FaceTask {
+  using L = EL<DIM, P>;
+  static constexpr int NF = L::NF, NFC = 2 * DIM;
+  int l, f, fn, nown, nn, nb;
+  __device__ FaceTask(int k, int e0, const Geo& g) {
+    l = k / (NFC * NF);
+    f = (k / NF) % NFC;
+    fn = k % NF;
+    const int d = f >> 1, side = f & 1;
+    nown = face_node<DIM, L::N1>(d, fn, side ? P : 0);
+    nn = face_node<DIM, L::N1>(d, fn, side ? 0 : P);
+    nb = e0 + l < g.E ? neighbour(g, e0 + l, d, side ? 1 : -1) : 0;
+  }
+};
+
+// The jumps q^+ - q^- at the face nodes of the workgroup's elements into
+// sdq (uo0: the outside state of task threadIdx.x, loaded by the caller).
+template <int DIM, int P>
+__device__ __forceinline__ void face_jumps(const double* __restrict__ u, long vs, const EqP& q, const Geo& g, int e0,
+                                           const double* sq, const double (&uo0)[DIM + 2], double* sdq) {
+  using L = EL<DIM, P>;
+  constexpr int NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2, NQ = DIM + 1, NTASK = EPB * 2 * DIM * NF;
+  const int t = threadIdx.x;
+  for (int k = t; k < NTASK; k += L::NTF) {
+    const FaceTask<DIM, P> ft(k, e0, g);
+    if (e0 + ft.l >= g.E) continue;
+    double uo[NV], qn[NQ];
+    for (int v = 0; v < NV; ++v) uo[v] = k == t ? uo0[v] : u[v * vs + (long)ft.nb * NP + ft.nn];
+    prim_q<DIM>(q, uo, qn);
+    for (int j = 0; j < NQ; ++j) sdq[k * NQ + j] = qn[j] - sq[(j * EPB + ft.l) * NP + ft.nown];
+  }
 }
 
 // Pass 1 of the viscous term: the viscous fluxes f_v,d at face nodes,
 // trace[v][e][d][side][f].
 template <int DIM, int P>
-__global__ void __launch_bounds__((EL<DIM, P>::NT))
+__global__ void __launch_bounds__((EL<DIM, P>::NTF))
 k_visc_trace(const double* __restrict__ u, double* __restrict__ trace, Geo g, EqP q, const double* __restrict__ tab,
              long vs) {
   using L = EL<DIM, P>;
-  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2, NQ = DIM + 1, NFC = 2 * DIM;
+  constexpr int NTASK = EPB * NFC * NF;
+  static_assert(L::NT >= N1 * N1, "a thread per entry of the tables");
   __shared__ double sD[N1 * N1], sw[N1];
-  __shared__ double sq[(DIM + 1) * EPB * NP];
+  __shared__ double sq[NQ * EPB * NP], su[NV * EPB * NP];
+  __shared__ double sdq[NTASK * NQ];
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+  const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB, e = e0 + le;
   const bool act = (le < EPB) && (e < g.E);
-  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
-  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
-  int ii[3];
-  decomp<DIM, N1>(n, ii);
-  double uu[NV], qo[DIM + 1];
+  double uu[NV], uo0[NV];
   for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
-  prim_q<DIM>(q, uu, qo);
-  if (act)
-    for (int j = 0; j <= DIM; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+  const double dv = t < N1 * N1 ? tab[t] : 0.0, wv = t < N1 ? tab[N1 * N1 + t] : 0.0;
+  if (t < NTASK) {
+    const FaceTask<DIM, P> ft(t, e0, g);
+    for (int v = 0; v < NV; ++v) uo0[v] = e0 + ft.l < g.E ? u[v * vs + (long)ft.nb * NP + ft.nn] : 1.0;
+  }
+  if (t < N1 * N1) sD[t] = dv;
+  if (t < N1) sw[t] = wv;
+  if (act) {
+    double qo[NQ];
+    prim_q<DIM>(q, uu, qo);
+    for (int j = 0; j < NQ; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+    for (int v = 0; v < NV; ++v) su[(v * EPB + le) * NP + n] = uu[v];
+  }
   __syncthreads();
-  if (!act) return;
-  bool face = false;
-  for (int d = 0; d < DIM; ++d) face = face || ii[d] == 0 || ii[d] == P;
-  if (!face) return;
-  double G[DIM][DIM + 1];
-  lifted_grad<DIM, P>(sq, le, n, ii, sD, sw, g, q, u, vs, e, qo, G);
-  for (int d = 0; d < DIM; ++d) {
-    const bool lo = ii[d] == 0, hi = ii[d] == P;
-    if (!lo && !hi) continue;
+  face_jumps<DIM, P>(u, vs, q, g, e0, sq, uo0, sdq);
+  __syncthreads();
+  // a face task per face node: the lifted gradient there and the flux
+  // normal to its face
+  for (int k = t; k < NTASK; k += L::NTF) {
+    const FaceTask<DIM, P> ft(k, e0, g);
+    if (e0 + ft.l >= g.E) continue;
+    int jj[3];
+    decomp<DIM, N1>(ft.nown, jj);
+    double G[DIM][NQ], uf[NV];
+    lifted_grad<DIM, P>(sq, sdq, ft.l, ft.nown, jj, sD, sw, g, G);
+    for (int v = 0; v < NV; ++v) uf[v] = su[(v * EPB + ft.l) * NP + ft.nown];
+    const int d = ft.f >> 1;
     double f[NV];
-    visc_flux<DIM>(q, d, uu, G, f);
-    for (int v = 0; v < NV; ++v) {
-      const long base = (((long)v * g.E + e) * DIM + d) * 2 * NF + face_index<DIM, N1>(d, ii);
-      if (lo) trace[base] = f[v];
-      if (hi) trace[base + NF] = f[v];
-    }
+    if (d == 0)  // the axis as a constant, so that G stays in registers
+      visc_flux<DIM>(q, 0, uf, G, f);
+    else if (d == 1)
+      visc_flux<DIM>(q, 1, uf, G, f);
+    else
+      visc_flux<DIM>(q, DIM - 1, uf, G, f);
+    for (int v = 0; v < NV; ++v)
+      trace[(((long)v * g.E + e0 + ft.l) * DIM + d) * 2 * NF + (ft.f & 1) * NF + ft.fn] = f[v];
   }
 }
 
@@ -346,29 +485,49 @@ k_visc_trace(const double* __restrict__ u, double* __restrict__ trace, Geo g, Eq
 // ({f_v} - f_v^-).n  (accumulated onto out, which holds C(u)); with add
 // != NULL, out = add + V(u) instead (add holds C(u), out is not read).
 template <int DIM, int P>
-__global__ void __launch_bounds__((EL<DIM, P>::NT))
+__global__ void __launch_bounds__((EL<DIM, P>::NTF))
 k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ trace, Geo g, EqP q,
              const double* __restrict__ tab, long vs, const double* __restrict__ add) {
   using L = EL<DIM, P>;
-  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2;
+  constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NV = DIM + 2, NQ = DIM + 1, NFC = 2 * DIM;
+  constexpr int NTASK = EPB * NFC * NF;
+  static_assert(L::NT >= N1 * N1, "a thread per entry of the tables");
   __shared__ double sD[N1 * N1], sw[N1];
-  __shared__ double sq[(DIM + 1) * EPB * NP];
+  __shared__ double sq[NQ * EPB * NP];
   __shared__ double sf[NV * EPB * NP];
+  __shared__ double sdq[NTASK * NQ];
+  __shared__ double sfc[NTASK * NV];  // face corrections (component 0 unused)
   const int t = threadIdx.x, le = t / NP, n = t - le * NP;
-  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+  const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB, e = e0 + le;
   const bool act = (le < EPB) && (e < g.E);
-  for (int k = t; k < N1 * N1; k += blockDim.x) sD[k] = tab[k];
-  for (int k = t; k < N1; k += blockDim.x) sw[k] = tab[N1 * N1 + k];
+  // the node's state, the tables, and for face task t the neighbour's state
+  // and its viscous flux on the shared face
+  double uu[NV], uo0[NV], tr0[NV];
+  for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
+  const double dv = t < N1 * N1 ? tab[t] : 0.0, wv = t < N1 ? tab[N1 * N1 + t] : 0.0;
+  if (t < NTASK) {
+    const FaceTask<DIM, P> ft(t, e0, g);
+    const bool in = e0 + ft.l < g.E;
+    const int d = ft.f >> 1, side = ft.f & 1;
+    for (int v = 0; v < NV; ++v) {
+      uo0[v] = in ? u[v * vs + (long)ft.nb * NP + ft.nn] : 1.0;
+      tr0[v] = in && v > 0 ? trace[(((long)v * g.E + ft.nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + ft.fn] : 0.0;
+    }
+  }
+  if (t < N1 * N1) sD[t] = dv;
+  if (t < N1) sw[t] = wv;
   int ii[3];
   decomp<DIM, N1>(n, ii);
-  double uu[NV], qo[DIM + 1];
-  for (int v = 0; v < NV; ++v) uu[v] = act ? u[v * vs + (long)e * NP + n] : 1.0;
-  prim_q<DIM>(q, uu, qo);
-  if (act)
-    for (int j = 0; j <= DIM; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+  if (act) {
+    double qo[NQ];
+    prim_q<DIM>(q, uu, qo);
+    for (int j = 0; j < NQ; ++j) sq[(j * EPB + le) * NP + n] = qo[j];
+  }
   __syncthreads();
-  double G[DIM][DIM + 1];
-  if (act) lifted_grad<DIM, P>(sq, le, n, ii, sD, sw, g, q, u, vs, e, qo, G);
+  face_jumps<DIM, P>(u, vs, q, g, e0, sq, uo0, sdq);
+  __syncthreads();
+  double G[DIM][NQ];
+  if (act) lifted_grad<DIM, P>(sq, sdq, le, n, ii, sD, sw, g, G);
   double acc[NV];
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   for (int d = 0; d < DIM; ++d) {
@@ -388,6 +547,19 @@ k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const doubl
         acc[v] += g.rh2[d] * s;
       }
     }
+    // the face corrections on the faces normal to d: J_f w_f (f^+ - f^-)/2 . n
+    for (int k = t; k < NTASK; k += L::NTF) {
+      const FaceTask<DIM, P> ft(k, e0, g);
+      if (e0 + ft.l >= g.E || (ft.f >> 1) != d) continue;
+      const int side = ft.f & 1;
+      const double wf = DIM == 2 ? sw[ft.fn] : sw[ft.fn % N1] * sw[ft.fn / N1];
+      const double jfwf = g.J * g.rh2[d] * wf;
+      for (int v = 1; v < NV; ++v) {
+        const double fnb =
+            k == t ? tr0[v] : trace[(((long)v * g.E + ft.nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + ft.fn];
+        sfc[k * NV + v] = jfwf * 0.5 * (side ? 1.0 : -1.0) * (fnb - sf[(v * EPB + ft.l) * NP + ft.nown]);
+      }
+    }
     __syncthreads();
   }
   if (!act) return;
@@ -397,15 +569,8 @@ k_visc_apply(const double* __restrict__ u, double* __restrict__ out, const doubl
   for (int d = 0; d < DIM; ++d)
     for (int side = 0; side < 2; ++side) {
       if (ii[d] != (side ? P : 0)) continue;
-      const double sgn = side ? 1.0 : -1.0;
-      const int nb = neighbour(g, e, d, side ? 1 : -1);
-      double f[NV];
-      visc_flux<DIM>(q, d, uu, G, f);
-      const double jfwf = g.J * g.rh2[d] * wn / sw[ii[d]];
-      for (int v = 1; v < NV; ++v) {
-        const double fnb = trace[(((long)v * g.E + nb) * DIM + d) * 2 * NF + (side ? 0 : NF) + face_index<DIM, N1>(d, ii)];
-        acc[v] += jfwf * 0.5 * sgn * (fnb - f[v]);
-      }
+      const double* c = &sfc[((le * NFC + 2 * d + side) * NF + face_index<DIM, N1>(d, ii)) * NV];
+      for (int v = 1; v < NV; ++v) acc[v] += c[v];
     }
   const long i0 = (long)e * NP + n;
   if (add) {
@@ -678,16 +843,6 @@ __device__ __forceinline__ void load_line(const T* __restrict__ xc, int e, int a
 // Axis D of the isotropic apply on the line (a, b) of element e: xl holds
 // the operand on the line; r[k] receives the volume and face terms of line
 // node k.
-// f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N-1>):
-// loop indices that are constant expressions.
-template <class F, int... Is>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
-  (f(std::integral_constant<int, Is>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
 
 // D[k][j] and w[k] of degree P as literal constants of type T
 template <typename T, int P, int K, int J>
@@ -886,11 +1041,19 @@ k_sipg_apply_iso3_brick(const T* __restrict__ x, const T* __restrict__ isc, T* _
   const long kx = per + (xcd < rem ? 1 : 0);
   const long lb0 = (long)xcd * per + (xcd < rem ? xcd : rem);
   const long ts = lb0 * ntask / G, te = (lb0 + kx) * ntask / G;
-  T dacc = T(0.0);
-  for (long t = ts + blockIdx.x / kXcd; t < te; t += kx) {
-    const int c = (int)(t / nbr);
+  // The task index t = ((c nbz + Bz) nby + By) nbx + Bx is decoded once; the
+  // stride kx is added digit by digit with carries, which keeps divisions out
+  // of the loop (each digit of kx is below its radix, so one carry suffices).
+  long t = ts + blockIdx.x / kXcd;
+  int c = (int)(t / nbr), Bx, By, Bz;
+  {
     const long br = t - (long)c * nbr;
-    const int Bx = (int)(br % nbx), By = (int)((br / nbx) % nby), Bz = (int)(br / ((long)nbx * nby));
+    Bx = (int)(br % nbx), By = (int)((br / nbx) % nby), Bz = (int)(br / ((long)nbx * nby));
+  }
+  const int dc = (int)(kx / nbr), dx = (int)((kx % nbr) % nbx), dy = (int)(((kx % nbr) / nbx) % nby),
+            dz = (int)((kx % nbr) / ((long)nbx * nby));
+  T dacc = T(0.0);
+  for (; t < te; t += kx) {
     const int ex = 2 * Bx + bx, ey = 2 * By + by, ez = 2 * Bz + bz;
     const int e = ex + g.ne[0] * (ey + g.ne[1] * ez);
     // the neighbour outside the brick along each axis (periodic)
@@ -948,10 +1111,20 @@ k_sipg_apply_iso3_brick(const T* __restrict__ x, const T* __restrict__ isc, T* _
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const T val = alpha * jab * w[k] * xl[k] + beta * (r[k] + R[a + SY * b + SZ * k]);
-      out[c * vs + (long)e * NP + line_node<2, N1>(k, a, b)] = val;
+      __builtin_nontemporal_store(val, &out[c * vs + (long)e * NP + line_node<2, N1>(k, a, b)]);
       dacc += val * xl[k];
     }
     __syncthreads();  // every wave is done with the brick and its R region
+    Bx += dx;
+    int cy = Bx >= nbx ? 1 : 0;
+    Bx -= cy * nbx;
+    By += dy + cy;
+    cy = By >= nby ? 1 : 0;
+    By -= cy * nby;
+    Bz += dz + cy;
+    cy = Bz >= nbz ? 1 : 0;
+    Bz -= cy * nbz;
+    c += dc + cy;
   }
   if (part != nullptr) {
     const T v1[1] = {dacc};
@@ -2092,9 +2265,9 @@ static hipError_t conv_dim_p(const double* u, double* out, const Geo& g, const E
   if (nodes < 1)
     return hipErrorInvalidValue;
   else if (q.nv == 1)
-    hipLaunchKernelGGL((k_conv<DIM, P, 1>), grid, dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+    hipLaunchKernelGGL((k_conv<DIM, P, 1>), grid, dim3(L::NTF), 0, s, u, out, g, q, tab, vs);
   else if (q.nv == DIM + 2)
-    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), grid, dim3(L::NT), 0, s, u, out, g, q, tab, vs);
+    hipLaunchKernelGGL((k_conv<DIM, P, DIM + 2>), grid, dim3(L::NTF), 0, s, u, out, g, q, tab, vs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -2171,11 +2344,12 @@ static hipError_t sipg_apply_t(const T* x, T* out, int nv, const CoefT<T>& cf, c
 
 template <typename T, int DIM, int P>
 static hipError_t diag_dim_p(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,
-                             hipStream_t s) {
+                             hipStream_t s, bool first_only = false) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_helm_diag<T, DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, diag, nv, vs, cf,
-                     dtm, ctau, g, tab);
+  // first_only: one workgroup, i.e. the first EPB elements, component 0
+  hipLaunchKernelGGL((k_helm_diag<T, DIM, P>), dim3(first_only ? 1 : elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, diag,
+                     first_only ? 1 : nv, vs, cf, dtm, ctau, g, tab);
   return hipGetLastError();
 }
 
@@ -2246,6 +2420,14 @@ static bool iso_path_t(const Geo& g, const CoefT<T>& cf) {
     if ((G_).dim == 2) { constexpr int DD = 2; SISDC_DISPATCH_P((G_).P, BODY); }          \
     return hipErrorInvalidValue;                                                          \
   } while (0)
+
+// The Helmholtz diagonal of the first element of component 0 of an
+// isotropic level (every element and component has the same one).
+template <typename T>
+static hipError_t iso_diag_first(T* diag, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,
+                                 hipStream_t s) {
+  SISDC_DISPATCH_ISO_DIM(g, return (diag_dim_p<T, DD, PP>(diag, 1, cf, dtm, ctau, g, tab, s, true)));
+}
 
 // grid of the isotropic CG kernels: the same partial count as the matvec
 template <int DIM, int P>
@@ -2420,7 +2602,12 @@ int iso_cg_grid(const Geo& g) {
     return cg_iter_t<T>(cg, nv, cf, g, tab, it, id, s);                                                         \
   }                                                                                                             \
   bool sipg_iso_path(const Geo& g, const CoefT<T>& cf) { return iso_path_t<T>(g, cf); }                         \
-  hipError_t launch_inv_table(const T* diag, T* idg, int np, hipStream_t s) {                                   \
+  hipError_t launch_iso_inv_diag(T* diag, T* idg, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab, \
+                                 hipStream_t s) {                                                               \
+    if (!iso_path_t<T>(g, cf)) return hipErrorInvalidValue;                                                     \
+    const hipError_t e = iso_diag_first<T>(diag, cf, dtm, ctau, g, tab, s);                                     \
+    if (e != hipSuccess) return e;                                                                              \
+    const int np = g.dim == 3 ? (g.P + 1) * (g.P + 1) * (g.P + 1) : (g.P + 1) * (g.P + 1);                     \
     hipLaunchKernelGGL((k_inv_table<T>), dim3((np + 255) / 256), dim3(256), 0, s, diag, idg, np);               \
     return hipGetLastError();                                                                                   \
   }                                                                                                             \
@@ -2452,8 +2639,8 @@ static hipError_t visc_dim_p(const double* u, const double* add, double* out, do
                              const EqP& q, const double* tab, hipStream_t s) {
   using L = EL<DIM, P>;
   const long vs = (long)g.E * L::NP;
-  hipLaunchKernelGGL((k_visc_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, trace, g, q, tab, vs);
-  hipLaunchKernelGGL((k_visc_apply<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NT), 0, s, u, out, trace, g, q, tab,
+  hipLaunchKernelGGL((k_visc_trace<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NTF), 0, s, u, trace, g, q, tab, vs);
+  hipLaunchKernelGGL((k_visc_apply<DIM, P>), dim3(elem_tiles<DIM, P>(g)), dim3(L::NTF), 0, s, u, out, trace, g, q, tab,
                      vs, add);
   return hipGetLastError();
 }

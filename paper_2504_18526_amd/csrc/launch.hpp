@@ -33,6 +33,10 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
                          const Geo& g, const T* tab, hipStream_t s);                                            \
   hipError_t launch_helm_diag(T* diag, int nv, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab,    \
                               hipStream_t s);                                                                   \
+  /* diag[0, NP) = the diagonal of M + dtm K_D on the first element of component 0 only (an isotropic level:   \
+     the same on every element and component), then idg = 1 / diag there */                                     \
+  hipError_t launch_iso_inv_diag(T* diag, T* idg, const CoefT<T>& cf, T dtm, T ctau, const Geo& g, const T* tab, \
+                                 hipStream_t s);                                                                \
   hipError_t launch_cg_start(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,     \
                              hipStream_t s);                                                                    \
   hipError_t launch_cg_iter(const CGStateT<T>& cg, int nv, const CoefT<T>& cf, const Geo& g, const T* tab,      \
@@ -41,7 +45,6 @@ hipError_t launch_conv(const double* u, double* out, const Geo& g, const EqP& q,
      the neighbours' face fluxes itself (no trace pass) and may scale its operand node by node by isc (NP       \
      values); the streaming CG kernels never store z = r idg (idg: NP-periodic inverse Jacobi diagonal). */      \
   bool sipg_iso_path(const Geo& g, const CoefT<T>& cf);                                                         \
-  hipError_t launch_inv_table(const T* diag, T* idg, int np, hipStream_t s);                                    \
   hipError_t launch_sipg_apply_iso(const T* x, const T* isc, T* out, int nv, const CoefT<T>& cf, T alpha,       \
                                    T beta, T ctau, const Geo& g, const T* tab, T* part, const int* done_gen,    \
                                    int id, hipStream_t s);                                                      \

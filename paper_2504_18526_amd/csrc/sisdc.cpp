@@ -751,8 +751,10 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
     cg.mass_total = (T)L.mass_total;
     if (L.nv > kMaxComp) fail(SISDC_EINVAL, "internal: more components than the conservation sums hold");
   }
-  HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
-  if (iso) HIPCHECK(launch_inv_table(B.diag, B.idg, L.np, s));
+  if (iso)
+    HIPCHECK(launch_iso_inv_diag(B.diag, B.idg, cf, dtm, ctau, L.g, B.tab, s));
+  else
+    HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
   if (x_is_zero) {  // start from x = 0, so A x0 = 0
     HIPCHECK(hipMemsetAsync(x, 0, L.vlen * sizeof(T), s));
     HIPCHECK(hipMemsetAsync(B.w, 0, L.vlen * sizeof(T), s));
@@ -2616,8 +2618,10 @@ int sisdc_profile_kernel(sisdc_handle* h, int kernel, int level, double dt_m, in
     CGState cg = cg_state<double>(h, bufs64(h, L), L.b, L.t2, 0.0);
     // the kernels the PCG of this level runs (isotropic hexahedral path or general path)
     const bool iso = sipg_iso_path(L.g, cf);
-    HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
-    if (iso) HIPCHECK(launch_inv_table(L.diag, L.idg, L.np, s));
+    if (iso)
+      HIPCHECK(launch_iso_inv_diag(L.diag, L.idg, cf, dt_m, h->ctau, L.g, L.tab, s));
+    else
+      HIPCHECK(launch_helm_diag(L.diag, L.nv, cf, dt_m, h->ctau, L.g, L.tab, s));
     HIPCHECK(launch_sipg(L.t2, L.cw, L.nv, cf, L.trace, 1.0, dt_m, h->ctau, L.g, L.tab, s));
     if (iso) {
       HIPCHECK(launch_cg_start_iso(cg, L.idg, L.nv, L.g, nullptr, L.mw, s));
