@@ -135,6 +135,11 @@ struct Transfer {  // between level i (fine) and i+1 (coarse)
 
 }  // namespace
 
+// Offset of the convergence word behind the result record, in the device
+// block that holds both and in their pinned host mirror.
+constexpr size_t kDoneOffset = 128;
+static_assert(sizeof(CGRes) <= kDoneOffset, "the result record fits before the convergence word");
+
 struct sisdc_handle {
   sisdc_problem prob{};
   sisdc_method meth{};
@@ -815,8 +820,12 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
       }
       if (timed) HIPCHECK(hipEventRecord(ev[2], s));
     }
-    HIPCHECK(hipMemcpyAsync(h->hres, B.res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(h->hdone, B.done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
+    if ((const char*)B.done_gen == (const char*)B.res + kDoneOffset) {  // one copy for both
+      HIPCHECK(hipMemcpyAsync(h->hres, B.res, kDoneOffset + sizeof(int), hipMemcpyDeviceToHost, s));
+    } else {
+      HIPCHECK(hipMemcpyAsync(h->hres, B.res, sizeof(CGRes), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(h->hdone, B.done_gen, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     HIPCHECK(hipStreamSynchronize(s));
     const bool done = *h->hdone == id;
     if (timed) {
@@ -2097,18 +2106,17 @@ int sisdc_create(const sisdc_problem* prob, const sisdc_method* meth, void* hip_
     h->partials32 = (float*)pf;
     h->alpha32 = h->partials32 + 7 * kElemCap;
     h->alpha = dalloc(2);
-    void* pi = nullptr;
-    if (hipMalloc(&pi, 64) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
-    h->done_gen = (int*)pi;
-    HIPCHECK(hipMemset(h->done_gen, 0, 64));
+    // the result record and the convergence word in one block, at the
+    // offsets of their pinned host mirrors, so one copy brings both back
     void* pr = nullptr;
-    if (hipMalloc(&pr, sizeof(CGRes)) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    if (hipMalloc(&pr, 256) != hipSuccess) fail(SISDC_ENOMEM, "hipMalloc failed");
+    HIPCHECK(hipMemset(pr, 0, 256));
     h->res = (CGRes*)pr;
-    HIPCHECK(hipMemset(h->res, 0, sizeof(CGRes)));
+    h->done_gen = (int*)((char*)pr + kDoneOffset);
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 256) != hipSuccess) fail(SISDC_ENOMEM, "hipHostMalloc failed");
     h->hres = (CGRes*)hp;
-    h->hdone = (int*)((char*)hp + 128);
+    h->hdone = (int*)((char*)hp + kDoneOffset);
     h->hlam = (double*)((char*)hp + 192);
     h->hir_tot = (double*)((char*)hp + 208 + 16);
     h->hnrej = (int*)((char*)hp + 248);
@@ -2179,8 +2187,7 @@ int sisdc_destroy(sisdc_handle* h) {
   if (h->ir_tot) (void)hipFree(h->ir_tot);
   if (h->gtot) (void)hipFree(h->gtot);
   if (h->nrej) (void)hipFree(h->nrej);
-  if (h->done_gen) (void)hipFree(h->done_gen);
-  if (h->res) (void)hipFree(h->res);
+  if (h->res) (void)hipFree(h->res);  // the block that holds done_gen too
   if (h->hres) (void)hipHostFree(h->hres);
   if (h->lam_dev) (void)hipFree(h->lam_dev);
   if (h->ppart) (void)hipFree(h->ppart);
