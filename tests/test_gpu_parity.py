@@ -63,6 +63,10 @@ OPS = [
     ("euler", 3, (3, 2, 2), 1),
     ("euler", 2, (3, 2), 8),
     ("ns", 2, (1, 4), 3),
+    # more face nodes than nodes per workgroup (the face-task kernels run
+    # max(nodes, face nodes) threads), and a last workgroup with empty slots
+    ("ns", 3, (2, 2, 3), 2),
+    ("ns", 2, (3, 3), 2),
 ]
 
 
