@@ -1,10 +1,10 @@
 """The library's largest shapes against the oracle, through the C ABI:
 degree P = 8 on hexahedra (729 nodes per element, the largest element
-tile) for the convective operator, f, the SIPG and Helmholtz operators and
-a Helmholtz solve, for a scalar equation and a system; M = 8 collocation
-nodes (the most the tables take) in a three-level step; and the smallest
-meshes (one element along an axis, where an element is its own
-neighbour)."""
+tile) for the convective operator, f (with the viscous term for
+Navier-Stokes), the SIPG and Helmholtz operators and a Helmholtz solve,
+for a scalar equation and two systems; M = 8 collocation nodes (the most
+the tables take) in a three-level step; and the smallest meshes (one
+element along an axis, where an element is its own neighbour)."""
 import numpy as np
 import pytest
 
@@ -34,7 +34,7 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("eq,n", [("burgers", (2, 1, 2)), ("euler", (1, 2, 2))])
+@pytest.mark.parametrize("eq,n", [("burgers", (2, 1, 2)), ("euler", (1, 2, 2)), ("ns", (1, 2, 1))])
 def test_hexahedra_of_degree_8(S, eq, n):
     dim, P = 3, 8
     lo = [0.0] * dim
