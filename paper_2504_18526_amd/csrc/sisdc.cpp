@@ -95,6 +95,15 @@ struct Level {
   float *ub32 = nullptr, *r32 = nullptr, *e32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
         *cs32 = nullptr, *cw32 = nullptr, *diag32 = nullptr, *trace32 = nullptr;
   float* idg32 = nullptr;
+  // Inverse Jacobi diagonals of the isotropic solves, by (dt_m, nu, C_tau):
+  // the same few recur within a time step (both stages of a node, every
+  // sweep), and each is formed once.
+  struct IdgCache {
+    static constexpr int kSlots = 8;
+    void* tab = nullptr;  // kSlots tables of NP values
+    double key[kSlots][3] = {};
+    int n = 0, next = 0;
+  } idgc64, idgc32;
   // learned initial guess (element-local MLP), see sisdc_net_*
   struct Net {
     bool on = false;          // initialised
@@ -725,6 +734,26 @@ bool persistent_solve(sisdc_handle* h, Level& L, const CoefP& cf, double dtm, co
 // Multi-kernel Jacobi-PCG (Chronopoulos-Gear form) in precision T; x holds
 // the initial guess on entry.  Iterations are enqueued in batches; the host
 // reads the convergence record once per batch.  Returns the iterations, the
+// The inverse Jacobi diagonal of an isotropic solve: from the level's cache
+// when the level's own buffers serve the solve, else formed into B.idg.
+template <typename T>
+const T* iso_idg(sisdc_handle* h, Level& L, const CGBufs<T>& B, const CoefT<T>& cf, T dtm, T ctau) {
+  constexpr bool f64 = std::is_same<T, double>::value;
+  Level::IdgCache& C = f64 ? L.idgc64 : L.idgc32;
+  if (!C.tab || (const void*)B.idg != (f64 ? (const void*)L.idg : (const void*)L.idg32)) {
+    HIPCHECK(launch_iso_inv_diag(B.diag, B.idg, cf, dtm, ctau, L.g, B.tab, h->stream));
+    return B.idg;
+  }
+  const double key[3] = {(double)dtm, (double)cf.nu, (double)ctau};
+  T* const tab = (T*)C.tab;
+  for (int k = 0; k < C.n; ++k)
+    if (C.key[k][0] == key[0] && C.key[k][1] == key[1] && C.key[k][2] == key[2]) return tab + (long)k * L.np;
+  const int k = C.n < Level::IdgCache::kSlots ? C.n++ : (C.next++ % Level::IdgCache::kSlots);
+  for (int j = 0; j < 3; ++j) C.key[k][j] = key[j];
+  HIPCHECK(launch_iso_inv_diag(B.diag, tab + (long)k * L.np, cf, dtm, ctau, L.g, B.tab, h->stream));
+  return tab + (long)k * L.np;
+}
+
 // convergence flag and the final relative (recurred) residual.
 template <typename T>
 // b == NULL: the right-hand side is the combination bl (isotropic levels
@@ -756,10 +785,8 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
     cg.mass_total = (T)L.mass_total;
     if (L.nv > kMaxComp) fail(SISDC_EINVAL, "internal: more components than the conservation sums hold");
   }
-  if (iso)
-    HIPCHECK(launch_iso_inv_diag(B.diag, B.idg, cf, dtm, ctau, L.g, B.tab, s));
-  else
-    HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
+  const T* const idg = iso ? iso_idg<T>(h, L, B, cf, dtm, ctau) : nullptr;
+  if (!iso) HIPCHECK(launch_helm_diag(B.diag, L.nv, cf, dtm, ctau, L.g, B.tab, s));
   if (x_is_zero) {  // start from x = 0, so A x0 = 0
     HIPCHECK(hipMemsetAsync(x, 0, L.vlen * sizeof(T), s));
     HIPCHECK(hipMemsetAsync(B.w, 0, L.vlen * sizeof(T), s));
@@ -778,9 +805,9 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
   };
   cg.zs = zfds;
   if (iso) {
-    HIPCHECK(launch_cg_start_iso(cg, B.idg, L.nv, L.g, b ? nullptr : bl, L.mw, s));
+    HIPCHECK(launch_cg_start_iso(cg, idg, L.nv, L.g, b ? nullptr : bl, L.mw, s));
     if (zfds) fds_step(0, nullptr, 0);
-    HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : B.idg, B.w, L.nv, cf, one, dtm, ctau, L.g,
+    HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : idg, B.w, L.nv, cf, one, dtm, ctau, L.g,
                                    B.tab, cg.del, (const int*)nullptr, 0, s));
   } else {
     HIPCHECK(launch_cg_start(cg, L.nv, cf, L.g, B.tab, s));
@@ -805,14 +832,14 @@ sisdc_solve_stats cg_multi(sisdc_handle* h, Level& L, const CGBufs<T>& B, const 
       hipEvent_t* ev = timed ? &h->mev[3 * (it - first)] : nullptr;
       if (timed) HIPCHECK(hipEventRecord(ev[0], s));
       if (iso)
-        HIPCHECK(launch_cg_iter_iso(cg, B.idg, L.nv, L.g, it, id, s));
+        HIPCHECK(launch_cg_iter_iso(cg, idg, L.nv, L.g, it, id, s));
       else
         HIPCHECK(launch_cg_iter(cg, L.nv, cf, L.g, B.tab, it, id, s));
       if (timed) HIPCHECK(hipEventRecord(ev[1], s));
       if (it < maxit) {
         if (zfds) fds_step(it + 1, (const int*)B.done_gen, id);
         if (iso)
-          HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : B.idg, B.w, L.nv, cf, one, dtm, ctau,
+          HIPCHECK(launch_sipg_apply_iso(zfds ? zfds : B.r, zfds ? nullptr : idg, B.w, L.nv, cf, one, dtm, ctau,
                                          L.g, B.tab, cg.del, (const int*)B.done_gen, id, s));
         else
           HIPCHECK(launch_sipg_apply(B.z, B.w, L.nv, cf, B.trace, one, dtm, ctau, L.g, B.tab, B.z, cg.del,
@@ -1727,6 +1754,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
   L.cw = dalloc(n);
   L.trace = dalloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
   L.idg = dalloc(L.np);
+  L.idgc64.tab = dalloc((size_t)Level::IdgCache::kSlots * L.np);
   if (L.nv == 1) {  // the persistent PCG serves scalar equations only
     const size_t words = (size_t)2 * 2 * L.nv * L.E * 2 * pr.dim * g.nf;
     void* pz = nullptr;
@@ -1757,6 +1785,7 @@ void build_level(sisdc_handle* h, Level& L, int P, int M, const int* ne) {
     L.diag32 = falloc(n);
     L.trace32 = falloc((size_t)L.nv * L.E * 2 * pr.dim * g.nf);
     L.idg32 = falloc(L.np);
+    L.idgc32.tab = falloc((size_t)Level::IdgCache::kSlots * L.np);
   }
   HIPCHECK(hipMemset(L.u, 0, (M + 1) * n * sizeof(double)));
   HIPCHECK(hipMemset(L.gf, 0, M * n * sizeof(double)));
@@ -1769,6 +1798,8 @@ void free_level(Level& L) {
     if (p) (void)hipFree(p);
   if (L.fz) (void)hipFree(L.fz);
   if (L.ft) (void)hipFree(L.ft);
+  if (L.idgc64.tab) (void)hipFree(L.idgc64.tab);
+  if (L.idgc32.tab) (void)hipFree(L.idgc32.tab);
   float* fptrs[] = {L.idg32, L.tab32, L.ub32, L.r32, L.e32, L.cr32, L.cz32, L.cp32, L.cs32, L.cw32, L.diag32, L.trace32,
                     L.net.theta, L.net.m, L.net.v, L.net.g, L.net.Xd, L.net.Td, L.net.Z1, L.net.A1, L.net.Z2,
                     L.net.A2, L.net.Y, L.net.dY, L.net.dA, L.net.dZ, L.net.Xi, L.net.A1i, L.net.A2i, L.net.Yi,
