@@ -209,14 +209,13 @@ __device__ __forceinline__ void face_neighbours(const Geo& g, int e0, int* snb) 
 // node threads subtract it; the neighbours of the workgroup's elements are
 // found once.
 template <int DIM, int P, int NV>
-__global__ void __launch_bounds__((EL<DIM, P>::NTF))
+__global__ void __launch_bounds__((EL<DIM, P>::NTF), 6)
 k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
        const double* __restrict__ tab, long vs) {
   using L = EL<DIM, P>;
   constexpr int N1 = L::N1, NP = L::NP, NF = L::NF, EPB = L::EPB, NFC = 2 * DIM;
   __shared__ double sD[N1 * N1], sw[N1];
   __shared__ double sf[EPB * NV * NP];
-  __shared__ double su[EPB * NV * NP];
   __shared__ double sF[EPB * NFC * NF * NV];
   __shared__ int snb[EPB * NFC];
   u += (long)blockIdx.y * NV * vs;  // node blockIdx.y of a batch of node vectors
@@ -234,10 +233,7 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
   if (t < N1) sw[t] = wv;
   int ii[3];
   decomp<DIM, N1>(n, ii);
-  for (int v = 0; v < NV; ++v) {
-    acc[v] = 0.0;
-    if (act) su[(le * NV + v) * NP + n] = uu[v];
-  }
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   __syncthreads();
   // face tasks, a thread per (element, face, face node): the neighbour's
   // state at the face node of task k
@@ -289,7 +285,7 @@ k_conv(const double* __restrict__ u, double* __restrict__ out, Geo g, EqP q,
       const double sgn = side ? 1.0 : -1.0;
       const int nown = face_node<DIM, N1>(d, fn, side ? P : 0);
       double ui[NV], fi[NV], fo[NV];
-      for (int v = 0; v < NV; ++v) ui[v] = su[(l * NV + v) * NP + nown];
+      for (int v = 0; v < NV; ++v) ui[v] = u[v * vs + (long)(e0 + l) * NP + nown];  // in L2 (read by this workgroup)
       flux<NV>(q, d, ui, fi);
       flux<NV>(q, d, uo, fo);
       const double lam = fmax(wave_speed<NV>(q, d, ui), wave_speed<NV>(q, d, uo));
