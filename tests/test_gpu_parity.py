@@ -312,6 +312,29 @@ def test_steps(S, case, variant):
     assert np.max(np.abs(fine.dg.integral(got) - mass0)) < 1e-12 * max(1.0, np.max(np.abs(mass0)))
 
 
+def test_steps_with_changing_dt(S):
+    """Time steps of changing size on an isotropic level (pure diffusion,
+    multi-kernel PCG): the library forms each inverse Jacobi diagonal once
+    per (dt_m, nu) and reuses it, also for a step size seen before."""
+    eq, dim, n, P, M, K = "convdiff", 3, (2, 3, 2), 3, 3, 3
+    lo, hi = [0.0] * dim, [1.0, 1.25, 1.5]
+    a = (0.0, 0.0, 0.0)
+    phys = oracle_phys(eq, dim, a=a, nu=0.05)
+    lv = DGLevel(phys, n, lo, hi, P, M, rtol=1e-14)
+    meth = S.make_method([P], [M], n_iter=K, cg_rtol=1e-14, cg_maxit=5000, cg_variant=S.CG_MULTI_KERNEL)
+    sv = S.Solver(lib_problem(S, eq, dim, n, lo, hi, a=a, nu=0.05), meth)
+    u = smooth_state(phys, lv, np.random.default_rng(71))
+    sv.set_state(dev(u.ravel()))
+    out = torch.empty(u.size, dtype=torch.float64, device="cuda")
+    for k, dt in enumerate([0.02, 0.01, 0.02, 0.005, 0.01]):
+        st = sv.step(dt)
+        u = osdc.sdc_step(lv, u, dt, K)
+        sv.get_state(out)
+        assert rel_l2(host(out), u) < TOL, (k, dt)
+        assert st["not_converged"] == 0
+    sv.close()
+
+
 # ---------------------------------------------------------------- IMEX Euler
 @pytest.mark.parametrize("variant", ["auto", "multi"])
 @pytest.mark.parametrize("case", ["convdiff_sl", "burgers_2l_cascade", "euler_3l_fmg", "ns_3d_2l"])
