@@ -42,9 +42,9 @@ MEASURED_TRAFFIC = {
     # profiles/hbm_traffic_cg_iter_iso_ns3d_taylor_green_16x16x16_P7-3.md (full-work dispatches)
     ("ns3d_taylor_green_mlsdc_16^3_P7-3_M4-2", "k_cg_iter_iso<512>"):
         {"fetch_kib": 176087.4, "write_kib": 284908.7, "src": "c38f10cbdb2c0e1c"},
-    # profiles/hbm_traffic_pcg_persistent_burgers2d_32x32_P8-4.md (timed-region dispatches)
+    # profiles/hbm_traffic_pcg_persistent_burgers2d_32x32_P8-4.md (the first 52 steps)
     ("burgers2d_mlsdc_32x32_P8-4_M5-3", "k_pcg_persistent<2,8,1>"):
-        {"fetch_kib": 16690.32, "write_kib": 53996.72, "src": "4118bc0ba6c77eb1"},
+        {"fetch_kib": 13661.7, "write_kib": 42690.7, "src": "97801ce289ad5faa"},
 }
 TRAFFIC_SOURCES = {
     "k_pcg_persistent": ["pcg_persistent.hip", "common.hpp", "xcd.hpp"],
