@@ -100,6 +100,10 @@ def parse():
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
                     help="only launch the fine level's CG matvec and vector update REPS times each, back to back "
                          "(for profiler counter runs), print their average times and exit")
+    ap.add_argument("--net-forward-only", type=int, default=0, metavar="REPS",
+                    help="only run the fine level's element network forward (BF16, then FP32) REPS times each on "
+                         "all of its rows, hidden width --net-hidden (for MFMA counter runs), print times and exit")
+    ap.add_argument("--net-hidden", type=int, default=256)
     ap.add_argument("--workload", default="ns",
                     help="ns (default: the two-level 3-D Navier-Stokes workload), burgers, convdiff, euler, "
                          "batch (64 independent instances)")
@@ -488,6 +492,24 @@ def main():
     ud = torch.from_numpy(u0).to(dev)
     sv.set_state(ud)
     dt = w["dt"]
+    if a.net_forward_only > 0:
+        rows = nv * E
+        sv.net_init(0, a.net_hidden, seed=1, max_batch=rows, max_rows=rows)
+        gen = torch.Generator(device=dev).manual_seed(5)
+        X = torch.randn(rows, Np, dtype=torch.float32, device=dev, generator=gen)
+        Y = torch.empty_like(X)
+        rec = {"workload": w["name"], "rows": rows, "inputs": Np, "hidden": a.net_hidden}
+        for name, bf16 in (("bf16_ms", True), ("fp32_ms", False)):
+            sv.net_forward(0, X, Y, bf16=bf16)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.net_forward_only):
+                sv.net_forward(0, X, Y, bf16=bf16)
+            torch.cuda.synchronize()
+            rec[name] = 1000.0 * (time.perf_counter() - t0) / a.net_forward_only
+        print(json.dumps(rec), flush=True)
+        sv.close()
+        return
     if a.kernels_only > 0:
         sv.update_step_params()
         rec = {"workload": w["name"], "dt_m": dt / M}
