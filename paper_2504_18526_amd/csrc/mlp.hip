@@ -46,13 +46,13 @@ typedef short shortx8 __attribute__((ext_vector_type(8)));
 
 template <bool BF16>
 struct GemmTile {
-  static constexpr int TM = 64, TN = 64, TK = 32;
+  static constexpr int TM = 64, TN = 64, TK = BF16 ? 128 : 64;  // K slab: four (BF16) or sixteen (FP32) MFMA steps
   static constexpr int LD = BF16 ? TK + 8 : TK + 4;  // padded row (k) length; 16-byte aligned rows
   using E = typename std::conditional<BF16, short, float>::type;
 };
 
 template <bool BF16>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 4)
 k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
        int transB, float* __restrict__ C, int ldc, const float* __restrict__ bias, int relu) {
   using G = GemmTile<BF16>;
@@ -74,7 +74,7 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, co
   for (int k0 = 0; k0 < K; k0 += TK) {
     // stage: 2048 values of each operand, 8 per thread, consecutive threads
     // along the operand's contiguous global axis
-#pragma unroll
+#pragma unroll 8
     for (int st = 0; st < (TM * TK) / 256; ++st) {
       const int idx = t + 256 * st;
       int i, k;
@@ -104,14 +104,19 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, co
     }
     __syncthreads();
     if constexpr (BF16) {
-      bf16x8 av[2], bv[2];
-      for (int a = 0; a < 2; ++a)
-        av[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8*>(&sA[(wi + 16 * a + r) * LD + 8 * q]));
-      for (int b = 0; b < 2; ++b)
-        bv[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8*>(&sB[(wj + 16 * b + r) * LD + 8 * q]));
-      for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 32) {
+        bf16x8 av[2], bv[2];
+        for (int a = 0; a < 2; ++a)
+          av[a] = __builtin_bit_cast(bf16x8,
+                                     *reinterpret_cast<const shortx8*>(&sA[(wi + 16 * a + r) * LD + kk + 8 * q]));
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+          bv[b] = __builtin_bit_cast(bf16x8,
+                                     *reinterpret_cast<const shortx8*>(&sB[(wj + 16 * b + r) * LD + kk + 8 * q]));
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     } else {
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
