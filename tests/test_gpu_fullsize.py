@@ -23,6 +23,10 @@
   the same state at the 1e-12 bar (PCG tolerance 1e-14), and the 100-step
   solution at the production tolerance against both the oracle's and the
   exact Fourier solution.
+* The shock workload (the Sod pair with artificial viscosity, 160 x 1
+  elements, P 5/3, M 7/5): two steps against the oracle at the 1e-12 bar.
+* The stacked 64-instance Burgers ensemble in the bench configuration: one
+  step, three sampled instances against the oracle at the 1e-8 bar.
 * The 64-instance batch: one batch step, every instance conserving its
   mass to round-off, and finite.
 """
@@ -322,4 +326,88 @@ def test_euler_workload_step_matches_oracle(S):
     assert rel_l2(got, ref) < 1e-12
     d = np.abs(got - ref).reshape(nv, E, Np).max(axis=(0, 2))
     assert d.max() <= 1e-11 * np.abs(ref).max()
+    sv.close()
+
+
+def test_sod_workload_steps_match_oracle(S):
+    """The shock workload at its full size (the periodic pair of Sod tubes,
+    160 x 1 elements, P 5/3, M 7/5, cascade start, 2 V-cycles + post-sweep,
+    artificial viscosity kappa_s = 2, c_s = 0.4): two steps, each against
+    the oracle's step from the same state at the 1e-12 bar (PCG tolerance
+    1e-14 on both sides), element by element, with density and pressure
+    positive.  The jumps of the initial state lie on element interfaces, so
+    the sensor stays off in the first step; in the second, the elements that
+    the fronts have entered carry the viscosity."""
+    from oracle.physics import Euler
+    from paper_2504_18526_amd.inputs import sod_pair
+    from paper_2504_18526_amd.workloads import sod_2level
+    w = sod_2level()
+    prob = S.make_problem(2, w["n_elem"], w["lo"], w["hi"], S.EQ_EULER, gamma=w["gamma"])
+    meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+                         post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=1e-14, cg_maxit=5000, av=w["av"])
+    sv = S.Solver(prob, meth)
+    E, Np, nv, M = sv.level_info(0)
+    ph = Euler(2, w["gamma"])
+    lv = [DGLevel(ph, w["n_elem"], w["lo"], w["hi"], P, Mm, rtol=1e-14) for P, Mm in zip(w["P"], w["M"])]
+    x = lv[0].coords()
+    h = (w["hi"][0] - w["lo"][0]) / w["n_elem"][0]
+    u = sod_pair([x[0], x[1]], h, gamma=w["gamma"])
+    ud = torch.from_numpy(np.ascontiguousarray(u.reshape(-1))).cuda()
+    sv.set_state(ud)
+    ml = MLSDC(list(reversed(lv)), n_coarse=w["n_coarse"], start="cascade", cycles=w["cycles"], post_sweep=True,
+               av=w["av"])
+    out = torch.empty_like(ud)
+    for k in range(2):
+        st = sv.step(w["dt"])
+        assert st["not_converged"] == 0
+        u = ml.step(u, w["dt"])
+        sv.get_state(out)
+        got = out.cpu().numpy().reshape(u.shape)
+        assert rel_l2(got, u) < 1e-12, k
+        d = np.abs(got - u).reshape(nv, E, Np).max(axis=(0, 2))
+        assert d.max() <= 1e-11 * np.abs(u).max(), k
+    # the second step ran with the viscosity of the first step's fronts on a few elements
+    assert 0 < np.count_nonzero(lv[0].av) < E * Np
+    rho = got[0]
+    p = (w["gamma"] - 1.0) * (got[3] - 0.5 * (got[1] ** 2 + got[2] ** 2) / rho)
+    assert rho.min() > 0.0 and p.min() > 0.0
+    sv.close()
+
+
+def test_ensemble_workload_sampled_instances_match_oracle(S):
+    """The stacked 64-instance Burgers ensemble at its full size, in the
+    configuration the bench times (persistent PCG, tolerance 1e-10, no
+    conservation shift): one step of all 64 instances in one handle, every
+    instance finite, and the first, a middle and the last instance against
+    the oracle stepping that instance alone at the same tolerance (the 1e-8
+    bar of the production tolerance)."""
+    from oracle.physics import Burgers
+    from paper_2504_18526_amd.inputs import burgers_field
+    from paper_2504_18526_amd.workloads import burgers_ensemble
+    w = burgers_ensemble()
+    B = w["stack"]
+    prob = S.make_problem(2, w["n_elem"], w["lo"], w["hi"], S.EQ_BURGERS, nu=w["nu"], stack=B)
+    meth = S.make_method(w["P"], w["M"], start=S.START_CASCADE, n_coarse_sweeps=w["n_coarse"],
+                         post_sweep=w["post_sweep"], n_iter=w["cycles"], cg_rtol=w["cg_rtol"], cg_maxit=2000,
+                         conserve=w["conserve"])
+    sv = S.Solver(prob, meth)
+    E, Np, nv, M = sv.level_info(0)
+    Ei = E // B
+    ph = Burgers(2, w["nu"])
+    lv = [DGLevel(ph, w["n_elem"], w["lo"], w["hi"], P, Mm, rtol=w["cg_rtol"]) for P, Mm in zip(w["P"], w["M"])]
+    assert Ei == lv[0].mesh.E
+    x = lv[0].coords()
+    u0 = [burgers_field([x[0], x[1]], seed=w["seed"] + k, kmax=w["kmax"])[None] for k in range(B)]
+    ud = torch.from_numpy(np.concatenate([u.reshape(-1) for u in u0])).cuda()
+    sv.set_state(ud)
+    st = sv.step(w["dt"])
+    assert st["not_converged"] == 0
+    out = torch.empty_like(ud)
+    sv.get_state(out)
+    assert bool(torch.isfinite(out).all())
+    got = out.cpu().numpy().reshape(B, -1)
+    for k in (0, B // 2 - 1, B - 1):
+        ml = MLSDC(list(reversed(lv)), n_coarse=w["n_coarse"], start="cascade", cycles=w["cycles"], post_sweep=True)
+        ref = ml.step(u0[k].reshape(lv[0].shape()), w["dt"])
+        assert rel_l2(got[k], ref.reshape(-1)) < 1e-8, k
     sv.close()
