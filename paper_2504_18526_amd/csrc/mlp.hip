@@ -10,6 +10,7 @@
 // b3, row-major [out][in].
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "common.hpp"
@@ -35,7 +36,10 @@ __device__ __forceinline__ short to_bf16(float f) {
 // LDS, k contiguous, rounded to bfloat16 on the way in (BF16) or kept in
 // FP32, and the waves read their operands from there.  Out-of-range
 // operands are staged as 0 and out-of-range results are not stored.  BF16:
-// FP32 accumulation.
+// FP32 accumulation.  VEC: op(A) and op(B)^T are k-contiguous in memory
+// (transA = 0, transB = 1; K, lda and ldb multiples of 4, A and B 16-byte
+// aligned, all checked at launch), so each thread stages four consecutive k
+// per load and per LDS store.
 //
 // MFMA operand layout (lane l of 64, r = l % 16, q = l / 16):
 //   16x16x32 bf16 (gfx950): A(row r, k 8q + t), B(k 8q + t, col r), t = 0..7;
@@ -43,6 +47,7 @@ __device__ __forceinline__ short to_bf16(float f) {
 //   result: lane l, register j holds row 4q + j, col r.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 template <bool BF16>
 struct GemmTile {
@@ -51,7 +56,7 @@ struct GemmTile {
   using E = typename std::conditional<BF16, short, float>::type;
 };
 
-template <bool BF16>
+template <bool BF16, bool VEC>
 __global__ void __launch_bounds__(256, 4)
 k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, const float* __restrict__ B, int ldb,
        int transB, float* __restrict__ C, int ldc, const float* __restrict__ bias, int relu) {
@@ -72,35 +77,57 @@ k_gemm(int M, int N, int K, const float* __restrict__ A, int lda, int transA, co
     else return v;
   };
   for (int k0 = 0; k0 < K; k0 += TK) {
-    // stage: 2048 values of each operand, 8 per thread, consecutive threads
-    // along the operand's contiguous global axis
+    if constexpr (VEC) {
+      // rows i of op(A) and of op(B)^T (TM = TN): four k per thread and step,
+      // consecutive threads along k; K % 4 == 0, so a group is all in or all out
+      constexpr int K4 = TK / 4;
+#pragma unroll
+      for (int st = 0; st < (TM * TK) / (4 * 256); ++st) {
+        const int idx = t + 256 * st;
+        const int i = idx / K4, k = 4 * (idx % K4), gk = k0 + k;
+        float4 v = {0.f, 0.f, 0.f, 0.f}, u = {0.f, 0.f, 0.f, 0.f};
+        if (i0 + i < M && gk < K) v = *reinterpret_cast<const float4*>(A + (long)(i0 + i) * lda + gk);
+        if (j0 + i < N && gk < K) u = *reinterpret_cast<const float4*>(B + (long)(j0 + i) * ldb + gk);
+        if constexpr (BF16) {
+          auto cvt = [](float4 f) { return shortx4{to_bf16(f.x), to_bf16(f.y), to_bf16(f.z), to_bf16(f.w)}; };
+          *reinterpret_cast<shortx4*>(&sA[i * LD + k]) = cvt(v);
+          *reinterpret_cast<shortx4*>(&sB[i * LD + k]) = cvt(u);
+        } else {
+          *reinterpret_cast<float4*>(&sA[i * LD + k]) = v;
+          *reinterpret_cast<float4*>(&sB[i * LD + k]) = u;
+        }
+      }
+    } else {
+      // stage: 2048 values of each operand, 8 per thread, consecutive threads
+      // along the operand's contiguous global axis
 #pragma unroll 8
-    for (int st = 0; st < (TM * TK) / 256; ++st) {
-      const int idx = t + 256 * st;
-      int i, k;
-      if (transA) {
-        k = idx / TM;
-        i = idx % TM;
-      } else {
-        i = idx / TK;
-        k = idx % TK;
+      for (int st = 0; st < (TM * TK) / 256; ++st) {
+        const int idx = t + 256 * st;
+        int i, k;
+        if (transA) {
+          k = idx / TM;
+          i = idx % TM;
+        } else {
+          i = idx / TK;
+          k = idx % TK;
+        }
+        const int gi = i0 + i, gk = k0 + k;
+        float v = 0.f;
+        if (gi < M && gk < K) v = transA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+        sA[i * LD + k] = put(v);
+        int j, kb;
+        if (transB) {
+          j = idx / TK;
+          kb = idx % TK;
+        } else {
+          kb = idx / TN;
+          j = idx % TN;
+        }
+        const int gj = j0 + j, gkb = k0 + kb;
+        float u = 0.f;
+        if (gj < N && gkb < K) u = transB ? B[(long)gj * ldb + gkb] : B[(long)gkb * ldb + gj];
+        sB[j * LD + kb] = put(u);
       }
-      const int gi = i0 + i, gk = k0 + k;
-      float v = 0.f;
-      if (gi < M && gk < K) v = transA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
-      sA[i * LD + k] = put(v);
-      int j, kb;
-      if (transB) {
-        j = idx / TK;
-        kb = idx % TK;
-      } else {
-        kb = idx / TN;
-        j = idx % TN;
-      }
-      const int gj = j0 + j, gkb = k0 + kb;
-      float u = 0.f;
-      if (gj < N && gkb < K) u = transB ? B[(long)gj * ldb + gkb] : B[(long)gkb * ldb + gj];
-      sB[j * LD + kb] = put(u);
     }
     __syncthreads();
     if constexpr (BF16) {
@@ -260,12 +287,15 @@ hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int transA,
                        float* C, int ldc, const float* bias, int relu, int bf16, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid((N + 63) / 64, (M + 63) / 64);
+  const bool vec = !transA && transB && K % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
+                   reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias, relu);
+  };
   if (bf16)
-    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
-                       relu);
+    vec ? go(k_gemm<true, true>) : go(k_gemm<true, false>);
   else
-    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, bias,
-                       relu);
+    vec ? go(k_gemm<false, true>) : go(k_gemm<false, false>);
   return hipGetLastError();
 }
 

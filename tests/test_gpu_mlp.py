@@ -42,10 +42,15 @@ def _random_net(S, sv, n, H, seed):
     return th, rng
 
 
+# (P, H): n = (P + 1)^2 inputs.  n = 25 stages operands one value at a time;
+# n = 16 and 64 with H = 40 and 136 take the four-wide staging (K % 4 == 0),
+# with ragged M, N and K tails (H = 136: two BF16 K slabs of 128, three FP32
+# slabs of 64, the last partial).
+@pytest.mark.parametrize("P,H", [(4, 40), (3, 40), (7, 136)])
 @pytest.mark.parametrize("rows", [1, 37, 100, 257])
-def test_forward_fp32_and_bf16(S, rows):
-    sv = small_solver(S)
-    n, H = 25, 40
+def test_forward_fp32_and_bf16(S, rows, P, H):
+    sv = small_solver(S, P=P)
+    n = (P + 1) ** 2
     sv.net_init(0, H, seed=1, max_batch=512, max_rows=0)
     th, rng = _random_net(S, sv, n, H, 11)
     X = rng.standard_normal((rows, n)).astype(np.float32)
@@ -61,10 +66,10 @@ def test_forward_fp32_and_bf16(S, rows):
     assert rel_l2(Y, y64) < 3e-2
 
 
-@pytest.mark.parametrize("rows", [7, 64, 200])
-def test_gradient_matches_oracle(S, rows):
-    sv = small_solver(S)
-    n, H = 25, 32
+@pytest.mark.parametrize("rows,P", [(7, 4), (64, 4), (200, 4), (200, 3)])
+def test_gradient_matches_oracle(S, rows, P):
+    sv = small_solver(S, P=P)
+    n, H = (P + 1) ** 2, 32
     sv.net_init(0, H, seed=2, max_batch=256, max_rows=0)
     th, rng = _random_net(S, sv, n, H, 12)
     X = rng.standard_normal((rows, n)).astype(np.float32)
